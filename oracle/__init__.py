@@ -1,0 +1,16 @@
+"""CPU oracle for the adaptive progressive compressor (test infrastructure only).
+
+A plain, slow, float64/int64 NumPy implementation of what the paper's method
+computes: multilevel interpolation decomposition (per-level and per-region,
+Section IV), error-bounded quantization of the coefficients, coefficient
+decomposition (Section V-B, Algorithm 1), generic bitplane encoding
+(Section VI-C), the retrieval interpreter with max ordering (Section V-C) and
+reconstruction (Algorithm 2), plus target-driven pipeline selection
+(Section VI-A).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+and never imports it; the two meet only on seeded inputs from ``fieldgen``.
+"""
+from .scheme import Scheme, Target  # noqa: F401
+from .pipeline import refactor, plan, retrieve, select_pipeline  # noqa: F401

@@ -1,0 +1,157 @@
+"""Generic bitplane encoding of integer coefficient streams (Section V-C;
+Section VI-C "optimized generic bitplane encoding"; Table I "generic
+bitplane").
+
+Sign-magnitude planes, most significant plane first.  A value's sign is
+recorded in the plane where its first 1-bit appears, so planes above a
+value's leading bit cost it nothing but its magnitude bit.  The paper gives no
+byte layout; the one used here (shared with the GPU path only through this
+written description) is:
+
+  n   = number of codes, B = bit length of max |q| (0 for an all-zero stream)
+  M   = ceil(n / 64) magnitude words per plane, C = ceil(n / 4096) chunks
+  plane j = 0 .. B-1 holds bit b = B-1-j.
+
+  index section  B*C little-endian uint32, plane-major: entry (j, c) = number
+                 of codes whose leading bit is b among codes [0, 4096*c)
+                 (lets a decoder place sign bits chunk by chunk); zero padded
+                 to a multiple of 8 bytes
+  magnitude      B*M little-endian uint64, plane-major: bit i of word w is
+                 bit b of |q[64*w + i]| (zero beyond n)
+  sign           plane-major, ceil(nsig_j / 64) uint64 words per plane: one
+                 bit per code whose leading bit is b, in stream order, least
+                 significant bit first, 1 = negative
+
+Fetching the first k planes reads k*C index entries, k*M magnitude words and
+the first k sign segments: bytes_j = 4*C + 8*M + 8*ceil(nsig_j / 64) per plane.
+Decoding k planes yields |q| with its low B-k bits cleared (truncation toward
+zero), so the error left by a stream after k planes is
+  delta(0) = max |q|,  delta(k) = 2**(B-k) - 1  (1 <= k <= B).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+CHUNK = 4096
+
+
+@dataclass
+class StreamMeta:
+    n: int
+    B: int
+    maxabs: int
+    nsig: List[int] = field(default_factory=list)
+
+    @property
+    def words(self) -> int:
+        return (self.n + 63) // 64
+
+    @property
+    def chunks(self) -> int:
+        return (self.n + CHUNK - 1) // CHUNK
+
+    def plane_bytes(self, j: int) -> int:
+        return 4 * self.chunks + 8 * self.words + 8 * ((self.nsig[j] + 63) // 64)
+
+    def delta(self, k: int) -> int:
+        if k <= 0:
+            return self.maxabs
+        return (1 << (self.B - k)) - 1
+
+
+def bitlength(mag: np.ndarray) -> np.ndarray:
+    """Bit length of each non-negative int64 (0 for 0), bit by bit."""
+    out = np.zeros(mag.shape, dtype=np.int64)
+    for b in range(63):
+        out[((mag >> b) & 1) == 1] = b + 1
+    return out
+
+
+def _pack_bits(bits: np.ndarray, nwords: int) -> bytes:
+    padded = np.zeros(nwords * 64, dtype=np.uint8)
+    padded[: bits.size] = bits
+    return np.packbits(padded, bitorder="little").tobytes()
+
+
+def _unpack_bits(buf: bytes, nbits: int) -> np.ndarray:
+    arr = np.frombuffer(buf, dtype=np.uint8)
+    return np.unpackbits(arr, bitorder="little")[:nbits].astype(np.int64)
+
+
+def encode(q: np.ndarray):
+    """Encode an int64 stream; returns (blob bytes, StreamMeta)."""
+    q = np.asarray(q, dtype=np.int64).ravel()
+    n = q.size
+    mag = np.abs(q)
+    maxabs = int(mag.max()) if n else 0
+    B = maxabs.bit_length()
+    meta = StreamMeta(n=n, B=B, maxabs=maxabs)
+    M, C = meta.words, meta.chunks
+    blen = bitlength(mag)
+    index_parts, mag_parts, sign_parts = [], [], []
+    for j in range(B):
+        b = B - 1 - j
+        bits = ((mag >> b) & 1).astype(np.uint8)
+        mag_parts.append(_pack_bits(bits, M))
+        newsig = blen == (b + 1)
+        meta.nsig.append(int(newsig.sum()))
+        signs = (q[newsig] < 0).astype(np.uint8)
+        sign_parts.append(_pack_bits(signs, (signs.size + 63) // 64))
+        before = np.concatenate([[0], np.cumsum(newsig.astype(np.int64))])
+        idx = np.array([before[min(CHUNK * c, n)] for c in range(C)], dtype="<u4")
+        index_parts.append(idx.tobytes())
+    index = b"".join(index_parts)
+    index += b"\0" * ((-len(index)) % 8)
+    blob = index + b"".join(mag_parts) + b"".join(sign_parts)
+    return blob, meta
+
+
+def section_offsets(meta: StreamMeta):
+    """Byte offsets (index, magnitude, sign) of the three sections of a blob."""
+    ib = 4 * meta.B * meta.chunks
+    ib += (-ib) % 8
+    return 0, ib, ib + 8 * meta.B * meta.words
+
+
+def decode(blob: bytes, meta: StreamMeta, k: int) -> np.ndarray:
+    """Decode the first k planes of a stream, reading magnitude and sign bits."""
+    n, B = meta.n, meta.B
+    k = max(0, min(int(k), B))
+    mag = np.zeros(n, dtype=np.int64)
+    neg = np.zeros(n, dtype=bool)
+    _, moff, soff = section_offsets(meta)
+    M = meta.words
+    for j in range(k):
+        b = B - 1 - j
+        w0 = moff + 8 * M * j
+        bits = _unpack_bits(blob[w0: w0 + 8 * M], n)
+        newsig = (mag == 0) & (bits == 1)
+        nwords = (meta.nsig[j] + 63) // 64
+        sbits = _unpack_bits(blob[soff: soff + 8 * nwords], meta.nsig[j])
+        soff += 8 * nwords
+        assert int(newsig.sum()) == meta.nsig[j]
+        neg[newsig] = sbits == 1
+        mag |= bits << b
+    return np.where(neg, -mag, mag)
+
+
+def read_index(blob: bytes, meta: StreamMeta) -> np.ndarray:
+    """Index section as a (B, C) uint32 array."""
+    C = meta.chunks
+    raw = np.frombuffer(blob[: 4 * meta.B * C], dtype="<u4")
+    return raw.reshape(meta.B, C) if meta.B else raw.reshape(0, C)
+
+
+def truncate(q: np.ndarray, B: int, k: int) -> np.ndarray:
+    """|q| with its low B-k bits cleared, sign kept (what decode(k) returns)."""
+    q = np.asarray(q, dtype=np.int64)
+    if k <= 0:
+        return np.zeros_like(q)
+    if k >= B:
+        return q.copy()
+    mask = ~np.int64((1 << (B - k)) - 1)
+    mag = np.abs(q) & mask
+    return np.where(q < 0, -mag, mag)
