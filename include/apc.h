@@ -1,0 +1,149 @@
+/*
+ * apc.h — C ABI of the MI355X (gfx950) adaptive progressive compressor.
+ *
+ * The method: a float field is refactored once into bitplane streams of
+ * quantized multilevel-interpolation coefficients (Section IV: per-level and
+ * per-region interpolation; Section V-B: coefficient decomposition;
+ * Section VI-C: generic bitplane encoding, Algorithm 1), and later retrieved
+ * progressively to a requested max-error bound or PSNR from only the planes
+ * that target needs (Section III-A problem statements; Section V-C error
+ * mapping and max ordering; Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns apc_status (0 = APC_OK, negative = error) and
+ *    never throws; apc_last_error() gives a message for the calling thread.
+ *  - Device pointers are HIP device addresses on the current device; host
+ *    pointers are plain host memory.  hip_stream is a hipStream_t (NULL =
+ *    the null stream); work is ordered on that stream.  Entry points that
+ *    return metadata synchronize the stream before returning.
+ *  - Fields are row-major with the last axis fastest, ndim 1..3.
+ *  - A handle is not thread-safe: callers serialize calls on one handle.
+ */
+#ifndef APC_H
+#define APC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apc_status;
+enum {
+  APC_OK = 0,
+  APC_E_INVALID = -1,        /* bad argument (dims, scheme, stream index, size) */
+  APC_E_DTYPE = -2,          /* dtype other than float32 / float64 */
+  APC_E_NONFINITE = -3,      /* field holds NaN or Inf (refactor rejects it) */
+  APC_E_BELOW_FLOOR = -4,    /* target tighter than the full representation */
+  APC_E_OOM = -5,            /* device allocation failed */
+  APC_E_HIP = -6,            /* HIP runtime error */
+  APC_E_BUSY = -7,           /* server admission refused (budget or queue full) */
+  APC_E_CORRUPT = -8,        /* serialized bytes fail their checks */
+  APC_E_NODEVICE = -9        /* no HIP device visible */
+};
+
+enum { APC_F32 = 0, APC_F64 = 1 };                 /* dtype */
+enum { APC_PER_LEVEL = 0, APC_PER_REGION = 1 };    /* apc_scheme.kind */
+enum { APC_EB_ABS = 0, APC_EB_REL = 1, APC_PSNR = 2, APC_RMSE_ABS = 3 };  /* apc_target.kind */
+enum { APC_MODE_EB = 0, APC_MODE_PSNR = 1 };       /* select_pipeline mode */
+
+/* Pipeline configuration (Table I: interpolation scheme, dimension order of
+ * per-region interpolation, coefficient-decomposition direction or none). */
+typedef struct {
+  int32_t kind;      /* APC_PER_LEVEL or APC_PER_REGION */
+  int32_t degree;    /* 1 = multilinear, 3 = cubic (Section IV) */
+  int32_t order[3];  /* per-region pass order, a permutation of 0..ndim-1
+                        (ignored for per-level, which goes fastest axis first) */
+  int32_t cd_axis;   /* -1 = no coefficient decomposition, else stacking axis
+                        0..ndim-1 (ndim >= 2) */
+  int32_t levels;    /* 0 = default L = 1 + ceil(log2(max dim - 1)) */
+} apc_scheme;
+
+/* Retrieval target (Section III-A).  APC_EB_ABS: max|x - x'| <= value;
+ * APC_EB_REL: max|x - x'| <= value * (max x - min x); APC_PSNR: PSNR in dB
+ * (20 log10(range / RMSE)) at least value; APC_RMSE_ABS: RMSE <= value. */
+typedef struct {
+  int32_t kind;
+  double value;
+} apc_target;
+
+typedef struct {
+  int64_t bytes_total;    /* S_tau: planes of the plan plus metadata */
+  int64_t bytes_fetched;  /* plane bytes this call decoded that earlier calls had not */
+  double bound;           /* error-model bound the plan achieves (max error or RMSE) */
+  double tau;             /* the absolute tolerance the plan was made for */
+  double bitrate;         /* 8 * bytes_total / n */
+  int32_t n_streams;
+  int32_t nsteps;         /* greedy steps taken */
+} apc_retrieve_info;
+
+typedef struct apc_handle apc_handle;
+
+/* Refactor a device-resident field (Algorithm 1).  field_dev: n elements of
+ * dtype (caller owned, read only, must stay valid until the stream passes
+ * this call).  On success *out owns every plane stream (device memory) and
+ * the host metadata; release it with apc_free.  The call synchronizes
+ * hip_stream (the quantization steps depend on global coefficient maxima).
+ * Errors: APC_E_INVALID (dims/scheme), APC_E_DTYPE, APC_E_NONFINITE,
+ * APC_E_OOM, APC_E_HIP; *out is untouched on error. */
+apc_status apc_refactor(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
+                        const apc_scheme* scheme, void* hip_stream, apc_handle** out);
+
+/* Plan only (Section V-C interpreter, host side, no device work): fills
+ * planes_out[n_streams] (may be NULL) and info.  APC_E_BELOW_FLOOR if the
+ * target cannot be met even with every plane. */
+apc_status apc_plan(apc_handle* h, const apc_target* target, int32_t* planes_out,
+                    apc_retrieve_info* info);
+
+/* Retrieve (Algorithm 2) to a target: plans, decodes the planes not yet
+ * decoded by earlier calls on this handle (incremental), recomposes and
+ * reconstructs into out_dev (n elements of the handle's dtype, caller owned).
+ * The result depends only on the plan, not on what earlier calls decoded.
+ * APC_E_BELOW_FLOOR leaves out_dev unwritten. */
+apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev,
+                        apc_retrieve_info* info, void* hip_stream);
+
+/* Retrieve with an explicit plane count per stream (planes[n_streams], each
+ * clamped to the stream's plane count). */
+apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream);
+
+/* Target-driven pipeline selection (Section VI-A): regular ~1% sample
+ * blocks, every candidate of Table I refactored on the sample, plan sizes at
+ * the nine tuning tolerances, majority vote (interpolation first, then the
+ * decomposition direction).  mode: APC_MODE_EB or APC_MODE_PSNR. */
+apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
+                               int32_t mode, apc_scheme* out, void* hip_stream);
+
+void apc_free(apc_handle* h);
+const char* apc_strerror(apc_status s);
+const char* apc_last_error(void);
+
+/* ---- introspection (tests, benchmarks, storage) ---------------------- */
+
+int32_t apc_num_streams(const apc_handle* h);
+int32_t apc_num_groups(const apc_handle* h);
+int64_t apc_num_points(const apc_handle* h);
+
+/* Stream s: code count, plane count B, max |code|, and its serialized size
+ * in bytes (index + magnitude + sign sections, as the format below). */
+apc_status apc_stream_info(const apc_handle* h, int32_t s, int64_t* n, int32_t* B, int64_t* maxabs,
+                           int64_t* blob_bytes);
+
+/* Copy stream s, serialized, to host memory (cap >= blob_bytes).  Layout:
+ * B*C uint32 index entries (C = ceil(n/4096)) padded to 8 bytes, then B*M
+ * uint64 magnitude words (M = ceil(n/64)), then the sign words of each
+ * plane, all little endian, planes most significant first. */
+apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64_t cap);
+
+/* Metadata as a JSON text (groups, streams, staircase, bounds). */
+apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_t* len);
+
+/* Host-only helper (no device needed): exact chain norms of the 1D
+ * interpolation chain on an axis of length n for levels 0..L-1, rounded to
+ * float64 (max row / column abs sums).  inf_out, one_out: L doubles. */
+apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out, double* one_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APC_H */

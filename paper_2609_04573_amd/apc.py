@@ -1,0 +1,258 @@
+"""ctypes binding of ``libapc.so`` (argument marshalling only).
+
+Every step of refactoring and retrieval runs in the library's HIP kernels;
+PyTorch only provides device memory and the current HIP stream.  There is no
+fallback: if the library is not built this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+APC_OK = 0
+APC_E_INVALID = -1
+APC_E_DTYPE = -2
+APC_E_NONFINITE = -3
+APC_E_BELOW_FLOOR = -4
+APC_E_OOM = -5
+APC_E_HIP = -6
+APC_E_BUSY = -7
+APC_E_CORRUPT = -8
+APC_E_NODEVICE = -9
+
+APC_F32, APC_F64 = 0, 1
+PER_LEVEL, PER_REGION = 0, 1
+TARGET_KINDS = {"abs": 0, "rel": 1, "psnr": 2, "rmse": 3}
+MODES = {"eb": 0, "psnr": 1}
+
+EXPORTED = [
+    "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline", "apc_free",
+    "apc_strerror", "apc_last_error", "apc_num_streams", "apc_num_groups", "apc_num_points", "apc_stream_info",
+    "apc_stream_blob", "apc_metadata_json", "apc_axis_norms",
+]
+
+
+class _Scheme(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("order", ctypes.c_int32 * 3),
+                ("cd_axis", ctypes.c_int32), ("levels", ctypes.c_int32)]
+
+
+class _Target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("bytes_total", ctypes.c_int64), ("bytes_fetched", ctypes.c_int64), ("bound", ctypes.c_double),
+                ("tau", ctypes.c_double), ("bitrate", ctypes.c_double), ("n_streams", ctypes.c_int32),
+                ("nsteps", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_lib.apc_refactor.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_Scheme), _vp, ctypes.POINTER(_vp)]
+_lib.apc_plan.argtypes = [_vp, ctypes.POINTER(_Target), ctypes.POINTER(_i32), ctypes.POINTER(_Info)]
+_lib.apc_retrieve.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
+_lib.apc_retrieve_planes.argtypes = [_vp, ctypes.POINTER(_i32), _vp, _vp]
+_lib.apc_select_pipeline.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, ctypes.POINTER(_Scheme), _vp]
+_lib.apc_free.argtypes = [_vp]
+_lib.apc_free.restype = None
+_lib.apc_strerror.argtypes = [_i32]
+_lib.apc_strerror.restype = ctypes.c_char_p
+_lib.apc_last_error.restype = ctypes.c_char_p
+_lib.apc_num_streams.argtypes = [_vp]
+_lib.apc_num_groups.argtypes = [_vp]
+_lib.apc_num_points.argtypes = [_vp]
+_lib.apc_num_points.restype = _i64
+_lib.apc_stream_info.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                 ctypes.POINTER(_i64)]
+_lib.apc_stream_blob.argtypes = [_vp, _i32, _vp, _i64]
+_lib.apc_metadata_json.argtypes = [_vp, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
+_lib.apc_axis_norms.argtypes = [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
+              "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms"):
+    getattr(_lib, _name).restype = _i32
+
+
+class ApcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.apc_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+class BelowFloor(ApcError):
+    pass
+
+
+def _check(status: int):
+    if status != APC_OK:
+        msg = (_lib.apc_last_error() or b"").decode(errors="replace")
+        if status == APC_E_BELOW_FLOOR:
+            raise BelowFloor(status, msg)
+        raise ApcError(status, msg)
+
+
+@dataclass(frozen=True)
+class Scheme:
+    kind: str = "level"                      # "level" or "region"
+    degree: int = 3
+    order: Optional[Tuple[int, ...]] = None  # per-region pass order (axes)
+    cd_axis: Optional[int] = None
+    levels: int = 0
+
+    def _c(self, ndim: int) -> _Scheme:
+        s = _Scheme()
+        s.kind = PER_LEVEL if self.kind == "level" else PER_REGION
+        s.degree = self.degree
+        order = self.order if self.order is not None else tuple(range(ndim - 1, -1, -1))
+        for i in range(3):
+            s.order[i] = order[i] if i < len(order) else 0
+        s.cd_axis = -1 if self.cd_axis is None else int(self.cd_axis)
+        s.levels = int(self.levels or 0)
+        return s
+
+    @staticmethod
+    def _from_c(s: _Scheme, ndim: int) -> "Scheme":
+        return Scheme(kind="level" if s.kind == PER_LEVEL else "region", degree=s.degree,
+                      order=None if s.kind == PER_LEVEL else tuple(s.order[i] for i in range(ndim)),
+                      cd_axis=None if s.cd_axis < 0 else s.cd_axis, levels=s.levels)
+
+
+@dataclass(frozen=True)
+class Target:
+    kind: str     # "abs", "rel", "psnr", "rmse"
+    value: float
+
+    def _c(self) -> _Target:
+        t = _Target()
+        t.kind = TARGET_KINDS[self.kind]
+        t.value = float(self.value)
+        return t
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return APC_F32
+    if t.dtype == torch.float64:
+        return APC_F64
+    raise ApcError(APC_E_DTYPE, f"unsupported dtype {t.dtype}")
+
+
+def _info_dict(inf: _Info) -> dict:
+    return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+
+class Handle:
+    """A refactored field (owns device plane streams; not thread-safe)."""
+
+    def __init__(self, ptr: int, shape: Tuple[int, ...], dtype):
+        self._h = ctypes.c_void_p(ptr)
+        self.shape = tuple(shape)
+        self.dtype = dtype
+
+    def close(self):
+        if self._h:
+            _lib.apc_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_streams(self) -> int:
+        return _lib.apc_num_streams(self._h)
+
+    def plan(self, target: Target):
+        planes = (ctypes.c_int32 * self.num_streams)()
+        inf = _Info()
+        _check(_lib.apc_plan(self._h, ctypes.byref(target._c()), planes, ctypes.byref(inf)))
+        return list(planes), _info_dict(inf)
+
+    def retrieve(self, target: Target, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        assert out.is_contiguous() and out.dtype == self.dtype and tuple(out.shape) == self.shape
+        inf = _Info()
+        _check(_lib.apc_retrieve(self._h, ctypes.byref(target._c()), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.byref(inf), _stream_ptr(stream)))
+        return out, _info_dict(inf)
+
+    def retrieve_planes(self, planes: Sequence[int], out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        assert out.is_contiguous() and out.dtype == self.dtype and tuple(out.shape) == self.shape
+        arr = (ctypes.c_int32 * self.num_streams)(*[int(p) for p in planes])
+        _check(_lib.apc_retrieve_planes(self._h, arr, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def stream_info(self, s: int) -> dict:
+        n, B, mx, nb = _i64(), _i32(), _i64(), _i64()
+        _check(_lib.apc_stream_info(self._h, s, ctypes.byref(n), ctypes.byref(B), ctypes.byref(mx), ctypes.byref(nb)))
+        return {"n": n.value, "B": B.value, "maxabs": mx.value, "blob_bytes": nb.value}
+
+    def stream_blob(self, s: int) -> bytes:
+        nb = self.stream_info(s)["blob_bytes"]
+        buf = ctypes.create_string_buffer(max(1, nb))
+        _check(_lib.apc_stream_blob(self._h, s, buf, max(1, nb)))
+        return buf.raw[:nb]
+
+    def metadata(self) -> dict:
+        ln = _i64()
+        _check(_lib.apc_metadata_json(self._h, None, 0, ctypes.byref(ln)))
+        buf = ctypes.create_string_buffer(ln.value + 1)
+        _check(_lib.apc_metadata_json(self._h, buf, ln.value + 1, None))
+        return json.loads(buf.value.decode())
+
+
+def refactor(field, scheme: Scheme = Scheme(), stream=None) -> Handle:
+    """Refactor a contiguous CUDA (HIP) float32/float64 tensor of 1-3 dims."""
+    assert field.is_cuda and field.is_contiguous(), "field must be a contiguous device tensor"
+    dims = (ctypes.c_int64 * field.dim())(*field.shape)
+    out = ctypes.c_void_p()
+    _check(_lib.apc_refactor(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(),
+                             ctypes.byref(scheme._c(field.dim())), _stream_ptr(stream), ctypes.byref(out)))
+    return Handle(out.value, tuple(field.shape), field.dtype)
+
+
+def select_pipeline(field, mode: str = "eb", stream=None) -> Scheme:
+    assert field.is_cuda and field.is_contiguous()
+    dims = (ctypes.c_int64 * field.dim())(*field.shape)
+    s = _Scheme()
+    _check(_lib.apc_select_pipeline(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(),
+                                    MODES[mode], ctypes.byref(s), _stream_ptr(stream)))
+    return Scheme._from_c(s, field.dim())
+
+
+def axis_norms(n: int, L: int, degree: int) -> Tuple[List[float], List[float]]:
+    """Host-only: exact 1D chain norms (max row / column abs sums) per level."""
+    a = (ctypes.c_double * L)()
+    b = (ctypes.c_double * L)()
+    _check(_lib.apc_axis_norms(n, L, degree, a, b))
+    return list(a), list(b)
+
+
+def library():
+    return _lib

@@ -1,0 +1,100 @@
+// Host-side metadata of a refactored field and the retrieval interpreter.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace apc {
+
+enum GroupKind { G_COARSE = 0, G_LEVEL = 1, G_REGION = 2 };
+enum StreamKind { S_COARSE = 0, S_LEVEL = 1, S_REGION = 2, S_CD = 3 };
+enum CdKind { CD_NONE = 0, CD_SUM = 1, CD_STAIR = 2 };
+
+struct Group {
+  int kind = 0, level = 0, rho = 0;
+  int64_t n = 0;
+  double M = 0.0;     // max |coefficient|
+  int E = 0;          // frexp exponent of M
+  double delta = 0.0; // quantization step 2^(E-P) (0 for an all-zero group)
+  int k_shift = 0;    // P - E
+  double w = 1.0, rho_w = 0.0;   // max-error and RMSE weights
+  double wd_inf = 0.0, wd_2 = 0.0;
+  int cd = CD_NONE;
+};
+
+struct Stream {
+  int kind = 0, level = 0, rho = 0, t = 0;
+  int group = 0;
+  int64_t n = 0;
+  int B = 0;
+  int64_t maxabs = 0;
+  int64_t code_off = 0;  // in the region code buffer, or the decomposition buffer
+  bool use_cd = false;
+  std::vector<int64_t> nsig;  // per plane (most significant first)
+  std::vector<int64_t> pso;   // per plane: sign words before it in this stream
+  int64_t mag_off = 0, idx_off = 0, sign_off = 0;
+
+  int64_t words() const { return (n + 63) / 64; }
+  int64_t chunks() const { return (n + 4095) / 4096; }
+  int64_t sign_words() const {
+    int64_t s = 0;
+    for (int64_t v : nsig) s += (v + 63) / 64;
+    return s;
+  }
+  int64_t plane_bytes(int j) const { return 4 * chunks() + 8 * words() + 8 * ((nsig[j] + 63) / 64); }
+  int64_t delta(int k) const {
+    if (k <= 0) return maxabs;
+    return (int64_t)((1ull << (B - k)) - 1ull);
+  }
+  int64_t blob_bytes() const {
+    int64_t ib = 4 * (int64_t)B * chunks();
+    ib += (8 - ib % 8) % 8;
+    return ib + 8 * (int64_t)B * words() + 8 * sign_words();
+  }
+};
+
+struct Unit {
+  int group = 0;
+  bool stair = false;
+  int stream = -1;
+  std::vector<int64_t> levels, seg_bytes;
+  std::vector<std::vector<std::pair<int, int>>> seg_steps;  // (stream, plane) per segment
+};
+
+struct Meta {
+  int d = 3, L = 1, P = 29;
+  int64_t n = 0;
+  double xmin = 0, xmax = 0, A = 0;
+  double eps_fp = 0;
+  int64_t meta_bytes = 0;
+  std::vector<Group> groups;
+  std::vector<Stream> streams;
+  std::vector<Unit> units;
+  std::vector<std::vector<int>> group_units;
+  std::vector<int> group_order;
+  // greedy sequences, per mode (0 = max error, 1 = RMSE)
+  bool seq_ready[2] = {false, false};
+  double seq_E0[2] = {0, 0};
+  std::vector<std::pair<int, double>> seq[2];
+
+  double range() const { return xmax - xmin; }
+};
+
+// Planner (plan.cpp)
+void axis_norms(int64_t n, int L, int degree, std::vector<double>& inf, std::vector<double>& one);
+Unit build_staircase(int group, const std::vector<std::vector<int>>& region_streams,
+                     const std::vector<Stream>& streams);
+void finalize_meta(Meta& m);
+int64_t unit_err(const Meta& m, const Unit& u, int k);
+int unit_nsteps(const Meta& m, const Unit& u);
+double bound(const Meta& m, const std::vector<int>& state, int mode);
+void ensure_sequence(Meta& m, int mode);
+// Returns 0 on success, -1 if tau is below the floor.
+int make_plan(Meta& m, double tau, int mode, std::vector<int>& planes, double& bound_out, int& nsteps);
+int64_t plan_bytes(const Meta& m, const std::vector<int>& planes);
+std::string meta_json(const Meta& m);
+
+}  // namespace apc

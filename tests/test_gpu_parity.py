@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU
+oracle on the same seeded inputs.  Integer data (codes, plane streams, plans)
+must match bit for bit; reconstructions must match bit for bit as well (the
+float64 arithmetic is done in the same order on both sides)."""
+import math
+
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [
+    ("level", 3, None, None),
+    ("region", 3, None, None),
+    ("level", 3, None, 0),
+    ("region", 3, (0, 1, 2), 2),
+    ("level", 1, None, None),
+    ("region", 1, (1, 0, 2), 1),
+    ("level", 3, None, 2),
+    ("region", 3, (2, 0, 1), 0),
+]
+REL = (1e-2, 1e-3, 1e-4, 1e-6)
+PSNR = (40, 60, 80)
+
+
+def _apc():
+    import paper_2609_04573_amd as apc
+    return apc
+
+
+def _schemes(kind, degree, order, cd):
+    apc = _apc()
+    return (apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
+            oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd))
+
+
+def _bits(a):
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def _check_metadata(h, ref):
+    md = h.metadata()
+    assert md["L"] == ref.L and md["P"] == ref.P
+    assert md["xmin"] == ref.xmin and md["xmax"] == ref.xmax and md["A"] == ref.A
+    assert len(md["groups"]) == len(ref.groups)
+    for gg, og in zip(md["groups"], ref.groups):
+        assert gg["n"] == og.n
+        assert gg["M"] == og.M, (gg, og)
+        assert gg["delta"] == og.delta
+        assert gg["w"] == og.w and gg["rho_w"] == og.rho
+    assert len(md["streams"]) == len(ref.streams)
+    for gs, os_ in zip(md["streams"], ref.streams):
+        assert gs["n"] == os_.meta.n and gs["B"] == os_.meta.B and gs["maxabs"] == os_.meta.maxabs
+        assert gs["nsig"] == os_.meta.nsig
+    assert md["eps_fp"] == ref.eps_fp
+    assert md["meta_bytes"] == ref.meta_bytes
+
+
+def _check_streams(h, ref):
+    for s, st in enumerate(ref.streams):
+        blob = h.stream_blob(s)
+        assert len(blob) == len(st.blob), f"stream {s} size"
+        assert blob == st.blob, f"stream {s} bytes differ"
+
+
+def _check_retrievals(h, ref, x):
+    apc = _apc()
+    xf = x.astype(np.float64)
+    targets = [("rel", r) for r in REL] + [("psnr", p) for p in PSNR]
+    for kind, val in targets:
+        pl = oracle.plan(ref, oracle.Target(kind, val))
+        planes, info = h.plan(apc.Target(kind, val))
+        assert planes == pl.planes, (kind, val)
+        assert info["bound"] == pl.bound and info["bytes_total"] == pl.bytes
+        out, _ = h.retrieve(apc.Target(kind, val))
+        got = out.cpu().numpy()
+        want = oracle.retrieve(ref, pl)
+        assert np.array_equal(_bits(got), _bits(want)), (kind, val, np.abs(got - want).max())
+        err = np.abs(got.astype(np.float64) - xf)
+        if kind == "rel":
+            assert err.max() <= val * ref.range
+        else:
+            rmse = math.sqrt(np.mean(err ** 2))
+            assert 20 * math.log10(ref.range / rmse) >= val
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=lambda s: f"{s[0]}-d{s[1]}-o{s[2]}-cd{s[3]}")
+def test_config1_parity(config1_field, scheme):
+    apc = _apc()
+    x = config1_field
+    gs, os_ = _schemes(*scheme)
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    _check_retrievals(h, ref, x)
+    h.close()
+
+
+@pytest.mark.parametrize("shape,scheme", [
+    ((17, 30, 45), ("level", 3, None, 1)),
+    ((17, 30, 45), ("region", 3, (1, 2, 0), 0)),
+    ((5, 64, 3), ("level", 3, None, None)),
+    ((2, 3, 130), ("region", 3, (0, 2, 1), 2)),
+    ((37, 129), ("level", 3, None, 0)),
+    ((37, 129), ("region", 3, (0, 1), 1)),
+    ((1000,), ("level", 3, None, None)),
+    ((4097,), ("region", 1, (0,), None)),
+    ((1, 1, 1), ("level", 3, None, None)),
+    ((3, 1, 2), ("region", 3, (2, 1, 0), None)),
+    ((9, 9, 9), ("level", 3, None, 0)),
+], ids=str)
+def test_ragged_shapes_parity(shape, scheme):
+    apc = _apc()
+    x = fieldgen.power_law_field(shape, seed=11, dtype=np.float32) if len(shape) > 1 else \
+        np.cumsum(np.random.default_rng(5).standard_normal(shape)).astype(np.float32)
+    gs, os_ = _schemes(*scheme)
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    _check_retrievals(h, ref, x)
+    h.close()
+
+
+@pytest.mark.parametrize("scheme", [("level", 3, None, 0), ("region", 3, None, None)], ids=str)
+def test_float64_parity(scheme):
+    apc = _apc()
+    x = fieldgen.power_law_field((33, 40, 50), seed=7, dtype=np.float64)
+    gs, os_ = _schemes(*scheme)
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    for rel in (1e-3, 1e-7, 1e-11):
+        pl = oracle.plan(ref, oracle.Target("rel", rel))
+        out, _ = h.retrieve(apc.Target("rel", rel))
+        assert np.array_equal(_bits(out.cpu().numpy()), _bits(oracle.retrieve(ref, pl)))
+    h.close()
+
+
+def test_incremental_ladder_equals_single_shot(config1_field):
+    """Retrievals that reuse planes decoded by earlier calls give the same
+    bytes as a fresh handle asked once (both directions of the ladder)."""
+    apc = _apc()
+    x = torch.from_numpy(config1_field).cuda()
+    sc = apc.Scheme(kind="level", cd_axis=0)
+    h = apc.refactor(x, sc)
+    ladder = [("rel", 1e-2), ("rel", 1e-4), ("psnr", 60), ("rel", 1e-6), ("rel", 1e-3), ("psnr", 90)]
+    for kind, val in ladder:
+        got, info = h.retrieve(apc.Target(kind, val))
+        fresh = apc.refactor(x, sc)
+        want, _ = fresh.retrieve(apc.Target(kind, val))
+        assert torch.equal(got.view(torch.int32), want.view(torch.int32)), (kind, val)
+        fresh.close()
+    h.close()
+
+
+def test_explicit_planes_full_is_quantized_field(config1_field):
+    apc = _apc()
+    ref = oracle.refactor(config1_field, oracle.Scheme("region", cd_axis=1))
+    h = apc.refactor(torch.from_numpy(config1_field).cuda(), apc.Scheme("region", cd_axis=1))
+    full = [st.meta.B for st in ref.streams]
+    got = h.retrieve_planes(full).cpu().numpy()
+    want = oracle.pipeline.quantized_field(ref)
+    assert np.array_equal(_bits(got), _bits(want))
+    zero = h.retrieve_planes([0] * len(full)).cpu().numpy()
+    assert np.array_equal(_bits(zero), _bits(oracle.retrieve(ref, [0] * len(full))))
+    h.close()
+
+
+def test_errors_are_reported():
+    apc = _apc()
+    c = torch.full((9, 9, 9), 2.5, device="cuda")
+    h = apc.refactor(c, apc.Scheme())
+    with pytest.raises(apc.BelowFloor):
+        h.retrieve(apc.Target("rel", 1e-3))
+    out, _ = h.retrieve(apc.Target("abs", 1e-3))
+    assert torch.equal(out, c)
+    h.close()
+    bad = torch.zeros((8, 8, 8), device="cuda")
+    bad[1, 2, 3] = float("nan")
+    with pytest.raises(apc.ApcError) as ei:
+        apc.refactor(bad, apc.Scheme())
+    assert ei.value.status == -3
+    with pytest.raises(apc.ApcError):
+        apc.refactor(torch.zeros(16, device="cuda"), apc.Scheme(cd_axis=0))
