@@ -1,0 +1,166 @@
+"""Benchmark: refactor + retrieve of a 512^3 float32 turbulence-like field.
+
+One step = refactor the field (every level, both coefficient passes,
+coefficient decomposition, bitplane encoding) and retrieve it at a max-error
+bound of 1e-4 * range from a freshly refactored handle (plan, decode,
+recompose, reconstruct).  Inputs are resident in HBM before timing starts.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s
+
+
+def _pct(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[i]
+
+
+def cpu_baseline(x_full, rel: float, side: int = 256):
+    """The CPU oracle on a bounded sample of the same field: a side^3 block."""
+    import numpy as np
+
+    import oracle
+
+    blk = np.ascontiguousarray(x_full[:side, :side, :side])
+    sc = oracle.Scheme(kind="level", cd_axis=0)
+    t0 = time.perf_counter()
+    ref = oracle.refactor(blk, sc)
+    t1 = time.perf_counter()
+    pl = oracle.plan(ref, oracle.Target("rel", rel))
+    xr = oracle.retrieve(ref, pl)
+    t2 = time.perf_counter()
+    assert float(np.abs(xr.astype(np.float64) - blk).max()) <= rel * ref.range
+    nbytes = blk.size * blk.itemsize
+    return {
+        "value": nbytes / (t2 - t0) / 1e9,
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{side}^3 corner block of the same field, refactor + retrieve at rel 1e-4, single-threaded NumPy",
+        "refactor_s": t1 - t0,
+        "retrieve_s": t2 - t1,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--rel", type=float, default=1e-4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by independent "
+              "fields/blocks and is measured per GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_2609_04573_amd as apc
+
+    n = args.size
+    x = fieldgen.config2_field(n)
+    xd = torch.from_numpy(x).cuda()
+    torch.cuda.synchronize()
+    scheme = apc.Scheme(kind="level", cd_axis=0)
+    target = apc.Target("rel", args.rel)
+    out = torch.empty_like(xd)
+    nbytes = x.size * x.itemsize
+
+    def step():
+        t0 = time.perf_counter()
+        h = apc.refactor(xd, scheme)
+        t1 = time.perf_counter()
+        _, info = h.retrieve(target, out=out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        streams = sum(h.stream_info(s)["blob_bytes"] for s in range(h.num_streams))
+        h.close()
+        return t1 - t0, t2 - t1, info, streams
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    apc.apc.profile_enable(True)
+    t_start = time.perf_counter()
+    rec = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    apc.apc.profile_enable(False)
+    prof = apc.apc.profile_report()
+
+    err = float((out.double() - xd.double()).abs().max().item())
+    rng = float(xd.max().item() - xd.min().item())
+    assert err <= args.rel * rng, "retrieval violated its error bound"
+    t_ref = sorted(r[0] for r in rec)[len(rec) // 2]
+    t_ret = sorted(r[1] for r in rec)[len(rec) // 2]
+    info, streams = rec[-1][2], rec[-1][3]
+    ref_alg = nbytes + streams
+    ret_alg = info["bytes_total"] + nbytes
+    line = {
+        "metric": "refactor & retrieve GB/s (frac. HBM peak) at eb=1e-4*range; p50/p99 retrieve ms",
+        "value": nbytes * args.steps / total / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 float32 k^-5/3 Gaussian random field (seed 1); per-level cubic interpolation + "
+                        f"coefficient decomposition on axis 0; refactor then retrieve at eb={args.rel:g}*range",
+            "field_dtype": "float32",
+            "points": int(x.size),
+        },
+        "refactor_GBps": nbytes / t_ref / 1e9,
+        "refactor_hbm_frac": ref_alg / t_ref / HBM_PEAK,
+        "retrieve_GBps": nbytes / t_ret / 1e9,
+        "retrieve_hbm_frac": ret_alg / t_ret / HBM_PEAK,
+        "retrieve_ms_p50": _pct([r[1] * 1e3 for r in rec], 50),
+        "retrieve_ms_p99": _pct([r[1] * 1e3 for r in rec], 99),
+        "stream_bytes": streams,
+        "plan_bytes": info["bytes_total"],
+        "bitrate": info["bitrate"],
+        "max_error": err,
+        "tau": args.rel * rng,
+    }
+    # Roofline of the kernel with the largest share of event-timed time.
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK / 1e9,
+                        "unit": "GB/s", "frac": achieved / (HBM_PEAK / 1e9), "traffic": None,
+                        "launches_per_step": d["count"] / args.steps,
+                        "ms_per_step": d["ms"] / args.steps}
+    line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4) for k, v in
+                                   sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x, args.rel)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

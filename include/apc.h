@@ -143,6 +143,14 @@ apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_
  * float64 (max row / column abs sums).  inf_out, one_out: L doubles. */
 apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out, double* one_out);
 
+/* Launch profiling (measurement only).  While enabled, every kernel launch
+ * is bracketed by HIP events recorded on the stream it runs on.
+ * apc_profile_report waits for the recorded events and returns, per kernel,
+ * {"count", "ms" (summed event time), "bytes" (data the launches must read
+ * and write)} as JSON, then clears the records.  Not thread-safe. */
+apc_status apc_profile_enable(int32_t on);
+apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,7 +39,7 @@ MODES = {"eb": 0, "psnr": 1}
 EXPORTED = [
     "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline", "apc_free",
     "apc_strerror", "apc_last_error", "apc_num_streams", "apc_num_groups", "apc_num_points", "apc_stream_info",
-    "apc_stream_blob", "apc_metadata_json", "apc_axis_norms",
+    "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
 ]
 
 
@@ -80,8 +80,11 @@ _lib.apc_stream_info.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER
 _lib.apc_stream_blob.argtypes = [_vp, _i32, _vp, _i64]
 _lib.apc_metadata_json.argtypes = [_vp, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 _lib.apc_axis_norms.argtypes = [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.apc_profile_enable.argtypes = [_i32]
+_lib.apc_profile_report.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
-              "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms"):
+              "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable",
+              "apc_profile_report"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -252,6 +255,19 @@ def axis_norms(n: int, L: int, degree: int) -> Tuple[List[float], List[float]]:
     b = (ctypes.c_double * L)()
     _check(_lib.apc_axis_norms(n, L, degree, a, b))
     return list(a), list(b)
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.apc_profile_enable(1 if on else 0))
+
+
+def profile_report() -> dict:
+    """Per-kernel launch counts, event-timed milliseconds and bytes moved."""
+    ln = _i64()
+    _check(_lib.apc_profile_report(None, 0, ctypes.byref(ln)))
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    _check(_lib.apc_profile_report(buf, ln.value + 1, None))
+    return json.loads(buf.value.decode())
 
 
 def library():

@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +47,107 @@ apc_status fail(apc_status s, const char* fmt, ...) {
     if (_s != APC_OK) return _s;   \
   } while (0)
 
+// Launch profiler: when enabled, every kernel launch is bracketed by two HIP
+// events on its own stream and tagged with the bytes it must move.
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double bytes;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+Profiler g_prof;
+
+struct ProfMark {
+  int rec = -1;
+  hipStream_t st;
+  ProfMark(const char* name, double bytes, hipStream_t s) : st(s) {
+    if (!g_prof.on) return;
+    ProfRec r{name, g_prof.get(), g_prof.get(), bytes};
+    (void)hipEventRecord(r.a, st);
+    g_prof.recs.push_back(r);
+    rec = (int)g_prof.recs.size() - 1;
+  }
+  void stop() {
+    if (rec >= 0) (void)hipEventRecord(g_prof.recs[rec].b, st);
+  }
+};
+
+#define LAUNCH(name, bytes, st, expr)    \
+  do {                                  \
+    ProfMark _pm(name, (double)(bytes), st); \
+    HIP_TRY(expr);                      \
+    _pm.stop();                         \
+  } while (0)
+
+// Caching device allocator: freed blocks are kept per size and handed back to
+// later requests of the same or slightly smaller size, so repeated refactors
+// and retrievals do not pay hipMalloc / hipFree (both synchronize the device).
+struct Pool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+  size_t cached = 0;
+  size_t limit = (size_t)32 << 30;
+
+  hipError_t get(size_t n, void** p, size_t* got) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = free_blocks.lower_bound(n);
+      if (it != free_blocks.end() && it->first <= n + n / 8 + 4096) {
+        *p = it->second;
+        *got = it->first;
+        cached -= it->first;
+        free_blocks.erase(it);
+        return hipSuccess;
+      }
+    }
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipErrorOutOfMemory) {
+      trim(0);
+      e = hipMalloc(p, n);
+    }
+    *got = n;
+    return e;
+  }
+  void put(void* p, size_t n) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_blocks.insert({n, p});
+    cached += n;
+    while (cached > limit && !free_blocks.empty()) {
+      auto it = std::prev(free_blocks.end());
+      (void)hipFree(it->second);
+      cached -= it->first;
+      free_blocks.erase(it);
+    }
+  }
+  void trim(size_t keep) {
+    std::lock_guard<std::mutex> lk(mu);
+    while (cached > keep && !free_blocks.empty()) {
+      auto it = std::prev(free_blocks.end());
+      (void)hipFree(it->second);
+      cached -= it->first;
+      free_blocks.erase(it);
+    }
+  }
+};
+Pool& pool() {
+  static Pool* p = new Pool();  // never destroyed: blocks outlive static teardown order
+  return *p;
+}
+
 // Device allocation owned by a host object.
 struct DevBuf {
   void* p = nullptr;
@@ -54,21 +157,22 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool().put(p, bytes);
     p = nullptr;
     bytes = 0;
   }
   apc_status alloc(size_t nbytes) {
     if (nbytes <= bytes && p) return APC_OK;
     release();
-    if (nbytes == 0) nbytes = 8;
-    hipError_t e = hipMalloc(&p, nbytes);
+    nbytes = (std::max<size_t>(nbytes, 8) + 255) & ~(size_t)255;
+    size_t got = 0;
+    hipError_t e = pool().get(nbytes, &p, &got);
     if (e != hipSuccess) {
       p = nullptr;
       return fail(e == hipErrorOutOfMemory ? APC_E_OOM : APC_E_HIP, "hipMalloc(%zu): %s", nbytes,
                   hipGetErrorString(e));
     }
-    bytes = nbytes;
+    bytes = got;
     return APC_OK;
   }
   template <typename X>
@@ -441,7 +545,8 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
   APC_TRY(grids.alloc(sizeof(T) * (size_t)gtot));
   auto grid_ptr = [&](int l) -> const T* { return l == 0 ? x : grids.as<T>() + goff[l]; };
   for (int l = 1; l < L; ++l)
-    HIP_TRY(launch_subsample<T>(grid_ptr(l - 1), g.m[l - 1].data(), grids.as<T>() + goff[l], g.m[l].data(), st));
+    LAUNCH("subsample", 2.0 * sizeof(T) * g.m[l][0] * g.m[l][1] * g.m[l][2], st,
+           launch_subsample<T>(grid_ptr(l - 1), g.m[l - 1].data(), grids.as<T>() + goff[l], g.m[l].data(), st));
 
   build_layout(h, P, 0, 0, 0);
   Meta& m = h->meta;
@@ -453,7 +558,7 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
   std::vector<unsigned long long> init(4 + ng + ns, 0ull);
   init[0] = ~0ull;
   HIP_TRY(hipMemcpyAsync(acc, init.data(), 8 * init.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_range<T>(x, n, acc, st));
+  LAUNCH("range", (double)sizeof(T) * n, st, launch_range<T>(x, n, acc, st));
 
   if (per_level && d >= 2) {
     APC_TRY(h->pr[0].alloc(8 * (size_t)lat_count(lattice(g, 0, 0))));
@@ -472,10 +577,13 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
   for (int l = 0; l < L - 1; ++l)
     for (int rho = 0; rho < d; ++rho) {
       RegionArgs ra = region_args<Q>(h, l, rho, per_level, per_level, per_level);
-      HIP_TRY((launch_coef<T, Q>(grid_ptr(l), ra, 0, gmax + group_of(l, rho), 0, (Q*)nullptr, st)));
+      const double nr = (double)lat_count(ra.lat);
+      LAUNCH("coef_max", nr * sizeof(T) + (ra.pr_out ? 8.0 * nr : 0.0), st,
+             (launch_coef<T, Q>(grid_ptr(l), ra, 0, gmax + group_of(l, rho), 0, (Q*)nullptr, st)));
     }
   const int64_t ncoarse = m.streams[0].n;
-  HIP_TRY((launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 0, gmax + 0, 0, (Q*)nullptr, st)));
+  LAUNCH("coarse", (double)sizeof(T) * ncoarse, st,
+         (launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 0, gmax + 0, 0, (Q*)nullptr, st)));
   std::vector<unsigned long long> hv(4 + ng);
   HIP_TRY(hipMemcpyAsync(hv.data(), acc, 8 * hv.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -505,17 +613,20 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
     for (int rho = 0; rho < d; ++rho) {
       RegionArgs ra = region_args<Q>(h, l, rho, per_level, per_level, per_level);
       const Group& gr = m.groups[group_of(l, rho)];
-      HIP_TRY((launch_coef<T, Q>(grid_ptr(l), ra, 1, nullptr, gr.k_shift, codes.as<Q>() + h->region_off[l * 3 + rho],
-                                 st)));
+      const double nr = (double)lat_count(ra.lat);
+      LAUNCH("coef_quant", nr * (sizeof(T) + sizeof(Q)) + (ra.pr_out ? 8.0 * nr : 0.0), st,
+             (launch_coef<T, Q>(grid_ptr(l), ra, 1, nullptr, gr.k_shift, codes.as<Q>() + h->region_off[l * 3 + rho], st)));
     }
-  HIP_TRY((launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 1, nullptr, m.groups[0].k_shift, codes.as<Q>(), st)));
+  LAUNCH("coarse", (double)(sizeof(T) + sizeof(Q)) * ncoarse, st,
+         (launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 1, nullptr, m.groups[0].k_shift, codes.as<Q>(), st)));
   grids.release();
 
   // coefficient decomposition of level 0
   if (h->scheme.cd_axis >= 0 && L >= 2) {
     APC_TRY(cdc.alloc(sizeof(Q) * (size_t)std::max<int64_t>(1, h->cd_n)));
     for (int rho = 0; rho < d; ++rho)
-      HIP_TRY((launch_cd_forward<Q>(codes.as<Q>() + h->region_off[rho], h->cd[rho], cdc.as<Q>(), smax, st)));
+      LAUNCH("cd_forward", 2.0 * sizeof(Q) * h->cd[rho].c[0] * h->cd[rho].c[1] * h->cd[rho].c[2], st,
+             (launch_cd_forward<Q>(codes.as<Q>() + h->region_off[rho], h->cd[rho], cdc.as<Q>(), smax, st)));
     std::vector<unsigned long long> sv(ns);
     HIP_TRY(hipMemcpyAsync(sv.data(), smax, 8 * ns, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -567,8 +678,11 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
   APC_TRY(sdd.alloc(sizeof(StreamDev) * std::max<size_t>(1, sds.size())));
   if (!sds.empty()) {
     HIP_TRY(hipMemcpyAsync(sdd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY((launch_encode<Q>(codes.as<Q>(), cdc.as<Q>(), sdd.as<StreamDev>(), (int)sds.size(), chunks, nullptr, 0,
-                              h->mag.as<uint64_t>(), cnt.as<uint32_t>(), stage.as<uint64_t>(), st)));
+    double eb = 8.0 * mag_words + 8.0 * stage_words + 4.0 * idx_n;
+    for (const StreamDev& sd : sds) eb += (double)sizeof(Q) * sd.n;
+    LAUNCH("encode", eb, st,
+           (launch_encode<Q>(codes.as<Q>(), cdc.as<Q>(), sdd.as<StreamDev>(), (int)sds.size(), chunks, nullptr, 0,
+                             h->mag.as<uint64_t>(), cnt.as<uint32_t>(), stage.as<uint64_t>(), st)));
   }
   std::vector<int32_t> job_s, job_j;
   for (size_t i = 0; i < sds.size(); ++i)
@@ -583,7 +697,7 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
   if (njobs) {
     HIP_TRY(hipMemcpyAsync(jobs.p, job_s.data(), 4 * njobs, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(jobs.as<int32_t>() + njobs, job_j.data(), 4 * njobs, hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_scan(sdd.as<StreamDev>(), jobs.as<int32_t>(), jobs.as<int32_t>() + njobs, njobs,
+    LAUNCH("scan", 8.0 * idx_n, st, launch_scan(sdd.as<StreamDev>(), jobs.as<int32_t>(), jobs.as<int32_t>() + njobs, njobs,
                         cnt.as<uint32_t>(), h->idx.as<uint32_t>(), totals.as<int64_t>(), st));
     HIP_TRY(hipMemcpyAsync(tot.data(), totals.p, 8 * njobs, hipMemcpyDeviceToHost, st));
   }
@@ -614,7 +728,7 @@ apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(h->pso.p, pso_all.data(), 8 * pso_all.size(), hipMemcpyHostToDevice, st));
   if (!sds.empty()) {
     HIP_TRY(hipMemcpyAsync(sdd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_sign_move(sdd.as<StreamDev>(), (int)sds.size(), chunks, cnt.as<uint32_t>(), h->idx.as<uint32_t>(),
+    LAUNCH("sign_move", 8.0 * (stage_words + sign_words), st, launch_sign_move(sdd.as<StreamDev>(), (int)sds.size(), chunks, cnt.as<uint32_t>(), h->idx.as<uint32_t>(),
                              h->pso.as<int64_t>(), stage.as<uint64_t>(), h->sign.as<uint64_t>(), st));
   }
   HIP_TRY(hipStreamSynchronize(st));
@@ -661,6 +775,7 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   std::vector<StreamDev>& sds = h->sd_host;
   sds.clear();
   int64_t chunks = 0, fb = 0;
+  double db = 0.0;
   for (int s = 0; s < (int)m.streams.size(); ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= h->k_res[s]) continue;
@@ -682,7 +797,11 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
     int psb = 0;
     for (int s2 = 0; s2 < s; ++s2) psb += m.streams[s2].n > 0 ? m.streams[s2].B : 0;
     sd.psb = psb;
-    for (int j = sd.k0; j < sd.k1; ++j) fb += S.plane_bytes(j);
+    for (int j = sd.k0; j < sd.k1; ++j) {
+      fb += S.plane_bytes(j);
+      db += 8.0 * ((S.nsig[j] + 63) / 64);
+    }
+    db += (double)(sd.k1 - sd.k0) * (8.0 * sd.M + 4.0 * sd.C) + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
     chunks += sd.C;
     sds.push_back(sd);
     h->k_res[s] = planes[s];
@@ -690,7 +809,7 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   if (fetched) *fetched = fb;
   if (!sds.empty()) {
     HIP_TRY(hipMemcpyAsync(h->sd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY((launch_decode<Q>(h->sd.as<StreamDev>(), (int)sds.size(), chunks, h->mag.as<uint64_t>(),
+    LAUNCH("decode", db, st, (launch_decode<Q>(h->sd.as<StreamDev>(), (int)sds.size(), chunks, h->mag.as<uint64_t>(),
                               h->idx.as<uint32_t>(), h->sign.as<uint64_t>(), h->pso.as<int64_t>(), h->codes.as<Q>(),
                               h->cd_codes.as<Q>(), st)));
   }
@@ -698,9 +817,9 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   const Stream& s0 = m.streams[0];
   const Group& g0 = m.groups[s0.group];
   double* xc = h->xc.as<double>();
-  HIP_TRY((launch_coarsest_q<Q>(h->codes.as<Q>(), s0.n, s0.B, planes[0], g0.delta, xc, st)));
+  LAUNCH("coarsest", (8.0 + sizeof(Q)) * s0.n, st, (launch_coarsest_q<Q>(h->codes.as<Q>(), s0.n, s0.B, planes[0], g0.delta, xc, st)));
   if (L == 1) {
-    HIP_TRY(launch_cast<T>(xc, s0.n, out, st));
+    LAUNCH("cast", (8.0 + sizeof(T)) * s0.n, st, launch_cast<T>(xc, s0.n, out, st));
     return APC_OK;
   }
   // stream of each (level, region)
@@ -717,9 +836,9 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
     double* xout = l > 0 ? h->xb[l % 2].as<double>() : nullptr;
     const int32_t* cm = g.m[l + 1].data();
     if (l > 0)
-      HIP_TRY(launch_inject<double>(xin, cm, xout, g.m[l].data(), st));
+      LAUNCH("inject", 16.0 * cm[0] * cm[1] * cm[2], st, launch_inject<double>(xin, cm, xout, g.m[l].data(), st));
     else
-      HIP_TRY(launch_inject<T>(xin, cm, out, g.m[0].data(), st));
+      LAUNCH("inject", (8.0 + sizeof(T)) * cm[0] * cm[1] * cm[2], st, launch_inject<T>(xin, cm, out, g.m[0].data(), st));
     for (int rho = 0; rho < d; ++rho) {
       RegionArgs ra = region_args<Q>(h, l, rho, per_level, true, true);
       const Q* q;
@@ -732,7 +851,8 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
           ca.B[t] = S.B;
           ca.k[t] = planes[ca.s_idx[t]];
         }
-        HIP_TRY((launch_cd_inverse<Q>(h->cd_codes.as<Q>(), ca, h->cdreg.as<Q>(), st)));
+        LAUNCH("cd_inverse", 2.0 * sizeof(Q) * ca.c[0] * ca.c[1] * ca.c[2], st,
+               (launch_cd_inverse<Q>(h->cd_codes.as<Q>(), ca, h->cdreg.as<Q>(), st)));
         q = h->cdreg.as<Q>();
         B = 64;
         k = 64;
@@ -746,9 +866,11 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
         delta = m.groups[S.group].delta;
       }
       if (l > 0)
-        HIP_TRY((launch_recon<double, Q>(xin, cm, ra, q, B, k, delta, xout, st)));
+        LAUNCH("recon", (double)lat_count(ra.lat) * (sizeof(Q) + 8 + (ra.pr_out ? 8 : 0)), st,
+               (launch_recon<double, Q>(xin, cm, ra, q, B, k, delta, xout, st)));
       else
-        HIP_TRY((launch_recon<T, Q>(xin, cm, ra, q, B, k, delta, out, st)));
+        LAUNCH("recon", (double)lat_count(ra.lat) * (sizeof(Q) + sizeof(T) + (ra.pr_out ? 8 : 0)), st,
+               (launch_recon<T, Q>(xin, cm, ra, q, B, k, delta, out, st)));
     }
     xin = xout;
   }
@@ -868,7 +990,13 @@ apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_d
   return do_retrieve(h, p, out_dev, hip_stream, nullptr);
 }
 
-void apc_free(apc_handle* h) { delete h; }
+void apc_free(apc_handle* h) {
+  if (!h) return;
+  // Work queued on any stream may still read this handle's buffers; they go
+  // back to the shared pool only once the device is idle.
+  (void)hipDeviceSynchronize();
+  delete h;
+}
 
 int32_t apc_num_streams(const apc_handle* h) { return h ? (int32_t)h->meta.streams.size() : 0; }
 int32_t apc_num_groups(const apc_handle* h) { return h ? (int32_t)h->meta.groups.size() : 0; }
@@ -921,6 +1049,51 @@ apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out,
   for (int l = 0; l < L; ++l) {
     inf_out[l] = a[l];
     one_out[l] = b[l];
+  }
+  return APC_OK;
+}
+
+apc_status apc_profile_enable(int32_t on) {
+  g_prof.on = on != 0;
+  return APC_OK;
+}
+
+apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len) {
+  // Per kernel name: launches, total milliseconds, total bytes moved.
+  std::vector<std::string> names;
+  std::vector<double> ms, bytes;
+  std::vector<int64_t> count;
+  for (ProfRec& r : g_prof.recs) {
+    (void)hipEventSynchronize(r.b);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, r.a, r.b);
+    size_t k = 0;
+    while (k < names.size() && names[k] != r.name) ++k;
+    if (k == names.size()) {
+      names.push_back(r.name);
+      ms.push_back(0);
+      bytes.push_back(0);
+      count.push_back(0);
+    }
+    ms[k] += t;
+    bytes[k] += r.bytes;
+    count[k] += 1;
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.recs.clear();
+  std::string js = "{";
+  char tmp[256];
+  for (size_t k = 0; k < names.size(); ++k) {
+    snprintf(tmp, sizeof(tmp), "%s\"%s\":{\"count\":%lld,\"ms\":%.6f,\"bytes\":%.0f}", k ? "," : "", names[k].c_str(),
+             (long long)count[k], ms[k], bytes[k]);
+    js += tmp;
+  }
+  js += "}";
+  if (len) *len = (int64_t)js.size();
+  if (buf) {
+    if (cap < (int64_t)js.size() + 1) return fail(APC_E_INVALID, "buffer too small");
+    memcpy(buf, js.c_str(), js.size() + 1);
   }
   return APC_OK;
 }

@@ -5,6 +5,8 @@
 // Floating point: every interpolation is evaluated in float64 with exactly
 // the operation order of the stencil definitions (the library is built with
 // -ffp-contract=off, so no multiply-add is fused).  Codes are exact integers.
+#include <algorithm>
+
 #include "apc_internal.h"
 
 namespace apc {
@@ -212,9 +214,8 @@ __global__ __launch_bounds__(kThreads) void k_coef(const T* __restrict__ G, Regi
                                                     unsigned long long* gmax, int k_shift, Q* __restrict__ codes) {
   const Lattice& L = ra.lat;
   const int64_t total = (int64_t)L.c[0] * L.c[1] * L.c[2];
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double am = 0.0;
-  if (e < total) {
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThreads) {
     int i[3], t[3];
     lattice_node(L, e, i, t);
     const int ax = L.ax;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const T* __restrict__ G, Regi
     if (ra.pr_out) ra.pr_out[e] = p;
     const double c = xv - p;
     if (MODE == 0) {
-      am = fabs(c);
+      am = fmax(am, fabs(c));
     } else {
       codes[e] = (Q)(long long)rint(ldexp(c, k_shift));
     }
@@ -275,13 +276,16 @@ __device__ __forceinline__ int64_t cls_count(int cls, Rng1 ru, Rng1 rv) {
 }
 // Position of lattice element t among the elements of class cls, in
 // row-major order of the lattice.
+template <int A, int U, int V>
 __device__ __forceinline__ int64_t class_rank(int cls, const int t[3], const CDArgs& ca) {
   int64_t total = 0;
+#pragma unroll
   for (int s = 0; s < 3; ++s) {
     Rng1 r[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a)
       r[a] = (a < s) ? rng_single(t[a]) : (a == s ? rng_prefix(t[a]) : rng_prefix(ca.c[a]));
-    total += r[ca.a].call * cls_count(cls, r[ca.u], r[ca.v]);
+    total += r[A].call * cls_count(cls, r[U], r[V]);
   }
   return total;
 }
@@ -308,7 +312,7 @@ __device__ __forceinline__ void block_max3_atomic(double v[3], unsigned long lon
 }
 
 // Forward 2D integer lifting of one region lattice into S1/S2/S3.
-template <typename Q>
+template <typename Q, int A, int U, int V>
 __global__ __launch_bounds__(kThreads) void k_cd_forward(const Q* __restrict__ R, CDArgs ca, Q* __restrict__ out,
                                                           unsigned long long* smax) {
   const int64_t total = (int64_t)ca.c[0] * ca.c[1] * ca.c[2];
@@ -320,10 +324,10 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const Q* __restrict__ R
     const int64_t r = e / ca.c[2];
     t[1] = (int)(r % ca.c[1]);
     t[0] = (int)(r / ca.c[1]);
-    const int u = t[ca.u], v = t[ca.v];
-    const int Nu = ca.c[ca.u], Nv = ca.c[ca.v];
+    const int u = t[U], v = t[V];
+    const int Nu = ca.c[U], Nv = ca.c[V];
     const int64_t ls[3] = {(int64_t)ca.c[1] * ca.c[2], (int64_t)ca.c[2], 1};
-    const int64_t su = ls[ca.u], sv = ls[ca.v];
+    const int64_t su = ls[U], sv = ls[V];
     auto T = [&](int uu, int vv) -> int64_t { return (int64_t)R[e + (int64_t)(uu - u) * su + (int64_t)(vv - v) * sv]; };
     const int cls = cd_class(u, v);
     int64_t res;
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const Q* __restrict__ R
       }
       res = T(u, v) - p;
     }
-    out[ca.s_off[cls] + class_rank(cls, t, ca)] = (Q)res;
+    out[ca.s_off[cls] + class_rank<A, U, V>(cls, t, ca)] = (Q)res;
     am[cls] = (double)(res < 0 ? -res : res);
   }
   block_max3_atomic<Q>(am, smax, ca.s_idx);
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const Q* __restrict__ R
 // Inverse lifting.  PHASE 0 rebuilds the stride-2 points (S1 and S2 classes)
 // from the truncated S1/S2 streams; PHASE 1 rebuilds the rest from S3 and the
 // stride-2 points written by phase 0.
-template <typename Q, int PHASE>
+template <typename Q, int PHASE, int A, int U, int V>
 __global__ __launch_bounds__(kThreads) void k_cd_inverse(const Q* __restrict__ S, CDArgs ca, Q* __restrict__ out) {
   const int64_t total = (int64_t)ca.c[0] * ca.c[1] * ca.c[2];
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -373,16 +377,16 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const Q* __restrict__ S
   const int64_t r = e / ca.c[2];
   t[1] = (int)(r % ca.c[1]);
   t[0] = (int)(r / ca.c[1]);
-  const int u = t[ca.u], v = t[ca.v];
-  const int Nu = ca.c[ca.u], Nv = ca.c[ca.v];
+  const int u = t[U], v = t[V];
+  const int Nu = ca.c[U], Nv = ca.c[V];
   const int cls = cd_class(u, v);
   if (PHASE == 0 && cls == 2) return;
   if (PHASE == 1 && cls != 2) return;
   auto stream_val = [&](int c, int uu, int vv) -> int64_t {
     int tt[3] = {t[0], t[1], t[2]};
-    tt[ca.u] = uu;
-    tt[ca.v] = vv;
-    return (int64_t)mask_code<Q>(S[ca.s_off[c] + class_rank(c, tt, ca)], ca.B[c], ca.k[c]);
+    tt[U] = uu;
+    tt[V] = vv;
+    return (int64_t)mask_code<Q>(S[ca.s_off[c] + class_rank<A, U, V>(c, tt, ca)], ca.B[c], ca.k[c]);
   };
   if (PHASE == 0) {
     int64_t val;
@@ -405,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const Q* __restrict__ S
     out[e] = (Q)val;
   } else {
     const int64_t ls[3] = {(int64_t)ca.c[1] * ca.c[2], (int64_t)ca.c[2], 1};
-    const int64_t su = ls[ca.u], sv = ls[ca.v];
+    const int64_t su = ls[U], sv = ls[V];
     auto H1 = [&](int uu, int vv) -> int64_t { return (int64_t)out[e + (int64_t)(uu - u) * su + (int64_t)(vv - v) * sv]; };
     int64_t p;
     if ((u & 1) == 0) {
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const Q* __restrict__ codes
   const int64_t chunk = gch - S.chunk_begin;
   const Q* src = (S.use_cd ? cd_codes : codes) + S.code_off;
   const int B = S.B;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint64_t lt = lanemask_lt(lane);
 
   int blen_r[16];
@@ -598,14 +602,15 @@ __global__ __launch_bounds__(kThreads) void k_sign_move(const StreamDev* __restr
 // Incremental decode of planes [k0, k1) of each listed stream into its
 // resident codes.  The sign of a code that becomes significant at plane j is
 // found at index[j][chunk] + (rank among this chunk's plane-j newcomers).
-template <typename Q>
+template <typename Q, int MAXB>
 __global__ __launch_bounds__(kThreads) void k_decode(const StreamDev* __restrict__ sd, int ns,
                                                       const uint64_t* __restrict__ mag,
                                                       const uint32_t* __restrict__ idx,
                                                       const uint64_t* __restrict__ sign,
                                                       const int64_t* __restrict__ pso, Q* __restrict__ codes,
                                                       Q* __restrict__ cd_codes) {
-  __shared__ uint16_t wpre[64][64];
+  __shared__ uint16_t wpre[MAXB][64];
+  __shared__ uint64_t mws[MAXB][64];
   __shared__ int s_u;
   const int64_t gch = blockIdx.x;
   if (threadIdx.x == 0) s_u = find_stream(sd, ns, gch);
@@ -614,7 +619,12 @@ __global__ __launch_bounds__(kThreads) void k_decode(const StreamDev* __restrict
   const int64_t chunk = gch - S.chunk_begin;
   Q* dst = (S.use_cd ? cd_codes : codes) + S.code_off;
   const int B = S.B, k0 = S.k0, k1 = S.k1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int p = wave; p < k1 - k0; p += 4) {
+    const int64_t w = chunk * 64 + lane;
+    mws[p][lane] = (w < S.M) ? mag[S.mag_off + (int64_t)(k0 + p) * S.M + w] : 0ull;
+  }
+  __syncthreads();
   const uint64_t lt = lanemask_lt(lane);
 
   uint64_t nm_r[16];
@@ -632,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(const StreamDev* __restrict
     uint64_t nm = 0;
     int pl = -1, rk = 0;
     for (int j = k0; j < k1; ++j) {
-      const uint64_t mw = (word < S.M) ? mag[S.mag_off + (int64_t)j * S.M + word] : 0ull;
+      const uint64_t mw = mws[j - k0][wl];
       const bool bit = (mw >> lane) & 1ull;
       const bool nsg = bit && !sig;
       sig = sig || bit;
@@ -766,7 +776,8 @@ hipError_t launch_coef(const T* G, const RegionArgs& ra, int mode, unsigned long
   const int64_t n = (int64_t)ra.lat.c[0] * ra.lat.c[1] * ra.lat.c[2];
   if (n == 0) return hipSuccess;
   if (mode == 0)
-    hipLaunchKernelGGL((k_coef<T, Q, 0>), dim3(nblocks(n)), dim3(kThreads), 0, s, G, ra, gmax, (int)k_shift, codes);
+    hipLaunchKernelGGL((k_coef<T, Q, 0>), dim3(std::min<unsigned>(nblocks(n), 4096u)), dim3(kThreads), 0, s, G, ra, gmax,
+                       (int)k_shift, codes);
   else
     hipLaunchKernelGGL((k_coef<T, Q, 1>), dim3(nblocks(n)), dim3(kThreads), 0, s, G, ra, gmax, (int)k_shift, codes);
   return hipGetLastError();
@@ -788,7 +799,12 @@ hipError_t launch_cd_forward(const Q* region_codes, const CDArgs& ca, Q* cd_code
                              hipStream_t s) {
   const int64_t n = (int64_t)ca.c[0] * ca.c[1] * ca.c[2];
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cd_forward<Q>), dim3(nblocks(n)), dim3(kThreads), 0, s, region_codes, ca, cd_codes, smax);
+  if (ca.a == 0)
+    hipLaunchKernelGGL((k_cd_forward<Q, 0, 1, 2>), dim3(nblocks(n)), dim3(kThreads), 0, s, region_codes, ca, cd_codes, smax);
+  else if (ca.a == 1)
+    hipLaunchKernelGGL((k_cd_forward<Q, 1, 0, 2>), dim3(nblocks(n)), dim3(kThreads), 0, s, region_codes, ca, cd_codes, smax);
+  else
+    hipLaunchKernelGGL((k_cd_forward<Q, 2, 0, 1>), dim3(nblocks(n)), dim3(kThreads), 0, s, region_codes, ca, cd_codes, smax);
   return hipGetLastError();
 }
 
@@ -796,11 +812,21 @@ template <typename Q>
 hipError_t launch_cd_inverse(const Q* cd_codes, const CDArgs& ca, Q* region_out, hipStream_t s) {
   const int64_t n = (int64_t)ca.c[0] * ca.c[1] * ca.c[2];
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cd_inverse<Q, 0>), dim3(nblocks(n)), dim3(kThreads), 0, s, cd_codes, ca, region_out);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_cd_inverse<Q, 1>), dim3(nblocks(n)), dim3(kThreads), 0, s, cd_codes, ca, region_out);
-  return hipGetLastError();
+#define APC_CDINV(PH, A_, U_, V_) \
+  hipLaunchKernelGGL((k_cd_inverse<Q, PH, A_, U_, V_>), dim3(nblocks(n)), dim3(kThreads), 0, s, cd_codes, ca, region_out)
+  for (int ph = 0; ph < 2; ++ph) {
+    if (ca.a == 0) {
+      if (ph == 0) APC_CDINV(0, 0, 1, 2); else APC_CDINV(1, 0, 1, 2);
+    } else if (ca.a == 1) {
+      if (ph == 0) APC_CDINV(0, 1, 0, 2); else APC_CDINV(1, 1, 0, 2);
+    } else {
+      if (ph == 0) APC_CDINV(0, 2, 0, 1); else APC_CDINV(1, 2, 0, 1);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+#undef APC_CDINV
+  return hipSuccess;
 }
 
 template <typename Q>
@@ -835,8 +861,9 @@ hipError_t launch_decode(const StreamDev* sd_dev, int nstreams, int64_t total_ch
                          const uint32_t* idx, const uint64_t* sign, const int64_t* pso, Q* codes, Q* cd_codes,
                          hipStream_t s) {
   if (total_chunks == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_decode<Q>), dim3((unsigned)total_chunks), dim3(kThreads), 0, s, sd_dev, nstreams, mag, idx,
-                     sign, pso, codes, cd_codes);
+  constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
+  hipLaunchKernelGGL((k_decode<Q, MAXB>), dim3((unsigned)total_chunks), dim3(kThreads), 0, s, sd_dev, nstreams, mag,
+                     idx, sign, pso, codes, cd_codes);
   return hipGetLastError();
 }
 
