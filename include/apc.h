@@ -89,6 +89,16 @@ typedef struct apc_handle apc_handle;
 apc_status apc_refactor(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
                         const apc_scheme* scheme, void* hip_stream, apc_handle** out);
 
+/* Refactor many fields of one dtype together (batching): every pass is one
+ * launch over the segments of all fields, and the host synchronizes three
+ * times for the whole batch instead of three times per field.  fields_dev[f]
+ * has ndims[f] dims, read consecutively from dims; schemes[f] applies to
+ * field f.  out[f] receives a handle identical (same streams, same metadata)
+ * to apc_refactor of that field alone.  On error no handle is returned. */
+apc_status apc_refactor_batch(const void* const* fields_dev, int32_t dtype, const int64_t* dims,
+                              const int32_t* ndims, const apc_scheme* schemes, int32_t nfields,
+                              void* hip_stream, apc_handle** out);
+
 /* Plan only (Section V-C interpreter, host side, no device work): fills
  * planes_out[n_streams] (may be NULL) and info.  APC_E_BELOW_FLOOR if the
  * target cannot be met even with every plane. */
@@ -106,6 +116,19 @@ apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev,
 /* Retrieve with an explicit plane count per stream (planes[n_streams], each
  * clamped to the stream's plane count). */
 apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream);
+
+/* Retrieval ladder as one HIP graph: the plans of targets[0..n) are made
+ * now, their decode / recompose / reconstruct launches are captured once,
+ * and apc_ladder_launch replays them on any stream, writing step i to
+ * outs_dev[i] (caller owned, n elements each).  Every replay starts from no
+ * resident planes, so it gives the same bytes as n single apc_retrieve calls
+ * on a fresh handle.  The ladder borrows the handle's work buffers: do not
+ * run other retrievals on the same handle while a replay is in flight. */
+typedef struct apc_ladder apc_ladder;
+apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n, void* const* outs_dev,
+                             void* hip_stream, apc_ladder** out);
+apc_status apc_ladder_launch(apc_ladder* ladder, void* hip_stream);
+void apc_ladder_free(apc_ladder* ladder);
 
 /* Target-driven pipeline selection (Section VI-A): regular ~1% sample
  * blocks, every candidate of Table I refactored on the sample, plan sizes at

@@ -40,6 +40,7 @@ EXPORTED = [
     "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline", "apc_free",
     "apc_strerror", "apc_last_error", "apc_num_streams", "apc_num_groups", "apc_num_points", "apc_stream_info",
     "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
+    "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free",
 ]
 
 
@@ -81,10 +82,17 @@ _lib.apc_stream_blob.argtypes = [_vp, _i32, _vp, _i64]
 _lib.apc_metadata_json.argtypes = [_vp, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 _lib.apc_axis_norms.argtypes = [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.apc_profile_enable.argtypes = [_i32]
+_lib.apc_refactor_batch.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                                    ctypes.POINTER(_Scheme), _i32, _vp, ctypes.POINTER(_vp)]
+_lib.apc_ladder_create.argtypes = [_vp, ctypes.POINTER(_Target), _i32, ctypes.POINTER(_vp), _vp,
+                                   ctypes.POINTER(_vp)]
+_lib.apc_ladder_launch.argtypes = [_vp, _vp]
+_lib.apc_ladder_free.argtypes = [_vp]
+_lib.apc_ladder_free.restype = None
 _lib.apc_profile_report.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
               "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable",
-              "apc_profile_report"):
+              "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -238,6 +246,55 @@ def refactor(field, scheme: Scheme = Scheme(), stream=None) -> Handle:
     _check(_lib.apc_refactor(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(),
                              ctypes.byref(scheme._c(field.dim())), _stream_ptr(stream), ctypes.byref(out)))
     return Handle(out.value, tuple(field.shape), field.dtype)
+
+
+def refactor_batch(fields, schemes, stream=None) -> List[Handle]:
+    """Refactor many contiguous device tensors (one dtype) in shared launches."""
+    nf = len(fields)
+    assert nf == len(schemes) and nf > 0
+    dt = _dtype_code(fields[0])
+    ptrs = (ctypes.c_void_p * nf)(*[f.data_ptr() for f in fields])
+    dims = []
+    for f in fields:
+        assert f.is_cuda and f.is_contiguous() and _dtype_code(f) == dt
+        dims.extend(int(v) for v in f.shape)
+    cdims = (ctypes.c_int64 * len(dims))(*dims)
+    nds = (ctypes.c_int32 * nf)(*[f.dim() for f in fields])
+    cs = (_Scheme * nf)(*[sc._c(f.dim()) for sc, f in zip(schemes, fields)])
+    outs = (ctypes.c_void_p * nf)()
+    _check(_lib.apc_refactor_batch(ptrs, dt, cdims, nds, cs, nf, _stream_ptr(stream), outs))
+    return [Handle(outs[i], tuple(f.shape), f.dtype) for i, f in enumerate(fields)]
+
+
+class Ladder:
+    """A retrieval ladder captured as one HIP graph (replayable)."""
+
+    def __init__(self, handle: Handle, targets: Sequence[Target], outs=None, stream=None):
+        import torch
+        n = len(targets)
+        self.handle = handle
+        self.outs = outs if outs is not None else [torch.empty(handle.shape, dtype=handle.dtype, device="cuda")
+                                                   for _ in range(n)]
+        tg = (_Target * n)(*[t._c() for t in targets])
+        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
+        out = ctypes.c_void_p()
+        _check(_lib.apc_ladder_create(handle._h, tg, n, ptrs, _stream_ptr(stream), ctypes.byref(out)))
+        self._p = out
+
+    def launch(self, stream=None):
+        _check(_lib.apc_ladder_launch(self._p, _stream_ptr(stream)))
+        return self.outs
+
+    def close(self):
+        if self._p:
+            _lib.apc_ladder_free(self._p)
+            self._p = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def select_pipeline(field, mode: str = "eb", stream=None) -> Scheme:

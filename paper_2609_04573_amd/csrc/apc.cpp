@@ -7,9 +7,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -219,6 +222,8 @@ Lattice lattice(const Geo& g, int l, int rho) {
     L.c[a] = L.kind[a] == AX_ALL ? m : (L.kind[a] == AX_ODD ? m / 2 : (m + 1) / 2);
   }
   L.ax = g.sigma3[rho];
+  L.f2 = make_fastdiv((uint32_t)std::max(1, L.c[2]));
+  L.f1 = make_fastdiv((uint32_t)std::max(1, L.c[1]));
   return L;
 }
 
@@ -259,6 +264,15 @@ double unordered(unsigned long long ob) {
 
 }  // namespace
 
+// One level-0 region under coefficient decomposition.
+struct CDInfo {
+  int32_t c[3];      // region lattice dims
+  int32_t a;         // stacking axis (3D)
+  int s_idx[3];      // streams S1..S3
+  int64_t s_off[3];  // their offsets in the decomposition code buffer
+  int64_t reg_off;   // offset of the region in the recomposition buffer
+};
+
 struct apc_handle {
   Meta meta;
   Geo geo;
@@ -267,20 +281,127 @@ struct apc_handle {
   std::vector<int64_t> region_off;  // (l * 3 + rho) -> offset in the region code buffer
   int64_t code_n = 0;               // codes in the region code buffer
   int64_t cd_n = 0;                 // codes in the decomposition buffer
-  std::vector<CDArgs> cd;           // per level-0 region
+  int64_t cdreg_n = 0;              // codes in the recomposition buffer
+  std::vector<CDInfo> cd;           // per level-0 region
+  std::vector<int> psb;             // per stream: first entry in pso
   // stored representation
   DevBuf mag, idx, sign, pso;
-  // retrieval state
+  // retrieval state: decoded codes and planes decoded so far per stream
   DevBuf codes, cd_codes;
   std::vector<int> k_res;
-  DevBuf xc, xb[2], pr[2], cdreg, sd, tmp;
-  std::vector<StreamDev> sd_host;   // source of the last decode-table upload
+  DevBuf xc, xb[2], pr[2], cdreg, tables;
   bool work_ready = false;
+  void* pinned = nullptr;  // staging of table uploads
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  ~apc_handle() {
+    if (pinned) (void)hipHostFree(pinned);
+    if (upload_done) (void)hipEventDestroy(upload_done);
+  }
 };
 
 namespace {
 
 size_t qsize(int dtype) { return dtype == APC_F32 ? 4 : 8; }
+
+// ------------------------------------------------------------ segment tables
+struct TableBuilder {
+  std::vector<char> bytes;
+  template <typename S>
+  size_t add(const std::vector<S>& v) {
+    size_t off = (bytes.size() + 255) & ~(size_t)255;
+    bytes.resize(off + sizeof(S) * v.size());
+    if (!v.empty()) memcpy(bytes.data() + off, v.data(), sizeof(S) * v.size());
+    return off;
+  }
+};
+
+enum LaunchKind {
+  K_RANGE, K_GATHER, K_COEF0, K_COEF1, K_COARSE0, K_COARSE1, K_CDF, K_CDI0, K_CDI1,
+  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON
+};
+
+struct Launch {
+  int kind;
+  size_t off;
+  int nseg;
+  int64_t nblk;   // work blocks, or chunks for the codec kernels
+  int a;          // stacking axis (decomposition kernels)
+  double bytes;   // bytes the launch must move (profiling)
+  const char* name;
+};
+
+template <typename S>
+int64_t assign_blocks(std::vector<S>& segs, std::function<int64_t(const S&)> count) {
+  int64_t b = 0;
+  for (S& s : segs) {
+    s.blk_begin = b;
+    b += (count(s) + kBlockElems - 1) / kBlockElems;
+  }
+  return b;
+}
+
+template <typename T, typename Q>
+apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st) {
+  for (const Launch& l : ls) {
+    const void* p = base + l.off;
+    switch (l.kind) {
+      case K_RANGE: LAUNCH(l.name, l.bytes, st, launch_range<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
+      case K_GATHER: LAUNCH(l.name, l.bytes, st, launch_gather<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
+      case K_COEF0: LAUNCH(l.name, l.bytes, st, (launch_coef<T, Q>((const CoefSeg*)p, l.nseg, l.nblk, 0, st))); break;
+      case K_COEF1: LAUNCH(l.name, l.bytes, st, (launch_coef<T, Q>((const CoefSeg*)p, l.nseg, l.nblk, 1, st))); break;
+      case K_COARSE0:
+        LAUNCH(l.name, l.bytes, st, (launch_coarse<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, 0, st)));
+        break;
+      case K_COARSE1:
+        LAUNCH(l.name, l.bytes, st, (launch_coarse<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, 1, st)));
+        break;
+      case K_CDF: LAUNCH(l.name, l.bytes, st, launch_cd_forward<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, st)); break;
+      case K_CDI0:
+        LAUNCH(l.name, l.bytes, st, launch_cd_inverse<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 0, st));
+        break;
+      case K_CDI1:
+        LAUNCH(l.name, l.bytes, st, launch_cd_inverse<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 1, st));
+        break;
+      case K_ENCODE: LAUNCH(l.name, l.bytes, st, launch_encode<Q>((const StreamDev*)p, l.nseg, l.nblk, st)); break;
+      case K_SIGN: LAUNCH(l.name, l.bytes, st, launch_sign_move((const StreamDev*)p, l.nseg, l.nblk, st)); break;
+      case K_DECODE: LAUNCH(l.name, l.bytes, st, launch_decode<Q>((const StreamDev*)p, l.nseg, l.nblk, st)); break;
+      case K_COARSEST:
+        LAUNCH(l.name, l.bytes, st, (launch_coarsest<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, st)));
+        break;
+      case K_INJECT: LAUNCH(l.name, l.bytes, st, launch_inject<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
+      case K_RECON: LAUNCH(l.name, l.bytes, st, (launch_recon<T, Q>((const ReconSeg*)p, l.nseg, l.nblk, st))); break;
+      default: return fail(APC_E_INVALID, "unknown launch kind");
+    }
+  }
+  return APC_OK;
+}
+
+// Pinned staging that stays valid until the process ends; append-only
+// within one refactor call.
+struct Staging {
+  void* p = nullptr;
+  size_t cap = 0, used = 0;
+  ~Staging() {
+    if (p) (void)hipHostFree(p);
+  }
+  apc_status put(const std::vector<char>& bytes, void* dev, hipStream_t st) {
+    if (bytes.empty()) return APC_OK;
+    if (used + bytes.size() > cap) {
+      // grow: the old buffer may still feed queued copies, so wait first
+      HIP_TRY(hipStreamSynchronize(st));
+      if (p) (void)hipHostFree(p);
+      cap = std::max<size_t>(bytes.size() * 2, (size_t)1 << 20);
+      HIP_TRY(hipHostMalloc(&p, cap));
+      used = 0;
+    }
+    char* dst = (char*)p + used;
+    memcpy(dst, bytes.data(), bytes.size());
+    used += (bytes.size() + 255) & ~(size_t)255;
+    HIP_TRY(hipMemcpyAsync(dev, dst, bytes.size(), hipMemcpyHostToDevice, st));
+    return APC_OK;
+  }
+};
 
 apc_status setup_geometry(apc_handle* h, const int64_t* dims, int32_t ndim, const apc_scheme* sc) {
   if (ndim < 1 || ndim > 3) return fail(APC_E_INVALID, "ndim must be 1..3 (got %d)", ndim);
@@ -288,10 +409,11 @@ apc_status setup_geometry(apc_handle* h, const int64_t* dims, int32_t ndim, cons
   g.d = ndim;
   for (int a = 0; a < 3; ++a) g.N[a] = 1;
   for (int a = 0; a < ndim; ++a) {
-    if (dims[a] < 1 || dims[a] > (1ll << 30)) return fail(APC_E_INVALID, "dims[%d]=%lld out of range", a, (long long)dims[a]);
+    if (dims[a] < 1 || dims[a] > (1ll << 30))
+      return fail(APC_E_INVALID, "dims[%d]=%lld out of range", a, (long long)dims[a]);
     g.N[3 - ndim + a] = dims[a];
   }
-  if (g.n() > (1ll << 34)) return fail(APC_E_INVALID, "field too large");
+  if (g.n() > (1ll << 32) - 1) return fail(APC_E_INVALID, "field too large (more than 2^32-1 points)");
   if (sc->kind != APC_PER_LEVEL && sc->kind != APC_PER_REGION) return fail(APC_E_INVALID, "scheme.kind");
   if (sc->degree != 1 && sc->degree != 3) return fail(APC_E_INVALID, "scheme.degree must be 1 or 3");
   if (sc->cd_axis < -1 || sc->cd_axis >= ndim) return fail(APC_E_INVALID, "scheme.cd_axis out of range");
@@ -318,7 +440,7 @@ apc_status setup_geometry(apc_handle* h, const int64_t* dims, int32_t ndim, cons
 }
 
 // Groups, streams, units and buffer offsets, in unit order.
-void build_layout(apc_handle* h, int P, double xmin, double xmax, double A) {
+void build_layout(apc_handle* h, int P) {
   Geo& g = h->geo;
   Meta& m = h->meta;
   const int d = g.d, L = g.L;
@@ -329,9 +451,6 @@ void build_layout(apc_handle* h, int P, double xmin, double xmax, double A) {
   m.L = L;
   m.P = P;
   m.n = g.n();
-  m.xmin = xmin;
-  m.xmax = xmax;
-  m.A = A;
   h->region_off.assign((size_t)std::max(1, L) * 3, 0);
   int64_t off = 0;
   const int64_t ncoarse = (int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2];
@@ -362,18 +481,17 @@ void build_layout(apc_handle* h, int P, double xmin, double xmax, double A) {
 
   h->cd.clear();
   h->cd_n = 0;
+  h->cdreg_n = 0;
   for (int l = L - 2; l >= 0; --l) {
     const bool use_cd = cd_axis >= 0 && l == 0;
     auto add_cd = [&](int rho, int group) {
       const Lattice lat = lattice(g, 0, rho);
-      CDArgs ca{};
-      for (int a = 0; a < 3; ++a) ca.c[a] = lat.c[a];
-      ca.a = cd_axis + (3 - d);
+      CDInfo ci{};
+      for (int a = 0; a < 3; ++a) ci.c[a] = lat.c[a];
+      ci.a = cd_axis + (3 - d);
       int rest[2], nr = 0;
       for (int a = 0; a < 3; ++a)
-        if (a != ca.a) rest[nr++] = a;
-      ca.u = rest[0];
-      ca.v = rest[1];
+        if (a != ci.a) rest[nr++] = a;
       std::vector<int> trip;
       for (int t = 0; t < 3; ++t) {
         Stream s;
@@ -382,16 +500,18 @@ void build_layout(apc_handle* h, int P, double xmin, double xmax, double A) {
         s.rho = rho;
         s.t = t + 1;
         s.group = group;
-        s.n = (int64_t)ca.c[ca.a] * cls_count_h(t, prefix_h(ca.c[ca.u]), prefix_h(ca.c[ca.v]));
+        s.n = (int64_t)ci.c[ci.a] * cls_count_h(t, prefix_h(ci.c[rest[0]]), prefix_h(ci.c[rest[1]]));
         s.use_cd = true;
         s.code_off = h->cd_n;
-        ca.s_off[t] = h->cd_n;
-        ca.s_idx[t] = (int)m.streams.size();
+        ci.s_off[t] = h->cd_n;
+        ci.s_idx[t] = (int)m.streams.size();
         h->cd_n += s.n;
         trip.push_back((int)m.streams.size());
         m.streams.push_back(s);
       }
-      h->cd.push_back(ca);
+      ci.reg_off = h->cdreg_n;
+      h->cdreg_n += lat_count(lat);
+      h->cd.push_back(ci);
       return trip;
     };
     if (per_level) {
@@ -415,14 +535,10 @@ void build_layout(apc_handle* h, int P, double xmin, double xmax, double A) {
         m.streams.push_back(s);
         m.units.push_back(u);
       } else {
-        std::vector<std::vector<int>> rs;
-        for (int rho = 0; rho < d; ++rho) rs.push_back(add_cd(rho, gi));
-        Unit u;  // staircase filled once plane counts are known
+        for (int rho = 0; rho < d; ++rho) add_cd(rho, gi);
+        Unit u;  // the staircase is built once plane counts are known
         u.group = gi;
         u.stair = true;
-        u.seg_steps.clear();
-        u.levels.clear();
-        // remember the triples in seg_steps[0] temporarily is not needed: rebuilt in finalize
         m.units.push_back(u);
       }
     } else {
@@ -507,8 +623,8 @@ void finalize_units(apc_handle* h) {
   finalize_meta(m);
 }
 
-template <typename Q>
-RegionArgs region_args(apc_handle* h, int l, int rho, bool per_level, bool with_pr, bool write_pr) {
+RegionArgs region_args(const apc_handle* h, int l, int rho, bool per_level, double* const pr[2], bool with_pr,
+                       bool write_pr) {
   const Geo& g = h->geo;
   RegionArgs ra{};
   ra.lat = lattice(g, l, rho);
@@ -519,225 +635,423 @@ RegionArgs region_args(apc_handle* h, int l, int rho, bool per_level, bool with_
   for (int r = 0; r < 2; ++r) {
     if (r < rho && with_pr) {
       ra.prl[r] = lattice(g, l, r);
-      ra.pr[r] = h->pr[r].as<double>();
+      ra.pr[r] = pr[r];
     }
   }
-  ra.pr_out = (write_pr && rho < g.d - 1) ? h->pr[rho].as<double>() : nullptr;
+  ra.pr_out = (write_pr && rho < g.d - 1) ? pr[rho] : nullptr;
   return ra;
 }
 
+int group_of(const Meta& m, int l, int rho) {
+  for (int gi = 0; gi < (int)m.groups.size(); ++gi) {
+    const Group& gr = m.groups[gi];
+    if (gr.kind == G_LEVEL && gr.level == l) return gi;
+    if (gr.kind == G_REGION && gr.level == l && gr.rho == rho) return gi;
+  }
+  return 0;
+}
+
+int stream_of(const Meta& m, int l, int rho) {
+  for (int s = 0; s < (int)m.streams.size(); ++s) {
+    const Stream& S = m.streams[s];
+    if (S.kind == S_LEVEL && S.level == l) return s;
+    if (S.kind == S_REGION && S.level == l && S.rho == rho) return s;
+  }
+  return -1;
+}
+
+// ------------------------------------------------------------- refactoring
+// Refactor a batch of fields (one dtype): every pass is one launch over the
+// segments of all fields; the host syncs three times for the whole batch.
 template <typename T, typename Q>
-apc_status refactor_impl(apc_handle* h, const T* x, hipStream_t st) {
-  Geo& g = h->geo;
-  const int d = g.d, L = g.L;
+apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T*>& X, hipStream_t st) {
+  const int nf = (int)H.size();
   const int P = sizeof(T) == 4 ? 29 : 52;
-  const bool per_level = h->scheme.kind == APC_PER_LEVEL;
-  const int64_t n = g.n();
-
-  // grids of levels 1..L-1 (compact copies of the original values)
-  std::vector<int64_t> goff(L, 0);
-  int64_t gtot = 0;
-  for (int l = 1; l < L; ++l) {
-    goff[l] = gtot;
-    gtot += (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
-  }
-  DevBuf grids, small, codes, cdc;
-  APC_TRY(grids.alloc(sizeof(T) * (size_t)gtot));
-  auto grid_ptr = [&](int l) -> const T* { return l == 0 ? x : grids.as<T>() + goff[l]; };
-  for (int l = 1; l < L; ++l)
-    LAUNCH("subsample", 2.0 * sizeof(T) * g.m[l][0] * g.m[l][1] * g.m[l][2], st,
-           launch_subsample<T>(grid_ptr(l - 1), g.m[l - 1].data(), grids.as<T>() + goff[l], g.m[l].data(), st));
-
-  build_layout(h, P, 0, 0, 0);
-  Meta& m = h->meta;
-  const int ng = (int)m.groups.size(), ns = (int)m.streams.size();
-  APC_TRY(small.alloc(8 * (size_t)(4 + ng + ns)));
-  unsigned long long* acc = small.as<unsigned long long>();
-  unsigned long long* gmax = acc + 4;
-  unsigned long long* smax = gmax + ng;
-  std::vector<unsigned long long> init(4 + ng + ns, 0ull);
-  init[0] = ~0ull;
-  HIP_TRY(hipMemcpyAsync(acc, init.data(), 8 * init.size(), hipMemcpyHostToDevice, st));
-  LAUNCH("range", (double)sizeof(T) * n, st, launch_range<T>(x, n, acc, st));
-
-  if (per_level && d >= 2) {
-    APC_TRY(h->pr[0].alloc(8 * (size_t)lat_count(lattice(g, 0, 0))));
-    if (d >= 3) APC_TRY(h->pr[1].alloc(8 * (size_t)lat_count(lattice(g, 0, 1))));
-  }
-  // group index of (level, region)
-  auto group_of = [&](int l, int rho) {
-    for (int gi = 0; gi < ng; ++gi) {
-      const Group& gr = m.groups[gi];
-      if (gr.kind == G_LEVEL && gr.level == l) return gi;
-      if (gr.kind == G_REGION && gr.level == l && gr.rho == rho) return gi;
-    }
-    return 0;
+  struct Tmp {
+    DevBuf grids, codes, cdc, prb;
+    std::vector<int64_t> goff;   // level -> offset in grids
+    std::vector<int64_t> proff;  // (level * 2 + region) -> offset in prb
+    int64_t acc = 0;             // offset in the accumulator buffer
   };
-  // pass 1: coefficient maxima
-  for (int l = 0; l < L - 1; ++l)
-    for (int rho = 0; rho < d; ++rho) {
-      RegionArgs ra = region_args<Q>(h, l, rho, per_level, per_level, per_level);
-      const double nr = (double)lat_count(ra.lat);
-      LAUNCH("coef_max", nr * sizeof(T) + (ra.pr_out ? 8.0 * nr : 0.0), st,
-             (launch_coef<T, Q>(grid_ptr(l), ra, 0, gmax + group_of(l, rho), 0, (Q*)nullptr, st)));
+  std::vector<Tmp> tmp(nf);
+  int64_t nacc = 0;
+  for (int f = 0; f < nf; ++f) {
+    apc_handle* h = H[f];
+    build_layout(h, P);
+    const Geo& g = h->geo;
+    Tmp& t = tmp[f];
+    t.goff.assign(g.L, 0);
+    int64_t gtot = 0;
+    for (int l = 1; l < g.L; ++l) {
+      t.goff[l] = gtot;
+      gtot += (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
     }
-  const int64_t ncoarse = m.streams[0].n;
-  LAUNCH("coarse", (double)sizeof(T) * ncoarse, st,
-         (launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 0, gmax + 0, 0, (Q*)nullptr, st)));
-  std::vector<unsigned long long> hv(4 + ng);
+    APC_TRY(t.grids.alloc(sizeof(T) * (size_t)gtot));
+    APC_TRY(t.codes.alloc(sizeof(Q) * (size_t)h->code_n));
+    if (h->cd_n) APC_TRY(t.cdc.alloc(sizeof(Q) * (size_t)h->cd_n));
+    t.proff.assign((size_t)std::max(1, g.L) * 2, 0);
+    int64_t ptot = 0;
+    if (h->scheme.kind == APC_PER_LEVEL)
+      for (int l = 0; l < g.L - 1; ++l)
+        for (int r = 0; r < std::min(2, g.d - 1); ++r) {
+          t.proff[l * 2 + r] = ptot;
+          ptot += lat_count(lattice(g, l, r));
+        }
+    if (ptot) APC_TRY(t.prb.alloc(8 * (size_t)ptot));
+    t.acc = nacc;
+    nacc += 4 + (int64_t)h->meta.groups.size() + (int64_t)h->meta.streams.size();
+  }
+  DevBuf accb, tab;
+  APC_TRY(accb.alloc(8 * (size_t)nacc));
+  std::vector<unsigned long long> init((size_t)nacc, 0ull);
+  for (int f = 0; f < nf; ++f) init[(size_t)tmp[f].acc] = ~0ull;
+  Staging stage;
+  {
+    std::vector<char> b(init.size() * 8);
+    memcpy(b.data(), init.data(), b.size());
+    APC_TRY(stage.put(b, accb.p, st));
+  }
+  unsigned long long* acc = accb.as<unsigned long long>();
+  auto grid_ptr = [&](int f, int l) -> const T* { return l == 0 ? X[f] : tmp[f].grids.template as<T>() + tmp[f].goff[l]; };
+  auto pr_ptrs = [&](int f, int l, double* pr[2]) {
+    for (int r = 0; r < 2; ++r)
+      pr[r] = tmp[f].prb.p ? tmp[f].prb.template as<double>() + tmp[f].proff[l * 2 + r] : nullptr;
+  };
+
+  // ---- tables of the first pass
+  TableBuilder tb;
+  std::vector<Launch> ls;
+  {
+    std::vector<FlatSeg> rs, gs;
+    for (int f = 0; f < nf; ++f) {
+      FlatSeg s{};
+      s.src = X[f];
+      s.n = H[f]->geo.n();
+      s.acc = acc + tmp[f].acc;
+      rs.push_back(s);
+      const Geo& g = H[f]->geo;
+      for (int l = 1; l < g.L; ++l) {
+        FlatSeg q{};
+        q.src = X[f];
+        q.dst = tmp[f].grids.template as<T>() + tmp[f].goff[l];
+        q.n = (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
+        const int64_t sl = (int64_t)1 << l;
+        q.s[0] = sl * g.N[1] * g.N[2];
+        q.s[1] = sl * g.N[2];
+        q.s[2] = sl;
+        for (int a = 0; a < 3; ++a) q.dm[a] = g.m[l][a];
+        q.f2 = make_fastdiv((uint32_t)q.dm[2]);
+        q.f1 = make_fastdiv((uint32_t)q.dm[1]);
+        gs.push_back(q);
+      }
+    }
+    double nb = 0, gb = 0;
+    for (auto& s : rs) nb += (double)sizeof(T) * s.n;
+    for (auto& s : gs) gb += 2.0 * sizeof(T) * s.n;
+    const int64_t b1 = assign_blocks<FlatSeg>(rs, [](const FlatSeg& s) { return s.n; });
+    const int64_t b2 = assign_blocks<FlatSeg>(gs, [](const FlatSeg& s) { return s.n; });
+    ls.push_back({K_RANGE, tb.add(rs), (int)rs.size(), b1, 0, nb, "range"});
+    ls.push_back({K_GATHER, tb.add(gs), (int)gs.size(), b2, 0, gb, "subsample"});
+    for (int rho = 0; rho < 3; ++rho) {
+      std::vector<CoefSeg> cs;
+      double by = 0;
+      for (int f = 0; f < nf; ++f) {
+        const apc_handle* h = H[f];
+        if (rho >= h->geo.d) continue;
+        const bool per_level = h->scheme.kind == APC_PER_LEVEL;
+        for (int l = 0; l < h->geo.L - 1; ++l) {
+          CoefSeg c{};
+          double* pr[2];
+          pr_ptrs(f, l, pr);
+          c.ra = region_args(h, l, rho, per_level, pr, per_level, per_level);
+          if (lat_count(c.ra.lat) == 0) continue;
+          c.G = grid_ptr(f, l);
+          c.gmax = acc + tmp[f].acc + 4 + group_of(h->meta, l, rho);
+          by += (double)lat_count(c.ra.lat) * (sizeof(T) + (c.ra.pr_out ? 8 : 0));
+          cs.push_back(c);
+        }
+      }
+      const int64_t nbk = assign_blocks<CoefSeg>(cs, [](const CoefSeg& c) { return lat_count(c.ra.lat); });
+      if (!cs.empty()) ls.push_back({K_COEF0, tb.add(cs), (int)cs.size(), nbk, 0, by, "coef_max"});
+    }
+    std::vector<FlatSeg> cs;
+    double by = 0;
+    for (int f = 0; f < nf; ++f) {
+      FlatSeg s{};
+      s.src = grid_ptr(f, H[f]->geo.L - 1);
+      s.n = H[f]->meta.streams[0].n;
+      s.acc = acc + tmp[f].acc + 4;
+      by += (double)sizeof(T) * s.n;
+      cs.push_back(s);
+    }
+    const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
+    ls.push_back({K_COARSE0, tb.add(cs), (int)cs.size(), nbk, 0, by, "coarse"});
+  }
+  APC_TRY(tab.alloc(tb.bytes.size()));
+  APC_TRY(stage.put(tb.bytes, tab.p, st));
+  APC_TRY((issue<T, Q>(ls, (const char*)tab.p, st)));
+  std::vector<unsigned long long> hv((size_t)nacc);
   HIP_TRY(hipMemcpyAsync(hv.data(), acc, 8 * hv.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (hv[3]) return fail(APC_E_NONFINITE, "field holds NaN or Inf");
-  m.xmin = unordered(hv[0]);
-  m.xmax = unordered(hv[1]);
-  m.A = bits_double(hv[2]);
-  for (int gi = 0; gi < ng; ++gi) {
-    Group& gr = m.groups[gi];
-    gr.M = bits_double(hv[4 + gi]);
-    if (gr.M > 0.0) {
-      int E;
-      frexp(gr.M, &E);
-      gr.E = E;
-      gr.k_shift = P - E;
-      gr.delta = ldexp(1.0, E - P);
-    } else {
-      gr.E = 0;
-      gr.k_shift = 0;
-      gr.delta = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const unsigned long long* v = hv.data() + tmp[f].acc;
+    if (v[3]) return fail(APC_E_NONFINITE, "field %d holds NaN or Inf", f);
+    Meta& m = H[f]->meta;
+    m.xmin = unordered(v[0]);
+    m.xmax = unordered(v[1]);
+    m.A = bits_double(v[2]);
+    for (size_t gi = 0; gi < m.groups.size(); ++gi) {
+      Group& gr = m.groups[gi];
+      gr.M = bits_double(v[4 + gi]);
+      if (gr.M > 0.0) {
+        int E;
+        frexp(gr.M, &E);
+        gr.E = E;
+        gr.k_shift = P - E;
+        gr.delta = ldexp(1.0, E - P);
+      } else {
+        gr.E = 0;
+        gr.k_shift = 0;
+        gr.delta = 0.0;
+      }
     }
   }
 
-  // pass 2: quantized codes
-  APC_TRY(codes.alloc(sizeof(Q) * (size_t)h->code_n));
-  for (int l = 0; l < L - 1; ++l)
-    for (int rho = 0; rho < d; ++rho) {
-      RegionArgs ra = region_args<Q>(h, l, rho, per_level, per_level, per_level);
-      const Group& gr = m.groups[group_of(l, rho)];
-      const double nr = (double)lat_count(ra.lat);
-      LAUNCH("coef_quant", nr * (sizeof(T) + sizeof(Q)) + (ra.pr_out ? 8.0 * nr : 0.0), st,
-             (launch_coef<T, Q>(grid_ptr(l), ra, 1, nullptr, gr.k_shift, codes.as<Q>() + h->region_off[l * 3 + rho], st)));
+  // ---- second pass: codes, then coefficient decomposition
+  TableBuilder tb2;
+  ls.clear();
+  bool any_cd = false;
+  for (int rho = 0; rho < 3; ++rho) {
+    std::vector<CoefSeg> cs;
+    double by = 0;
+    for (int f = 0; f < nf; ++f) {
+      const apc_handle* h = H[f];
+      if (rho >= h->geo.d) continue;
+      const bool per_level = h->scheme.kind == APC_PER_LEVEL;
+      for (int l = 0; l < h->geo.L - 1; ++l) {
+        CoefSeg c{};
+        double* pr[2];
+        pr_ptrs(f, l, pr);
+        c.ra = region_args(h, l, rho, per_level, pr, per_level, per_level);
+        if (lat_count(c.ra.lat) == 0) continue;
+        c.G = grid_ptr(f, l);
+        c.codes = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
+        c.k_shift = h->meta.groups[group_of(h->meta, l, rho)].k_shift;
+        by += (double)lat_count(c.ra.lat) * (sizeof(T) + sizeof(Q) + (c.ra.pr_out ? 8 : 0));
+        cs.push_back(c);
+      }
     }
-  LAUNCH("coarse", (double)(sizeof(T) + sizeof(Q)) * ncoarse, st,
-         (launch_coarse<T, Q>(grid_ptr(L - 1), ncoarse, 1, nullptr, m.groups[0].k_shift, codes.as<Q>(), st)));
-  grids.release();
-
-  // coefficient decomposition of level 0
-  if (h->scheme.cd_axis >= 0 && L >= 2) {
-    APC_TRY(cdc.alloc(sizeof(Q) * (size_t)std::max<int64_t>(1, h->cd_n)));
-    for (int rho = 0; rho < d; ++rho)
-      LAUNCH("cd_forward", 2.0 * sizeof(Q) * h->cd[rho].c[0] * h->cd[rho].c[1] * h->cd[rho].c[2], st,
-             (launch_cd_forward<Q>(codes.as<Q>() + h->region_off[rho], h->cd[rho], cdc.as<Q>(), smax, st)));
-    std::vector<unsigned long long> sv(ns);
-    HIP_TRY(hipMemcpyAsync(sv.data(), smax, 8 * ns, hipMemcpyDeviceToHost, st));
+    const int64_t nbk = assign_blocks<CoefSeg>(cs, [](const CoefSeg& c) { return lat_count(c.ra.lat); });
+    if (!cs.empty()) ls.push_back({K_COEF1, tb2.add(cs), (int)cs.size(), nbk, 0, by, "coef_quant"});
+  }
+  {
+    std::vector<FlatSeg> cs;
+    double by = 0;
+    for (int f = 0; f < nf; ++f) {
+      FlatSeg s{};
+      s.src = grid_ptr(f, H[f]->geo.L - 1);
+      s.dst = tmp[f].codes.p;
+      s.n = H[f]->meta.streams[0].n;
+      s.k_shift = H[f]->meta.groups[0].k_shift;
+      by += (double)(sizeof(T) + sizeof(Q)) * s.n;
+      cs.push_back(s);
+    }
+    const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
+    ls.push_back({K_COARSE1, tb2.add(cs), (int)cs.size(), nbk, 0, by, "coarse"});
+  }
+  for (int a3 = 0; a3 < 3; ++a3) {
+    std::vector<CDSeg> cs;
+    double by = 0;
+    for (int f = 0; f < nf; ++f) {
+      apc_handle* h = H[f];
+      for (int rho = 0; rho < (int)h->cd.size(); ++rho) {
+        const CDInfo& ci = h->cd[rho];
+        if (ci.a != a3) continue;
+        CDSeg c{};
+        for (int a = 0; a < 3; ++a) c.c[a] = ci.c[a];
+        c.f2 = make_fastdiv((uint32_t)std::max(1, c.c[2]));
+        c.f1 = make_fastdiv((uint32_t)std::max(1, c.c[1]));
+        c.R = tmp[f].codes.template as<Q>() + h->region_off[0 * 3 + rho];
+        for (int t = 0; t < 3; ++t) {
+          c.S[t] = tmp[f].cdc.template as<Q>() + ci.s_off[t];
+          c.smax[t] = acc + tmp[f].acc + 4 + h->meta.groups.size() + ci.s_idx[t];
+        }
+        const int64_t cnt = (int64_t)c.c[0] * c.c[1] * c.c[2];
+        if (cnt == 0) continue;
+        by += 2.0 * sizeof(Q) * cnt;
+        cs.push_back(c);
+      }
+    }
+    if (cs.empty()) continue;
+    any_cd = true;
+    const int64_t nbk = assign_blocks<CDSeg>(cs, [](const CDSeg& c) { return (int64_t)c.c[0] * c.c[1] * c.c[2]; });
+    ls.push_back({K_CDF, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
+  }
+  DevBuf tab2;
+  APC_TRY(tab2.alloc(tb2.bytes.size()));
+  APC_TRY(stage.put(tb2.bytes, tab2.p, st));
+  APC_TRY((issue<T, Q>(ls, (const char*)tab2.p, st)));
+  if (any_cd) {
+    HIP_TRY(hipMemcpyAsync(hv.data(), acc, 8 * hv.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    for (int s = 0; s < ns; ++s)
-      if (m.streams[s].use_cd) m.streams[s].maxabs = (int64_t)bits_double(sv[s]);
   }
-  for (Stream& s : m.streams) {
-    if (!s.use_cd) {
-      const Group& gr = m.groups[s.group];
-      s.maxabs = gr.M > 0.0 ? (int64_t)rint(ldexp(gr.M, gr.k_shift)) : 0;
+  for (int f = 0; f < nf; ++f) {
+    apc_handle* h = H[f];
+    Meta& m = h->meta;
+    const unsigned long long* v = hv.data() + tmp[f].acc + 4 + m.groups.size();
+    for (int s = 0; s < (int)m.streams.size(); ++s) {
+      Stream& S = m.streams[s];
+      if (S.use_cd) {
+        S.maxabs = (int64_t)bits_double(v[s]);
+      } else {
+        const Group& gr = m.groups[S.group];
+        S.maxabs = gr.M > 0.0 ? (int64_t)rint(ldexp(gr.M, gr.k_shift)) : 0;
+      }
+      if (S.n == 0) S.maxabs = 0;
+      S.B = bitlen(S.maxabs);
     }
-    if (s.n == 0) s.maxabs = 0;
-    s.B = bitlen(s.maxabs);
   }
 
-  // bitplane encoding: magnitude words, per-chunk counts, staged signs
-  int64_t mag_words = 0, idx_n = 0, stage_words = 0, chunks = 0;
+  // ---- bitplane encoding of every stream of every field
   std::vector<StreamDev> sds;
-  std::vector<int> sd_stream;
-  for (int s = 0; s < ns; ++s) {
-    Stream& S = m.streams[s];
-    if (S.B == 0 || S.n == 0) continue;
-    S.mag_off = mag_words;
-    S.idx_off = idx_n;
-    StreamDev sd{};
-    sd.n = S.n;
-    sd.code_off = S.code_off;
-    sd.M = S.words();
-    sd.C = S.chunks();
-    sd.mag_off = mag_words;
-    sd.idx_off = idx_n;
-    sd.cnt_off = idx_n;
-    sd.stage_off = stage_words;
-    sd.chunk_begin = chunks;
-    sd.B = S.B;
-    sd.use_cd = S.use_cd ? 1 : 0;
-    mag_words += (int64_t)S.B * sd.M;
-    idx_n += (int64_t)S.B * sd.C;
-    stage_words += 64 * sd.C;
-    chunks += sd.C;
-    sds.push_back(sd);
-    sd_stream.push_back(s);
-  }
-  APC_TRY(h->mag.alloc(8 * (size_t)mag_words));
-  APC_TRY(h->idx.alloc(4 * (size_t)idx_n));
-  DevBuf cnt, stage, sdd, jobs, totals;
-  APC_TRY(cnt.alloc(4 * (size_t)idx_n));
-  APC_TRY(stage.alloc(8 * (size_t)stage_words));
-  APC_TRY(sdd.alloc(sizeof(StreamDev) * std::max<size_t>(1, sds.size())));
-  if (!sds.empty()) {
-    HIP_TRY(hipMemcpyAsync(sdd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    double eb = 8.0 * mag_words + 8.0 * stage_words + 4.0 * idx_n;
-    for (const StreamDev& sd : sds) eb += (double)sizeof(Q) * sd.n;
-    LAUNCH("encode", eb, st,
-           (launch_encode<Q>(codes.as<Q>(), cdc.as<Q>(), sdd.as<StreamDev>(), (int)sds.size(), chunks, nullptr, 0,
-                             h->mag.as<uint64_t>(), cnt.as<uint32_t>(), stage.as<uint64_t>(), st)));
-  }
-  std::vector<int32_t> job_s, job_j;
-  for (size_t i = 0; i < sds.size(); ++i)
-    for (int j = 0; j < sds[i].B; ++j) {
-      job_s.push_back((int32_t)i);
-      job_j.push_back(j);
+  std::vector<std::pair<int, int>> sd_of;  // (field, stream)
+  int64_t chunks = 0, cnt_n = 0, stage_w = 0;
+  for (int f = 0; f < nf; ++f) {
+    apc_handle* h = H[f];
+    Meta& m = h->meta;
+    int64_t mag_w = 0, idx_n = 0;
+    for (Stream& S : m.streams) {
+      S.mag_off = mag_w;
+      S.idx_off = idx_n;
+      if (S.B == 0 || S.n == 0) continue;
+      mag_w += (int64_t)S.B * S.words();
+      idx_n += (int64_t)S.B * S.chunks();
     }
-  const int njobs = (int)job_s.size();
-  APC_TRY(jobs.alloc(8 * (size_t)std::max(1, njobs)));
-  APC_TRY(totals.alloc(8 * (size_t)std::max(1, njobs)));
-  std::vector<int64_t> tot(njobs);
-  if (njobs) {
-    HIP_TRY(hipMemcpyAsync(jobs.p, job_s.data(), 4 * njobs, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(jobs.as<int32_t>() + njobs, job_j.data(), 4 * njobs, hipMemcpyHostToDevice, st));
-    LAUNCH("scan", 8.0 * idx_n, st, launch_scan(sdd.as<StreamDev>(), jobs.as<int32_t>(), jobs.as<int32_t>() + njobs, njobs,
-                        cnt.as<uint32_t>(), h->idx.as<uint32_t>(), totals.as<int64_t>(), st));
-    HIP_TRY(hipMemcpyAsync(tot.data(), totals.p, 8 * njobs, hipMemcpyDeviceToHost, st));
-  }
-  HIP_TRY(hipStreamSynchronize(st));
-  // sign sections
-  int64_t sign_words = 0;
-  std::vector<int64_t> pso_all;
-  for (size_t i = 0, jb = 0; i < sds.size(); ++i) {
-    Stream& S = m.streams[sd_stream[i]];
-    S.nsig.assign(S.B, 0);
-    S.pso.assign(S.B, 0);
-    S.sign_off = sign_words;
-    sds[i].sign_off = sign_words;
-    sds[i].psb = (int32_t)pso_all.size();
-    int64_t w = 0;
-    for (int j = 0; j < S.B; ++j, ++jb) {
-      S.nsig[j] = tot[jb];
-      S.pso[j] = w;
-      pso_all.push_back(w);
-      w += (tot[jb] + 63) / 64;
+    APC_TRY(h->mag.alloc(8 * (size_t)std::max<int64_t>(1, mag_w)));
+    APC_TRY(h->idx.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
+    for (int s = 0; s < (int)m.streams.size(); ++s) {
+      Stream& S = m.streams[s];
+      if (S.B == 0 || S.n == 0) continue;
+      StreamDev sd{};
+      sd.codes = (S.use_cd ? tmp[f].cdc.template as<Q>() : tmp[f].codes.template as<Q>()) + S.code_off;
+      sd.mag = h->mag.as<uint64_t>() + S.mag_off;
+      sd.idx = h->idx.as<uint32_t>() + S.idx_off;
+      sd.cnt = (uint32_t*)(intptr_t)cnt_n;      // offsets, rebased below
+      sd.stage = (uint64_t*)(intptr_t)stage_w;
+      sd.n = S.n;
+      sd.M = S.words();
+      sd.C = S.chunks();
+      sd.chunk_begin = chunks;
+      sd.B = S.B;
+      cnt_n += (int64_t)S.B * sd.C;
+      stage_w += 64 * sd.C;
+      chunks += sd.C;
+      sds.push_back(sd);
+      sd_of.push_back({f, s});
     }
-    sign_words += w;
   }
-  APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_words)));
-  APC_TRY(h->pso.alloc(8 * std::max<size_t>(1, pso_all.size())));
-  HIP_TRY(hipMemsetAsync(h->sign.p, 0, 8 * (size_t)std::max<int64_t>(1, sign_words), st));
-  if (!pso_all.empty())
-    HIP_TRY(hipMemcpyAsync(h->pso.p, pso_all.data(), 8 * pso_all.size(), hipMemcpyHostToDevice, st));
+  DevBuf cntb, stageb, sdb, jobs, totals;
+  APC_TRY(cntb.alloc(4 * (size_t)std::max<int64_t>(1, cnt_n)));
+  APC_TRY(stageb.alloc(8 * (size_t)std::max<int64_t>(1, stage_w)));
+  double eb = 0;
+  for (StreamDev& sd : sds) {
+    sd.cnt = cntb.as<uint32_t>() + (intptr_t)sd.cnt;
+    sd.stage = stageb.as<uint64_t>() + (intptr_t)sd.stage;
+    eb += (double)sizeof(Q) * sd.n + 8.0 * sd.B * sd.M + 512.0 * sd.C + 4.0 * sd.B * sd.C;
+  }
+  std::vector<int32_t> job;
+  int njobs = 0;
+  for (size_t i = 0; i < sds.size(); ++i) njobs += sds[i].B;
+  job.resize(2 * (size_t)njobs);
+  {
+    int k = 0;
+    for (size_t i = 0; i < sds.size(); ++i)
+      for (int j = 0; j < sds[i].B; ++j, ++k) {
+        job[k] = (int32_t)i;
+        job[njobs + k] = j;
+      }
+  }
+  std::vector<int64_t> tot((size_t)njobs);
   if (!sds.empty()) {
-    HIP_TRY(hipMemcpyAsync(sdd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    LAUNCH("sign_move", 8.0 * (stage_words + sign_words), st, launch_sign_move(sdd.as<StreamDev>(), (int)sds.size(), chunks, cnt.as<uint32_t>(), h->idx.as<uint32_t>(),
-                             h->pso.as<int64_t>(), stage.as<uint64_t>(), h->sign.as<uint64_t>(), st));
+    TableBuilder tb3;
+    const size_t o_sd = tb3.add(sds);
+    const size_t o_job = tb3.add(job);
+    APC_TRY(sdb.alloc(tb3.bytes.size()));
+    APC_TRY(totals.alloc(8 * (size_t)njobs));
+    APC_TRY(stage.put(tb3.bytes, sdb.p, st));
+    const StreamDev* sdd = (const StreamDev*)((const char*)sdb.p + o_sd);
+    const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
+    LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
+    LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
+    HIP_TRY(hipMemcpyAsync(tot.data(), totals.p, 8 * (size_t)njobs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
   }
-  HIP_TRY(hipStreamSynchronize(st));
-  assign_weights(h);
-  finalize_units(h);
-  h->k_res.assign(ns, 0);
+  // ---- sign sections
+  {
+    size_t jb = 0, i = 0;
+    std::vector<std::vector<int64_t>> pso_host(nf);
+    std::vector<int64_t> sign_words(nf, 0);
+    for (int f = 0; f < nf; ++f) {
+      H[f]->psb.assign(H[f]->meta.streams.size(), 0);
+      for (Stream& S : H[f]->meta.streams) {
+        S.nsig.clear();
+        S.pso.clear();
+      }
+    }
+    for (i = 0; i < sds.size(); ++i) {
+      const int f = sd_of[i].first, s = sd_of[i].second;
+      Stream& S = H[f]->meta.streams[s];
+      S.nsig.assign(S.B, 0);
+      S.pso.assign(S.B, 0);
+      S.sign_off = sign_words[f];
+      H[f]->psb[s] = (int)pso_host[f].size();
+      int64_t w = 0;
+      for (int j = 0; j < S.B; ++j, ++jb) {
+        S.nsig[j] = tot[jb];
+        S.pso[j] = w;
+        pso_host[f].push_back(w);
+        w += (tot[jb] + 63) / 64;
+      }
+      sign_words[f] += w;
+    }
+    for (int f = 0; f < nf; ++f) {
+      apc_handle* h = H[f];
+      APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_words[f])));
+      APC_TRY(h->pso.alloc(8 * std::max<size_t>(1, pso_host[f].size())));
+      HIP_TRY(hipMemsetAsync(h->sign.p, 0, 8 * (size_t)std::max<int64_t>(1, sign_words[f]), st));
+      std::vector<char> b(8 * pso_host[f].size());
+      if (!b.empty()) memcpy(b.data(), pso_host[f].data(), b.size());
+      APC_TRY(stage.put(b, h->pso.p, st));
+    }
+    double sb = 0;
+    for (i = 0; i < sds.size(); ++i) {
+      const int f = sd_of[i].first, s = sd_of[i].second;
+      const Stream& S = H[f]->meta.streams[s];
+      sds[i].sign = H[f]->sign.as<uint64_t>() + S.sign_off;
+      sds[i].pso = H[f]->pso.as<int64_t>() + H[f]->psb[s];
+      sds[i].sign_n = S.sign_words();
+      sb += 512.0 * sds[i].C + 8.0 * sds[i].sign_n;
+    }
+    if (!sds.empty()) {
+      TableBuilder tb4;
+      const size_t o_sd = tb4.add(sds);
+      DevBuf sdb2;
+      APC_TRY(sdb2.alloc(tb4.bytes.size()));
+      APC_TRY(stage.put(tb4.bytes, sdb2.p, st));
+      LAUNCH("sign_move", sb, st,
+             launch_sign_move((const StreamDev*)((const char*)sdb2.p + o_sd), (int)sds.size(), chunks, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+  }
+  for (int f = 0; f < nf; ++f) {
+    assign_weights(H[f]);
+    finalize_units(H[f]);
+    H[f]->k_res.assign(H[f]->meta.streams.size(), 0);
+  }
   return APC_OK;
 }
 
+// ---------------------------------------------------------------- retrieval
 apc_status ensure_work(apc_handle* h) {
   if (h->work_ready) return APC_OK;
   const Geo& g = h->geo;
@@ -748,55 +1062,48 @@ apc_status ensure_work(apc_handle* h) {
   const int64_t nc = (int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2];
   APC_TRY(h->xc.alloc(8 * (size_t)nc));
   if (L >= 2) {
-    const int64_t n1 = (int64_t)g.m[std::min(1, L - 1)][0] * g.m[std::min(1, L - 1)][1] * g.m[std::min(1, L - 1)][2];
+    const int64_t n1 = (int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2];
     APC_TRY(h->xb[0].alloc(8 * (size_t)n1));
     APC_TRY(h->xb[1].alloc(8 * (size_t)n1));
-    if (g.d >= 2) APC_TRY(h->pr[0].alloc(8 * (size_t)lat_count(lattice(g, 0, 0))));
-    if (g.d >= 3) APC_TRY(h->pr[1].alloc(8 * (size_t)lat_count(lattice(g, 0, 1))));
-    if (h->scheme.cd_axis >= 0) {
-      int64_t mx = 0;
-      for (int rho = 0; rho < g.d; ++rho) mx = std::max(mx, lat_count(lattice(g, 0, rho)));
-      APC_TRY(h->cdreg.alloc(qs * (size_t)std::max<int64_t>(1, mx)));
-    }
+    if (g.d >= 2) APC_TRY(h->pr[0].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 0)))));
+    if (g.d >= 3) APC_TRY(h->pr[1].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 1)))));
+    if (h->cdreg_n) APC_TRY(h->cdreg.alloc(qs * (size_t)h->cdreg_n));
   }
-  APC_TRY(h->sd.alloc(sizeof(StreamDev) * std::max<size_t>(1, h->meta.streams.size())));
+  HIP_TRY(hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming));
   h->work_ready = true;
   return APC_OK;
 }
 
+// Tables and launches of one retrieval; kres tracks the planes resident
+// after it (incremental decode).
 template <typename T, typename Q>
-apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, hipStream_t st, int64_t* fetched) {
-  APC_TRY(ensure_work(h));
+void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::vector<int>& kres,
+                    TableBuilder& tb, std::vector<Launch>& ls, int64_t* fetched) {
   Meta& m = h->meta;
   const Geo& g = h->geo;
   const int d = g.d, L = g.L;
   const bool per_level = h->scheme.kind == APC_PER_LEVEL;
-  // incremental decode of the planes not resident yet
-  std::vector<StreamDev>& sds = h->sd_host;
-  sds.clear();
+  std::vector<StreamDev> sds;
   int64_t chunks = 0, fb = 0;
   double db = 0.0;
   for (int s = 0; s < (int)m.streams.size(); ++s) {
     const Stream& S = m.streams[s];
-    if (S.B == 0 || S.n == 0 || planes[s] <= h->k_res[s]) continue;
+    if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
     StreamDev sd{};
+    sd.codes = (S.use_cd ? h->cd_codes.as<Q>() : h->codes.as<Q>()) + S.code_off;
+    sd.mag = h->mag.as<uint64_t>() + S.mag_off;
+    sd.idx = h->idx.as<uint32_t>() + S.idx_off;
+    sd.sign = h->sign.as<uint64_t>() + S.sign_off;
+    sd.pso = h->pso.as<int64_t>() + h->psb[s];
+    sd.sign_n = S.sign_words();
     sd.n = S.n;
-    sd.code_off = S.code_off;
     sd.M = S.words();
     sd.C = S.chunks();
-    sd.mag_off = S.mag_off;
-    sd.idx_off = S.idx_off;
-    sd.sign_off = S.sign_off;
-    sd.sign_n = S.sign_words();
     sd.chunk_begin = chunks;
     sd.B = S.B;
-    sd.use_cd = S.use_cd ? 1 : 0;
-    sd.k0 = h->k_res[s];
+    sd.k0 = kres[s];
     sd.k1 = planes[s];
-    sd.fresh = h->k_res[s] == 0 ? 1 : 0;
-    int psb = 0;
-    for (int s2 = 0; s2 < s; ++s2) psb += m.streams[s2].n > 0 ? m.streams[s2].B : 0;
-    sd.psb = psb;
+    sd.fresh = kres[s] == 0 ? 1 : 0;
     for (int j = sd.k0; j < sd.k1; ++j) {
       fb += S.plane_bytes(j);
       db += 8.0 * ((S.nsig[j] + 63) / 64);
@@ -804,76 +1111,136 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
     db += (double)(sd.k1 - sd.k0) * (8.0 * sd.M + 4.0 * sd.C) + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
     chunks += sd.C;
     sds.push_back(sd);
-    h->k_res[s] = planes[s];
+    kres[s] = planes[s];
   }
   if (fetched) *fetched = fb;
-  if (!sds.empty()) {
-    HIP_TRY(hipMemcpyAsync(h->sd.p, sds.data(), sizeof(StreamDev) * sds.size(), hipMemcpyHostToDevice, st));
-    LAUNCH("decode", db, st, (launch_decode<Q>(h->sd.as<StreamDev>(), (int)sds.size(), chunks, h->mag.as<uint64_t>(),
-                              h->idx.as<uint32_t>(), h->sign.as<uint64_t>(), h->pso.as<int64_t>(), h->codes.as<Q>(),
-                              h->cd_codes.as<Q>(), st)));
+  if (!sds.empty()) ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, 0, db, "decode"});
+  // inverse decomposition of every level-0 region
+  if (!h->cd.empty() && L >= 2) {
+    std::vector<CDSeg> cs;
+    double by = 0;
+    for (int rho = 0; rho < (int)h->cd.size(); ++rho) {
+      const CDInfo& ci = h->cd[rho];
+      CDSeg c{};
+      for (int a = 0; a < 3; ++a) c.c[a] = ci.c[a];
+      c.f2 = make_fastdiv((uint32_t)std::max(1, c.c[2]));
+      c.f1 = make_fastdiv((uint32_t)std::max(1, c.c[1]));
+      c.Rout = h->cdreg.as<Q>() + ci.reg_off;
+      for (int t = 0; t < 3; ++t) {
+        c.S[t] = h->cd_codes.as<Q>() + ci.s_off[t];
+        c.B[t] = m.streams[ci.s_idx[t]].B;
+        c.k[t] = planes[ci.s_idx[t]];
+      }
+      const int64_t cnt = (int64_t)c.c[0] * c.c[1] * c.c[2];
+      if (cnt == 0) continue;
+      by += 2.0 * sizeof(Q) * cnt;
+      cs.push_back(c);
+    }
+    if (!cs.empty()) {
+      const int64_t nbk = assign_blocks<CDSeg>(cs, [](const CDSeg& c) { return (int64_t)c.c[0] * c.c[1] * c.c[2]; });
+      const size_t off = tb.add(cs);
+      const int a3 = h->cd[0].a;
+      ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+      ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+    }
   }
   // coarsest level
-  const Stream& s0 = m.streams[0];
-  const Group& g0 = m.groups[s0.group];
-  double* xc = h->xc.as<double>();
-  LAUNCH("coarsest", (8.0 + sizeof(Q)) * s0.n, st, (launch_coarsest_q<Q>(h->codes.as<Q>(), s0.n, s0.B, planes[0], g0.delta, xc, st)));
-  if (L == 1) {
-    LAUNCH("cast", (8.0 + sizeof(T)) * s0.n, st, launch_cast<T>(xc, s0.n, out, st));
-    return APC_OK;
+  {
+    const Stream& s0 = m.streams[0];
+    FlatSeg c{};
+    c.src = h->codes.as<Q>();
+    c.dst = L == 1 ? (void*)out : (void*)h->xc.p;
+    c.n = s0.n;
+    c.B = s0.B;
+    c.k = planes[0];
+    c.delta = m.groups[s0.group].delta;
+    c.final_out = L == 1 ? 1 : 0;
+    std::vector<FlatSeg> cs{c};
+    const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
+    ls.push_back({K_COARSEST, tb.add(cs), 1, nbk, 0, (8.0 + sizeof(Q)) * s0.n, "coarsest"});
   }
-  // stream of each (level, region)
-  auto stream_of = [&](int l, int rho) {
-    for (int s = 0; s < (int)m.streams.size(); ++s) {
-      const Stream& S = m.streams[s];
-      if (S.kind == S_LEVEL && S.level == l) return s;
-      if (S.kind == S_REGION && S.level == l && S.rho == rho) return s;
-    }
-    return -1;
-  };
-  const double* xin = xc;
+  const double* xin = h->xc.as<double>();
   for (int l = L - 2; l >= 0; --l) {
     double* xout = l > 0 ? h->xb[l % 2].as<double>() : nullptr;
-    const int32_t* cm = g.m[l + 1].data();
-    if (l > 0)
-      LAUNCH("inject", 16.0 * cm[0] * cm[1] * cm[2], st, launch_inject<double>(xin, cm, xout, g.m[l].data(), st));
-    else
-      LAUNCH("inject", (8.0 + sizeof(T)) * cm[0] * cm[1] * cm[2], st, launch_inject<T>(xin, cm, out, g.m[0].data(), st));
+    void* dst = l > 0 ? (void*)xout : (void*)out;
+    {
+      FlatSeg c{};
+      c.src = xin;
+      c.dst = dst;
+      for (int a = 0; a < 3; ++a) c.dm[a] = g.m[l + 1][a];
+      c.n = (int64_t)c.dm[0] * c.dm[1] * c.dm[2];
+      c.f2 = make_fastdiv((uint32_t)c.dm[2]);
+      c.f1 = make_fastdiv((uint32_t)c.dm[1]);
+      c.dst_m1 = g.m[l][1];
+      c.dst_m2 = g.m[l][2];
+      c.final_out = l == 0 ? 1 : 0;
+      std::vector<FlatSeg> cs{c};
+      const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
+      ls.push_back({K_INJECT, tb.add(cs), 1, nbk, 0, (8.0 + (l ? 8 : sizeof(T))) * c.n, "inject"});
+    }
     for (int rho = 0; rho < d; ++rho) {
-      RegionArgs ra = region_args<Q>(h, l, rho, per_level, true, true);
-      const Q* q;
-      int B, k;
-      double delta;
-      if (l == 0 && h->scheme.cd_axis >= 0) {
-        CDArgs ca = h->cd[rho];
-        for (int t = 0; t < 3; ++t) {
-          const Stream& S = m.streams[ca.s_idx[t]];
-          ca.B[t] = S.B;
-          ca.k[t] = planes[ca.s_idx[t]];
-        }
-        LAUNCH("cd_inverse", 2.0 * sizeof(Q) * ca.c[0] * ca.c[1] * ca.c[2], st,
-               (launch_cd_inverse<Q>(h->cd_codes.as<Q>(), ca, h->cdreg.as<Q>(), st)));
-        q = h->cdreg.as<Q>();
-        B = 64;
-        k = 64;
-        delta = m.groups[m.streams[ca.s_idx[0]].group].delta;
+      ReconSeg r{};
+      double* pr[2] = {h->pr[0].as<double>(), h->pr[1].as<double>()};
+      r.ra = region_args(h, l, rho, per_level, pr, true, true);
+      const int64_t cnt = lat_count(r.ra.lat);
+      if (cnt == 0) continue;
+      r.xc = xin;
+      r.cm1 = g.m[l + 1][1];
+      r.cm2 = g.m[l + 1][2];
+      if (l == 0 && !h->cd.empty()) {
+        const CDInfo& ci = h->cd[rho];
+        r.q = h->cdreg.as<Q>() + ci.reg_off;
+        r.B = 64;
+        r.k = 64;
+        r.delta = m.groups[m.streams[ci.s_idx[0]].group].delta;
       } else {
-        const int s = stream_of(l, rho);
+        const int s = stream_of(m, l, rho);
         const Stream& S = m.streams[s];
-        q = h->codes.as<Q>() + h->region_off[l * 3 + rho];
-        B = S.B;
-        k = planes[s];
-        delta = m.groups[S.group].delta;
+        r.q = h->codes.as<Q>() + h->region_off[l * 3 + rho];
+        r.B = S.B;
+        r.k = planes[s];
+        r.delta = m.groups[S.group].delta;
       }
-      if (l > 0)
-        LAUNCH("recon", (double)lat_count(ra.lat) * (sizeof(Q) + 8 + (ra.pr_out ? 8 : 0)), st,
-               (launch_recon<double, Q>(xin, cm, ra, q, B, k, delta, xout, st)));
-      else
-        LAUNCH("recon", (double)lat_count(ra.lat) * (sizeof(Q) + sizeof(T) + (ra.pr_out ? 8 : 0)), st,
-               (launch_recon<T, Q>(xin, cm, ra, q, B, k, delta, out, st)));
+      r.out = dst;
+      r.final_out = l == 0 ? 1 : 0;
+      std::vector<ReconSeg> cs{r};
+      const int64_t nbk = assign_blocks<ReconSeg>(cs, [](const ReconSeg& s) { return lat_count(s.ra.lat); });
+      const double by = (double)cnt * (sizeof(Q) + (l ? 8 : sizeof(T)) + (r.ra.pr_out ? 8 : 0));
+      ls.push_back({K_RECON, tb.add(cs), 1, nbk, 0, by, "recon"});
     }
     xin = xout;
   }
+}
+
+apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStream_t st) {
+  if (bytes.empty()) return APC_OK;
+  if (h->pinned_bytes < bytes.size()) {
+    if (h->pinned) {
+      HIP_TRY(hipEventSynchronize(h->upload_done));
+      (void)hipHostFree(h->pinned);
+    }
+    h->pinned_bytes = std::max<size_t>(bytes.size() * 2, 1 << 16);
+    HIP_TRY(hipHostMalloc(&h->pinned, h->pinned_bytes));
+  } else {
+    HIP_TRY(hipEventSynchronize(h->upload_done));  // the previous copy has left the staging
+  }
+  memcpy(h->pinned, bytes.data(), bytes.size());
+  APC_TRY(h->tables.alloc(bytes.size()));
+  HIP_TRY(hipMemcpyAsync(h->tables.p, h->pinned, bytes.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(h->upload_done, st));
+  return APC_OK;
+}
+
+template <typename T, typename Q>
+apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, hipStream_t st, int64_t* fetched) {
+  APC_TRY(ensure_work(h));
+  TableBuilder tb;
+  std::vector<Launch> ls;
+  std::vector<int> kres = h->k_res;
+  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched);
+  APC_TRY(upload_tables(h, tb.bytes, st));
+  APC_TRY((issue<T, Q>(ls, (const char*)h->tables.p, st)));
+  h->k_res = kres;
   return APC_OK;
 }
 
@@ -901,7 +1268,79 @@ apc_status target_tau(const apc_handle* h, const apc_target* t, double& tau, int
   }
 }
 
+apc_status plan_for(apc_handle* h, const apc_target* target, std::vector<int>& planes, apc_retrieve_info* info) {
+  double tau;
+  int mode;
+  APC_TRY(target_tau(h, target, tau, mode));
+  double b;
+  int nsteps;
+  if (make_plan(h->meta, tau, mode, planes, b, nsteps) != 0)
+    return fail(APC_E_BELOW_FLOOR, "tolerance %.17g is below the floor of this representation", tau);
+  if (info) {
+    info->bytes_total = plan_bytes(h->meta, planes);
+    info->bytes_fetched = 0;
+    info->bound = b;
+    info->tau = tau;
+    info->bitrate = 8.0 * (double)info->bytes_total / (double)h->meta.n;
+    info->n_streams = (int32_t)planes.size();
+    info->nsteps = nsteps;
+  }
+  return APC_OK;
+}
+
+apc_status do_retrieve(apc_handle* h, const std::vector<int>& planes, void* out_dev, void* hip_stream,
+                       int64_t* fetched) {
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (h->dtype == APC_F32) return retrieve_impl<float, int32_t>(h, planes, (float*)out_dev, st, fetched);
+  return retrieve_impl<double, int64_t>(h, planes, (double*)out_dev, st, fetched);
+}
+
+apc_status make_handles(int nf, const int32_t dtype, const int64_t* dims, const int32_t* ndims,
+                        const apc_scheme* schemes, std::vector<std::unique_ptr<apc_handle>>& own) {
+  own.clear();
+  int64_t doff = 0;
+  for (int f = 0; f < nf; ++f) {
+    std::unique_ptr<apc_handle> h(new apc_handle());
+    h->dtype = dtype;
+    APC_TRY(setup_geometry(h.get(), dims + doff, ndims[f], &schemes[f]));
+    doff += ndims[f];
+    own.push_back(std::move(h));
+  }
+  return APC_OK;
+}
+
+apc_status refactor_many(const void* const* fields, int32_t dtype, const int64_t* dims, const int32_t* ndims,
+                         const apc_scheme* schemes, int32_t nf, hipStream_t st,
+                         std::vector<std::unique_ptr<apc_handle>>& own) {
+  if (dtype != APC_F32 && dtype != APC_F64) return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
+  APC_TRY(make_handles(nf, dtype, dims, ndims, schemes, own));
+  std::vector<apc_handle*> hs;
+  for (auto& h : own) hs.push_back(h.get());
+  if (dtype == APC_F32) {
+    std::vector<const float*> xs;
+    for (int f = 0; f < nf; ++f) xs.push_back((const float*)fields[f]);
+    return refactor_batch<float, int32_t>(hs, xs, st);
+  }
+  std::vector<const double*> xs;
+  for (int f = 0; f < nf; ++f) xs.push_back((const double*)fields[f]);
+  return refactor_batch<double, int64_t>(hs, xs, st);
+}
+
 }  // namespace
+
+// Retrieval ladder captured as one HIP graph (a sequence of targets, each
+// written to its own output).
+struct apc_ladder {
+  apc_handle* h = nullptr;
+  DevBuf tables;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> k_after;
+  ~apc_ladder() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
 
 extern "C" {
 
@@ -926,58 +1365,42 @@ const char* apc_last_error(void) { return g_last_error.c_str(); }
 apc_status apc_refactor(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
                         const apc_scheme* scheme, void* hip_stream, apc_handle** out) {
   if (!field_dev || !dims || !scheme || !out) return fail(APC_E_INVALID, "null argument");
-  if (dtype != APC_F32 && dtype != APC_F64) return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
-  std::unique_ptr<apc_handle> h(new apc_handle());
-  h->dtype = dtype;
-  APC_TRY(setup_geometry(h.get(), dims, ndim, scheme));
-  hipStream_t st = (hipStream_t)hip_stream;
-  apc_status s = dtype == APC_F32 ? refactor_impl<float, int32_t>(h.get(), (const float*)field_dev, st)
-                                  : refactor_impl<double, int64_t>(h.get(), (const double*)field_dev, st);
-  if (s != APC_OK) return s;
-  *out = h.release();
+  std::vector<std::unique_ptr<apc_handle>> own;
+  const void* f[1] = {field_dev};
+  APC_TRY(refactor_many(f, dtype, dims, &ndim, scheme, 1, (hipStream_t)hip_stream, own));
+  *out = own[0].release();
+  return APC_OK;
+}
+
+apc_status apc_refactor_batch(const void* const* fields_dev, int32_t dtype, const int64_t* dims,
+                              const int32_t* ndims, const apc_scheme* schemes, int32_t nfields, void* hip_stream,
+                              apc_handle** out) {
+  if (!fields_dev || !dims || !ndims || !schemes || !out || nfields < 1) return fail(APC_E_INVALID, "bad argument");
+  for (int f = 0; f < nfields; ++f)
+    if (!fields_dev[f]) return fail(APC_E_INVALID, "null field %d", f);
+  std::vector<std::unique_ptr<apc_handle>> own;
+  APC_TRY(refactor_many(fields_dev, dtype, dims, ndims, schemes, nfields, (hipStream_t)hip_stream, own));
+  for (int f = 0; f < nfields; ++f) out[f] = own[f].release();
   return APC_OK;
 }
 
 apc_status apc_plan(apc_handle* h, const apc_target* target, int32_t* planes_out, apc_retrieve_info* info) {
   if (!h || !target) return fail(APC_E_INVALID, "null argument");
-  double tau;
-  int mode;
-  APC_TRY(target_tau(h, target, tau, mode));
   std::vector<int> planes;
-  double b;
-  int nsteps;
-  if (make_plan(h->meta, tau, mode, planes, b, nsteps) != 0)
-    return fail(APC_E_BELOW_FLOOR, "tolerance %.17g is below the floor of this representation", tau);
+  APC_TRY(plan_for(h, target, planes, info));
   if (planes_out)
     for (size_t s = 0; s < planes.size(); ++s) planes_out[s] = planes[s];
-  if (info) {
-    info->bytes_total = plan_bytes(h->meta, planes);
-    info->bytes_fetched = 0;
-    info->bound = b;
-    info->tau = tau;
-    info->bitrate = 8.0 * (double)info->bytes_total / (double)h->meta.n;
-    info->n_streams = (int32_t)planes.size();
-    info->nsteps = nsteps;
-  }
   return APC_OK;
-}
-
-static apc_status do_retrieve(apc_handle* h, const std::vector<int>& planes, void* out_dev, void* hip_stream,
-                              int64_t* fetched) {
-  hipStream_t st = (hipStream_t)hip_stream;
-  if (h->dtype == APC_F32) return retrieve_impl<float, int32_t>(h, planes, (float*)out_dev, st, fetched);
-  return retrieve_impl<double, int64_t>(h, planes, (double*)out_dev, st, fetched);
 }
 
 apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev, apc_retrieve_info* info,
                         void* hip_stream) {
   if (!h || !target || !out_dev) return fail(APC_E_INVALID, "null argument");
-  std::vector<int32_t> planes(h->meta.streams.size());
+  std::vector<int> planes;
   apc_retrieve_info inf{};
-  APC_TRY(apc_plan(h, target, planes.data(), &inf));
-  std::vector<int> p(planes.begin(), planes.end());
+  APC_TRY(plan_for(h, target, planes, &inf));
   int64_t fetched = 0;
-  APC_TRY(do_retrieve(h, p, out_dev, hip_stream, &fetched));
+  APC_TRY(do_retrieve(h, planes, out_dev, hip_stream, &fetched));
   inf.bytes_fetched = fetched;
   if (info) *info = inf;
   return APC_OK;
@@ -988,6 +1411,69 @@ apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_d
   std::vector<int> p(h->meta.streams.size());
   for (size_t s = 0; s < p.size(); ++s) p[s] = std::max(0, std::min<int>(planes[s], h->meta.streams[s].B));
   return do_retrieve(h, p, out_dev, hip_stream, nullptr);
+}
+
+apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n, void* const* outs_dev,
+                             void* hip_stream, apc_ladder** out) {
+  if (!h || !targets || !outs_dev || !out || n < 1) return fail(APC_E_INVALID, "bad argument");
+  APC_TRY(ensure_work(h));
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::unique_ptr<apc_ladder> ld(new apc_ladder());
+  ld->h = h;
+  TableBuilder tb;
+  std::vector<Launch> ls;
+  std::vector<int> kres(h->meta.streams.size(), 0);  // a replay starts from nothing resident
+  for (int i = 0; i < n; ++i) {
+    std::vector<int> planes;
+    APC_TRY(plan_for(h, &targets[i], planes, nullptr));
+    if (h->dtype == APC_F32)
+      build_retrieve<float, int32_t>(h, planes, (float*)outs_dev[i], kres, tb, ls, nullptr);
+    else
+      build_retrieve<double, int64_t>(h, planes, (double*)outs_dev[i], kres, tb, ls, nullptr);
+  }
+  ld->k_after = kres;
+  APC_TRY(ld->tables.alloc(tb.bytes.size()));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(ld->tables.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice));
+  // Capture on a private stream (the legacy null stream cannot be captured);
+  // the graph is later launched on the caller's stream.
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e0 = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e0 != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(APC_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e0));
+  }
+  const bool prof = g_prof.on;
+  g_prof.on = false;  // no timing events inside a capture
+  apc_status s = h->dtype == APC_F32 ? issue<float, int32_t>(ls, (const char*)ld->tables.p, cs)
+                                     : issue<double, int64_t>(ls, (const char*)ld->tables.p, cs);
+  g_prof.on = prof;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (s != APC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(APC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  ld->graph = graph;
+  HIP_TRY(hipGraphInstantiate(&ld->exec, graph, nullptr, nullptr, 0));
+  *out = ld.release();
+  return APC_OK;
+}
+
+apc_status apc_ladder_launch(apc_ladder* ld, void* hip_stream) {
+  if (!ld) return fail(APC_E_INVALID, "null ladder");
+  HIP_TRY(hipGraphLaunch(ld->exec, (hipStream_t)hip_stream));
+  ld->h->k_res = ld->k_after;
+  return APC_OK;
+}
+
+void apc_ladder_free(apc_ladder* ld) {
+  if (!ld) return;
+  (void)hipDeviceSynchronize();
+  delete ld;
 }
 
 void apc_free(apc_handle* h) {
@@ -1058,48 +1544,232 @@ apc_status apc_profile_enable(int32_t on) {
   return APC_OK;
 }
 
+static std::string g_prof_last = "{}";
+
 apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len) {
-  // Per kernel name: launches, total milliseconds, total bytes moved.
-  std::vector<std::string> names;
-  std::vector<double> ms, bytes;
-  std::vector<int64_t> count;
-  for (ProfRec& r : g_prof.recs) {
-    (void)hipEventSynchronize(r.b);
-    float t = 0.f;
-    (void)hipEventElapsedTime(&t, r.a, r.b);
-    size_t k = 0;
-    while (k < names.size() && names[k] != r.name) ++k;
-    if (k == names.size()) {
-      names.push_back(r.name);
-      ms.push_back(0);
-      bytes.push_back(0);
-      count.push_back(0);
+  // Per kernel name: launches, total milliseconds, total bytes moved.  The
+  // records are consumed once; the text stays available for a second call
+  // (callers ask for the length first).
+  if (!g_prof.recs.empty()) {
+    std::vector<std::string> names;
+    std::vector<double> ms, bytes;
+    std::vector<int64_t> count;
+    for (ProfRec& r : g_prof.recs) {
+      (void)hipEventSynchronize(r.b);
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, r.a, r.b);
+      size_t k = 0;
+      while (k < names.size() && names[k] != r.name) ++k;
+      if (k == names.size()) {
+        names.push_back(r.name);
+        ms.push_back(0);
+        bytes.push_back(0);
+        count.push_back(0);
+      }
+      ms[k] += t;
+      bytes[k] += r.bytes;
+      count[k] += 1;
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
     }
-    ms[k] += t;
-    bytes[k] += r.bytes;
-    count[k] += 1;
-    g_prof.pool.push_back(r.a);
-    g_prof.pool.push_back(r.b);
+    g_prof.recs.clear();
+    std::string js = "{";
+    char tmp[256];
+    for (size_t k = 0; k < names.size(); ++k) {
+      snprintf(tmp, sizeof(tmp), "%s\"%s\":{\"count\":%lld,\"ms\":%.6f,\"bytes\":%.0f}", k ? "," : "",
+               names[k].c_str(), (long long)count[k], ms[k], bytes[k]);
+      js += tmp;
+    }
+    js += "}";
+    g_prof_last = js;
   }
-  g_prof.recs.clear();
-  std::string js = "{";
-  char tmp[256];
-  for (size_t k = 0; k < names.size(); ++k) {
-    snprintf(tmp, sizeof(tmp), "%s\"%s\":{\"count\":%lld,\"ms\":%.6f,\"bytes\":%.0f}", k ? "," : "", names[k].c_str(),
-             (long long)count[k], ms[k], bytes[k]);
-    js += tmp;
-  }
-  js += "}";
-  if (len) *len = (int64_t)js.size();
+  if (len) *len = (int64_t)g_prof_last.size();
   if (buf) {
-    if (cap < (int64_t)js.size() + 1) return fail(APC_E_INVALID, "buffer too small");
-    memcpy(buf, js.c_str(), js.size() + 1);
+    if (cap < (int64_t)g_prof_last.size() + 1) return fail(APC_E_INVALID, "buffer too small");
+    memcpy(buf, g_prof_last.c_str(), g_prof_last.size() + 1);
   }
   return APC_OK;
 }
 
-apc_status apc_select_pipeline(const void*, int32_t, const int64_t*, int32_t, int32_t, apc_scheme*, void*) {
-  return fail(APC_E_INVALID, "select_pipeline is not available yet");
+}  // extern "C"
+
+// ------------------------------------------------------ pipeline selection
+namespace {
+
+// Regular sample blocks of the field (about 1%): side b at every e-th block
+// position per axis; at least one block per axis.
+void sample_blocks(const Geo& g, std::vector<std::array<int64_t, 6>>& blocks) {
+  const int d = g.d;
+  const int64_t side = d == 3 ? 32 : (d == 2 ? 128 : 4096);
+  const int64_t every = d == 3 ? 5 : (d == 2 ? 10 : 100);
+  std::vector<int64_t> pos[3];
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = g.N[a];
+    if (a < 3 - d) {
+      pos[a].push_back(-1);  // embedded axis: whole (length 1)
+      continue;
+    }
+    const int64_t nb = std::max<int64_t>(1, n / side);
+    for (int64_t p = 0; p < nb; p += every) pos[a].push_back(p);
+  }
+  for (int64_t p0 : pos[0])
+    for (int64_t p1 : pos[1])
+      for (int64_t p2 : pos[2]) {
+        std::array<int64_t, 6> b{};
+        const int64_t ps[3] = {p0, p1, p2};
+        for (int a = 0; a < 3; ++a) {
+          if (ps[a] < 0) {
+            b[a] = 0;
+            b[3 + a] = 1;
+          } else {
+            b[a] = ps[a] * side;
+            b[3 + a] = std::min(g.N[a], (ps[a] + 1) * side) - b[a];
+          }
+        }
+        blocks.push_back(b);
+      }
 }
 
-}  // extern "C"
+const double kTuneTol[9] = {1e-3, 5e-4, 1e-4, 5e-5, 1e-5, 5e-6, 1e-6, 5e-7, 1e-7};
+
+template <typename T>
+apc_status select_impl(const T* field, int32_t dtype, const Geo& g, int mode, apc_scheme* out, hipStream_t st) {
+  std::vector<std::array<int64_t, 6>> blocks;
+  sample_blocks(g, blocks);
+  const int nb = (int)blocks.size();
+  int64_t tot = 0;
+  std::vector<int64_t> boff(nb);
+  for (int b = 0; b < nb; ++b) {
+    boff[b] = tot;
+    tot += blocks[b][3] * blocks[b][4] * blocks[b][5];
+  }
+  DevBuf samp, tab, accb;
+  APC_TRY(samp.alloc(sizeof(T) * (size_t)tot));
+  APC_TRY(accb.alloc(32));
+  std::vector<FlatSeg> gs, rs;
+  for (int b = 0; b < nb; ++b) {
+    FlatSeg q{};
+    q.src = field + (blocks[b][0] * g.N[1] + blocks[b][1]) * g.N[2] + blocks[b][2];
+    q.dst = samp.as<T>() + boff[b];
+    for (int a = 0; a < 3; ++a) q.dm[a] = (int32_t)blocks[b][3 + a];
+    q.n = (int64_t)q.dm[0] * q.dm[1] * q.dm[2];
+    q.s[0] = g.N[1] * g.N[2];
+    q.s[1] = g.N[2];
+    q.s[2] = 1;
+    q.f2 = make_fastdiv((uint32_t)q.dm[2]);
+    q.f1 = make_fastdiv((uint32_t)q.dm[1]);
+    gs.push_back(q);
+  }
+  FlatSeg r{};
+  r.src = field;
+  r.n = g.n();
+  r.acc = accb.as<unsigned long long>();
+  rs.push_back(r);
+  TableBuilder tb;
+  const int64_t b1 = assign_blocks<FlatSeg>(gs, [](const FlatSeg& s) { return s.n; });
+  const int64_t b2 = assign_blocks<FlatSeg>(rs, [](const FlatSeg& s) { return s.n; });
+  std::vector<Launch> ls{{K_GATHER, tb.add(gs), (int)gs.size(), b1, 0, 2.0 * sizeof(T) * tot, "subsample"},
+                         {K_RANGE, tb.add(rs), 1, b2, 0, (double)sizeof(T) * g.n(), "range"}};
+  unsigned long long init[4] = {~0ull, 0ull, 0ull, 0ull};
+  HIP_TRY(hipMemcpyAsync(accb.p, init, 32, hipMemcpyHostToDevice, st));
+  APC_TRY(tab.alloc(tb.bytes.size()));
+  HIP_TRY(hipMemcpyAsync(tab.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, st));
+  typedef typename std::conditional<sizeof(T) == 4, int32_t, int64_t>::type Q;
+  APC_TRY((issue<T, Q>(ls, (const char*)tab.p, st)));
+  unsigned long long hv[4];
+  HIP_TRY(hipMemcpyAsync(hv, accb.p, 32, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hv[3]) return fail(APC_E_NONFINITE, "field holds NaN or Inf");
+  const double rng = unordered(hv[1]) - unordered(hv[0]);
+
+  std::vector<const void*> fptr(nb);
+  std::vector<int64_t> dims;
+  std::vector<int32_t> nds(nb, g.d);
+  for (int b = 0; b < nb; ++b) {
+    fptr[b] = samp.as<T>() + boff[b];
+    for (int a = 3 - g.d; a < 3; ++a) dims.push_back(blocks[b][3 + a]);
+  }
+  auto vote = [&](const std::vector<apc_scheme>& cands, int& winner) -> apc_status {
+    std::vector<std::array<int64_t, 9>> sizes(cands.size());
+    for (size_t c = 0; c < cands.size(); ++c) {
+      std::vector<apc_scheme> sc(nb, cands[c]);
+      std::vector<std::unique_ptr<apc_handle>> own;
+      APC_TRY(refactor_many(fptr.data(), dtype, dims.data(), nds.data(), sc.data(), nb, st, own));
+      for (int t = 0; t < 9; ++t) {
+        int64_t total = 0;
+        for (auto& h : own) {
+          std::vector<int> planes;
+          double b;
+          int ns;
+          if (make_plan(h->meta, kTuneTol[t] * rng, mode, planes, b, ns) != 0) {
+            planes.assign(h->meta.streams.size(), 0);
+            for (size_t s = 0; s < planes.size(); ++s) planes[s] = h->meta.streams[s].B;
+          }
+          total += plan_bytes(h->meta, planes);
+        }
+        sizes[c][t] = total;
+      }
+    }
+    std::vector<int> votes(cands.size(), 0);
+    for (int t = 0; t < 9; ++t) {
+      size_t best = 0;
+      for (size_t c = 1; c < cands.size(); ++c)
+        if (sizes[c][t] < sizes[best][t]) best = c;
+      ++votes[best];
+    }
+    winner = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+      if (votes[c] > votes[winner]) winner = (int)c;
+    return APC_OK;
+  };
+  std::vector<apc_scheme> cands;
+  apc_scheme base{};
+  base.degree = 3;
+  base.cd_axis = -1;
+  if (mode == 0) {
+    apc_scheme s = base;
+    s.kind = APC_PER_LEVEL;
+    for (int j = 0; j < g.d; ++j) s.order[j] = g.d - 1 - j;
+    cands.push_back(s);
+  }
+  int perm[3] = {0, 1, 2};
+  do {
+    apc_scheme s = base;
+    s.kind = APC_PER_REGION;
+    for (int j = 0; j < g.d; ++j) s.order[j] = perm[j];
+    cands.push_back(s);
+  } while (std::next_permutation(perm, perm + g.d));
+  int w = 0;
+  APC_TRY(vote(cands, w));
+  apc_scheme best = cands[w];
+  if (g.d >= 2) {
+    std::vector<apc_scheme> cc{best};
+    for (int a = 0; a < g.d; ++a) {
+      apc_scheme s = best;
+      s.cd_axis = a;
+      cc.push_back(s);
+    }
+    APC_TRY(vote(cc, w));
+    best = cc[w];
+  }
+  *out = best;
+  return APC_OK;
+}
+
+}  // namespace
+
+extern "C" apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
+                                          int32_t mode, apc_scheme* out, void* hip_stream) {
+  if (!field_dev || !dims || !out) return fail(APC_E_INVALID, "null argument");
+  if (mode != APC_MODE_EB && mode != APC_MODE_PSNR) return fail(APC_E_INVALID, "mode");
+  apc_handle probe;
+  apc_scheme def{};
+  def.kind = APC_PER_LEVEL;
+  def.degree = 3;
+  def.cd_axis = -1;
+  APC_TRY(setup_geometry(&probe, dims, ndim, &def));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (dtype == APC_F32) return select_impl<float>((const float*)field_dev, dtype, probe.geo, mode, out, st);
+  if (dtype == APC_F64) return select_impl<double>((const double*)field_dev, dtype, probe.geo, mode, out, st);
+  return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
+}

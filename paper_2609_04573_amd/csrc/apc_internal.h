@@ -1,5 +1,7 @@
 // Internal declarations shared by the host orchestration and the gfx950
 // kernels.  Fields are handled in a 3D embedding (leading axes of length 1).
+// Every pass is one launch over a table of segments (one per field, level
+// and region), so many fields of uneven shapes share each launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,9 +10,17 @@
 namespace apc {
 
 constexpr int kChunk = 4096;        // codes per chunk (sign index granularity)
-constexpr int kWordsPerChunk = 64;  // 64-bit magnitude words per chunk
+constexpr int kBlockElems = 4096;   // lattice elements per work block (16 per thread)
 
 enum AxisKind : int32_t { AX_ALL = 0, AX_ODD = 1, AX_EVEN = 2 };
+
+// Division by a run-time constant: q = high64(M * n) with M = floor((2^64-1)/d)+1,
+// exact for every 32-bit n (d = 1 is special-cased).
+struct FastDiv {
+  uint64_t M;
+  uint32_t d;
+  uint32_t one;
+};
 
 // One region of one level, as a lattice on that level's compact grid:
 // node coordinate i = t (all), 2t+1 (odd) or 2t (even) on each axis.
@@ -19,6 +29,7 @@ struct Lattice {
   int32_t c[3];     // lattice dims
   int32_t kind[3];  // AxisKind per axis
   int32_t ax;       // interpolation axis of the region (the odd one)
+  FastDiv f2, f1;   // division by c[2] and by c[1]
 };
 
 // Where the interpolation of one region reads its neighbours.
@@ -33,74 +44,114 @@ struct RegionArgs {
   double* pr_out;         // this region's buffer to fill (null if not needed)
 };
 
-// Device-side description of one bitplane stream for the codec kernels.
-struct StreamDev {
-  int64_t n;          // codes
-  int64_t code_off;   // offset of the stream's codes in its code buffer
-  int64_t M;          // magnitude words per plane
-  int64_t C;          // chunks
-  int64_t mag_off;    // words, in the magnitude arena
-  int64_t idx_off;    // uint32 entries, in the index arena
-  int64_t cnt_off;    // uint32 entries, in the per-chunk count scratch (B*C)
-  int64_t stage_off;  // words, in the sign staging scratch (64 per chunk)
-  int64_t sign_off;   // words, in the sign arena
-  int64_t sign_n;     // sign words of the stream (decode bound)
-  int64_t chunk_begin;// first global chunk id of this stream (combined launches)
-  int32_t B;          // planes
-  int32_t use_cd;     // codes live in the decomposition code buffer
-  int32_t k0, k1;     // decode: planes [k0, k1) to add
-  int32_t fresh;      // decode: resident codes are all zero (skip reading them)
-  int32_t psb;        // first entry of this stream's per-plane sign offsets (pso array)
+// Coefficient pass over one (field, level, region).
+struct CoefSeg {
+  RegionArgs ra;
+  const void* G;              // the level's compact grid of original values (T)
+  void* codes;                // Q*, pass 2 output (lattice order)
+  unsigned long long* gmax;   // pass 1: max |c| of the group (double bits)
+  int64_t blk_begin;          // first global work block of this segment
+  int32_t k_shift;            // pass 2: P - E of the group
+  int32_t pad;
+};
+
+// Reconstruction of one (field, level, region).
+struct ReconSeg {
+  RegionArgs ra;
+  const double* xc;     // reconstructed coarser level (float64 compact grid)
+  int32_t cm1, cm2;     // its dims 1 and 2
+  const void* q;        // codes of the region (Q*, lattice order)
+  void* out;            // float64 grid of this level, or the output field (T) at level 0
+  double delta;
+  int64_t blk_begin;
+  int32_t B, k;         // truncation of the codes to k of B planes
+  int32_t final_out;    // 1: out is the T output field
+  int32_t pad;
+};
+
+// Flat segments: range pass, compact grids, coarsest level, injection.
+struct FlatSeg {
+  const void* src;
+  void* dst;
+  int64_t n;            // elements
+  int64_t blk_begin;
+  int64_t s[3];         // source strides (elements) per destination axis
+  int32_t dm[3];        // destination-space dims (iteration space)
+  FastDiv f2, f1;       // division by dm[2], dm[1]
+  int32_t dst_m1, dst_m2;   // inject: fine grid dims 1, 2 (destination index 2i)
+  int32_t final_out;        // inject / coarsest: destination is the T output field
+  int32_t B, k;             // coarsest: truncation
+  int32_t k_shift;          // coarse quantization: P - E
+  double delta;             // coarsest: step
+  unsigned long long* acc;  // range: 4 accumulators; coarse pass 1: group max
 };
 
 // Coefficient-decomposition view of one level-0 region lattice.
-struct CDArgs {
-  int32_t c[3];       // lattice dims
-  int32_t a, u, v;    // stacking axis and the slower / faster slice axes (3D)
-  int64_t s_off[3];   // stream offsets of S1, S2, S3 in the decomposition code buffer
-  int32_t s_idx[3];   // stream indices (for maxima)
-  int32_t B[3], k[3]; // decode masks for S1..S3 (retrieve)
+struct CDSeg {
+  int32_t c[3];        // lattice dims
+  int32_t pad;
+  FastDiv f2, f1;
+  const void* R;       // region codes (forward input)
+  void* Rout;          // region codes (inverse output)
+  void* S[3];          // S1, S2, S3 codes (stream order)
+  unsigned long long* smax[3];
+  int64_t blk_begin;
+  int32_t B[3], k[3];  // decode masks (inverse)
 };
+
+// Device-side description of one bitplane stream for the codec kernels.
+struct StreamDev {
+  void* codes;          // Q*, stream order
+  uint64_t* mag;        // magnitude section (B*M words)
+  uint32_t* idx;        // index section (B*C entries)
+  uint32_t* cnt;        // per-chunk counts scratch (B*C, refactor)
+  uint64_t* stage;      // sign staging scratch (64 words per chunk, refactor)
+  uint64_t* sign;       // sign section
+  const int64_t* pso;   // per plane: sign words before it
+  int64_t n, M, C;
+  int64_t chunk_begin;  // first global chunk id of this stream in the launch
+  int64_t sign_n;       // sign words of the stream
+  int32_t B;
+  int32_t k0, k1;       // decode: planes [k0, k1) to add
+  int32_t fresh;        // decode: resident codes are all zero (skip reading them)
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.one = d <= 1 ? 1u : 0u;
+  f.M = d <= 1 ? 0ull : (~0ull / d + 1ull);
+  return f;
+}
 
 }  // namespace apc
 
-// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+// Kernel launchers (kernels.hip).  Segment tables live in device memory;
+// nblk is the total number of 4096-element work blocks of the table.
 namespace apc {
 template <typename T>
-hipError_t launch_range(const T* x, int64_t n, unsigned long long* acc4, hipStream_t s);
+hipError_t launch_range(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T>
-hipError_t launch_subsample(const T* src, const int32_t* msrc, T* dst, const int32_t* mdst, hipStream_t s);
+hipError_t launch_gather(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T, typename Q>
-hipError_t launch_coef(const T* G, const RegionArgs& ra, int mode, unsigned long long* gmax, int64_t k_shift,
-                       Q* codes, hipStream_t s);
+hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename T, typename Q>
-hipError_t launch_coarse(const T* G, int64_t n, int mode, unsigned long long* gmax, int64_t k_shift, Q* codes,
-                         hipStream_t s);
+hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename Q>
-hipError_t launch_cd_forward(const Q* region_codes, const CDArgs& ca, Q* cd_codes, unsigned long long* smax,
-                             hipStream_t s);
+hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, hipStream_t s);
 template <typename Q>
-hipError_t launch_cd_inverse(const Q* cd_codes, const CDArgs& ca, Q* region_out, hipStream_t s);
+hipError_t launch_cd_inverse(const CDSeg* segs, int nseg, int64_t nblk, int a, int phase, hipStream_t s);
 template <typename Q>
-hipError_t launch_encode(const Q* codes, const Q* cd_codes, const StreamDev* sd_dev, int nstreams,
-                         int64_t total_chunks, const int64_t* chunk_begin_host, int B_max, uint64_t* mag,
-                         uint32_t* cnt, uint64_t* stage, hipStream_t s);
-hipError_t launch_scan(const StreamDev* sd_dev, const int32_t* job_stream, const int32_t* job_plane, int njobs,
-                       const uint32_t* cnt, uint32_t* idx, int64_t* totals, hipStream_t s);
-hipError_t launch_sign_move(const StreamDev* sd_dev, int nstreams, int64_t total_chunks, const uint32_t* cnt,
-                            const uint32_t* idx, const int64_t* plane_sign_off, const uint64_t* stage,
-                            uint64_t* sign, hipStream_t s);
+hipError_t launch_encode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
+hipError_t launch_scan(const StreamDev* sd, const int32_t* job_s, const int32_t* job_j, int njobs, int64_t* totals,
+                       hipStream_t s);
+hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
-hipError_t launch_decode(const StreamDev* sd_dev, int nstreams, int64_t total_chunks, const uint64_t* mag,
-                         const uint32_t* idx, const uint64_t* sign, const int64_t* plane_sign_off, Q* codes,
-                         Q* cd_codes, hipStream_t s);
-template <typename Q>
-hipError_t launch_coarsest_q(const Q* q, int64_t n, int32_t B, int32_t k, double delta, double* xc, hipStream_t s);
-template <typename OutT, typename Q>
-hipError_t launch_recon(const double* xc, const int32_t* cm, const RegionArgs& ra, const Q* q, int32_t B, int32_t k,
-                        double delta, OutT* out, hipStream_t s);
-template <typename OutT>
-hipError_t launch_inject(const double* xc, const int32_t* cm, OutT* out, const int32_t* m, hipStream_t s);
-template <typename OutT>
-hipError_t launch_cast(const double* xc, int64_t n, OutT* out, hipStream_t s);
+hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
+template <typename T, typename Q>
+hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
+template <typename T>
+hipError_t launch_inject(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
+template <typename T, typename Q>
+hipError_t launch_recon(const ReconSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 }  // namespace apc

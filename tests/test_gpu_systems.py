@@ -1,0 +1,119 @@
+"""GPU tests of the systems layer: batched refactoring of uneven fields,
+hipGraph-captured retrieval ladders, and target-driven pipeline selection
+(Section VI-A) against the CPU oracle's vote."""
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _apc():
+    import paper_2609_04573_amd as apc
+    return apc
+
+
+def _fields():
+    rng = np.random.default_rng(9)
+    return [
+        (fieldgen.power_law_field((17, 30, 45), seed=21), ("level", 3, None, 1)),
+        (fieldgen.config1_field(), ("region", 3, (0, 2, 1), 0)),
+        (fieldgen.power_law_field((37, 129), seed=22), ("level", 3, None, 0)),
+        (np.cumsum(rng.standard_normal(1000)).astype(np.float32), ("region", 1, (0,), None)),
+        (fieldgen.power_law_field((9, 9, 9), seed=23), ("level", 1, None, None)),
+        (fieldgen.power_law_field((40, 33, 70), seed=24), ("region", 3, (2, 1, 0), 2)),
+    ]
+
+
+def test_batch_refactor_equals_single_and_oracle():
+    apc = _apc()
+    fs = _fields()
+    xs = [torch.from_numpy(x).cuda() for x, _ in fs]
+    schemes = [apc.Scheme(kind=k, degree=d, order=o, cd_axis=c) for _, (k, d, o, c) in fs]
+    hb = apc.refactor_batch(xs, schemes)
+    for i, ((x, (k, d, o, c)), h) in enumerate(zip(fs, hb)):
+        hs = apc.refactor(xs[i], schemes[i])
+        assert h.metadata() == hs.metadata(), i
+        for s in range(h.num_streams):
+            assert h.stream_blob(s) == hs.stream_blob(s), (i, s)
+        ref = oracle.refactor(x, oracle.Scheme(kind=k, degree=d, order=o, cd_axis=c))
+        for s, st in enumerate(ref.streams):
+            assert h.stream_blob(s) == st.blob, (i, s)
+        got, _ = h.retrieve(apc.Target("rel", 1e-4))
+        want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", 1e-4)))
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want.view(np.uint32)), i
+        hs.close()
+        h.close()
+
+
+def test_batch_rejects_mixed_dtypes_and_bad_fields():
+    apc = _apc()
+    a = torch.zeros((8, 8, 8), device="cuda")
+    b = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(AssertionError):
+        apc.refactor_batch([a, b], [apc.Scheme(), apc.Scheme()])
+    c = torch.zeros((8, 8, 8), device="cuda")
+    c[0, 0, 0] = float("inf")
+    with pytest.raises(apc.ApcError) as ei:
+        apc.refactor_batch([a, c], [apc.Scheme(), apc.Scheme()])
+    assert ei.value.status == -3
+
+
+def test_ladder_graph_replays_match_single_shot(config1_field):
+    apc = _apc()
+    x = torch.from_numpy(config1_field).cuda()
+    sc = apc.Scheme(kind="level", cd_axis=0)
+    targets = [apc.Target("rel", r) for r in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)] + [apc.Target("psnr", 70)]
+    want = []
+    for t in targets:
+        fresh = apc.refactor(x, sc)
+        out, _ = fresh.retrieve(t)
+        want.append(out.clone())
+        fresh.close()
+    h = apc.refactor(x, sc)
+    ladder = apc.Ladder(h, targets)
+    other = apc.refactor(x, apc.Scheme(kind="region"))
+    for rep in range(3):
+        for o in ladder.outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        outs = ladder.launch()
+        torch.cuda.synchronize()
+        for i, (g, w) in enumerate(zip(outs, want)):
+            assert torch.equal(g.view(torch.int32), w.view(torch.int32)), (rep, i)
+        # eager work between replays: other retrievals and a torch reduction
+        other.retrieve(apc.Target("rel", 1e-3))
+        _ = (x * 2).sum().item()
+        torch.cuda.synchronize()
+    # after a replay the handle continues incrementally from the ladder's last planes
+    got, _ = h.retrieve(apc.Target("rel", 1e-3))
+    fresh = apc.refactor(x, sc)
+    ref, _ = fresh.retrieve(apc.Target("rel", 1e-3))
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
+    ladder.close()
+    other.close()
+    fresh.close()
+    h.close()
+
+
+@pytest.mark.parametrize("mode", ["eb", "psnr"])
+def test_select_pipeline_matches_oracle(config1_field, mode):
+    apc = _apc()
+    got = apc.select_pipeline(torch.from_numpy(config1_field).cuda(), mode)
+    want = oracle.select_pipeline(config1_field, mode)
+    assert (got.kind, got.cd_axis) == (want.kind, want.cd_axis)
+    if want.kind == "region":
+        assert tuple(got.order) == tuple(want.order)
+
+
+def test_select_pipeline_2d_matches_oracle():
+    apc = _apc()
+    x = fieldgen.zonal_bands((300, 600), seed=2)
+    got = apc.select_pipeline(torch.from_numpy(x).cuda(), "eb")
+    want = oracle.select_pipeline(x, "eb")
+    assert (got.kind, got.cd_axis) == (want.kind, want.cd_axis)
+    if want.kind == "region":
+        assert tuple(got.order) == tuple(want.order)
