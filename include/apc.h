@@ -130,6 +130,35 @@ apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n
 apc_status apc_ladder_launch(apc_ladder* ladder, void* hip_stream);
 void apc_ladder_free(apc_ladder* ladder);
 
+/* Serving: a request loop over resident refactored fields with continuous
+ * batching.  Requests are admitted in arrival order whenever one of
+ * max_slots slot streams is free and the request's work buffers fit in
+ * hbm_budget_bytes (the decoded-code buffers of the fields are resident and
+ * not counted); admitted requests run concurrently.  Only planes no earlier
+ * request has fetched are decoded (per field, on the field's own stream);
+ * each request reads the resident codes truncated to its own plan, so its
+ * output equals that of the same request made alone.  The server owns the
+ * fields' retrieval state until apc_server_destroy (which lets queued work
+ * finish); handles stay owned by the caller and must outlive the server.
+ *   submit: plans on the host and queues; APC_E_BELOW_FLOOR for an
+ *           unreachable target; APC_E_BUSY if the queue is full or the
+ *           request alone exceeds the budget.  out_dev (caller owned, n
+ *           elements of the field's dtype) is written asynchronously.
+ *   poll / wait: completion of a ticket (wait also returns the plan info and
+ *           forgets the ticket).
+ *   stats: latency from submit to completion over completed requests. */
+typedef struct apc_server apc_server;
+apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t hbm_budget_bytes,
+                             int32_t max_slots, apc_server** out);
+apc_status apc_server_submit(apc_server* sv, int32_t field, const apc_target* target, void* out_dev,
+                             int64_t* ticket);
+apc_status apc_server_poll(apc_server* sv, int64_t ticket, int32_t* done);
+apc_status apc_server_wait(apc_server* sv, int64_t ticket, apc_retrieve_info* info);
+apc_status apc_server_stats(apc_server* sv, double* p50_ms, double* p99_ms, double* mean_ms, int64_t* completed,
+                            int64_t* max_running);
+apc_status apc_server_reset_stats(apc_server* sv);
+void apc_server_destroy(apc_server* sv);
+
 /* Target-driven pipeline selection (Section VI-A): regular ~1% sample
  * blocks, every candidate of Table I refactored on the sample, plan sizes at
  * the nine tuning tolerances, majority vote (interpolation first, then the

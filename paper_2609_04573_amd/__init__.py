@@ -5,5 +5,5 @@ at any max-error bound or PSNR; ``select_pipeline`` picks the interpolation
 scheme and coefficient-decomposition direction from a sample.  All work runs
 in the HIP library ``libapc.so`` (see ``include/apc.h``).
 """
-from .apc import (ApcError, BelowFloor, Handle, Ladder, Scheme, Target, axis_norms, refactor,  # noqa: F401
-                  refactor_batch, select_pipeline)
+from .apc import (ApcError, BelowFloor, Handle, Ladder, Scheme, Server, Target, axis_norms,  # noqa: F401
+                  refactor, refactor_batch, select_pipeline)

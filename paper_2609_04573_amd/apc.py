@@ -40,7 +40,9 @@ EXPORTED = [
     "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline", "apc_free",
     "apc_strerror", "apc_last_error", "apc_num_streams", "apc_num_groups", "apc_num_points", "apc_stream_info",
     "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
-    "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free",
+    "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
+    "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
+    "apc_server_destroy",
 ]
 
 
@@ -89,10 +91,20 @@ _lib.apc_ladder_create.argtypes = [_vp, ctypes.POINTER(_Target), _i32, ctypes.PO
 _lib.apc_ladder_launch.argtypes = [_vp, _vp]
 _lib.apc_ladder_free.argtypes = [_vp]
 _lib.apc_ladder_free.restype = None
+_lib.apc_server_create.argtypes = [ctypes.POINTER(_vp), _i32, _i64, _i32, ctypes.POINTER(_vp)]
+_lib.apc_server_submit.argtypes = [_vp, _i32, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_i64)]
+_lib.apc_server_poll.argtypes = [_vp, _i64, ctypes.POINTER(_i32)]
+_lib.apc_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(_Info)]
+_lib.apc_server_stats.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)] * 2
+_lib.apc_server_reset_stats.argtypes = [_vp]
+_lib.apc_server_destroy.argtypes = [_vp]
+_lib.apc_server_destroy.restype = None
 _lib.apc_profile_report.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
               "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable",
-              "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch"):
+              "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
+              "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
+              "apc_server_reset_stats"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -288,6 +300,57 @@ class Ladder:
     def close(self):
         if self._p:
             _lib.apc_ladder_free(self._p)
+            self._p = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching retrieval server over resident refactored fields."""
+
+    def __init__(self, handles: Sequence[Handle], budget_bytes: int, max_slots: int = 4):
+        self.handles = list(handles)
+        arr = (ctypes.c_void_p * len(self.handles))(*[h._h.value for h in self.handles])
+        out = ctypes.c_void_p()
+        _check(_lib.apc_server_create(arr, len(self.handles), int(budget_bytes), int(max_slots), ctypes.byref(out)))
+        self._p = out
+
+    def submit(self, field: int, target: Target, out) -> int:
+        h = self.handles[field]
+        assert out.is_contiguous() and out.dtype == h.dtype and tuple(out.shape) == h.shape
+        t = _i64()
+        _check(_lib.apc_server_submit(self._p, int(field), ctypes.byref(target._c()), ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = _i32()
+        _check(_lib.apc_server_poll(self._p, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> dict:
+        inf = _Info()
+        _check(_lib.apc_server_wait(self._p, int(ticket), ctypes.byref(inf)))
+        return _info_dict(inf)
+
+    def stats(self) -> dict:
+        p50, p99, mean = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        done, mr = _i64(), _i64()
+        _check(_lib.apc_server_stats(self._p, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(mean),
+                                     ctypes.byref(done), ctypes.byref(mr)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "mean_ms": mean.value, "completed": done.value,
+                "max_running": mr.value}
+
+    def reset_stats(self):
+        _check(_lib.apc_server_reset_stats(self._p))
+
+    def close(self):
+        if self._p:
+            _lib.apc_server_destroy(self._p)
             self._p = ctypes.c_void_p(0)
 
     def __del__(self):

@@ -8,6 +8,10 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <functional>
 #include <map>
 #include <memory>
@@ -1052,12 +1056,62 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
 }
 
 // ---------------------------------------------------------------- retrieval
+// Work buffers of one retrieval (the handle's own, or a server slot's).
+struct WorkPtrs {
+  double* xc = nullptr;
+  double* xb[2] = {nullptr, nullptr};
+  double* pr[2] = {nullptr, nullptr};
+  void* cdreg = nullptr;
+};
+
+// Bytes of work buffers a retrieval of this handle needs (layout of carve_work).
+size_t work_bytes(const apc_handle* h) {
+  const Geo& g = h->geo;
+  const int L = g.L;
+  size_t b = 8 * (size_t)((int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2]) + 256;
+  if (L >= 2) {
+    b += 2 * (8 * (size_t)((int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2]) + 256);
+    if (g.d >= 2) b += 8 * (size_t)lat_count(lattice(g, 0, 0)) + 256;
+    if (g.d >= 3) b += 8 * (size_t)lat_count(lattice(g, 0, 1)) + 256;
+    b += qsize(h->dtype) * (size_t)h->cdreg_n + 256;
+  }
+  return b;
+}
+
+WorkPtrs carve_work(const apc_handle* h, void* base) {
+  const Geo& g = h->geo;
+  const int L = g.L;
+  WorkPtrs w;
+  char* p = (char*)base;
+  auto take = [&](size_t n) {
+    char* r = p;
+    p += (n + 255) & ~(size_t)255;
+    return r;
+  };
+  w.xc = (double*)take(8 * (size_t)((int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2]));
+  if (L >= 2) {
+    const size_t n1 = (size_t)((int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2]);
+    w.xb[0] = (double*)take(8 * n1);
+    w.xb[1] = (double*)take(8 * n1);
+    if (g.d >= 2) w.pr[0] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 0)));
+    if (g.d >= 3) w.pr[1] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 1)));
+    w.cdreg = take(qsize(h->dtype) * (size_t)h->cdreg_n);
+  }
+  return w;
+}
+
+apc_status ensure_codes(apc_handle* h) {
+  const size_t qs = qsize(h->dtype);
+  if (!h->codes.p) APC_TRY(h->codes.alloc(qs * (size_t)std::max<int64_t>(1, h->code_n)));
+  if (!h->cd_codes.p) APC_TRY(h->cd_codes.alloc(qs * (size_t)std::max<int64_t>(1, h->cd_n)));
+  return APC_OK;
+}
+
 apc_status ensure_work(apc_handle* h) {
   if (h->work_ready) return APC_OK;
   const Geo& g = h->geo;
   const size_t qs = qsize(h->dtype);
-  APC_TRY(h->codes.alloc(qs * (size_t)std::max<int64_t>(1, h->code_n)));
-  APC_TRY(h->cd_codes.alloc(qs * (size_t)std::max<int64_t>(1, h->cd_n)));
+  APC_TRY(ensure_codes(h));
   const int L = g.L;
   const int64_t nc = (int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2];
   APC_TRY(h->xc.alloc(8 * (size_t)nc));
@@ -1074,11 +1128,24 @@ apc_status ensure_work(apc_handle* h) {
   return APC_OK;
 }
 
+WorkPtrs handle_work(apc_handle* h) {
+  WorkPtrs w;
+  w.xc = h->xc.as<double>();
+  w.xb[0] = h->xb[0].as<double>();
+  w.xb[1] = h->xb[1].as<double>();
+  w.pr[0] = h->pr[0].as<double>();
+  w.pr[1] = h->pr[1].as<double>();
+  w.cdreg = h->cdreg.p;
+  return w;
+}
+
 // Tables and launches of one retrieval; kres tracks the planes resident
-// after it (incremental decode).
+// after it (incremental decode).  The decode part and the reconstruction
+// part can be built separately (a server runs them on different streams).
 template <typename T, typename Q>
 void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::vector<int>& kres,
-                    TableBuilder& tb, std::vector<Launch>& ls, int64_t* fetched) {
+                    TableBuilder& tb, std::vector<Launch>& ls, int64_t* fetched, const WorkPtrs& w,
+                    bool with_decode = true, bool with_recon = true) {
   Meta& m = h->meta;
   const Geo& g = h->geo;
   const int d = g.d, L = g.L;
@@ -1086,7 +1153,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   std::vector<StreamDev> sds;
   int64_t chunks = 0, fb = 0;
   double db = 0.0;
-  for (int s = 0; s < (int)m.streams.size(); ++s) {
+  for (int s = 0; s < (int)m.streams.size() && with_decode; ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
     StreamDev sd{};
@@ -1115,6 +1182,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   }
   if (fetched) *fetched = fb;
   if (!sds.empty()) ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, 0, db, "decode"});
+  if (!with_recon) return;
   // inverse decomposition of every level-0 region
   if (!h->cd.empty() && L >= 2) {
     std::vector<CDSeg> cs;
@@ -1125,7 +1193,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       for (int a = 0; a < 3; ++a) c.c[a] = ci.c[a];
       c.f2 = make_fastdiv((uint32_t)std::max(1, c.c[2]));
       c.f1 = make_fastdiv((uint32_t)std::max(1, c.c[1]));
-      c.Rout = h->cdreg.as<Q>() + ci.reg_off;
+      c.Rout = (Q*)w.cdreg + ci.reg_off;
       for (int t = 0; t < 3; ++t) {
         c.S[t] = h->cd_codes.as<Q>() + ci.s_off[t];
         c.B[t] = m.streams[ci.s_idx[t]].B;
@@ -1149,7 +1217,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     const Stream& s0 = m.streams[0];
     FlatSeg c{};
     c.src = h->codes.as<Q>();
-    c.dst = L == 1 ? (void*)out : (void*)h->xc.p;
+    c.dst = L == 1 ? (void*)out : (void*)w.xc;
     c.n = s0.n;
     c.B = s0.B;
     c.k = planes[0];
@@ -1159,9 +1227,9 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
     ls.push_back({K_COARSEST, tb.add(cs), 1, nbk, 0, (8.0 + sizeof(Q)) * s0.n, "coarsest"});
   }
-  const double* xin = h->xc.as<double>();
+  const double* xin = w.xc;
   for (int l = L - 2; l >= 0; --l) {
-    double* xout = l > 0 ? h->xb[l % 2].as<double>() : nullptr;
+    double* xout = l > 0 ? w.xb[l % 2] : nullptr;
     void* dst = l > 0 ? (void*)xout : (void*)out;
     {
       FlatSeg c{};
@@ -1180,7 +1248,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     }
     for (int rho = 0; rho < d; ++rho) {
       ReconSeg r{};
-      double* pr[2] = {h->pr[0].as<double>(), h->pr[1].as<double>()};
+      double* pr[2] = {w.pr[0], w.pr[1]};
       r.ra = region_args(h, l, rho, per_level, pr, true, true);
       const int64_t cnt = lat_count(r.ra.lat);
       if (cnt == 0) continue;
@@ -1189,7 +1257,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       r.cm2 = g.m[l + 1][2];
       if (l == 0 && !h->cd.empty()) {
         const CDInfo& ci = h->cd[rho];
-        r.q = h->cdreg.as<Q>() + ci.reg_off;
+        r.q = (const Q*)w.cdreg + ci.reg_off;
         r.B = 64;
         r.k = 64;
         r.delta = m.groups[m.streams[ci.s_idx[0]].group].delta;
@@ -1237,7 +1305,7 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   TableBuilder tb;
   std::vector<Launch> ls;
   std::vector<int> kres = h->k_res;
-  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched);
+  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched, handle_work(h));
   APC_TRY(upload_tables(h, tb.bytes, st));
   APC_TRY((issue<T, Q>(ls, (const char*)h->tables.p, st)));
   h->k_res = kres;
@@ -1427,9 +1495,9 @@ apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n
     std::vector<int> planes;
     APC_TRY(plan_for(h, &targets[i], planes, nullptr));
     if (h->dtype == APC_F32)
-      build_retrieve<float, int32_t>(h, planes, (float*)outs_dev[i], kres, tb, ls, nullptr);
+      build_retrieve<float, int32_t>(h, planes, (float*)outs_dev[i], kres, tb, ls, nullptr, handle_work(h));
     else
-      build_retrieve<double, int64_t>(h, planes, (double*)outs_dev[i], kres, tb, ls, nullptr);
+      build_retrieve<double, int64_t>(h, planes, (double*)outs_dev[i], kres, tb, ls, nullptr, handle_work(h));
   }
   ld->k_after = kres;
   APC_TRY(ld->tables.alloc(tb.bytes.size()));
@@ -1773,3 +1841,340 @@ extern "C" apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, 
   if (dtype == APC_F64) return select_impl<double>((const double*)field_dev, dtype, probe.geo, mode, out, st);
   return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
 }
+
+// ------------------------------------------------------------------ serving
+// A request loop over resident refactored fields with continuous batching:
+// requests are admitted in arrival order whenever a slot stream is free and
+// their work buffers fit the HBM budget, so new requests start while earlier
+// ones are still on the device.  Missing planes of a field are decoded on
+// that field's own stream (decodes of one field are serialized and only add
+// planes); each request then recomposes and reconstructs on its slot stream
+// after the decode that covers its plan, reading the shared codes truncated
+// to its own plan, so its result does not depend on what else is in flight.
+namespace {
+
+struct SrvRequest {
+  int64_t ticket = 0;
+  int field = 0;
+  void* out = nullptr;
+  std::vector<int> planes;
+  apc_retrieve_info info{};
+  size_t footprint = 0;
+  int slot = -1;
+  int state = 0;  // 0 pending, 1 running, 2 done, 3 failed
+  apc_status status = APC_OK;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  DevBuf work;
+  hipEvent_t done_ev = nullptr;
+};
+
+struct SrvStaging {  // device table buffer fed from pinned memory
+  DevBuf dev;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t copied = nullptr;
+  bool used = false;
+  ~SrvStaging() {
+    if (pinned) (void)hipHostFree(pinned);
+    if (copied) (void)hipEventDestroy(copied);
+  }
+  apc_status put(const std::vector<char>& b, hipStream_t st) {
+    if (b.empty()) return APC_OK;
+    if (!copied) HIP_TRY(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    if (used) HIP_TRY(hipEventSynchronize(copied));
+    if (pinned_bytes < b.size()) {
+      if (pinned) (void)hipHostFree(pinned);
+      pinned_bytes = std::max<size_t>(2 * b.size(), 1 << 16);
+      HIP_TRY(hipHostMalloc(&pinned, pinned_bytes));
+    }
+    memcpy(pinned, b.data(), b.size());
+    if (dev.bytes < b.size()) {
+      // the old table may still be read by queued work on this stream: the
+      // pool hands it out again only after the device has moved past it
+      HIP_TRY(hipStreamSynchronize(st));
+      APC_TRY(dev.alloc(b.size()));
+    }
+    HIP_TRY(hipMemcpyAsync(dev.p, pinned, b.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(copied, st));
+    used = true;
+    return APC_OK;
+  }
+};
+
+struct SrvSlot {
+  hipStream_t st = nullptr;
+  SrvStaging tab;
+  int64_t req = -1;
+};
+
+struct SrvField {
+  apc_handle* h = nullptr;
+  hipStream_t dec_st = nullptr;
+  hipEvent_t dec_ev = nullptr;
+  bool has_dec = false;
+  std::vector<int> k_issued;
+  SrvStaging tab;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct apc_server {
+  int device = 0;
+  std::vector<std::unique_ptr<SrvField>> fields;
+  std::vector<std::unique_ptr<SrvSlot>> slots;
+  std::map<int64_t, std::unique_ptr<SrvRequest>> reqs;
+  std::deque<int64_t> pending;
+  std::vector<double> lat_ms;
+  int64_t next_ticket = 1;
+  size_t budget = 0, in_use = 0;
+  int max_queue = 1 << 16;
+  int64_t completed = 0, failed = 0, max_running = 0;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::thread worker;
+  bool stop = false;
+
+  template <typename T, typename Q>
+  apc_status start(SrvRequest& r, SrvSlot& sl) {
+    SrvField& f = *fields[r.field];
+    apc_handle* h = f.h;
+    // decode of the planes no request has asked for yet, on the field's stream
+    TableBuilder tbd;
+    std::vector<Launch> ld;
+    int64_t fetched = 0;
+    build_retrieve<T, Q>(h, r.planes, (T*)r.out, f.k_issued, tbd, ld, &fetched, WorkPtrs(), true, false);
+    r.info.bytes_fetched = fetched;
+    if (!ld.empty()) {
+      APC_TRY(f.tab.put(tbd.bytes, f.dec_st));
+      APC_TRY((issue<T, Q>(ld, (const char*)f.tab.dev.p, f.dec_st)));
+      HIP_TRY(hipEventRecord(f.dec_ev, f.dec_st));
+      f.has_dec = true;
+    }
+    // recomposition and reconstruction on the slot stream, after the decode
+    // that covers this plan
+    if (f.has_dec) HIP_TRY(hipStreamWaitEvent(sl.st, f.dec_ev, 0));
+    APC_TRY(r.work.alloc(r.footprint));
+    const WorkPtrs w = carve_work(h, r.work.p);
+    TableBuilder tbr;
+    std::vector<Launch> lr;
+    std::vector<int> kdone = f.k_issued;  // no decode in this part
+    build_retrieve<T, Q>(h, r.planes, (T*)r.out, kdone, tbr, lr, nullptr, w, false, true);
+    APC_TRY(sl.tab.put(tbr.bytes, sl.st));
+    APC_TRY((issue<T, Q>(lr, (const char*)sl.tab.dev.p, sl.st)));
+    if (!r.done_ev) HIP_TRY(hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(r.done_ev, sl.st));
+    return APC_OK;
+  }
+
+  void loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop) {
+      bool busy = false;
+      int running = 0;
+      for (auto& slp : slots) {
+        SrvSlot& sl = *slp;
+        if (sl.req < 0) continue;
+        SrvRequest& r = *reqs[sl.req];
+        const hipError_t q = hipEventQuery(r.done_ev);
+        if (q == hipErrorNotReady) {
+          busy = true;
+          ++running;
+          continue;
+        }
+        r.t_done = now_s();
+        r.state = q == hipSuccess ? 2 : 3;
+        if (q != hipSuccess) r.status = APC_E_HIP;
+        lat_ms.push_back((r.t_done - r.t_submit) * 1e3);
+        ++completed;
+        r.work.release();
+        in_use -= r.footprint;
+        sl.req = -1;
+        done_cv.notify_all();
+      }
+      while (!pending.empty()) {
+        SrvRequest& r = *reqs[pending.front()];
+        int free_slot = -1;
+        for (size_t i = 0; i < slots.size(); ++i)
+          if (slots[i]->req < 0) {
+            free_slot = (int)i;
+            break;
+          }
+        if (free_slot < 0 || in_use + r.footprint > budget) break;
+        pending.pop_front();
+        SrvSlot& sl = *slots[free_slot];
+        r.slot = free_slot;
+        r.t_start = now_s();
+        const apc_status s = fields[r.field]->h->dtype == APC_F32 ? start<float, int32_t>(r, sl)
+                                                                : start<double, int64_t>(r, sl);
+        if (s != APC_OK) {
+          r.state = 3;
+          r.status = s;
+          ++failed;
+          r.work.release();
+          done_cv.notify_all();
+          continue;
+        }
+        r.state = 1;
+        in_use += r.footprint;
+        sl.req = r.ticket;
+        busy = true;
+        ++running;
+      }
+      max_running = std::max<int64_t>(max_running, running);
+      if (busy) {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      } else {
+        cv.wait_for(lk, std::chrono::milliseconds(50));
+      }
+    }
+  }
+};
+
+extern "C" {
+
+apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t hbm_budget_bytes, int32_t max_slots,
+                             apc_server** out) {
+  if (!fields || nfields < 1 || max_slots < 1 || max_slots > 64 || hbm_budget_bytes <= 0 || !out)
+    return fail(APC_E_INVALID, "bad argument");
+  std::unique_ptr<apc_server> sv(new apc_server());
+  HIP_TRY(hipGetDevice(&sv->device));
+  sv->budget = (size_t)hbm_budget_bytes;
+  for (int f = 0; f < nfields; ++f) {
+    if (!fields[f]) return fail(APC_E_INVALID, "null field handle %d", f);
+    sv->fields.emplace_back(new SrvField());
+    SrvField& F = *sv->fields.back();
+    F.h = fields[f];
+    APC_TRY(ensure_codes(F.h));
+    F.k_issued = F.h->k_res;
+    HIP_TRY(hipStreamCreateWithFlags(&F.dec_st, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&F.dec_ev, hipEventDisableTiming));
+  }
+  for (int i = 0; i < max_slots; ++i) {
+    sv->slots.emplace_back(new SrvSlot());
+    HIP_TRY(hipStreamCreateWithFlags(&sv->slots.back()->st, hipStreamNonBlocking));
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  apc_server* raw = sv.get();
+  sv->worker = std::thread([raw] { raw->loop(); });
+  *out = sv.release();
+  return APC_OK;
+}
+
+apc_status apc_server_submit(apc_server* sv, int32_t field, const apc_target* target, void* out_dev,
+                             int64_t* ticket) {
+  if (!sv || !target || !out_dev || !ticket) return fail(APC_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (field < 0 || field >= (int32_t)sv->fields.size()) return fail(APC_E_INVALID, "bad field %d", field);
+  if ((int)sv->pending.size() >= sv->max_queue) return fail(APC_E_BUSY, "request queue full");
+  std::unique_ptr<SrvRequest> r(new SrvRequest());
+  r->field = field;
+  r->out = out_dev;
+  apc_handle* h = sv->fields[field]->h;
+  APC_TRY(plan_for(h, target, r->planes, &r->info));
+  r->footprint = work_bytes(h);
+  if (r->footprint > sv->budget)
+    return fail(APC_E_BUSY, "request needs %zu bytes of work buffers, budget is %zu", r->footprint, sv->budget);
+  r->ticket = sv->next_ticket++;
+  r->t_submit = now_s();
+  *ticket = r->ticket;
+  sv->pending.push_back(r->ticket);
+  sv->reqs[r->ticket] = std::move(r);
+  sv->cv.notify_all();
+  return APC_OK;
+}
+
+apc_status apc_server_wait(apc_server* sv, int64_t ticket, apc_retrieve_info* info) {
+  if (!sv) return fail(APC_E_INVALID, "null server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(APC_E_INVALID, "unknown ticket");
+  SrvRequest* r = it->second.get();
+  sv->done_cv.wait(lk, [&] { return r->state >= 2; });
+  const apc_status s = r->status;
+  if (info) *info = r->info;
+  if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+  sv->reqs.erase(it);
+  if (s != APC_OK) return fail(s, "request %lld failed", (long long)ticket);
+  return APC_OK;
+}
+
+apc_status apc_server_poll(apc_server* sv, int64_t ticket, int32_t* done) {
+  if (!sv || !done) return fail(APC_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(APC_E_INVALID, "unknown ticket");
+  *done = it->second->state >= 2 ? 1 : 0;
+  return APC_OK;
+}
+
+apc_status apc_server_stats(apc_server* sv, double* p50_ms, double* p99_ms, double* mean_ms, int64_t* completed,
+                            int64_t* max_running) {
+  if (!sv) return fail(APC_E_INVALID, "null server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::vector<double> v = sv->lat_ms;
+  std::sort(v.begin(), v.end());
+  auto pct = [&](double q) {
+    if (v.empty()) return 0.0;
+    size_t i = (size_t)std::ceil(q / 100.0 * (double)v.size());
+    i = std::min(v.size() - 1, i ? i - 1 : 0);
+    return v[i];
+  };
+  double sum = 0;
+  for (double x : v) sum += x;
+  if (p50_ms) *p50_ms = pct(50);
+  if (p99_ms) *p99_ms = pct(99);
+  if (mean_ms) *mean_ms = v.empty() ? 0.0 : sum / (double)v.size();
+  if (completed) *completed = sv->completed;
+  if (max_running) *max_running = sv->max_running;
+  return APC_OK;
+}
+
+apc_status apc_server_reset_stats(apc_server* sv) {
+  if (!sv) return fail(APC_E_INVALID, "null server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->lat_ms.clear();
+  sv->completed = 0;
+  sv->max_running = 0;
+  return APC_OK;
+}
+
+void apc_server_destroy(apc_server* sv) {
+  if (!sv) return;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    // let queued and running requests finish
+    sv->done_cv.wait(lk, [&] {
+      if (!sv->pending.empty()) return false;
+      for (const auto& s : sv->slots)
+        if (s->req >= 0) return false;
+      return true;
+    });
+    sv->stop = true;
+    sv->cv.notify_all();
+  }
+  sv->worker.join();
+  (void)hipDeviceSynchronize();
+  for (SrvRequest* r : [&] {
+         std::vector<SrvRequest*> v;
+         for (auto& kv : sv->reqs) v.push_back(kv.second.get());
+         return v;
+       }())
+    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+  for (auto& s : sv->slots)
+    if (s->st) (void)hipStreamDestroy(s->st);
+  for (auto& f : sv->fields) {
+    f->h->k_res = f->k_issued;
+    if (f->dec_ev) (void)hipEventDestroy(f->dec_ev);
+    if (f->dec_st) (void)hipStreamDestroy(f->dec_st);
+  }
+  delete sv;
+}
+
+}  // extern "C"
