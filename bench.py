@@ -57,6 +57,106 @@ def cpu_baseline(x_full, rel: float, side: int = 256):
     }
 
 
+def batch_leg(apc, torch, fieldgen, full: bool):
+    """Uneven fields refactored in one batched call vs one call per field."""
+    import numpy as np
+
+    rng = np.random.default_rng(2)
+    n2, n3, nc = (32, 32, 32) if full else (4, 4, 8)
+    fields = []
+    for i in range(n2):
+        fields.append(fieldgen.zonal_bands((1800, 3600), seed=1000 + i))
+    for i in range(n3):
+        fields.append(fieldgen.power_law_field((100, 500, 500), seed=2000 + i))
+    for i in range(nc):
+        m = int(rng.integers(64, 385))
+        fields.append(fieldgen.power_law_field((m, m, m), seed=3000 + i))
+    xs = [torch.from_numpy(f).cuda() for f in fields]
+    schemes = [apc.Scheme(kind="level", cd_axis=0) for _ in xs]
+    nbytes = sum(x.numel() * x.element_size() for x in xs)
+    torch.cuda.synchronize()
+
+    def per_field():
+        t0 = time.perf_counter()
+        hs = [apc.refactor(x, s) for x, s in zip(xs, schemes)]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, hs
+
+    def batched():
+        t0 = time.perf_counter()
+        hs = apc.refactor_batch(xs, schemes)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, hs
+
+    for fn in (per_field, batched):  # warm-up
+        _, hs = fn()
+        for h in hs:
+            h.close()
+    tp, hp = per_field()
+    tb, hb = batched()
+    same = all(a.metadata() == b.metadata() for a, b in zip(hp, hb))
+    same = same and all(hp[i].stream_blob(s) == hb[i].stream_blob(s)
+                        for i in (0, len(hp) - 1) for s in range(hp[i].num_streams))
+    for h in hp + hb:
+        h.close()
+    return {"fields": len(xs), "GB": nbytes / 1e9, "per_field_s": tp, "batched_s": tb,
+            "per_field_GBps": nbytes / tp / 1e9, "batched_GBps": nbytes / tb / 1e9, "speedup": tp / tb,
+            "identical_output": bool(same),
+            "workload": f"{n2} x 1800x3600 zonal bands + k^-3, {n3} x 100x500x500 and {nc} cubes 64..384 "
+                        "k^-5/3, seed 2; per-level cubic + decomposition axis 0"}
+
+
+def serve_leg(apc, torch, fieldgen, full: bool):
+    """Poisson request stream over resident fields: continuous batching vs
+    one request at a time."""
+    import numpy as np
+
+    side = 256 if full else 128
+    xs = [torch.from_numpy(fieldgen.power_law_field((side,) * 3, seed=3 + i)).cuda() for i in range(16)]
+    schemes = [apc.Scheme(kind="level", cd_axis=0) for _ in xs]
+    rates = (100, 200, 500, 1000, 2000, 5000) if full else (500, 2000)
+    nreq = 2000 if full else 300
+    eb = (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
+    psnr = (40, 50, 60, 70, 80, 90, 100)
+    out = {"workload": f"16 resident {side}^3 float32 k^-5/3 fields (seeds 3-18), Poisson arrivals, "
+                       "targets uniform over eb 1e-2..1e-6 and PSNR 40..100 dB, incremental planes",
+           "rates": {}}
+    for ri, rate in enumerate(rates):
+        res = {}
+        for slots, name in ((4, "continuous"), (1, "fifo")):
+            hs = apc.refactor_batch(xs, schemes)
+            srv = apc.Server(hs, budget_bytes=4 << 30, max_slots=slots)
+            rng = np.random.default_rng(100 + ri)
+            gaps = rng.exponential(1.0 / rate, size=nreq)
+            reqs = []
+            for _ in range(nreq):
+                f = int(rng.integers(0, len(xs)))
+                t = apc.Target("rel", float(rng.choice(eb))) if rng.random() < 0.5 else \
+                    apc.Target("psnr", float(rng.choice(psnr)))
+                reqs.append((f, t))
+            outs = [torch.empty_like(xs[0]) for _ in range(8)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            due = t0
+            tickets = []
+            for k, ((f, t), g) in enumerate(zip(reqs, gaps)):
+                due += g
+                while time.perf_counter() < due:
+                    pass
+                tickets.append(srv.submit(f, t, outs[k % len(outs)]))
+            for tk in tickets:
+                srv.wait(tk)
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            srv.close()
+            for h in hs:
+                h.close()
+            res[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                         "req_per_s": nreq / wall, "max_concurrent": st["max_running"]}
+        out["rates"][str(rate)] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +165,8 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--rel", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-systems", action="store_true", help="skip the batching and serving legs")
+    ap.add_argument("--full", action="store_true", help="full-size batching and serving workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by independent "
@@ -141,6 +243,7 @@ def main():
         "retrieve_hbm_frac": ret_alg / t_ret / HBM_PEAK,
         "retrieve_ms_p50": _pct([r[1] * 1e3 for r in rec], 50),
         "retrieve_ms_p99": _pct([r[1] * 1e3 for r in rec], 99),
+        "single_field_retrieve_ms_p50": _pct([r[1] * 1e3 for r in rec], 50),
         "stream_bytes": streams,
         "plan_bytes": info["bytes_total"],
         "bitrate": info["bitrate"],
@@ -157,6 +260,13 @@ def main():
                         "ms_per_step": d["ms"] / args.steps}
     line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4) for k, v in
                                    sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_systems:
+        line["batch"] = batch_leg(apc, torch, fieldgen, args.full)
+        line["serve"] = serve_leg(apc, torch, fieldgen, args.full)
+        top = line["serve"]["rates"][max(line["serve"]["rates"], key=int)]["continuous"]
+        line["retrieve_ms_p50"] = top["p50_ms"]
+        line["retrieve_ms_p99"] = top["p99_ms"]
+        line["retrieve_latency_source"] = "serving leg, highest arrival rate, continuous batching"
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, args.rel)
     print(json.dumps(line))
