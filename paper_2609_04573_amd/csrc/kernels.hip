@@ -1,6 +1,7 @@
-// gfx950 kernels of the progressive compressor.  Wave64 throughout: the
-// bitplane transpose uses one ballot per plane per 64-code word, and the sign
-// bits of newly significant codes are ranked with popcounts of ballot masks.
+// gfx950 kernels of the progressive compressor.  Wave64 throughout: in the
+// bitplane codec each lane owns one 64-code word and moves between codes and
+// plane words with in-register bit-matrix transposes; sign bits of newly
+// significant codes are placed through per-(plane, word) cursors in LDS.
 //
 // Every kernel walks a table of segments (field x level x region) in
 // 4096-element work blocks with a persistent block loop, so one launch serves
@@ -207,18 +208,31 @@ __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ 
     const FlatSeg& S = segs[si];
     const T* x = (const T*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
+    auto take = [&](double v) {
+      if (!isfinite(v)) {
+        bad = true;
+      } else {
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+        am = fmax(am, fabs(v));
+      }
+    };
+    constexpr int VW = 16 / sizeof(T);  // elements per 16-byte load
+    if (e0 + kBlockElems <= S.n && (((uintptr_t)(x + e0)) & 15) == 0) {
+      typedef T vec_t __attribute__((ext_vector_type(VW)));
+      const vec_t* xv = (const vec_t*)(x + e0);
+      vec_t r[kPerThread / VW];
+#pragma unroll
+      for (int it = 0; it < kPerThread / VW; ++it) r[it] = xv[it * kThreads + threadIdx.x];
+#pragma unroll
+      for (int it = 0; it < kPerThread / VW; ++it)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) take((double)r[it][c]);
+    } else {
 #pragma unroll 4
-    for (int it = 0; it < kPerThread; ++it) {
-      const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e < S.n) {
-        const double v = (double)x[e];
-        if (!isfinite(v)) {
-          bad = true;
-        } else {
-          lo = fmin(lo, v);
-          hi = fmax(hi, v);
-          am = fmax(am, fabs(v));
-        }
+      for (int it = 0; it < kPerThread; ++it) {
+        const int64_t e = e0 + it * kThreads + threadIdx.x;
+        if (e < S.n) take((double)x[e]);
       }
     }
   }
@@ -274,9 +288,10 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     const int ax = L.ax;
     const int64_t gs[3] = {(int64_t)L.m[1] * L.m[2], (int64_t)L.m[2], 1};
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) break;
+      if (e >= total) continue;
       int i[3];
       lattice_node(L, (uint32_t)e, i);
       const int j = i[ax];
@@ -324,9 +339,10 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
     const FlatSeg& S = segs[si];
     const T* G = (const T*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= S.n) break;
+      if (e >= S.n) continue;
       const double v = (double)G[e];
       if (MODE == 0)
         am = fmax(am, fabs(v));
@@ -407,9 +423,10 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
     const int Nu = S.c[U], Nv = S.c[V];
     const int64_t ls[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
     const int64_t su = ls[U], sv = ls[V];
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) break;
+      if (e >= total) continue;
       int t[3];
       cd_coords(S, (uint32_t)e, t);
       const int u = t[U], v = t[V];
@@ -464,9 +481,10 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
     const int Nu = S.c[U], Nv = S.c[V];
     const int64_t ls[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
     const int64_t su = ls[U], sv = ls[V];
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) break;
+      if (e >= total) continue;
       int t[3];
       cd_coords(S, (uint32_t)e, t);
       const int u = t[U], v = t[V];
@@ -531,85 +549,141 @@ __device__ __forceinline__ int find_stream(const StreamDev* sd, int ns, int64_t 
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// One block per 4096-code chunk: magnitude words of every plane (one ballot
-// per plane per word, written plane-major and coalesced from LDS), per-plane
-// counts of codes whose leading bit is that plane, and the chunk's sign bits
-// packed in chunk-local plane-major order.
+// Bit-matrix transpose of 32 words: afterwards bit k of a[p] is what bit p of
+// a[k] was (five rounds of block swaps, 2s x 2s blocks at round s).
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) {
+    const uint32_t m = s == 16 ? 0x0000FFFFu
+                     : s == 8  ? 0x00FF00FFu
+                     : s == 4  ? 0x0F0F0F0Fu
+                     : s == 2  ? 0x33333333u
+                               : 0x55555555u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      if (k & s) continue;
+      const uint32_t t = ((a[k] >> s) ^ a[k + s]) & m;
+      a[k] ^= t << s;
+      a[k + s] ^= t;
+    }
+  }
+}
+
+constexpr int kRow = 33;  // LDS row pitch (codes) of the half-word staging tile
+
+// Stage half h of every 64-code word of a chunk in LDS: row r holds codes
+// base + 64 r + 32 h + [0, 32) (zero past n).  Lane pairs of rows per load.
+template <typename Q>
+__device__ __forceinline__ void stage_half(const Q* src, int64_t base, int64_t n, int h, Q* cst, int lane) {
+  const int k = lane & 31, rr = lane >> 5;
+#pragma unroll 8
+  for (int it = 0; it < 32; ++it) {
+    const int r = 2 * it + rr;
+    const int64_t e = base + 64 * r + 32 * h + k;
+    cst[r * kRow + k] = e < n ? src[e] : (Q)0;
+  }
+}
+template <typename Q>
+__device__ __forceinline__ void unstage_half(Q* dst, int64_t base, int64_t n, int h, const Q* cst, int lane) {
+  const int k = lane & 31, rr = lane >> 5;
+#pragma unroll 8
+  for (int it = 0; it < 32; ++it) {
+    const int r = 2 * it + rr;
+    const int64_t e = base + 64 * r + 32 * h + k;
+    if (e < n) dst[e] = cst[r * kRow + k];
+  }
+}
+
+// One wave per 4096-code chunk, one lane per 64-code word.  Each lane
+// transposes its word into per-plane magnitude words (stored plane-major,
+// coalesced across lanes), counts the codes that become significant at each
+// plane, and a wave scan of those counts gives every word its offset in the
+// chunk's plane-major sign staging.  The sign bits are then placed with one
+// LDS fetch-and-add per nonzero code on a (plane, word) cursor, visiting the
+// word's codes in order.
 template <typename Q, int MAXB>
-__global__ __launch_bounds__(kThreads) void k_encode(const StreamDev* __restrict__ sd, int ns) {
-  __shared__ uint64_t magbuf[MAXB][64];
-  __shared__ uint16_t wpre[MAXB][64];
-  __shared__ uint32_t tot[MAXB];
-  __shared__ uint32_t toff[MAXB];
+__global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd, int ns) {
+  constexpr int QW = (int)sizeof(Q) / 4;
+  constexpr int kStageBytes = 64 * kRow * (int)sizeof(Q);
+  constexpr int kTabBytes = MAXB * 64 * 4;
+  __shared__ __align__(16) unsigned char lds[kStageBytes > kTabBytes ? kStageBytes : kTabBytes];
   __shared__ unsigned long long sstage[64];
+  Q* cst = (Q*)lds;                 // half-word staging tile
+  uint32_t* ptab = (uint32_t*)lds;  // then: next staging position per (plane, word)
+  const int lane = threadIdx.x;
   const int64_t gch = blockIdx.x;
   const int u = find_stream(sd, ns, gch);
-  if (threadIdx.x < 64) sstage[threadIdx.x] = 0ull;
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
   const Q* src = (const Q*)S.codes;
   const int B = S.B;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const uint64_t lt = lanemask_lt(lane);
+  const int64_t base = chunk * kChunk;
+  const int64_t w = chunk * 64 + lane;
+  sstage[lane] = 0ull;
 
-  int blen_r[16];
-  int neg_r[16];
-  int rank_r[16];
+  uint64_t P[MAXB];   // P[b]: bit b of the word's 64 magnitudes
+  uint32_t lead[16];  // per code: 0x80 | plane << 1 | negative; 0 for a zero code
 #pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int wl = wave + 4 * it;
-    const int64_t idx = (chunk * 64 + wl) * 64 + lane;
-    const Q qv = (idx < S.n) ? src[idx] : (Q)0;
-    const uint64_t mg = absq(qv);
-    const int bl = bitlen64(mg);
-    blen_r[it] = bl;
-    neg_r[it] = qv < 0;
-    int rk = 0;
-    for (int j = 0; j < B; ++j) {
-      const int b = B - 1 - j;
-      const uint64_t mw = __ballot((mg >> b) & 1ull);
-      const uint64_t nsm = __ballot(bl == b + 1);
-      if (lane == 0) {
-        magbuf[j][wl] = mw;
-        wpre[j][wl] = (uint16_t)__popcll(nsm);
+  for (int b = 0; b < MAXB; ++b) P[b] = 0ull;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lead[i] = 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    stage_half<Q>(src, base, S.n, h, cst, lane);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < QW; ++p) {
+      uint32_t r[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        const Q q = cst[lane * kRow + k];
+        const uint64_t mg = absq(q);
+        r[k] = (uint32_t)(mg >> (32 * p));
+        if (p == 0 && mg) {
+          const int kk = 32 * h + k;
+          const uint32_t v = 0x80u | (((uint32_t)(B - bitlen64(mg)) & 63u) << 1) | (q < 0 ? 1u : 0u);
+          lead[kk >> 2] |= v << (8 * (kk & 3));
+        }
       }
-      if (bl == b + 1) rk = __popcll(nsm & lt);
-    }
-    rank_r[it] = rk;
-  }
-  __syncthreads();
-  for (int j = wave; j < B; j += 4) {
-    const uint32_t v = wpre[j][lane];
-    const uint32_t incl = wave_incl_scan(v, lane);
-    wpre[j][lane] = (uint16_t)(incl - v);
-    if (lane == 63) tot[j] = incl;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t off = 0;
-    for (int j = 0; j < B; ++j) {
-      toff[j] = off;
-      off += tot[j];
-      S.cnt[(int64_t)j * S.C + chunk] = tot[j];
-    }
-  }
-  for (int j = wave; j < B; j += 4) {
-    const int64_t w = chunk * 64 + lane;
-    if (w < S.M) S.mag[(int64_t)j * S.M + w] = magbuf[j][lane];
-  }
-  __syncthreads();
+      transpose32(r);
 #pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int bl = blen_r[it];
-    if (bl > 0 && neg_r[it]) {
-      const int j = B - bl;
-      const int wl = wave + 4 * it;
-      const uint32_t pos = toff[j] + wpre[j][wl] + rank_r[it];
-      atomicOr(&sstage[pos >> 6], 1ull << (pos & 63));
+      for (int bb = 0; bb < 32; ++bb)
+        if (32 * p + bb < MAXB) P[32 * p + bb] |= (uint64_t)r[bb] << (32 * h);
+    }
+    __syncthreads();
+  }
+
+  // planes from the most significant: magnitude words, newcomer counts, cursors
+  uint64_t sig = 0ull;
+  uint32_t toff = 0;
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    if (b >= B) continue;
+    const int j = B - 1 - b;
+    const uint64_t pw = P[b];
+    if (w < S.M) S.mag[(int64_t)j * S.M + w] = pw;
+    const uint32_t c = (uint32_t)__popcll(pw & ~sig);
+    sig |= pw;
+    const uint32_t incl = wave_incl_scan(c, lane);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (lane == 0) S.cnt[(int64_t)j * S.C + chunk] = tot;
+    ptab[j * 64 + lane] = toff + incl - c;
+    toff += tot;
+  }
+  // sign bits, word by word in code order (each lane owns its cursor column)
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    const uint32_t v = (lead[k >> 2] >> (8 * (k & 3))) & 0xffu;
+    if (v & 0x80u) {
+      const int j = (int)((v >> 1) & 63u);
+      if (j < MAXB) {
+        const uint32_t pos = atomicAdd(&ptab[j * 64 + lane], 1u);
+        if ((v & 1u) && pos < (uint32_t)kChunk) atomicOr(&sstage[pos >> 6], 1ull << (pos & 63));
+      }
     }
   }
   __syncthreads();
-  if (threadIdx.x < 64) S.stage[chunk * 64 + threadIdx.x] = sstage[threadIdx.x];
+  S.stage[chunk * 64 + lane] = sstage[lane];
 }
 
 // Exclusive scan of the per-chunk counts of one (stream, plane): the index
@@ -681,80 +755,120 @@ __global__ __launch_bounds__(kThreads) void k_sign_move(const StreamDev* __restr
 }
 
 // Incremental decode of planes [k0, k1) of each listed stream into its
-// resident codes.  The sign of a code that becomes significant at plane j is
-// found at index[j][chunk] + (rank among this chunk's plane-j newcomers).
+// resident codes; one wave per chunk, one lane per 64-code word.  The plane
+// words are transposed back onto the word's codes.  A code that becomes
+// significant at plane j takes the next bit of its (plane, word) cursor in
+// the chunk's run of plane-j sign bits, which starts at index[j][chunk]; the
+// sign words each plane needs are first copied into LDS.
 template <typename Q, int MAXB>
-__global__ __launch_bounds__(kThreads) void k_decode(const StreamDev* __restrict__ sd, int ns) {
-  __shared__ uint16_t wpre[MAXB][64];
-  __shared__ uint64_t mws[MAXB][64];
+__global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd, int ns) {
+  constexpr int QW = (int)sizeof(Q) / 4;
+  constexpr int kSignWords = 64 + 2 * MAXB;
+  __shared__ Q cst[64 * kRow];
+  __shared__ uint32_t ptab[MAXB * 64];
+  __shared__ unsigned long long sw[kSignWords];
+  __shared__ int64_t pw0[MAXB];     // first sign word of each decoded plane's run
+  __shared__ uint32_t pwoff[MAXB + 1];  // its LDS offset (prefix over decoded planes)
+  const int lane = threadIdx.x;
   const int64_t gch = blockIdx.x;
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
   Q* dst = (Q*)S.codes;
   const int B = S.B, k0 = S.k0, k1 = S.k1;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const uint64_t lt = lanemask_lt(lane);
-  for (int p = wave; p < k1 - k0; p += 4) {
-    const int64_t w = chunk * 64 + lane;
-    mws[p][lane] = (w < S.M) ? S.mag[(int64_t)(k0 + p) * S.M + w] : 0ull;
+  const bool fresh = S.fresh != 0;
+  const int64_t base = chunk * kChunk;
+  const int64_t w = chunk * 64 + lane;
+
+  // significance before plane k0 = nonzero resident codes
+  uint64_t sig = 0ull;
+  if (!fresh) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      stage_half<Q>(dst, base, S.n, h, cst, lane);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if (cst[lane * kRow + k] != (Q)0) sig |= 1ull << (32 * h + k);
+      __syncthreads();
+    }
+  }
+  uint64_t P[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = B - 1 - b;
+    P[b] = (b < B && j >= k0 && j < k1 && w < S.M) ? S.mag[(int64_t)j * S.M + w] : 0ull;
+  }
+  // newcomer counts -> cursors; runs of sign words to fetch
+  uint32_t woff = 0;
+  int np = 0;
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    const int j = B - 1 - b;
+    if (b >= B || j < k0 || j >= k1) continue;
+    const uint64_t pw = P[b];
+    const uint32_t c = (uint32_t)__popcll(pw & ~sig);
+    sig |= pw;
+    const uint32_t incl = wave_incl_scan(c, lane);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const int64_t D = S.pso[j] * 64 + (int64_t)S.idx[(int64_t)j * S.C + chunk];
+    const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
+    ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl - c;
+    if (lane == 0) {
+      pw0[np] = D >> 6;
+      pwoff[np] = woff;
+    }
+    woff += nw;
+    ++np;
+  }
+  if (lane == 0) pwoff[np] = woff;
+  __syncthreads();
+  // fetch the sign words of every run (woff <= 64 + 2 * planes by construction)
+  for (uint32_t i = lane; i < woff && i < (uint32_t)kSignWords; i += 64) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pwoff[mid] <= i)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t gw = pw0[lo] + (int64_t)(i - pwoff[lo]);
+    sw[i] = (gw >= 0 && gw < S.sign_n) ? S.sign[gw] : 0ull;
   }
   __syncthreads();
 
-  uint64_t nm_r[16];
-  int pl_r[16];
-  int rk_r[16];
-  Q q_r[16];
 #pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int wl = wave + 4 * it;
-    const int64_t e = (chunk * 64 + wl) * 64 + lane;
-    const bool valid = e < S.n;
-    const Q qres = (!S.fresh && valid) ? dst[e] : (Q)0;
-    bool sig = qres != 0;
-    uint64_t nm = 0;
-    int pl = -1, rk = 0;
-    for (int j = k0; j < k1; ++j) {
-      const uint64_t mw = mws[j - k0][wl];
-      const bool bit = (mw >> lane) & 1ull;
-      const bool nsg = bit && !sig;
-      sig = sig || bit;
-      if (bit) nm |= 1ull << (B - 1 - j);
-      const uint64_t nsm = __ballot(nsg);
-      if (lane == 0) wpre[j - k0][wl] = (uint16_t)__popcll(nsm);
-      if (nsg) {
-        pl = j;
-        rk = __popcll(nsm & lt);
+  for (int h = 0; h < 2; ++h) {
+    if (!fresh) {
+      stage_half<Q>(dst, base, S.n, h, cst, lane);
+      __syncthreads();
+    }
+    uint32_t nb[QW][32];
+#pragma unroll
+    for (int p = 0; p < QW; ++p) {
+#pragma unroll
+      for (int bb = 0; bb < 32; ++bb) nb[p][bb] = (32 * p + bb < MAXB) ? (uint32_t)(P[32 * p + bb] >> (32 * h)) : 0u;
+      transpose32(nb[p]);
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const Q old = fresh ? (Q)0 : cst[lane * kRow + k];
+      uint64_t mg = absq(old) | (uint64_t)nb[0][k];
+      if (QW == 2) mg |= (uint64_t)nb[QW - 1][k] << 32;
+      bool neg = old < 0;
+      if (old == (Q)0 && mg) {
+        const int j = B - bitlen64(mg);
+        if (j >= 0 && j < MAXB) {
+          const uint32_t pos = atomicAdd(&ptab[j * 64 + lane], 1u);
+          neg = pos < (uint32_t)(kSignWords * 64) && ((sw[pos >> 6] >> (pos & 63)) & 1ull);
+        }
       }
+      cst[lane * kRow + k] = neg ? (Q)(-(int64_t)mg) : (Q)mg;
     }
-    nm_r[it] = nm;
-    pl_r[it] = pl;
-    rk_r[it] = rk;
-    q_r[it] = qres;
-  }
-  __syncthreads();
-  for (int j = wave; j < k1 - k0; j += 4) {
-    const uint32_t v = wpre[j][lane];
-    const uint32_t incl = wave_incl_scan(v, lane);
-    wpre[j][lane] = (uint16_t)(incl - v);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int wl = wave + 4 * it;
-    const int64_t e = (chunk * 64 + wl) * 64 + lane;
-    if (e >= S.n) continue;
-    const Q qres = q_r[it];
-    const uint64_t m = absq(qres) | nm_r[it];
-    bool neg = qres < 0;
-    const int pl = pl_r[it];
-    if (pl >= 0) {
-      const uint64_t pos = (uint64_t)S.idx[(int64_t)pl * S.C + chunk] + wpre[pl - k0][wl] + rk_r[it];
-      const int64_t sw_i = S.pso[pl] + (int64_t)(pos >> 6);
-      const uint64_t sw = sw_i < S.sign_n ? S.sign[sw_i] : 0ull;
-      neg = (sw >> (pos & 63)) & 1ull;
-    }
-    dst[e] = neg ? (Q)(-(int64_t)m) : (Q)m;
+    __syncthreads();
+    unstage_half<Q>(dst, base, S.n, h, cst, lane);
+    __syncthreads();
   }
 }
 
@@ -766,9 +880,10 @@ __global__ __launch_bounds__(kThreads) void k_coarsest(const FlatSeg* __restrict
     const FlatSeg& S = segs[si];
     const Q* q = (const Q*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= S.n) break;
+      if (e >= S.n) continue;
       const double x = (double)mask_code<Q>(q[e], S.B, S.k) * S.delta;
       if (S.final_out)
         ((T*)S.dst)[e] = (T)x;
@@ -785,9 +900,10 @@ __global__ __launch_bounds__(kThreads) void k_inject(const FlatSeg* __restrict__
     const FlatSeg& S = segs[si];
     const double* xc = (const double*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= S.n) break;
+      if (e >= S.n) continue;
       const uint32_t r = fdiv((uint32_t)e, S.f2);
       const uint32_t i2 = (uint32_t)e - r * (uint32_t)S.dm[2];
       const uint32_t i0 = fdiv(r, S.f1);
@@ -817,9 +933,10 @@ __global__ __launch_bounds__(kThreads) void k_recon(const ReconSeg* __restrict__
     const int ax = L.ax;
     const Q* q = (const Q*)S.q;
     const int64_t cs[3] = {(int64_t)S.cm1 * S.cm2, (int64_t)S.cm2, 1};
+#pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) break;
+      if (e >= total) continue;
       int i[3];
       lattice_node(L, (uint32_t)e, i);
       const int j = i[ax];
@@ -896,7 +1013,7 @@ template <typename Q>
 hipError_t launch_encode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
-  hipLaunchKernelGGL((k_encode<Q, MAXB>), dim3((unsigned)chunks), dim3(kThreads), 0, s, sd, ns);
+  hipLaunchKernelGGL((k_encode<Q, MAXB>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   return hipGetLastError();
 }
 hipError_t launch_scan(const StreamDev* sd, const int32_t* job_s, const int32_t* job_j, int njobs, int64_t* totals,
@@ -914,7 +1031,7 @@ template <typename Q>
 hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
-  hipLaunchKernelGGL((k_decode<Q, MAXB>), dim3((unsigned)chunks), dim3(kThreads), 0, s, sd, ns);
+  hipLaunchKernelGGL((k_decode<Q, MAXB>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   return hipGetLastError();
 }
 template <typename T, typename Q>
