@@ -322,7 +322,7 @@ struct TableBuilder {
 
 enum LaunchKind {
   K_RANGE, K_GATHER, K_COEF0, K_COEF1, K_COARSE0, K_COARSE1, K_CDF, K_CDI0, K_CDI1,
-  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON
+  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2
 };
 
 struct Launch {
@@ -341,6 +341,28 @@ int64_t assign_blocks(std::vector<S>& segs, std::function<int64_t(const S&)> cou
   for (S& s : segs) {
     s.blk_begin = b;
     b += (count(s) + kBlockElems - 1) / kBlockElems;
+  }
+  return b;
+}
+
+// Per-level pass geometry of level l (the coarser level is l + 1).
+LevelSeg level_seg(const apc_handle* h, int l) {
+  const Geo& g = h->geo;
+  LevelSeg s{};
+  for (int a = 0; a < 3; ++a) {
+    s.m[a] = g.m[l][a];
+    s.mc[a] = g.m[l + 1][a];
+  }
+  s.degree = h->scheme.degree;
+  s.nt1 = (s.m[1] + kLvlT1 - 1) / kLvlT1;
+  s.nt2 = (s.m[2] + kLvlT2 - 1) / kLvlT2;
+  return s;
+}
+int64_t assign_level_blocks(std::vector<LevelSeg>& segs) {
+  int64_t b = 0;
+  for (LevelSeg& s : segs) {
+    s.blk_begin = b;
+    b += (int64_t)s.nt1 * s.nt2 * ((s.m[0] + kLvlCH - 1) / kLvlCH);
   }
   return b;
 }
@@ -375,6 +397,12 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
         break;
       case K_INJECT: LAUNCH(l.name, l.bytes, st, launch_inject<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_RECON: LAUNCH(l.name, l.bytes, st, (launch_recon<T, Q>((const ReconSeg*)p, l.nseg, l.nblk, st))); break;
+      case K_LEVEL0:
+      case K_LEVEL1:
+      case K_LEVEL2:
+        LAUNCH(l.name, l.bytes, st,
+               (launch_level<T, Q>((const LevelSeg*)p, l.nseg, l.nblk, l.kind - K_LEVEL0, st)));
+        break;
       default: return fail(APC_E_INVALID, "unknown launch kind");
     }
   }
@@ -672,9 +700,8 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   const int nf = (int)H.size();
   const int P = sizeof(T) == 4 ? 29 : 52;
   struct Tmp {
-    DevBuf grids, codes, cdc, prb;
+    DevBuf grids, codes, cdc;
     std::vector<int64_t> goff;   // level -> offset in grids
-    std::vector<int64_t> proff;  // (level * 2 + region) -> offset in prb
     int64_t acc = 0;             // offset in the accumulator buffer
   };
   std::vector<Tmp> tmp(nf);
@@ -693,15 +720,6 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     APC_TRY(t.grids.alloc(sizeof(T) * (size_t)gtot));
     APC_TRY(t.codes.alloc(sizeof(Q) * (size_t)h->code_n));
     if (h->cd_n) APC_TRY(t.cdc.alloc(sizeof(Q) * (size_t)h->cd_n));
-    t.proff.assign((size_t)std::max(1, g.L) * 2, 0);
-    int64_t ptot = 0;
-    if (h->scheme.kind == APC_PER_LEVEL)
-      for (int l = 0; l < g.L - 1; ++l)
-        for (int r = 0; r < std::min(2, g.d - 1); ++r) {
-          t.proff[l * 2 + r] = ptot;
-          ptot += lat_count(lattice(g, l, r));
-        }
-    if (ptot) APC_TRY(t.prb.alloc(8 * (size_t)ptot));
     t.acc = nacc;
     nacc += 4 + (int64_t)h->meta.groups.size() + (int64_t)h->meta.streams.size();
   }
@@ -717,9 +735,25 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   }
   unsigned long long* acc = accb.as<unsigned long long>();
   auto grid_ptr = [&](int f, int l) -> const T* { return l == 0 ? X[f] : tmp[f].grids.template as<T>() + tmp[f].goff[l]; };
-  auto pr_ptrs = [&](int f, int l, double* pr[2]) {
-    for (int r = 0; r < 2; ++r)
-      pr[r] = tmp[f].prb.p ? tmp[f].prb.template as<double>() + tmp[f].proff[l * 2 + r] : nullptr;
+  // per-level fields: one tensor-product pass per level (all levels in one launch)
+  auto level_segs = [&](int mode, double& by) {
+    std::vector<LevelSeg> ls2;
+    for (int f = 0; f < nf; ++f) {
+      const apc_handle* h = H[f];
+      if (h->scheme.kind != APC_PER_LEVEL) continue;
+      for (int l = 0; l < h->geo.L - 1; ++l) {
+        LevelSeg c = level_seg(h, l);
+        c.src = grid_ptr(f, l);
+        const int gi = group_of(h->meta, l, 0);
+        c.gmax = acc + tmp[f].acc + 4 + gi;
+        c.k_shift = h->meta.groups[gi].k_shift;
+        for (int rho = 0; rho < h->geo.d; ++rho) c.q[rho] = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
+        const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
+        by += (double)n * (sizeof(T) + (mode == 1 ? sizeof(Q) : 0));
+        ls2.push_back(c);
+      }
+    }
+    return ls2;
   };
 
   // ---- tables of the first pass
@@ -756,22 +790,26 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     const int64_t b2 = assign_blocks<FlatSeg>(gs, [](const FlatSeg& s) { return s.n; });
     ls.push_back({K_RANGE, tb.add(rs), (int)rs.size(), b1, 0, nb, "range"});
     ls.push_back({K_GATHER, tb.add(gs), (int)gs.size(), b2, 0, gb, "subsample"});
-    for (int rho = 0; rho < 3; ++rho) {
+    {
+      double by = 0;
+      std::vector<LevelSeg> lv = level_segs(0, by);
+      const int64_t nbk = assign_level_blocks(lv);
+      if (!lv.empty()) ls.push_back({K_LEVEL0, tb.add(lv), (int)lv.size(), nbk, 0, by, "coef_max"});
+    }
+    for (int rho = 0; rho < 3; ++rho) {  // per-region fields: one pass per region
       std::vector<CoefSeg> cs;
       double by = 0;
       for (int f = 0; f < nf; ++f) {
         const apc_handle* h = H[f];
-        if (rho >= h->geo.d) continue;
-        const bool per_level = h->scheme.kind == APC_PER_LEVEL;
+        if (rho >= h->geo.d || h->scheme.kind == APC_PER_LEVEL) continue;
         for (int l = 0; l < h->geo.L - 1; ++l) {
           CoefSeg c{};
-          double* pr[2];
-          pr_ptrs(f, l, pr);
-          c.ra = region_args(h, l, rho, per_level, pr, per_level, per_level);
+          double* pr[2] = {nullptr, nullptr};
+          c.ra = region_args(h, l, rho, false, pr, false, false);
           if (lat_count(c.ra.lat) == 0) continue;
           c.G = grid_ptr(f, l);
           c.gmax = acc + tmp[f].acc + 4 + group_of(h->meta, l, rho);
-          by += (double)lat_count(c.ra.lat) * (sizeof(T) + (c.ra.pr_out ? 8 : 0));
+          by += (double)lat_count(c.ra.lat) * sizeof(T);
           cs.push_back(c);
         }
       }
@@ -825,23 +863,27 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   TableBuilder tb2;
   ls.clear();
   bool any_cd = false;
+  {
+    double by = 0;
+    std::vector<LevelSeg> lv = level_segs(1, by);
+    const int64_t nbk = assign_level_blocks(lv);
+    if (!lv.empty()) ls.push_back({K_LEVEL1, tb2.add(lv), (int)lv.size(), nbk, 0, by, "coef_quant"});
+  }
   for (int rho = 0; rho < 3; ++rho) {
     std::vector<CoefSeg> cs;
     double by = 0;
     for (int f = 0; f < nf; ++f) {
       const apc_handle* h = H[f];
-      if (rho >= h->geo.d) continue;
-      const bool per_level = h->scheme.kind == APC_PER_LEVEL;
+      if (rho >= h->geo.d || h->scheme.kind == APC_PER_LEVEL) continue;
       for (int l = 0; l < h->geo.L - 1; ++l) {
         CoefSeg c{};
-        double* pr[2];
-        pr_ptrs(f, l, pr);
-        c.ra = region_args(h, l, rho, per_level, pr, per_level, per_level);
+        double* pr[2] = {nullptr, nullptr};
+        c.ra = region_args(h, l, rho, false, pr, false, false);
         if (lat_count(c.ra.lat) == 0) continue;
         c.G = grid_ptr(f, l);
         c.codes = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
         c.k_shift = h->meta.groups[group_of(h->meta, l, rho)].k_shift;
-        by += (double)lat_count(c.ra.lat) * (sizeof(T) + sizeof(Q) + (c.ra.pr_out ? 8 : 0));
+        by += (double)lat_count(c.ra.lat) * (sizeof(T) + sizeof(Q));
         cs.push_back(c);
       }
     }
@@ -1071,8 +1113,10 @@ size_t work_bytes(const apc_handle* h) {
   size_t b = 8 * (size_t)((int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2]) + 256;
   if (L >= 2) {
     b += 2 * (8 * (size_t)((int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2]) + 256);
-    if (g.d >= 2) b += 8 * (size_t)lat_count(lattice(g, 0, 0)) + 256;
-    if (g.d >= 3) b += 8 * (size_t)lat_count(lattice(g, 0, 1)) + 256;
+    if (h->scheme.kind != APC_PER_LEVEL) {  // earlier regions' values (per-region reconstruction)
+      if (g.d >= 2) b += 8 * (size_t)lat_count(lattice(g, 0, 0)) + 256;
+      if (g.d >= 3) b += 8 * (size_t)lat_count(lattice(g, 0, 1)) + 256;
+    }
     b += qsize(h->dtype) * (size_t)h->cdreg_n + 256;
   }
   return b;
@@ -1093,8 +1137,10 @@ WorkPtrs carve_work(const apc_handle* h, void* base) {
     const size_t n1 = (size_t)((int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2]);
     w.xb[0] = (double*)take(8 * n1);
     w.xb[1] = (double*)take(8 * n1);
-    if (g.d >= 2) w.pr[0] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 0)));
-    if (g.d >= 3) w.pr[1] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 1)));
+    if (h->scheme.kind != APC_PER_LEVEL) {
+      if (g.d >= 2) w.pr[0] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 0)));
+      if (g.d >= 3) w.pr[1] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 1)));
+    }
     w.cdreg = take(qsize(h->dtype) * (size_t)h->cdreg_n);
   }
   return w;
@@ -1119,8 +1165,10 @@ apc_status ensure_work(apc_handle* h) {
     const int64_t n1 = (int64_t)g.m[1][0] * g.m[1][1] * g.m[1][2];
     APC_TRY(h->xb[0].alloc(8 * (size_t)n1));
     APC_TRY(h->xb[1].alloc(8 * (size_t)n1));
-    if (g.d >= 2) APC_TRY(h->pr[0].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 0)))));
-    if (g.d >= 3) APC_TRY(h->pr[1].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 1)))));
+    if (h->scheme.kind != APC_PER_LEVEL) {  // earlier regions' values (per-region reconstruction)
+      if (g.d >= 2) APC_TRY(h->pr[0].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 0)))));
+      if (g.d >= 3) APC_TRY(h->pr[1].alloc(8 * (size_t)std::max<int64_t>(1, lat_count(lattice(g, 0, 1)))));
+    }
     if (h->cdreg_n) APC_TRY(h->cdreg.alloc(qs * (size_t)h->cdreg_n));
   }
   HIP_TRY(hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming));
@@ -1231,6 +1279,33 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   for (int l = L - 2; l >= 0; --l) {
     double* xout = l > 0 ? w.xb[l % 2] : nullptr;
     void* dst = l > 0 ? (void*)xout : (void*)out;
+    if (per_level) {  // one tensor-product pass writes the whole level grid
+      LevelSeg c = level_seg(h, l);
+      c.src = xin;
+      c.out = dst;
+      c.final_out = l == 0 ? 1 : 0;
+      c.delta = m.groups[group_of(m, l, 0)].delta;
+      const bool cd0 = l == 0 && !h->cd.empty();
+      const int s = cd0 ? -1 : stream_of(m, l, 0);
+      for (int rho = 0; rho < d; ++rho) {
+        if (cd0) {
+          c.q[rho] = (Q*)w.cdreg + h->cd[rho].reg_off;
+          c.B[rho] = 64;
+          c.k[rho] = 64;
+        } else {
+          c.q[rho] = h->codes.as<Q>() + h->region_off[l * 3 + rho];
+          c.B[rho] = m.streams[s].B;
+          c.k[rho] = planes[s];
+        }
+      }
+      std::vector<LevelSeg> cs{c};
+      const int64_t nbk = assign_level_blocks(cs);
+      const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
+      const double by = (double)n * (sizeof(Q) + (l ? 8 : sizeof(T))) + 8.0 * c.mc[0] * c.mc[1] * c.mc[2];
+      ls.push_back({K_LEVEL2, tb.add(cs), 1, nbk, 0, by, "recon"});
+      xin = xout;
+      continue;
+    }
     {
       FlatSeg c{};
       c.src = xin;

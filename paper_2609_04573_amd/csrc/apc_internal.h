@@ -11,6 +11,7 @@ namespace apc {
 
 constexpr int kChunk = 4096;        // codes per chunk (sign index granularity)
 constexpr int kBlockElems = 4096;   // lattice elements per work block (16 per thread)
+constexpr int kLvlT1 = 16, kLvlT2 = 64, kLvlCH = 32;  // per-level pass: tile rows, columns, planes
 
 enum AxisKind : int32_t { AX_ALL = 0, AX_ODD = 1, AX_EVEN = 2 };
 
@@ -66,6 +67,25 @@ struct ReconSeg {
   int64_t blk_begin;
   int32_t B, k;         // truncation of the codes to k of B planes
   int32_t final_out;    // 1: out is the T output field
+  int32_t pad;
+};
+
+// Per-level tensor-product pass over one (field, level): tiles of 16 x 64
+// points of (axis 1, axis 2) by runs of 32 planes along axis 0.
+struct LevelSeg {
+  int32_t m[3];          // level grid dims
+  int32_t mc[3];         // coarser level grid dims
+  int32_t degree;
+  int32_t nt1, nt2;      // tiles along axes 1 and 2
+  int32_t final_out;     // reconstruction: out is the T output field
+  int64_t blk_begin;     // first work block (tiles x runs) of this segment
+  const void* src;       // refactor: level grid (T); reconstruction: coarser level (double)
+  void* out;             // reconstruction: level grid (double), or the T output field
+  void* q[3];            // codes of regions 0, 1, 2 (Q*, lattice order)
+  int32_t B[3], k[3];    // reconstruction: truncation of each region's codes
+  double delta;          // reconstruction: quantization step
+  unsigned long long* gmax;  // max pass: max |c| of the level (double bits)
+  int32_t k_shift;       // quantization: P - E
   int32_t pad;
 };
 
@@ -135,6 +155,8 @@ template <typename T>
 hipError_t launch_gather(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
+template <typename T, typename Q>
+hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename Q>

@@ -321,6 +321,171 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
   }
 }
 
+// ------------------------------------------------- per-level tensor-product pass
+// Per-level interpolation predicts every point of level l from the coarser
+// level by one-dimensional stencils along axis 2, then axis 1, then axis 0,
+// each pass reading the predictions of the previous one (tensor product).
+// A block owns a 16 x 64 tile of (axis 1, axis 2) and walks a run of 32
+// planes along axis 0: each coarse plane is upsampled in-plane through LDS
+// (axis 2, then axis 1) into registers, a four-plane register window gives
+// the axis-0 stencil, and every point of the level is visited once.
+// MODE 0: max |x - p| of the level.  MODE 1: codes q = rint(c * 2^k_shift)
+// into the three region lattices.  MODE 2: x = p + Delta * q' on the level
+// grid (coarse points are copied).
+constexpr int kT1 = kLvlT1, kT2 = kLvlT2, kCH = kLvlCH;
+constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
+
+template <typename T, typename Q, int MODE>
+__global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  __shared__ double ctile[kC1 * kC2];
+  __shared__ double u2[kC1 * kT2];
+  int cur = -1;
+  double am = 0.0;
+  const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int si = find_seg(segs, nseg, b);
+    if (MODE == 0 && si != cur) {
+      if (cur >= 0) {
+        const double m = block_max(am);
+        if (tid == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
+      }
+      cur = si;
+      am = 0.0;
+    }
+    const LevelSeg& S = segs[si];
+    const int m0 = S.m[0], m1 = S.m[1], m2 = S.m[2];
+    const int mc0 = S.mc[0], mc1 = S.mc[1], mc2 = S.mc[2];
+    const int deg = S.degree;
+    int lb = (int)(b - S.blk_begin);
+    const int t2 = (lb % S.nt2) * kT2;
+    lb /= S.nt2;
+    const int t1 = (lb % S.nt1) * kT1;
+    const int f0a = (lb / S.nt1) * kCH;
+    const int f0b = min(m0, f0a + kCH);
+    const int c1s = t1 / 2 - 1, c2s = t2 / 2 - 1;
+
+    // in-plane geometry of this thread (constant along axis 0)
+    const int f2 = t2 + col;
+    const bool odd2 = f2 & 1;
+    const int sk2 = odd2 ? stencil_kind(f2, m2, deg) : 0;
+    const int tc2 = odd2 ? ((f2 - 1) >> 1) - c2s : (f2 >> 1) - c2s;  // coarse tile column of f2 (or left of it)
+    int sk1[4], tr1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f1 = t1 + 4 * rg + i;
+      sk1[i] = (f1 & 1) ? stencil_kind(f1, m1, deg) : 0;
+      tr1[i] = (f1 & 1) ? ((f1 - 1) >> 1) - c1s : (f1 >> 1) - c1s;
+    }
+
+    // prediction of coarse plane cc on the thread's four points (block-uniform call)
+    auto plane = [&](int cc, double (&u)[4]) {
+      __syncthreads();
+      for (int e = tid; e < kC1 * kC2; e += kThreads) {
+        const int r = e / kC2, k = e - r * kC2;
+        const int c1 = c1s + r, c2 = c2s + k;
+        double v = 0.0;
+        if (c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2) {
+          if (MODE == 2)
+            v = ((const double*)S.src)[((int64_t)cc * mc1 + c1) * mc2 + c2];
+          else
+            v = (double)((const T*)S.src)[((int64_t)(2 * cc) * m1 + 2 * c1) * m2 + 2 * c2];
+        }
+        ctile[e] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int r = rg + 4 * k;
+        if (r < kC1) {
+          const double* row = ctile + r * kC2 + tc2;
+          u2[r * kT2 + col] = odd2 ? stencil_eval(sk2, [&](int o) { return row[(o + 1) / 2]; }) : row[0];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double* cp = u2 + tr1[i] * kT2 + col;
+        u[i] = ((t1 + 4 * rg + i) & 1) ? stencil_eval(sk1[i], [&](int o) { return cp[((o + 1) / 2) * kT2]; }) : cp[0];
+      }
+    };
+
+    // one point of fine plane f0 with prediction p
+    auto point = [&](int f0, int i, double p) {
+      const int f1 = t1 + 4 * rg + i;
+      if (f1 >= m1 || f2 >= m2) return;
+      const int64_t o = ((int64_t)f0 * m1 + f1) * m2 + f2;
+      int rr;
+      int64_t li;
+      if (f0 & 1) {
+        rr = 2;
+        li = ((int64_t)(f0 >> 1) * m1 + f1) * m2 + f2;
+      } else if (f1 & 1) {
+        rr = 1;
+        li = ((int64_t)(f0 >> 1) * (m1 >> 1) + (f1 >> 1)) * m2 + f2;
+      } else if (odd2) {
+        rr = 0;
+        li = ((int64_t)(f0 >> 1) * ((m1 + 1) >> 1) + (f1 >> 1)) * (m2 >> 1) + (f2 >> 1);
+      } else {
+        if (MODE == 2) {  // a coarse point: its reconstructed value
+          if (S.final_out)
+            ((T*)S.out)[o] = (T)p;
+          else
+            ((double*)S.out)[o] = p;
+        }
+        return;
+      }
+      if (MODE == 2) {
+        const double dq = (double)mask_code<Q>(((const Q*)S.q[rr])[li], S.B[rr], S.k[rr]) * S.delta;
+        const double x = p + dq;
+        if (S.final_out)
+          ((T*)S.out)[o] = (T)x;
+        else
+          ((double*)S.out)[o] = x;
+      } else {
+        const double c = (double)((const T*)S.src)[o] - p;
+        if (MODE == 0)
+          am = fmax(am, fabs(c));
+        else
+          ((Q*)S.q[rr])[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
+      }
+    };
+
+    double w0[4], w1[4], w2[4], w3[4];  // predictions of coarse planes c-1, c, c+1, c+2
+    const int cb = f0a >> 1;
+    if (cb - 1 >= 0) plane(cb - 1, w0);
+    plane(cb, w1);
+    if (cb + 1 < mc0) plane(cb + 1, w2);
+    if (cb + 2 < mc0) plane(cb + 2, w3);
+    for (int c = cb; 2 * c < f0b; ++c) {
+      if (c > cb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          w0[i] = w1[i];
+          w1[i] = w2[i];
+          w2[i] = w3[i];
+        }
+        if (c + 2 < mc0) plane(c + 2, w3);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) point(2 * c, i, w1[i]);
+      if (2 * c + 1 < f0b) {
+        const int sk0 = stencil_kind(2 * c + 1, m0, deg);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double p = stencil_eval(sk0, [&](int o) {
+            return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
+          });
+          point(2 * c + 1, i, p);
+        }
+      }
+    }
+  }
+  if (MODE == 0 && cur >= 0) {
+    const double m = block_max(am);
+    if (tid == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 // Coarsest level: the values themselves are the coefficients.
 template <typename T, typename Q, int MODE>
 __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
@@ -988,6 +1153,12 @@ hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hi
   APC_LAUNCH((k_coef<T, Q, 1>), nblk, segs, nseg, nblk);
 }
 template <typename T, typename Q>
+hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s) {
+  if (mode == 0) APC_LAUNCH((k_level<T, Q, 0>), nblk, segs, nseg, nblk);
+  if (mode == 1) APC_LAUNCH((k_level<T, Q, 1>), nblk, segs, nseg, nblk);
+  APC_LAUNCH((k_level<T, Q, 2>), nblk, segs, nseg, nblk);
+}
+template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s) {
   if (mode == 0) APC_LAUNCH((k_coarse<T, Q, 0>), nblk, segs, nseg, nblk);
   APC_LAUNCH((k_coarse<T, Q, 1>), nblk, segs, nseg, nblk);
@@ -1055,6 +1226,8 @@ template hipError_t launch_gather<float>(const FlatSeg*, int, int64_t, hipStream
 template hipError_t launch_gather<double>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_coef<float, int32_t>(const CoefSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coef<double, int64_t>(const CoefSeg*, int, int64_t, int, hipStream_t);
+template hipError_t launch_level<float, int32_t>(const LevelSeg*, int, int64_t, int, hipStream_t);
+template hipError_t launch_level<double, int64_t>(const LevelSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coarse<float, int32_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coarse<double, int64_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_cd_forward<int32_t>(const CDSeg*, int, int64_t, int, hipStream_t);
