@@ -19,6 +19,11 @@ namespace apc {
 namespace {
 
 constexpr int kThreads = 256;
+
+// Global-memory pointers: the tables hand out generic pointers, and loads
+// through them would compile to flat instructions (which also wait on LDS
+// traffic); every kernel re-types them into the global address space.
+#define GAS __attribute__((address_space(1)))
 constexpr int kPerThread = kBlockElems / kThreads;  // 16
 constexpr unsigned kMaxGrid = 4096;
 
@@ -165,7 +170,7 @@ __device__ __forceinline__ double predict_from_region(const RegionArgs& ra, int 
   int tt[3];
   for (int a = 0; a < 3; ++a) tt[a] = (a == ax) ? (j - 1) >> 1 : lat_of(i[a], PL.kind[a]);
   const int64_t ls[3] = {(int64_t)PL.c[1] * PL.c[2], (int64_t)PL.c[2], 1};
-  const double* pp = ra.pr[rp] + tt[0] * ls[0] + tt[1] * ls[1] + tt[2] * ls[2];
+  const GAS double* pp = (const GAS double*)ra.pr[rp] + tt[0] * ls[0] + tt[1] * ls[1] + tt[2] * ls[2];
   const int64_t st = ls[ax];
   return stencil_eval(sk, [&](int o) { return pp[((o + 1) / 2) * st]; });
 }
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ 
       bad = false;
     }
     const FlatSeg& S = segs[si];
-    const T* x = (const T*)S.src;
+    const GAS T* x = (const GAS T*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     auto take = [&](double v) {
       if (!isfinite(v)) {
@@ -220,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ 
     constexpr int VW = 16 / sizeof(T);  // elements per 16-byte load
     if (e0 + kBlockElems <= S.n && (((uintptr_t)(x + e0)) & 15) == 0) {
       typedef T vec_t __attribute__((ext_vector_type(VW)));
-      const vec_t* xv = (const vec_t*)(x + e0);
+      const GAS vec_t* xv = (const GAS vec_t*)(x + e0);
       vec_t r[kPerThread / VW];
 #pragma unroll
       for (int it = 0; it < kPerThread / VW; ++it) r[it] = xv[it * kThreads + threadIdx.x];
@@ -245,8 +250,8 @@ __global__ __launch_bounds__(kThreads) void k_gather(const FlatSeg* __restrict__
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     const FlatSeg& S = segs[si];
-    const T* src = (const T*)S.src;
-    T* dst = (T*)S.dst;
+    const GAS T* src = (const GAS T*)S.src;
+    GAS T* dst = (GAS T*)S.dst;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     for (int it = 0; it < kPerThread; ++it) {
       const int64_t e = e0 + it * kThreads + threadIdx.x;
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
     const CoefSeg& S = segs[si];
     const RegionArgs& ra = S.ra;
     const Lattice& L = ra.lat;
-    const T* G = (const T*)S.G;
+    const GAS T* G = (const GAS T*)S.G;
     const int64_t total = lat_count(L);
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     const int ax = L.ax;
@@ -301,18 +306,18 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
       const int rp = ra.per_level ? source_region(ra, i) : -1;
       double p;
       if (rp < 0) {
-        const T* g = G + gbase;
+        const GAS T* g = G + gbase;
         const int64_t st = gs[ax];
         p = stencil_eval(sk, [&](int o) { return (double)g[o * st]; });
       } else {
         p = predict_from_region(ra, rp, i, ax, j, sk);
       }
-      if (ra.pr_out) ra.pr_out[e] = p;
+      if (ra.pr_out) ((GAS double*)ra.pr_out)[e] = p;
       const double c = xv - p;
       if (MODE == 0)
         am = fmax(am, fabs(c));
       else
-        ((Q*)S.codes)[e] = (Q)(long long)rint(ldexp(c, S.k_shift));
+        ((GAS Q*)S.codes)[e] = (Q)(long long)rint(ldexp(c, S.k_shift));
     }
   }
   if (MODE == 0 && cur >= 0) {
@@ -386,9 +391,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         double v = 0.0;
         if (c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2) {
           if (MODE == 2)
-            v = ((const double*)S.src)[((int64_t)cc * mc1 + c1) * mc2 + c2];
+            v = ((const GAS double*)S.src)[((int64_t)cc * mc1 + c1) * mc2 + c2];
           else
-            v = (double)((const T*)S.src)[((int64_t)(2 * cc) * m1 + 2 * c1) * m2 + 2 * c2];
+            v = (double)((const GAS T*)S.src)[((int64_t)(2 * cc) * m1 + 2 * c1) * m2 + 2 * c2];
         }
         ctile[e] = v;
       }
@@ -428,25 +433,25 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       } else {
         if (MODE == 2) {  // a coarse point: its reconstructed value
           if (S.final_out)
-            ((T*)S.out)[o] = (T)p;
+            ((GAS T*)S.out)[o] = (T)p;
           else
-            ((double*)S.out)[o] = p;
+            ((GAS double*)S.out)[o] = p;
         }
         return;
       }
       if (MODE == 2) {
-        const double dq = (double)mask_code<Q>(((const Q*)S.q[rr])[li], S.B[rr], S.k[rr]) * S.delta;
+        const double dq = (double)mask_code<Q>(((const GAS Q*)S.q[rr])[li], S.B[rr], S.k[rr]) * S.delta;
         const double x = p + dq;
         if (S.final_out)
-          ((T*)S.out)[o] = (T)x;
+          ((GAS T*)S.out)[o] = (T)x;
         else
-          ((double*)S.out)[o] = x;
+          ((GAS double*)S.out)[o] = x;
       } else {
-        const double c = (double)((const T*)S.src)[o] - p;
+        const double c = (double)((const GAS T*)S.src)[o] - p;
         if (MODE == 0)
           am = fmax(am, fabs(c));
         else
-          ((Q*)S.q[rr])[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
+          ((GAS Q*)S.q[rr])[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
       }
     };
 
@@ -502,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
       am = 0.0;
     }
     const FlatSeg& S = segs[si];
-    const T* G = (const T*)S.src;
+    const GAS T* G = (const GAS T*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
 #pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
       if (MODE == 0)
         am = fmax(am, fabs(v));
       else
-        ((Q*)S.dst)[e] = (Q)(long long)rint(ldexp(v, S.k_shift));
+        ((GAS Q*)S.dst)[e] = (Q)(long long)rint(ldexp(v, S.k_shift));
     }
   }
   if (MODE == 0 && cur >= 0) {
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
       am[0] = am[1] = am[2] = 0.0;
     }
     const CDSeg& S = segs[si];
-    const Q* R = (const Q*)S.R;
+    const GAS Q* R = (const GAS Q*)S.R;
     const int64_t total = (int64_t)S.c[0] * S.c[1] * S.c[2];
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     const int Nu = S.c[U], Nv = S.c[V];
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
         }
         res = T(u, v) - p;
       }
-      ((Q*)S.S[cls])[class_rank<A, U, V>(cls, t, S.c)] = (Q)res;
+      ((GAS Q*)S.S[cls])[class_rank<A, U, V>(cls, t, S.c)] = (Q)res;
       am[cls] = fmax(am[cls], (double)(res < 0 ? -res : res));
     }
   }
@@ -640,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     const CDSeg& S = segs[si];
-    Q* out = (Q*)S.Rout;
+    GAS Q* out = (GAS Q*)S.Rout;
     const int64_t total = (int64_t)S.c[0] * S.c[1] * S.c[2];
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     const int Nu = S.c[U], Nv = S.c[V];
@@ -660,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
         int tt[3] = {t[0], t[1], t[2]};
         tt[U] = uu;
         tt[V] = vv;
-        return (int64_t)mask_code<Q>(((const Q*)S.S[c])[class_rank<A, U, V>(c, tt, S.c)], S.B[c], S.k[c]);
+        return (int64_t)mask_code<Q>(((const GAS Q*)S.S[c])[class_rank<A, U, V>(c, tt, S.c)], S.B[c], S.k[c]);
       };
       if (PHASE == 0) {
         int64_t val;
@@ -739,7 +744,7 @@ constexpr int kRow = 33;  // LDS row pitch (codes) of the half-word staging tile
 // Stage half h of every 64-code word of a chunk in LDS: row r holds codes
 // base + 64 r + 32 h + [0, 32) (zero past n).  Lane pairs of rows per load.
 template <typename Q>
-__device__ __forceinline__ void stage_half(const Q* src, int64_t base, int64_t n, int h, Q* cst, int lane) {
+__device__ __forceinline__ void stage_half(const GAS Q* src, int64_t base, int64_t n, int h, Q* cst, int lane) {
   const int k = lane & 31, rr = lane >> 5;
 #pragma unroll 8
   for (int it = 0; it < 32; ++it) {
@@ -749,7 +754,7 @@ __device__ __forceinline__ void stage_half(const Q* src, int64_t base, int64_t n
   }
 }
 template <typename Q>
-__device__ __forceinline__ void unstage_half(Q* dst, int64_t base, int64_t n, int h, const Q* cst, int lane) {
+__device__ __forceinline__ void unstage_half(GAS Q* dst, int64_t base, int64_t n, int h, const Q* cst, int lane) {
   const int k = lane & 31, rr = lane >> 5;
 #pragma unroll 8
   for (int it = 0; it < 32; ++it) {
@@ -780,7 +785,8 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  const Q* src = (const Q*)S.codes;
+  const GAS Q* src = (const GAS Q*)S.codes;
+  GAS uint64_t* mag = (GAS uint64_t*)S.mag;
   const int B = S.B;
   const int64_t base = chunk * kChunk;
   const int64_t w = chunk * 64 + lane;
@@ -826,12 +832,12 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     if (b >= B) continue;
     const int j = B - 1 - b;
     const uint64_t pw = P[b];
-    if (w < S.M) S.mag[(int64_t)j * S.M + w] = pw;
+    if (w < S.M) mag[(int64_t)j * S.M + w] = pw;
     const uint32_t c = (uint32_t)__popcll(pw & ~sig);
     sig |= pw;
     const uint32_t incl = wave_incl_scan(c, lane);
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (lane == 0) S.cnt[(int64_t)j * S.C + chunk] = tot;
+    if (lane == 0) ((GAS uint32_t*)S.cnt)[(int64_t)j * S.C + chunk] = tot;
     ptab[j * 64 + lane] = toff + incl - c;
     toff += tot;
   }
@@ -848,7 +854,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     }
   }
   __syncthreads();
-  S.stage[chunk * 64 + lane] = sstage[lane];
+  ((GAS uint64_t*)S.stage)[chunk * 64 + lane] = sstage[lane];
 }
 
 // Exclusive scan of the per-chunk counts of one (stream, plane): the index
@@ -859,8 +865,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   const int job = blockIdx.x;
   const StreamDev& S = sd[job_s[job]];
   const int j = job_j[job];
-  const uint32_t* c = S.cnt + (int64_t)j * S.C;
-  uint32_t* o = S.idx + (int64_t)j * S.C;
+  const GAS uint32_t* c = (const GAS uint32_t*)S.cnt + (int64_t)j * S.C;
+  GAS uint32_t* o = (GAS uint32_t*)S.idx + (int64_t)j * S.C;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint64_t carry = 0;
   for (int64_t base = 0; base < S.C; base += kThreads) {
@@ -881,7 +887,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   if (threadIdx.x == 0) totals[job] = (int64_t)carry;
 }
 
-__device__ __forceinline__ uint64_t extract_bits(const uint64_t* w, int pos, int nb, int nwords) {
+__device__ __forceinline__ uint64_t extract_bits(const GAS uint64_t* w, int pos, int nb, int nwords) {
   const int w0 = pos >> 6, sh = pos & 63;
   uint64_t v = w[w0] >> sh;
   if (sh && w0 + 1 < nwords) v |= w[w0 + 1] << (64 - sh);
@@ -897,13 +903,15 @@ __global__ __launch_bounds__(kThreads) void k_sign_move(const StreamDev* __restr
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  const uint64_t* st = S.stage + chunk * 64;
+  const GAS uint64_t* st = (const GAS uint64_t*)S.stage + chunk * 64;
   unsigned long long* sign = (unsigned long long*)S.sign;
+  const GAS uint32_t* cnt = (const GAS uint32_t*)S.cnt;
+  const GAS uint32_t* idx = (const GAS uint32_t*)S.idx;
   int64_t sbit = 0;
   for (int j = 0; j < S.B; ++j) {
-    const int64_t cj = S.cnt[(int64_t)j * S.C + chunk];
+    const int64_t cj = cnt[(int64_t)j * S.C + chunk];
     if (cj == 0) continue;
-    const int64_t D = S.pso[j] * 64 + (int64_t)S.idx[(int64_t)j * S.C + chunk];
+    const int64_t D = ((const GAS int64_t*)S.pso)[j] * 64 + (int64_t)idx[(int64_t)j * S.C + chunk];
     const int64_t first = D >> 6, last = (D + cj - 1) >> 6;
     for (int64_t w = first + threadIdx.x; w <= last; w += kThreads) {
       const int64_t lo = max(w * 64, D), hi = min(w * 64 + 64, D + cj);
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(kThreads) void k_sign_move(const StreamDev* __restr
       const uint64_t bits = extract_bits(st, (int)(lo - D + sbit), nb, 64);
       const uint64_t val = bits << (lo - w * 64);
       if (nb == 64)
-        sign[w] = val;
+        ((GAS unsigned long long*)sign)[w] = val;
       else if (val)
         atomicOr(&sign[w], (unsigned long long)val);
     }
@@ -939,7 +947,11 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  Q* dst = (Q*)S.codes;
+  GAS Q* dst = (GAS Q*)S.codes;
+  const GAS uint64_t* mag = (const GAS uint64_t*)S.mag;
+  const GAS uint32_t* idx = (const GAS uint32_t*)S.idx;
+  const GAS uint64_t* sign = (const GAS uint64_t*)S.sign;
+  const GAS int64_t* pso = (const GAS int64_t*)S.pso;
   const int B = S.B, k0 = S.k0, k1 = S.k1;
   const bool fresh = S.fresh != 0;
   const int64_t base = chunk * kChunk;
@@ -962,7 +974,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = B - 1 - b;
-    P[b] = (b < B && j >= k0 && j < k1 && w < S.M) ? S.mag[(int64_t)j * S.M + w] : 0ull;
+    P[b] = (b < B && j >= k0 && j < k1 && w < S.M) ? mag[(int64_t)j * S.M + w] : 0ull;
   }
   // newcomer counts -> cursors; runs of sign words to fetch
   uint32_t woff = 0;
@@ -976,7 +988,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
     sig |= pw;
     const uint32_t incl = wave_incl_scan(c, lane);
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    const int64_t D = S.pso[j] * 64 + (int64_t)S.idx[(int64_t)j * S.C + chunk];
+    const int64_t D = pso[j] * 64 + (int64_t)idx[(int64_t)j * S.C + chunk];
     const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
     ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl - c;
     if (lane == 0) {
@@ -999,7 +1011,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
         hi = mid - 1;
     }
     const int64_t gw = pw0[lo] + (int64_t)(i - pwoff[lo]);
-    sw[i] = (gw >= 0 && gw < S.sign_n) ? S.sign[gw] : 0ull;
+    sw[i] = (gw >= 0 && gw < S.sign_n) ? sign[gw] : 0ull;
   }
   __syncthreads();
 
@@ -1043,7 +1055,7 @@ __global__ __launch_bounds__(kThreads) void k_coarsest(const FlatSeg* __restrict
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     const FlatSeg& S = segs[si];
-    const Q* q = (const Q*)S.src;
+    const GAS Q* q = (const GAS Q*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
 #pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
@@ -1051,9 +1063,9 @@ __global__ __launch_bounds__(kThreads) void k_coarsest(const FlatSeg* __restrict
       if (e >= S.n) continue;
       const double x = (double)mask_code<Q>(q[e], S.B, S.k) * S.delta;
       if (S.final_out)
-        ((T*)S.dst)[e] = (T)x;
+        ((GAS T*)S.dst)[e] = (T)x;
       else
-        ((double*)S.dst)[e] = x;
+        ((GAS double*)S.dst)[e] = x;
     }
   }
 }
@@ -1063,7 +1075,7 @@ __global__ __launch_bounds__(kThreads) void k_inject(const FlatSeg* __restrict__
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     const FlatSeg& S = segs[si];
-    const double* xc = (const double*)S.src;
+    const GAS double* xc = (const GAS double*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
 #pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
@@ -1075,9 +1087,9 @@ __global__ __launch_bounds__(kThreads) void k_inject(const FlatSeg* __restrict__
       const uint32_t i1 = r - i0 * (uint32_t)S.dm[1];
       const int64_t o = ((int64_t)(2 * i0) * S.dst_m1 + 2 * i1) * S.dst_m2 + 2 * i2;
       if (S.final_out)
-        ((T*)S.dst)[o] = (T)xc[e];
+        ((GAS T*)S.dst)[o] = (T)xc[e];
       else
-        ((double*)S.dst)[o] = xc[e];
+        ((GAS double*)S.dst)[o] = xc[e];
     }
   }
 }
@@ -1096,7 +1108,7 @@ __global__ __launch_bounds__(kThreads) void k_recon(const ReconSeg* __restrict__
     const int64_t total = lat_count(L);
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
     const int ax = L.ax;
-    const Q* q = (const Q*)S.q;
+    const GAS Q* q = (const GAS Q*)S.q;
     const int64_t cs[3] = {(int64_t)S.cm1 * S.cm2, (int64_t)S.cm2, 1};
 #pragma unroll 4
     for (int it = 0; it < kPerThread; ++it) {
@@ -1111,7 +1123,7 @@ __global__ __launch_bounds__(kThreads) void k_recon(const ReconSeg* __restrict__
       if (rp < 0) {
         int ci[3];
         for (int a = 0; a < 3; ++a) ci[a] = (a == ax) ? (j - 1) >> 1 : i[a] >> 1;
-        const double* pc = S.xc + ci[0] * cs[0] + ci[1] * cs[1] + ci[2] * cs[2];
+        const GAS double* pc = (const GAS double*)S.xc + ci[0] * cs[0] + ci[1] * cs[1] + ci[2] * cs[2];
         const int64_t st = cs[ax];
         p = stencil_eval(sk, [&](int o) { return pc[((o + 1) / 2) * st]; });
       } else {
@@ -1121,10 +1133,10 @@ __global__ __launch_bounds__(kThreads) void k_recon(const ReconSeg* __restrict__
       const double x = p + dq;
       const int64_t o = ((int64_t)i[0] * L.m[1] + i[1]) * L.m[2] + i[2];
       if (S.final_out)
-        ((T*)S.out)[o] = (T)x;
+        ((GAS T*)S.out)[o] = (T)x;
       else
-        ((double*)S.out)[o] = x;
-      if (ra.pr_out) ra.pr_out[e] = ra.per_level ? p : x;
+        ((GAS double*)S.out)[o] = x;
+      if (ra.pr_out) ((GAS double*)ra.pr_out)[e] = ra.per_level ? p : x;
     }
   }
 }
