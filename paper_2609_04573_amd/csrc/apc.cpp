@@ -367,6 +367,16 @@ int64_t assign_level_blocks(std::vector<LevelSeg>& segs) {
   return b;
 }
 
+// Decomposition passes: one wave per lattice row, four rows a block.
+int64_t assign_cd_blocks(std::vector<CDSeg>& segs) {
+  int64_t b = 0;
+  for (CDSeg& s : segs) {
+    s.blk_begin = b;
+    b += ((int64_t)s.c[0] * s.c[1] + 3) / 4;
+  }
+  return b;
+}
+
 template <typename T, typename Q>
 apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st) {
   for (const Launch& l : ls) {
@@ -930,7 +940,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     }
     if (cs.empty()) continue;
     any_cd = true;
-    const int64_t nbk = assign_blocks<CDSeg>(cs, [](const CDSeg& c) { return (int64_t)c.c[0] * c.c[1] * c.c[2]; });
+    const int64_t nbk = assign_cd_blocks(cs);
     ls.push_back({K_CDF, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
   }
   DevBuf tab2;
@@ -1253,7 +1263,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       cs.push_back(c);
     }
     if (!cs.empty()) {
-      const int64_t nbk = assign_blocks<CDSeg>(cs, [](const CDSeg& c) { return (int64_t)c.c[0] * c.c[1] * c.c[2]; });
+      const int64_t nbk = assign_cd_blocks(cs);
       const size_t off = tb.add(cs);
       const int a3 = h->cd[0].a;
       ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});

@@ -11,6 +11,7 @@
 // the operation order of the stencil definitions (the library is built with
 // -ffp-contract=off, so no multiply-add is fused).  Codes are exact integers.
 #include <algorithm>
+#include <type_traits>
 
 #include "apc_internal.h"
 
@@ -527,7 +528,6 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
 }
 
 // ---------------------------------------------- coefficient decomposition
-__device__ __forceinline__ int64_t avg2(int64_t x, int64_t y) { return (x + y) >> 1; }
 
 struct Rng1 {
   int64_t c4, c2, call;
@@ -540,98 +540,135 @@ __device__ __forceinline__ int64_t cls_count(int cls, Rng1 ru, Rng1 rv) {
   const int64_t h2 = ru.c4 * rv.c4, h1 = ru.c2 * rv.c2, all = ru.call * rv.call;
   return cls == 0 ? h2 : (cls == 1 ? h1 - h2 : all - h1);
 }
-// Position of lattice element t among the elements of class cls, in
-// row-major order of the lattice.
-template <int A, int U, int V>
-__device__ __forceinline__ int64_t class_rank(int cls, const int t[3], const int32_t c[3]) {
-  int64_t total = 0;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    Rng1 r[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) r[a] = (a < s) ? rng_single(t[a]) : (a == s ? rng_prefix(t[a]) : rng_prefix(c[a]));
-    total += r[A].call * cls_count(cls, r[U], r[V]);
-  }
-  return total;
-}
 __device__ __forceinline__ int cd_class(int u, int v) {
   if ((u & 3) == 0 && (v & 3) == 0) return 0;
   if ((u & 1) == 0 && (v & 1) == 0) return 1;
   return 2;
 }
 
-__device__ __forceinline__ void cd_coords(const CDSeg& S, uint32_t e, int t[3]) {
-  const uint32_t r = fdiv(e, S.f2);
-  t[2] = (int)(e - r * (uint32_t)S.c[2]);
-  const uint32_t t0 = fdiv(r, S.f1);
-  t[1] = (int)(r - t0 * (uint32_t)S.c[1]);
-  t[0] = (int)t0;
+// Row walk of a region lattice: each wave takes whole lattice rows (t0, t1)
+// with lanes along t2, so the stacking axis a and the (u, v) plane give
+// per-row (uniform) stream offsets and every class stream is written in runs.
+constexpr int kCDRowsPerBlock = kThreads / 64;
+
+// Elements of class cls before the start of row (t0, t1) in row-major
+// lattice order, i.e. the rank of (t0, t1, 0) in the class-cls stream.
+template <int A>
+__device__ __forceinline__ int64_t cd_row_base(const CDSeg& S, int cls, int t0, int t1) {
+  if (A == 0)  // (a, u, v) = (t0, t1, t2)
+    return (int64_t)t0 * cls_count(cls, rng_prefix(S.c[1]), rng_prefix(S.c[2])) +
+           cls_count(cls, rng_prefix(t1), rng_prefix(S.c[2]));
+  if (A == 1)  // (u, a, v) = (t0, t1, t2)
+    return (int64_t)S.c[1] * cls_count(cls, rng_prefix(t0), rng_prefix(S.c[2])) +
+           (int64_t)t1 * cls_count(cls, rng_single(t0), rng_prefix(S.c[2]));
+  // (u, v, a) = (t0, t1, t2): whole rows belong to one class
+  return (int64_t)S.c[2] * (cls_count(cls, rng_prefix(t0), rng_prefix(S.c[1])) +
+                            cls_count(cls, rng_single(t0), rng_prefix(t1)));
+}
+// Elements of class cls in the row before column t2 (u is the row's plane
+// coordinate when v runs along the row).
+template <int A>
+__device__ __forceinline__ int64_t cd_in_row(int cls, int u, int t2) {
+  if (A == 2) return t2;
+  const int64_t u4 = (u & 3) == 0, u2 = (u & 1) == 0;
+  const int64_t c4 = (t2 + 3) >> 2, c2 = (t2 + 1) >> 1;
+  return cls == 0 ? u4 * c4 : (cls == 1 ? u2 * c2 - u4 * c4 : (int64_t)t2 - u2 * c2);
 }
 
-// Forward 2D integer lifting of each region lattice into S1/S2/S3.
-template <typename Q, int A, int U, int V>
+// Lifting arithmetic width: 32-bit codes stay below 2^30 in magnitude, so
+// their sums and residuals fit in int32.
+template <typename Q>
+using LiftT = typename std::conditional<sizeof(Q) == 4, int32_t, int64_t>::type;
+
+template <typename W>
+__device__ __forceinline__ W avgw(W x, W y) { return (x + y) >> 1; }
+
+// Prediction of an S2 point (u, v) from H2 values h(du, dv) at offsets in
+// multiples of 2 (Section V: stride-2 averages inside the stride-4 lattice).
+template <typename W, typename F>
+__device__ __forceinline__ W cd_pred_s2(int u, int v, int Nu, int Nv, F h) {
+  if ((u & 3) == 0) return (v + 2 <= Nv - 1) ? avgw<W>(h(0, -2), h(0, 2)) : h(0, -2);
+  auto Wr = [&](int du) -> W {
+    if ((v & 3) == 0) return h(du, 0);
+    return (v + 2 <= Nv - 1) ? avgw<W>(h(du, -2), h(du, 2)) : h(du, -2);
+  };
+  return (u + 2 <= Nu - 1) ? avgw<W>(Wr(-2), Wr(2)) : Wr(-2);
+}
+// Prediction of an S3 point from H1 values at offsets of 1.
+template <typename W, typename F>
+__device__ __forceinline__ W cd_pred_s3(int u, int v, int Nu, int Nv, F h) {
+  if ((u & 1) == 0) return (v + 1 <= Nv - 1) ? avgw<W>(h(0, -1), h(0, 1)) : h(0, -1);
+  auto Wr = [&](int du) -> W {
+    if ((v & 1) == 0) return h(du, 0);
+    return (v + 1 <= Nv - 1) ? avgw<W>(h(du, -1), h(du, 1)) : h(du, -1);
+  };
+  return (u + 1 <= Nu - 1) ? avgw<W>(Wr(-1), Wr(1)) : Wr(-1);
+}
+
+struct CDGeo {
+  int t0, t1;          // row
+  int Nu, Nv;
+  int64_t su, sv;      // lattice strides of u and v
+  int64_t rowoff;      // lattice offset of (t0, t1, 0)
+};
+template <int A>
+__device__ __forceinline__ CDGeo cd_geo(const CDSeg& S, uint32_t row) {
+  constexpr int U = A == 0 ? 1 : 0, V = A == 2 ? 1 : 2;
+  CDGeo g;
+  g.t0 = (int)fdiv(row, S.f1);
+  g.t1 = (int)(row - (uint32_t)g.t0 * (uint32_t)S.c[1]);
+  g.Nu = S.c[U];
+  g.Nv = S.c[V];
+  const int64_t st[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
+  g.su = st[U];
+  g.sv = st[V];
+  g.rowoff = (int64_t)row * S.c[2];
+  return g;
+}
+
+// Forward lifting of each region lattice into its S1/S2/S3 streams, with
+// the largest residual magnitude of each stream.
+template <typename Q, int A>
 __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using W = LiftT<Q>;
+  using UW = typename std::make_unsigned<W>::type;
   int cur = -1;
-  double am[3] = {0.0, 0.0, 0.0};
+  UW am[3] = {0, 0, 0};
   auto flush = [&](int si) {
     for (int c = 0; c < 3; ++c) {
-      const double m = block_max(am[c]);
+      const double m = block_max((double)am[c]);
       if (threadIdx.x == 0) atomicMax(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
     }
   };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     if (si != cur) {
       if (cur >= 0) flush(cur);
       cur = si;
-      am[0] = am[1] = am[2] = 0.0;
+      am[0] = am[1] = am[2] = 0;
     }
     const CDSeg& S = segs[si];
-    const GAS Q* R = (const GAS Q*)S.R;
-    const int64_t total = (int64_t)S.c[0] * S.c[1] * S.c[2];
-    const int64_t e0 = (b - S.blk_begin) * kBlockElems;
-    const int Nu = S.c[U], Nv = S.c[V];
-    const int64_t ls[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
-    const int64_t su = ls[U], sv = ls[V];
-#pragma unroll 4
-    for (int it = 0; it < kPerThread; ++it) {
-      const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) continue;
-      int t[3];
-      cd_coords(S, (uint32_t)e, t);
-      const int u = t[U], v = t[V];
-      auto T = [&](int uu, int vv) -> int64_t { return (int64_t)R[e + (int64_t)(uu - u) * su + (int64_t)(vv - v) * sv]; };
+    const int64_t row = (b - S.blk_begin) * kCDRowsPerBlock + wave;
+    if (row >= (int64_t)S.c[0] * S.c[1]) continue;
+    const CDGeo g = cd_geo<A>(S, (uint32_t)row);
+    const int64_t base[3] = {cd_row_base<A>(S, 0, g.t0, g.t1), cd_row_base<A>(S, 1, g.t0, g.t1),
+                             cd_row_base<A>(S, 2, g.t0, g.t1)};
+    const GAS Q* R = (const GAS Q*)S.R + g.rowoff;
+    for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
+      const int u = A == 0 ? g.t1 : g.t0, v = A == 2 ? g.t1 : t2;
+      const GAS Q* Rp = R + t2;
+      auto T = [&](int du, int dv) -> W { return (W)Rp[du * g.su + dv * g.sv]; };
       const int cls = cd_class(u, v);
-      int64_t res;
-      if (cls == 0) {
-        res = T(u, v);
-      } else if (cls == 1) {
-        int64_t p;
-        if ((u & 3) == 0) {
-          p = (v + 2 <= Nv - 1) ? avg2(T(u, v - 2), T(u, v + 2)) : T(u, v - 2);
-        } else {
-          auto W = [&](int uu) -> int64_t {
-            if ((v & 3) == 0) return T(uu, v);
-            return (v + 2 <= Nv - 1) ? avg2(T(uu, v - 2), T(uu, v + 2)) : T(uu, v - 2);
-          };
-          p = (u + 2 <= Nu - 1) ? avg2(W(u - 2), W(u + 2)) : W(u - 2);
-        }
-        res = T(u, v) - p;
-      } else {
-        int64_t p;
-        if ((u & 1) == 0) {
-          p = (v + 1 <= Nv - 1) ? avg2(T(u, v - 1), T(u, v + 1)) : T(u, v - 1);
-        } else {
-          auto W0 = [&](int uu) -> int64_t {
-            if ((v & 1) == 0) return T(uu, v);
-            return (v + 1 <= Nv - 1) ? avg2(T(uu, v - 1), T(uu, v + 1)) : T(uu, v - 1);
-          };
-          p = (u + 1 <= Nu - 1) ? avg2(W0(u - 1), W0(u + 1)) : W0(u - 1);
-        }
-        res = T(u, v) - p;
-      }
-      ((GAS Q*)S.S[cls])[class_rank<A, U, V>(cls, t, S.c)] = (Q)res;
-      am[cls] = fmax(am[cls], (double)(res < 0 ? -res : res));
+      W res = T(0, 0);
+      if (cls == 1)
+        res -= cd_pred_s2<W>(u, v, g.Nu, g.Nv, T);
+      else if (cls == 2)
+        res -= cd_pred_s3<W>(u, v, g.Nu, g.Nv, T);
+      const int64_t bs = cls == 0 ? base[0] : (cls == 1 ? base[1] : base[2]);
+      ((GAS Q*)S.S[cls])[bs + cd_in_row<A>(cls, u, t2)] = (Q)res;
+      const UW mag = res < 0 ? (UW)(-res) : (UW)res;
+      am[cls] = am[cls] > mag ? am[cls] : mag;
     }
   }
   if (cur >= 0) flush(cur);
@@ -640,67 +677,77 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
 // Inverse lifting.  PHASE 0 rebuilds the stride-2 points (S1 and S2 classes)
 // from the truncated S1/S2 streams; PHASE 1 rebuilds the rest from S3 and the
 // stride-2 points written by phase 0.
-template <typename Q, int PHASE, int A, int U, int V>
+template <typename Q, int PHASE, int A>
 __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using W = LiftT<Q>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     const CDSeg& S = segs[si];
-    GAS Q* out = (GAS Q*)S.Rout;
-    const int64_t total = (int64_t)S.c[0] * S.c[1] * S.c[2];
-    const int64_t e0 = (b - S.blk_begin) * kBlockElems;
-    const int Nu = S.c[U], Nv = S.c[V];
-    const int64_t ls[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
-    const int64_t su = ls[U], sv = ls[V];
-#pragma unroll 4
-    for (int it = 0; it < kPerThread; ++it) {
-      const int64_t e = e0 + it * kThreads + threadIdx.x;
-      if (e >= total) continue;
-      int t[3];
-      cd_coords(S, (uint32_t)e, t);
-      const int u = t[U], v = t[V];
-      const int cls = cd_class(u, v);
-      if (PHASE == 0 && cls == 2) continue;
-      if (PHASE == 1 && cls != 2) continue;
-      auto stream_val = [&](int c, int uu, int vv) -> int64_t {
-        int tt[3] = {t[0], t[1], t[2]};
-        tt[U] = uu;
-        tt[V] = vv;
-        return (int64_t)mask_code<Q>(((const GAS Q*)S.S[c])[class_rank<A, U, V>(c, tt, S.c)], S.B[c], S.k[c]);
-      };
-      if (PHASE == 0) {
-        int64_t val;
-        if (cls == 0) {
-          val = stream_val(0, u, v);
+    const int64_t row = (b - S.blk_begin) * kCDRowsPerBlock + wave;
+    if (row >= (int64_t)S.c[0] * S.c[1]) continue;
+    const CDGeo g = cd_geo<A>(S, (uint32_t)row);
+    const int ur = A == 0 ? g.t1 : g.t0;  // u of the row
+    if (PHASE == 0 && (ur & 1)) continue;
+    if (A == 2 && PHASE == 0 && (g.t1 & 1)) continue;
+    if (A == 2 && PHASE == 1 && !((ur & 1) || (g.t1 & 1))) continue;
+    GAS Q* out = (GAS Q*)S.Rout + g.rowoff;
+    const GAS Q* S1 = (const GAS Q*)S.S[0];
+    auto m1 = [&](Q x) -> W { return (W)mask_code<Q>(x, S.B[0], S.k[0]); };
+    if (PHASE == 0) {
+      // S1 offsets of the rows at u - 2, u, u + 2 (v along the row), or of
+      // the rows (u + du, v + dv) when whole rows share one class
+      int64_t b0[3], b0v[3][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int du = 2 * k - 2;
+        b0[k] = 0;
+        if (A != 2) {
+          const int uu = ur + du;
+          if (uu >= 0 && uu < g.Nu) b0[k] = A == 0 ? cd_row_base<A>(S, 0, g.t0, uu) : cd_row_base<A>(S, 0, uu, g.t1);
         } else {
-          auto H2 = [&](int uu, int vv) -> int64_t { return stream_val(0, uu, vv); };
-          int64_t p;
-          if ((u & 3) == 0) {
-            p = (v + 2 <= Nv - 1) ? avg2(H2(u, v - 2), H2(u, v + 2)) : H2(u, v - 2);
-          } else {
-            auto W = [&](int uu) -> int64_t {
-              if ((v & 3) == 0) return H2(uu, v);
-              return (v + 2 <= Nv - 1) ? avg2(H2(uu, v - 2), H2(uu, v + 2)) : H2(uu, v - 2);
-            };
-            p = (u + 2 <= Nu - 1) ? avg2(W(u - 2), W(u + 2)) : W(u - 2);
+#pragma unroll
+          for (int kv = 0; kv < 3; ++kv) {
+            const int uu = ur + du, vv = g.t1 + 2 * kv - 2;
+            b0v[k][kv] = (uu >= 0 && uu < g.Nu && vv >= 0 && vv < g.Nv) ? cd_row_base<A>(S, 0, uu, vv) : 0;
           }
-          val = stream_val(1, u, v) + p;
         }
-        out[e] = (Q)val;
-      } else {
-        auto H1 = [&](int uu, int vv) -> int64_t {
-          return (int64_t)out[e + (int64_t)(uu - u) * su + (int64_t)(vv - v) * sv];
-        };
-        int64_t p;
-        if ((u & 1) == 0) {
-          p = (v + 1 <= Nv - 1) ? avg2(H1(u, v - 1), H1(u, v + 1)) : H1(u, v - 1);
-        } else {
-          auto W0 = [&](int uu) -> int64_t {
-            if ((v & 1) == 0) return H1(uu, v);
-            return (v + 1 <= Nv - 1) ? avg2(H1(uu, v - 1), H1(uu, v + 1)) : H1(uu, v - 1);
+      }
+      const int64_t base1 = cd_row_base<A>(S, 1, g.t0, g.t1);
+      for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
+        const int u = ur, v = A == 2 ? g.t1 : t2;
+        if (v & 1) continue;
+        const int cls = cd_class(u, v);
+        W val;
+        if (A != 2) {
+          auto h2 = [&](int du, int dv) -> W {
+            const int64_t bb = du < 0 ? b0[0] : (du > 0 ? b0[2] : b0[1]);
+            return m1(S1[bb + ((v + dv) >> 2)]);
           };
-          p = (u + 1 <= Nu - 1) ? avg2(W0(u - 1), W0(u + 1)) : W0(u - 1);
+          val = cls == 0 ? h2(0, 0)
+                         : (W)mask_code<Q>(((const GAS Q*)S.S[1])[base1 + cd_in_row<A>(1, u, t2)], S.B[1], S.k[1]) +
+                               cd_pred_s2<W>(u, v, g.Nu, g.Nv, h2);
+        } else {
+          auto h2 = [&](int du, int dv) -> W {
+            const int ku = du < 0 ? 0 : (du > 0 ? 2 : 1), kv = dv < 0 ? 0 : (dv > 0 ? 2 : 1);
+            return m1(S1[b0v[ku][kv] + t2]);
+          };
+          val = cls == 0 ? h2(0, 0)
+                         : (W)mask_code<Q>(((const GAS Q*)S.S[1])[base1 + t2], S.B[1], S.k[1]) +
+                               cd_pred_s2<W>(u, v, g.Nu, g.Nv, h2);
         }
-        out[e] = (Q)(stream_val(2, u, v) + p);
+        out[t2] = (Q)val;
+      }
+    } else {
+      const int64_t base2 = cd_row_base<A>(S, 2, g.t0, g.t1);
+      for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
+        const int u = ur, v = A == 2 ? g.t1 : t2;
+        if (!((u & 1) || (v & 1))) continue;
+        const GAS Q* op = out + t2;
+        auto h1 = [&](int du, int dv) -> W { return (W)op[du * g.su + dv * g.sv]; };
+        const W val = (W)mask_code<Q>(((const GAS Q*)S.S[2])[base2 + cd_in_row<A>(2, u, t2)], S.B[2], S.k[2]) +
+                      cd_pred_s3<W>(u, v, g.Nu, g.Nv, h1);
+        out[t2] = (Q)val;
       }
     }
   }
@@ -887,7 +934,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   if (threadIdx.x == 0) totals[job] = (int64_t)carry;
 }
 
-__device__ __forceinline__ uint64_t extract_bits(const GAS uint64_t* w, int pos, int nb, int nwords) {
+// Bits [pos, pos + nb) of a little-endian bit string held in words w.
+__device__ __forceinline__ uint64_t extract_bits(const uint64_t* w, int pos, int nb, int nwords) {
   const int w0 = pos >> 6, sh = pos & 63;
   uint64_t v = w[w0] >> sh;
   if (sh && w0 + 1 < nwords) v |= w[w0 + 1] << (64 - sh);
@@ -895,35 +943,50 @@ __device__ __forceinline__ uint64_t extract_bits(const GAS uint64_t* w, int pos,
   return v;
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Move each chunk's staged sign bits to their place in the stream's sign
-// section (dense, plane-major).  Words shared with a neighbouring chunk are
-// combined with atomic OR; whole words are stored.
-__global__ __launch_bounds__(kThreads) void k_sign_move(const StreamDev* __restrict__ sd, int ns) {
+// section (dense, plane-major); one wave per chunk.  Lane j fetches plane j's
+// count and destination at once, a wave scan gives each plane's offset in
+// the staging, and the words are moved plane by plane.  Words shared with a
+// neighbouring chunk are combined with atomic OR; whole words are stored.
+__global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ sd, int ns) {
+  __shared__ uint64_t st[64];
   const int64_t gch = blockIdx.x;
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  const GAS uint64_t* st = (const GAS uint64_t*)S.stage + chunk * 64;
+  const int lane = threadIdx.x;
   unsigned long long* sign = (unsigned long long*)S.sign;
-  const GAS uint32_t* cnt = (const GAS uint32_t*)S.cnt;
-  const GAS uint32_t* idx = (const GAS uint32_t*)S.idx;
-  int64_t sbit = 0;
+  st[lane] = ((const GAS uint64_t*)S.stage)[chunk * 64 + lane];
+  uint32_t cj = 0;
+  int64_t Dj = 0;
+  if (lane < S.B) {
+    cj = ((const GAS uint32_t*)S.cnt)[(int64_t)lane * S.C + chunk];
+    Dj = ((const GAS int64_t*)S.pso)[lane] * 64 + (int64_t)((const GAS uint32_t*)S.idx)[(int64_t)lane * S.C + chunk];
+  }
+  const uint32_t sbj = wave_incl_scan(cj, lane) - cj;
+  __syncthreads();
   for (int j = 0; j < S.B; ++j) {
-    const int64_t cj = cnt[(int64_t)j * S.C + chunk];
-    if (cj == 0) continue;
-    const int64_t D = ((const GAS int64_t*)S.pso)[j] * 64 + (int64_t)idx[(int64_t)j * S.C + chunk];
-    const int64_t first = D >> 6, last = (D + cj - 1) >> 6;
-    for (int64_t w = first + threadIdx.x; w <= last; w += kThreads) {
-      const int64_t lo = max(w * 64, D), hi = min(w * 64 + 64, D + cj);
+    const int64_t c = (uint32_t)__builtin_amdgcn_readlane((int)cj, j);
+    if (c == 0) continue;
+    const int64_t D = readlane64(Dj, j);
+    const int sbit = __builtin_amdgcn_readlane((int)sbj, j);
+    const int64_t first = D >> 6, last = (D + c - 1) >> 6;
+    for (int64_t w = first + lane; w <= last; w += 64) {
+      const int64_t lo = max(w * 64, D), hi = min(w * 64 + 64, D + c);
       const int nb = (int)(hi - lo);
-      const uint64_t bits = extract_bits(st, (int)(lo - D + sbit), nb, 64);
+      const uint64_t bits = extract_bits(st, (int)(lo - D) + sbit, nb, 64);
       const uint64_t val = bits << (lo - w * 64);
       if (nb == 64)
         ((GAS unsigned long long*)sign)[w] = val;
       else if (val)
         atomicOr(&sign[w], (unsigned long long)val);
     }
-    sbit += cj;
   }
 }
 
@@ -1177,20 +1240,20 @@ hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, 
 }
 template <typename Q>
 hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, hipStream_t s) {
-  if (a == 0) APC_LAUNCH((k_cd_forward<Q, 0, 1, 2>), nblk, segs, nseg, nblk);
-  if (a == 1) APC_LAUNCH((k_cd_forward<Q, 1, 0, 2>), nblk, segs, nseg, nblk);
-  APC_LAUNCH((k_cd_forward<Q, 2, 0, 1>), nblk, segs, nseg, nblk);
+  if (a == 0) APC_LAUNCH((k_cd_forward<Q, 0>), nblk, segs, nseg, nblk);
+  if (a == 1) APC_LAUNCH((k_cd_forward<Q, 1>), nblk, segs, nseg, nblk);
+  APC_LAUNCH((k_cd_forward<Q, 2>), nblk, segs, nseg, nblk);
 }
 template <typename Q>
 hipError_t launch_cd_inverse(const CDSeg* segs, int nseg, int64_t nblk, int a, int phase, hipStream_t s) {
   if (phase == 0) {
-    if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 0, 0, 1, 2>), nblk, segs, nseg, nblk);
-    if (a == 1) APC_LAUNCH((k_cd_inverse<Q, 0, 1, 0, 2>), nblk, segs, nseg, nblk);
-    APC_LAUNCH((k_cd_inverse<Q, 0, 2, 0, 1>), nblk, segs, nseg, nblk);
+    if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 0, 0>), nblk, segs, nseg, nblk);
+    if (a == 1) APC_LAUNCH((k_cd_inverse<Q, 0, 1>), nblk, segs, nseg, nblk);
+    APC_LAUNCH((k_cd_inverse<Q, 0, 2>), nblk, segs, nseg, nblk);
   }
-  if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 1, 0, 1, 2>), nblk, segs, nseg, nblk);
-  if (a == 1) APC_LAUNCH((k_cd_inverse<Q, 1, 1, 0, 2>), nblk, segs, nseg, nblk);
-  APC_LAUNCH((k_cd_inverse<Q, 1, 2, 0, 1>), nblk, segs, nseg, nblk);
+  if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 1, 0>), nblk, segs, nseg, nblk);
+  if (a == 1) APC_LAUNCH((k_cd_inverse<Q, 1, 1>), nblk, segs, nseg, nblk);
+  APC_LAUNCH((k_cd_inverse<Q, 1, 2>), nblk, segs, nseg, nblk);
 }
 template <typename Q>
 hipError_t launch_encode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
@@ -1207,7 +1270,7 @@ hipError_t launch_scan(const StreamDev* sd, const int32_t* job_s, const int32_t*
 }
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sign_move, dim3((unsigned)chunks), dim3(kThreads), 0, s, sd, ns);
+  hipLaunchKernelGGL(k_sign_move, dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   return hipGetLastError();
 }
 template <typename Q>
