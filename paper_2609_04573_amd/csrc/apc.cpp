@@ -356,13 +356,17 @@ LevelSeg level_seg(const apc_handle* h, int l) {
   s.degree = h->scheme.degree;
   s.nt1 = (s.m[1] + kLvlT1 - 1) / kLvlT1;
   s.nt2 = (s.m[2] + kLvlT2 - 1) / kLvlT2;
+  // runs along axis 0: as long as possible while the level still spreads
+  // over enough blocks to fill the device
+  s.ch = kLvlCH;
+  while (s.ch > 2 && (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch) < 2048) s.ch /= 2;
   return s;
 }
 int64_t assign_level_blocks(std::vector<LevelSeg>& segs) {
   int64_t b = 0;
   for (LevelSeg& s : segs) {
     s.blk_begin = b;
-    b += (int64_t)s.nt1 * s.nt2 * ((s.m[0] + kLvlCH - 1) / kLvlCH);
+    b += (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch);
   }
   return b;
 }

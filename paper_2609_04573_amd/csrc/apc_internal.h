@@ -11,7 +11,7 @@ namespace apc {
 
 constexpr int kChunk = 4096;        // codes per chunk (sign index granularity)
 constexpr int kBlockElems = 4096;   // lattice elements per work block (16 per thread)
-constexpr int kLvlT1 = 16, kLvlT2 = 64, kLvlCH = 32;  // per-level pass: tile rows, columns, planes
+constexpr int kLvlT1 = 16, kLvlT2 = 64, kLvlCH = 32;  // per-level pass: tile rows, columns, longest run
 
 enum AxisKind : int32_t { AX_ALL = 0, AX_ODD = 1, AX_EVEN = 2 };
 
@@ -71,7 +71,7 @@ struct ReconSeg {
 };
 
 // Per-level tensor-product pass over one (field, level): tiles of 16 x 64
-// points of (axis 1, axis 2) by runs of 32 planes along axis 0.
+// points of (axis 1, axis 2) by runs of ch planes along axis 0.
 struct LevelSeg {
   int32_t m[3];          // level grid dims
   int32_t mc[3];         // coarser level grid dims
@@ -86,7 +86,7 @@ struct LevelSeg {
   double delta;          // reconstruction: quantization step
   unsigned long long* gmax;  // max pass: max |c| of the level (double bits)
   int32_t k_shift;       // quantization: P - E
-  int32_t pad;
+  int32_t ch;            // planes per run along axis 0 (even)
 };
 
 // Flat segments: range pass, compact grids, coarsest level, injection.

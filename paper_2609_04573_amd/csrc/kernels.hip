@@ -331,18 +331,23 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // Per-level interpolation predicts every point of level l from the coarser
 // level by one-dimensional stencils along axis 2, then axis 1, then axis 0,
 // each pass reading the predictions of the previous one (tensor product).
-// A block owns a 16 x 64 tile of (axis 1, axis 2) and walks a run of 32
-// planes along axis 0: each coarse plane is upsampled in-plane through LDS
+// A block owns a 16 x 64 tile of (axis 1, axis 2) and walks a run of up to
+// 32 planes along axis 0 (shorter runs on small levels, for parallelism): each coarse plane is upsampled in-plane through LDS
 // (axis 2, then axis 1) into registers, a four-plane register window gives
-// the axis-0 stencil, and every point of the level is visited once.
+// the axis-0 stencil, and every point of the level is visited once.  The
+// coarse tile of the next plane and the point values (or codes) of the
+// current planes are fetched one step ahead, so their latency overlaps the
+// LDS passes.
 // MODE 0: max |x - p| of the level.  MODE 1: codes q = rint(c * 2^k_shift)
 // into the three region lattices.  MODE 2: x = p + Delta * q' on the level
 // grid (coarse points are copied).
-constexpr int kT1 = kLvlT1, kT2 = kLvlT2, kCH = kLvlCH;
+constexpr int kT1 = kLvlT1, kT2 = kLvlT2;
 constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
+constexpr int kCPer = (kC1 * kC2 + kThreads - 1) / kThreads;  // coarse tile entries per thread
 
 template <typename T, typename Q, int MODE>
 __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using V = typename std::conditional<MODE == 2, Q, T>::type;  // per-point input: code or value
   __shared__ double ctile[kC1 * kC2];
   __shared__ double u2[kC1 * kT2];
   int cur = -1;
@@ -366,9 +371,13 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
     const int t2 = (lb % S.nt2) * kT2;
     lb /= S.nt2;
     const int t1 = (lb % S.nt1) * kT1;
-    const int f0a = (lb / S.nt1) * kCH;
-    const int f0b = min(m0, f0a + kCH);
+    const int f0a = (lb / S.nt1) * S.ch;
+    const int f0b = min(m0, f0a + S.ch);
     const int c1s = t1 / 2 - 1, c2s = t2 / 2 - 1;
+    // per-region operands, held in registers (a lane picks one by its region)
+    Q* const qr[3] = {(Q*)S.q[0], (Q*)S.q[1], (Q*)S.q[2]};
+    const int Br[3] = {S.B[0], S.B[1], S.B[2]}, kr[3] = {S.k[0], S.k[1], S.k[2]};
+    auto qptr = [&](int rr) -> GAS Q* { return (GAS Q*)(rr == 0 ? qr[0] : (rr == 1 ? qr[1] : qr[2])); };
 
     // in-plane geometry of this thread (constant along axis 0)
     const int f2 = t2 + col;
@@ -382,22 +391,38 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       sk1[i] = (f1 & 1) ? stencil_kind(f1, m1, deg) : 0;
       tr1[i] = (f1 & 1) ? ((f1 - 1) >> 1) - c1s : (f1 >> 1) - c1s;
     }
+    // coarse tile entries of this thread: global offsets within a plane (-1 = outside the grid)
+    int64_t coff[kCPer];
+#pragma unroll
+    for (int k = 0; k < kCPer; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e / kC2, kk = e - r * kC2;
+      const int c1 = c1s + r, c2 = c2s + kk;
+      coff[k] = -1;
+      if (e < kC1 * kC2 && c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2)
+        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * m2 + 2 * c2;
+    }
+    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : (int64_t)2 * m1 * m2;  // coarse plane stride
+    double cpre[kCPer];
+    auto fetch_tile = [&](int cc) {
+#pragma unroll
+      for (int k = 0; k < kCPer; ++k) {
+        cpre[k] = 0.0;
+        if (coff[k] >= 0) {
+          const int64_t o = (int64_t)cc * cplane + coff[k];
+          cpre[k] = MODE == 2 ? ((const GAS double*)S.src)[o] : (double)((const GAS T*)S.src)[o];
+        }
+      }
+    };
 
-    // prediction of coarse plane cc on the thread's four points (block-uniform call)
+    // prediction of coarse plane cc (its tile is in cpre) on the thread's
+    // four points; fetches the tile of cc + 1.  Block-uniform call.
     auto plane = [&](int cc, double (&u)[4]) {
       __syncthreads();
-      for (int e = tid; e < kC1 * kC2; e += kThreads) {
-        const int r = e / kC2, k = e - r * kC2;
-        const int c1 = c1s + r, c2 = c2s + k;
-        double v = 0.0;
-        if (c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2) {
-          if (MODE == 2)
-            v = ((const GAS double*)S.src)[((int64_t)cc * mc1 + c1) * mc2 + c2];
-          else
-            v = (double)((const GAS T*)S.src)[((int64_t)(2 * cc) * m1 + 2 * c1) * m2 + 2 * c2];
-        }
-        ctile[e] = v;
-      }
+#pragma unroll
+      for (int k = 0; k < kCPer; ++k)
+        if (tid + k * kThreads < kC1 * kC2) ctile[tid + k * kThreads] = cpre[k];
+      if (cc + 1 < mc0) fetch_tile(cc + 1);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -415,13 +440,11 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       }
     };
 
-    // one point of fine plane f0 with prediction p
-    auto point = [&](int f0, int i, double p) {
+    // point (f0, i): region (-1 = a coarse point), lattice index, grid offset
+    auto locate = [&](int f0, int i, int& rr, int64_t& li, int64_t& o) -> bool {
       const int f1 = t1 + 4 * rg + i;
-      if (f1 >= m1 || f2 >= m2) return;
-      const int64_t o = ((int64_t)f0 * m1 + f1) * m2 + f2;
-      int rr;
-      int64_t li;
+      if (f0 >= f0b || f1 >= m1 || f2 >= m2) return false;
+      o = ((int64_t)f0 * m1 + f1) * m2 + f2;
       if (f0 & 1) {
         rr = 2;
         li = ((int64_t)(f0 >> 1) * m1 + f1) * m2 + f2;
@@ -432,38 +455,60 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         rr = 0;
         li = ((int64_t)(f0 >> 1) * ((m1 + 1) >> 1) + (f1 >> 1)) * (m2 >> 1) + (f2 >> 1);
       } else {
-        if (MODE == 2) {  // a coarse point: its reconstructed value
-          if (S.final_out)
-            ((GAS T*)S.out)[o] = (T)p;
-          else
-            ((GAS double*)S.out)[o] = p;
-        }
-        return;
+        rr = -1;
+        li = 0;
       }
+      return true;
+    };
+    // inputs of the two fine planes 2c and 2c + 1
+    V in[8];
+    auto fetch_points = [&](int c) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int rr;
+          int64_t li, o;
+          in[h * 4 + i] = (V)0;
+          if (locate(2 * c + h, i, rr, li, o) && rr >= 0)
+            in[h * 4 + i] = MODE == 2 ? (V)qptr(rr)[li] : (V)((const GAS T*)S.src)[o];
+        }
+    };
+    auto emit = [&](int f0, int i, double p, V v) {
+      int rr;
+      int64_t li, o;
+      if (!locate(f0, i, rr, li, o)) return;
       if (MODE == 2) {
-        const double dq = (double)mask_code<Q>(((const GAS Q*)S.q[rr])[li], S.B[rr], S.k[rr]) * S.delta;
-        const double x = p + dq;
+        double x = p;  // a coarse point keeps its reconstructed value
+        if (rr >= 0) {
+          const int B = rr == 0 ? Br[0] : (rr == 1 ? Br[1] : Br[2]);
+          const int k = rr == 0 ? kr[0] : (rr == 1 ? kr[1] : kr[2]);
+          x = p + (double)mask_code<Q>((Q)v, B, k) * S.delta;
+        }
         if (S.final_out)
           ((GAS T*)S.out)[o] = (T)x;
         else
           ((GAS double*)S.out)[o] = x;
-      } else {
-        const double c = (double)((const GAS T*)S.src)[o] - p;
+      } else if (rr >= 0) {
+        const double c = (double)v - p;
         if (MODE == 0)
           am = fmax(am, fabs(c));
         else
-          ((GAS Q*)S.q[rr])[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
+          qptr(rr)[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
       }
     };
 
     double w0[4], w1[4], w2[4], w3[4];  // predictions of coarse planes c-1, c, c+1, c+2
     const int cb = f0a >> 1;
+    fetch_tile(max(cb - 1, 0));
     if (cb - 1 >= 0) plane(cb - 1, w0);
     plane(cb, w1);
+    fetch_points(cb);
     if (cb + 1 < mc0) plane(cb + 1, w2);
     if (cb + 2 < mc0) plane(cb + 2, w3);
     for (int c = cb; 2 * c < f0b; ++c) {
       if (c > cb) {
+        fetch_points(c);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           w0[i] = w1[i];
@@ -473,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         if (c + 2 < mc0) plane(c + 2, w3);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) point(2 * c, i, w1[i]);
+      for (int i = 0; i < 4; ++i) emit(2 * c, i, w1[i], in[i]);
       if (2 * c + 1 < f0b) {
         const int sk0 = stencil_kind(2 * c + 1, m0, deg);
 #pragma unroll
@@ -481,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
           const double p = stencil_eval(sk0, [&](int o) {
             return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
           });
-          point(2 * c + 1, i, p);
+          emit(2 * c + 1, i, p, in[4 + i]);
         }
       }
     }
@@ -655,6 +700,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
     const int64_t base[3] = {cd_row_base<A>(S, 0, g.t0, g.t1), cd_row_base<A>(S, 1, g.t0, g.t1),
                              cd_row_base<A>(S, 2, g.t0, g.t1)};
     const GAS Q* R = (const GAS Q*)S.R + g.rowoff;
+    GAS Q* const so[3] = {(GAS Q*)S.S[0] + base[0], (GAS Q*)S.S[1] + base[1], (GAS Q*)S.S[2] + base[2]};
     for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
       const int u = A == 0 ? g.t1 : g.t0, v = A == 2 ? g.t1 : t2;
       const GAS Q* Rp = R + t2;
@@ -665,8 +711,8 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
         res -= cd_pred_s2<W>(u, v, g.Nu, g.Nv, T);
       else if (cls == 2)
         res -= cd_pred_s3<W>(u, v, g.Nu, g.Nv, T);
-      const int64_t bs = cls == 0 ? base[0] : (cls == 1 ? base[1] : base[2]);
-      ((GAS Q*)S.S[cls])[bs + cd_in_row<A>(cls, u, t2)] = (Q)res;
+      GAS Q* dst = cls == 0 ? so[0] : (cls == 1 ? so[1] : so[2]);
+      dst[cd_in_row<A>(cls, u, t2)] = (Q)res;
       const UW mag = res < 0 ? (UW)(-res) : (UW)res;
       am[cls] = am[cls] > mag ? am[cls] : mag;
     }
