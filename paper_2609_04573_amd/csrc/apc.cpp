@@ -322,7 +322,7 @@ struct TableBuilder {
 
 enum LaunchKind {
   K_RANGE, K_GATHER, K_COEF0, K_COEF1, K_COARSE0, K_COARSE1, K_CDF, K_CDI0, K_CDI1,
-  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2
+  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2, K_CDIT
 };
 
 struct Launch {
@@ -381,6 +381,17 @@ int64_t assign_cd_blocks(std::vector<CDSeg>& segs) {
   return b;
 }
 
+// One-pass inverse decomposition: tiles of 8 rows x 256 columns per slice.
+int64_t assign_cd_tile_blocks(std::vector<CDSeg>& segs, int a) {
+  int64_t b = 0;
+  for (CDSeg& s : segs) {
+    s.blk_begin = b;
+    const int64_t nu = s.c[a == 0 ? 1 : 0];
+    b += (int64_t)s.c[a] * ((nu + 7) / 8) * ((s.c[2] + 255) / 256);
+  }
+  return b;
+}
+
 template <typename T, typename Q>
 apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st) {
   for (const Launch& l : ls) {
@@ -402,6 +413,9 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
         break;
       case K_CDI1:
         LAUNCH(l.name, l.bytes, st, launch_cd_inverse<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 1, st));
+        break;
+      case K_CDIT:
+        LAUNCH(l.name, l.bytes, st, launch_cd_inverse<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 2, st));
         break;
       case K_ENCODE: LAUNCH(l.name, l.bytes, st, launch_encode<Q>((const StreamDev*)p, l.nseg, l.nblk, st)); break;
       case K_SIGN: LAUNCH(l.name, l.bytes, st, launch_sign_move((const StreamDev*)p, l.nseg, l.nblk, st)); break;
@@ -1267,11 +1281,16 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       cs.push_back(c);
     }
     if (!cs.empty()) {
-      const int64_t nbk = assign_cd_blocks(cs);
-      const size_t off = tb.add(cs);
       const int a3 = h->cd[0].a;
-      ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
-      ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+      if (a3 < 2) {  // v runs along lattice rows: one pass over row tiles
+        const int64_t nbk = assign_cd_tile_blocks(cs, a3);
+        ls.push_back({K_CDIT, tb.add(cs), (int)cs.size(), nbk, a3, by, "cd_inverse"});
+      } else {
+        const int64_t nbk = assign_cd_blocks(cs);
+        const size_t off = tb.add(cs);
+        ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+        ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+      }
     }
   }
   // coarsest level

@@ -124,7 +124,7 @@ struct StreamDev {
   void* codes;          // Q*, stream order
   uint64_t* mag;        // magnitude section (B*M words)
   uint32_t* idx;        // index section (B*C entries)
-  uint32_t* cnt;        // per-chunk counts scratch (B*C, refactor)
+  uint32_t* cnt;        // per-chunk counts scratch (C*B, chunk-major, refactor)
   uint64_t* stage;      // sign staging scratch (64 words per chunk, refactor)
   uint64_t* sign;       // sign section
   const int64_t* pso;   // per plane: sign words before it

@@ -628,26 +628,50 @@ using LiftT = typename std::conditional<sizeof(Q) == 4, int32_t, int64_t>::type;
 template <typename W>
 __device__ __forceinline__ W avgw(W x, W y) { return (x + y) >> 1; }
 
-// Prediction of an S2 point (u, v) from H2 values h(du, dv) at offsets in
-// multiples of 2 (Section V: stride-2 averages inside the stride-4 lattice).
-template <typename W, typename F>
-__device__ __forceinline__ W cd_pred_s2(int u, int v, int Nu, int Nv, F h) {
-  if ((u & 3) == 0) return (v + 2 <= Nv - 1) ? avgw<W>(h(0, -2), h(0, 2)) : h(0, -2);
-  auto Wr = [&](int du) -> W {
-    if ((v & 3) == 0) return h(du, 0);
-    return (v + 2 <= Nv - 1) ? avgw<W>(h(du, -2), h(du, 2)) : h(du, -2);
-  };
-  return (u + 2 <= Nu - 1) ? avgw<W>(Wr(-2), Wr(2)) : Wr(-2);
+// Neighbour pattern of a lifting prediction: rows r0 (and r1 if hr), columns
+// c0 (and c1 if hc), in (u, v) offsets; the prediction averages over columns
+// and then over rows (Section V).
+struct CDNb {
+  int r0, r1, c0, c1;
+  bool hr, hc;
+};
+// S2 points from stride-4 (H2) neighbours at distance 2
+__device__ __forceinline__ CDNb cd_nb_s2(int u, int v, int Nu, int Nv) {
+  CDNb n;
+  if ((u & 3) == 0) {
+    n.r0 = n.r1 = 0;
+    n.hr = false;
+    n.c0 = -2, n.c1 = 2, n.hc = v + 2 <= Nv - 1;
+  } else {
+    n.r0 = -2, n.r1 = 2, n.hr = u + 2 <= Nu - 1;
+    if ((v & 3) == 0)
+      n.c0 = n.c1 = 0, n.hc = false;
+    else
+      n.c0 = -2, n.c1 = 2, n.hc = v + 2 <= Nv - 1;
+  }
+  return n;
 }
-// Prediction of an S3 point from H1 values at offsets of 1.
-template <typename W, typename F>
-__device__ __forceinline__ W cd_pred_s3(int u, int v, int Nu, int Nv, F h) {
-  if ((u & 1) == 0) return (v + 1 <= Nv - 1) ? avgw<W>(h(0, -1), h(0, 1)) : h(0, -1);
-  auto Wr = [&](int du) -> W {
-    if ((v & 1) == 0) return h(du, 0);
-    return (v + 1 <= Nv - 1) ? avgw<W>(h(du, -1), h(du, 1)) : h(du, -1);
-  };
-  return (u + 1 <= Nu - 1) ? avgw<W>(Wr(-1), Wr(1)) : Wr(-1);
+// S3 points from stride-2 (H1) neighbours at distance 1
+__device__ __forceinline__ CDNb cd_nb_s3(int u, int v, int Nu, int Nv) {
+  CDNb n;
+  if ((u & 1) == 0) {
+    n.r0 = n.r1 = 0;
+    n.hr = false;
+    n.c0 = -1, n.c1 = 1, n.hc = v + 1 <= Nv - 1;
+  } else {
+    n.r0 = -1, n.r1 = 1, n.hr = u + 1 <= Nu - 1;
+    if ((v & 1) == 0)
+      n.c0 = n.c1 = 0, n.hc = false;
+    else
+      n.c0 = -1, n.c1 = 1, n.hc = v + 1 <= Nv - 1;
+  }
+  return n;
+}
+template <typename W>
+__device__ __forceinline__ W cd_combine(const CDNb& n, W h00, W h01, W h10, W h11) {
+  const W a = n.hc ? avgw<W>(h00, h01) : h00;
+  const W b = n.hc ? avgw<W>(h10, h11) : h10;
+  return n.hr ? avgw<W>(a, b) : a;
 }
 
 struct CDGeo {
@@ -670,6 +694,8 @@ __device__ __forceinline__ CDGeo cd_geo(const CDSeg& S, uint32_t row) {
   g.rowoff = (int64_t)row * S.c[2];
   return g;
 }
+
+constexpr int kCDBatch = 4;  // row elements per lane whose loads are issued together
 
 // Forward lifting of each region lattice into its S1/S2/S3 streams, with
 // the largest residual magnitude of each stream.
@@ -697,32 +723,55 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
     const int64_t row = (b - S.blk_begin) * kCDRowsPerBlock + wave;
     if (row >= (int64_t)S.c[0] * S.c[1]) continue;
     const CDGeo g = cd_geo<A>(S, (uint32_t)row);
-    const int64_t base[3] = {cd_row_base<A>(S, 0, g.t0, g.t1), cd_row_base<A>(S, 1, g.t0, g.t1),
-                             cd_row_base<A>(S, 2, g.t0, g.t1)};
+    const int u = A == 0 ? g.t1 : g.t0;
+    GAS Q* const so[3] = {(GAS Q*)S.S[0] + cd_row_base<A>(S, 0, g.t0, g.t1),
+                          (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, g.t0, g.t1),
+                          (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, g.t0, g.t1)};
     const GAS Q* R = (const GAS Q*)S.R + g.rowoff;
-    GAS Q* const so[3] = {(GAS Q*)S.S[0] + base[0], (GAS Q*)S.S[1] + base[1], (GAS Q*)S.S[2] + base[2]};
-    for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
-      const int u = A == 0 ? g.t1 : g.t0, v = A == 2 ? g.t1 : t2;
-      const GAS Q* Rp = R + t2;
-      auto T = [&](int du, int dv) -> W { return (W)Rp[du * g.su + dv * g.sv]; };
-      const int cls = cd_class(u, v);
-      W res = T(0, 0);
-      if (cls == 1)
-        res -= cd_pred_s2<W>(u, v, g.Nu, g.Nv, T);
-      else if (cls == 2)
-        res -= cd_pred_s3<W>(u, v, g.Nu, g.Nv, T);
-      GAS Q* dst = cls == 0 ? so[0] : (cls == 1 ? so[1] : so[2]);
-      dst[cd_in_row<A>(cls, u, t2)] = (Q)res;
-      const UW mag = res < 0 ? (UW)(-res) : (UW)res;
-      am[cls] = am[cls] > mag ? am[cls] : mag;
+    for (int t2b = 0; t2b < S.c[2]; t2b += 64 * kCDBatch) {
+      W x[kCDBatch], h[kCDBatch][4];
+      CDNb nb[kCDBatch];
+      int cls[kCDBatch];
+#pragma unroll
+      for (int i = 0; i < kCDBatch; ++i) {
+        const int t2 = t2b + lane + 64 * i;
+        const int v = A == 2 ? g.t1 : t2;
+        cls[i] = cd_class(u, v);
+        nb[i] = cls[i] == 1 ? cd_nb_s2(u, v, g.Nu, g.Nv) : cd_nb_s3(u, v, g.Nu, g.Nv);
+        x[i] = 0;
+        h[i][0] = h[i][1] = h[i][2] = h[i][3] = 0;
+        if (t2 < S.c[2]) {
+          const GAS Q* p = R + t2;
+          x[i] = (W)p[0];
+          if (cls[i] != 0) {
+            const CDNb& n = nb[i];
+            h[i][0] = (W)p[n.r0 * g.su + n.c0 * g.sv];
+            if (n.hc) h[i][1] = (W)p[n.r0 * g.su + n.c1 * g.sv];
+            if (n.hr) h[i][2] = (W)p[n.r1 * g.su + n.c0 * g.sv];
+            if (n.hr && n.hc) h[i][3] = (W)p[n.r1 * g.su + n.c1 * g.sv];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kCDBatch; ++i) {
+        const int t2 = t2b + lane + 64 * i;
+        if (t2 >= S.c[2]) continue;
+        W res = x[i];
+        if (cls[i] != 0) res -= cd_combine<W>(nb[i], h[i][0], h[i][1], h[i][2], h[i][3]);
+        GAS Q* dst = cls[i] == 0 ? so[0] : (cls[i] == 1 ? so[1] : so[2]);
+        dst[cd_in_row<A>(cls[i], u, t2)] = (Q)res;
+        const UW mag = res < 0 ? (UW)(-res) : (UW)res;
+        am[cls[i]] = am[cls[i]] > mag ? am[cls[i]] : mag;
+      }
     }
   }
   if (cur >= 0) flush(cur);
 }
 
 // Inverse lifting.  PHASE 0 rebuilds the stride-2 points (S1 and S2 classes)
-// from the truncated S1/S2 streams; PHASE 1 rebuilds the rest from S3 and the
-// stride-2 points written by phase 0.
+// from the truncated S1/S2 streams (stride-4 neighbours read from S1 at their
+// stream offsets); PHASE 1 rebuilds the rest from S3 and the stride-2 points
+// written by phase 0.
 template <typename Q, int PHASE, int A>
 __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
   using W = LiftT<Q>;
@@ -733,67 +782,197 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
     const int64_t row = (b - S.blk_begin) * kCDRowsPerBlock + wave;
     if (row >= (int64_t)S.c[0] * S.c[1]) continue;
     const CDGeo g = cd_geo<A>(S, (uint32_t)row);
-    const int ur = A == 0 ? g.t1 : g.t0;  // u of the row
-    if (PHASE == 0 && (ur & 1)) continue;
+    const int u = A == 0 ? g.t1 : g.t0;  // u of the row
+    if (PHASE == 0 && (u & 1)) continue;
     if (A == 2 && PHASE == 0 && (g.t1 & 1)) continue;
-    if (A == 2 && PHASE == 1 && !((ur & 1) || (g.t1 & 1))) continue;
+    if (A == 2 && PHASE == 1 && !((u & 1) || (g.t1 & 1))) continue;
     GAS Q* out = (GAS Q*)S.Rout + g.rowoff;
+    const int Bc = PHASE == 0 ? S.B[1] : S.B[2], kc = PHASE == 0 ? S.k[1] : S.k[2];
+    const int B0 = S.B[0], k0 = S.k[0];
     const GAS Q* S1 = (const GAS Q*)S.S[0];
-    auto m1 = [&](Q x) -> W { return (W)mask_code<Q>(x, S.B[0], S.k[0]); };
+    const GAS Q* sc = (const GAS Q*)S.S[PHASE == 0 ? 1 : 2] + cd_row_base<A>(S, PHASE == 0 ? 1 : 2, g.t0, g.t1);
+    // phase 0: S1 offsets of the rows at u + du (du = -2, 0, 2; v along the
+    // row), or of the rows (u + du, v + dv) when whole rows share one class
+    int64_t b0[3][3];
     if (PHASE == 0) {
-      // S1 offsets of the rows at u - 2, u, u + 2 (v along the row), or of
-      // the rows (u + du, v + dv) when whole rows share one class
-      int64_t b0[3], b0v[3][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int du = 2 * k - 2;
-        b0[k] = 0;
-        if (A != 2) {
-          const int uu = ur + du;
-          if (uu >= 0 && uu < g.Nu) b0[k] = A == 0 ? cd_row_base<A>(S, 0, g.t0, uu) : cd_row_base<A>(S, 0, uu, g.t1);
-        } else {
+      for (int ku = 0; ku < 3; ++ku)
 #pragma unroll
-          for (int kv = 0; kv < 3; ++kv) {
-            const int uu = ur + du, vv = g.t1 + 2 * kv - 2;
-            b0v[k][kv] = (uu >= 0 && uu < g.Nu && vv >= 0 && vv < g.Nv) ? cd_row_base<A>(S, 0, uu, vv) : 0;
+        for (int kv = 0; kv < 3; ++kv) {
+          const int uu = u + 2 * ku - 2, vv = g.t1 + 2 * kv - 2;
+          b0[ku][kv] = 0;
+          if (A != 2) {
+            if (kv == 1 && uu >= 0 && uu < g.Nu)
+              b0[ku][kv] = A == 0 ? cd_row_base<A>(S, 0, g.t0, uu) : cd_row_base<A>(S, 0, uu, g.t1);
+          } else if (uu >= 0 && uu < g.Nu && vv >= 0 && vv < g.Nv) {
+            b0[ku][kv] = cd_row_base<A>(S, 0, uu, vv);
           }
         }
-      }
-      const int64_t base1 = cd_row_base<A>(S, 1, g.t0, g.t1);
-      for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
-        const int u = ur, v = A == 2 ? g.t1 : t2;
-        if (v & 1) continue;
-        const int cls = cd_class(u, v);
-        W val;
-        if (A != 2) {
-          auto h2 = [&](int du, int dv) -> W {
-            const int64_t bb = du < 0 ? b0[0] : (du > 0 ? b0[2] : b0[1]);
-            return m1(S1[bb + ((v + dv) >> 2)]);
-          };
-          val = cls == 0 ? h2(0, 0)
-                         : (W)mask_code<Q>(((const GAS Q*)S.S[1])[base1 + cd_in_row<A>(1, u, t2)], S.B[1], S.k[1]) +
-                               cd_pred_s2<W>(u, v, g.Nu, g.Nv, h2);
+    }
+    // H2 value at offset (du, dv) from column t2 (phase 0), as an S1 stream index
+    auto s1_at = [&](int du, int dv, int t2, int v) -> int64_t {
+      const int ku = du < 0 ? 0 : (du > 0 ? 2 : 1), kv = dv < 0 ? 0 : (dv > 0 ? 2 : 1);
+      return A == 2 ? b0[ku][kv] + t2 : b0[ku][1] + ((v + dv) >> 2);
+    };
+    for (int t2b = 0; t2b < S.c[2]; t2b += 64 * kCDBatch) {
+      W xs[kCDBatch], h[kCDBatch][4];
+      CDNb nb[kCDBatch];
+      int cls[kCDBatch];
+      bool act[kCDBatch];
+#pragma unroll
+      for (int i = 0; i < kCDBatch; ++i) {
+        const int t2 = t2b + lane + 64 * i;
+        const int v = A == 2 ? g.t1 : t2;
+        cls[i] = cd_class(u, v);
+        act[i] = t2 < S.c[2] && (PHASE == 0 ? cls[i] != 2 : cls[i] == 2);
+        nb[i] = PHASE == 0 ? cd_nb_s2(u, v, g.Nu, g.Nv) : cd_nb_s3(u, v, g.Nu, g.Nv);
+        xs[i] = 0;
+        h[i][0] = h[i][1] = h[i][2] = h[i][3] = 0;
+        if (!act[i]) continue;
+        const CDNb& n = nb[i];
+        if (PHASE == 0) {
+          if (cls[i] == 0) {
+            h[i][0] = (W)mask_code<Q>(S1[s1_at(0, 0, t2, v)], B0, k0);
+          } else {
+            xs[i] = (W)mask_code<Q>(sc[cd_in_row<A>(1, u, t2)], Bc, kc);
+            h[i][0] = (W)mask_code<Q>(S1[s1_at(n.r0, n.c0, t2, v)], B0, k0);
+            if (n.hc) h[i][1] = (W)mask_code<Q>(S1[s1_at(n.r0, n.c1, t2, v)], B0, k0);
+            if (n.hr) h[i][2] = (W)mask_code<Q>(S1[s1_at(n.r1, n.c0, t2, v)], B0, k0);
+            if (n.hr && n.hc) h[i][3] = (W)mask_code<Q>(S1[s1_at(n.r1, n.c1, t2, v)], B0, k0);
+          }
         } else {
-          auto h2 = [&](int du, int dv) -> W {
-            const int ku = du < 0 ? 0 : (du > 0 ? 2 : 1), kv = dv < 0 ? 0 : (dv > 0 ? 2 : 1);
-            return m1(S1[b0v[ku][kv] + t2]);
-          };
-          val = cls == 0 ? h2(0, 0)
-                         : (W)mask_code<Q>(((const GAS Q*)S.S[1])[base1 + t2], S.B[1], S.k[1]) +
-                               cd_pred_s2<W>(u, v, g.Nu, g.Nv, h2);
+          const GAS Q* p = out + t2;
+          xs[i] = (W)mask_code<Q>(sc[cd_in_row<A>(2, u, t2)], Bc, kc);
+          h[i][0] = (W)p[n.r0 * g.su + n.c0 * g.sv];
+          if (n.hc) h[i][1] = (W)p[n.r0 * g.su + n.c1 * g.sv];
+          if (n.hr) h[i][2] = (W)p[n.r1 * g.su + n.c0 * g.sv];
+          if (n.hr && n.hc) h[i][3] = (W)p[n.r1 * g.su + n.c1 * g.sv];
         }
+      }
+#pragma unroll
+      for (int i = 0; i < kCDBatch; ++i) {
+        if (!act[i]) continue;
+        const int t2 = t2b + lane + 64 * i;
+        const W val = (PHASE == 0 && cls[i] == 0) ? h[i][0] : xs[i] + cd_combine<W>(nb[i], h[i][0], h[i][1], h[i][2], h[i][3]);
         out[t2] = (Q)val;
       }
-    } else {
-      const int64_t base2 = cd_row_base<A>(S, 2, g.t0, g.t1);
-      for (int t2 = lane; t2 < S.c[2]; t2 += 64) {
-        const int u = ur, v = A == 2 ? g.t1 : t2;
-        if (!((u & 1) || (v & 1))) continue;
-        const GAS Q* op = out + t2;
-        auto h1 = [&](int du, int dv) -> W { return (W)op[du * g.su + dv * g.sv]; };
-        const W val = (W)mask_code<Q>(((const GAS Q*)S.S[2])[base2 + cd_in_row<A>(2, u, t2)], S.B[2], S.k[2]) +
-                      cd_pred_s3<W>(u, v, g.Nu, g.Nv, h1);
-        out[t2] = (Q)val;
+    }
+  }
+}
+
+// Inverse lifting in one pass when v runs along lattice rows (stacking axis
+// 0 or 1).  A block rebuilds a tile of 8 rows (u) x 256 columns (v) of one
+// slice: the stride-2 points of the tile and a one-point halo go to LDS first
+// (from the S1/S2 streams), then every row of the tile is written whole, the
+// remaining points rebuilt from S3 and those LDS values.  Whole rows keep the
+// stores full-width (no partial-line writes).
+constexpr int kCITU = 8, kCITV = 256;
+constexpr int kCIHU = kCITU / 2 + 1, kCIHV = kCITV / 2 + 1;  // stride-2 rows/columns incl. halo
+
+template <typename Q, int A>
+__global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using W = LiftT<Q>;
+  constexpr int U = A == 0 ? 1 : 0;
+  __shared__ W h1[kCIHU * kCIHV];
+  __shared__ int64_t rb0[kCIHU + 2], rb1[kCIHU], rb2[kCITU];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int si = find_seg(segs, nseg, b);
+    const CDSeg& S = segs[si];
+    const int Nu = S.c[U], Nv = S.c[2];
+    const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
+    int lb = (int)(b - S.blk_begin);
+    const int V0 = (lb % nTv) * kCITV;
+    lb /= nTv;
+    const int U0 = (lb % nTu) * kCITU;
+    const int sa = lb / nTu;  // index along the stacking axis
+    auto tt = [&](int u, int& t0, int& t1) {
+      t0 = A == 0 ? sa : u;
+      t1 = A == 0 ? u : sa;
+    };
+    auto rowoff = [&](int u) -> int64_t {
+      int t0, t1;
+      tt(u, t0, t1);
+      return ((int64_t)t0 * S.c[1] + t1) * S.c[2];
+    };
+    __syncthreads();  // LDS of the previous tile is free
+    // stream offsets of the rows this tile touches
+    if (tid < kCIHU + 2) {  // S1 rows U0 - 2 + 2k
+      const int u = U0 - 2 + 2 * tid;
+      int t0, t1;
+      tt(u, t0, t1);
+      rb0[tid] = (u >= 0 && u < Nu) ? cd_row_base<A>(S, 0, t0, t1) : 0;
+    } else if (tid >= 16 && tid < 16 + kCIHU) {  // S2 rows U0 + 2k
+      const int u = U0 + 2 * (tid - 16);
+      int t0, t1;
+      tt(u, t0, t1);
+      rb1[tid - 16] = (u < Nu) ? cd_row_base<A>(S, 1, t0, t1) : 0;
+    } else if (tid >= 32 && tid < 32 + kCITU) {  // S3 rows U0 + k
+      const int u = U0 + tid - 32;
+      int t0, t1;
+      tt(u, t0, t1);
+      rb2[tid - 32] = (u < Nu) ? cd_row_base<A>(S, 2, t0, t1) : 0;
+    }
+    __syncthreads();
+    // stride-2 points (u, v even) of the tile and halo
+    const GAS Q* S1 = (const GAS Q*)S.S[0];
+    const GAS Q* S2 = (const GAS Q*)S.S[1];
+    const GAS Q* S3 = (const GAS Q*)S.S[2];
+    for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
+      const int r = e / kCIHV, k = e - r * kCIHV;
+      const int u = U0 + 2 * r, v = V0 + 2 * k;
+      W val = 0;
+      if (u < Nu && v < Nv) {
+        auto s1 = [&](int du, int dv) -> W {
+          return (W)mask_code<Q>(S1[rb0[r + 1 + du / 2] + ((v + dv) >> 2)], S.B[0], S.k[0]);
+        };
+        if (cd_class(u, v) == 0) {
+          val = s1(0, 0);
+        } else {
+          const CDNb n = cd_nb_s2(u, v, Nu, Nv);
+          const W x = (W)mask_code<Q>(S2[rb1[r] + cd_in_row<A>(1, u, v)], S.B[1], S.k[1]);
+          const W a0 = s1(n.r0, n.c0);
+          const W a1 = n.hc ? s1(n.r0, n.c1) : a0;
+          const W a2 = n.hr ? s1(n.r1, n.c0) : a0;
+          const W a3 = (n.hr && n.hc) ? s1(n.r1, n.c1) : a0;
+          val = x + cd_combine<W>(n, a0, a1, a2, a3);
+        }
+      }
+      h1[e] = val;
+    }
+    __syncthreads();
+    // whole rows: stride-2 points from LDS, the rest from S3
+#pragma unroll
+    for (int rr = 0; rr < kCITU / 4; ++rr) {
+      const int r = wave * (kCITU / 4) + rr;
+      const int u = U0 + r;
+      if (u >= Nu) continue;
+      GAS Q* out = (GAS Q*)S.Rout + rowoff(u);
+      const int64_t b2 = rb2[r];
+      W xs[kCITV / 64];
+#pragma unroll
+      for (int c = 0; c < kCITV / 64; ++c) {
+        const int v = V0 + c * 64 + lane;
+        xs[c] = 0;
+        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)mask_code<Q>(S3[b2 + cd_in_row<A>(2, u, v)], S.B[2], S.k[2]);
+      }
+#pragma unroll
+      for (int c = 0; c < kCITV / 64; ++c) {
+        const int v = V0 + c * 64 + lane;
+        if (v >= Nv) continue;
+        auto h = [&](int du, int dv) -> W { return h1[((r + du) >> 1) * kCIHV + ((v + dv - V0) >> 1)]; };
+        W val;
+        if (!((u & 1) || (v & 1))) {
+          val = h(0, 0);
+        } else {
+          const CDNb n = cd_nb_s3(u, v, Nu, Nv);
+          const W a0 = h(n.r0, n.c0);
+          const W a1 = n.hc ? h(n.r0, n.c1) : a0;
+          const W a2 = n.hr ? h(n.r1, n.c0) : a0;
+          const W a3 = (n.hr && n.hc) ? h(n.r1, n.c1) : a0;
+          val = xs[c] + cd_combine<W>(n, a0, a1, a2, a3);
+        }
+        out[v] = (Q)val;
       }
     }
   }
@@ -930,7 +1109,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     sig |= pw;
     const uint32_t incl = wave_incl_scan(c, lane);
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (lane == 0) ((GAS uint32_t*)S.cnt)[(int64_t)j * S.C + chunk] = tot;
+    if (lane == 0) ((GAS uint32_t*)S.cnt)[chunk * B + j] = tot;
     ptab[j * 64 + lane] = toff + incl - c;
     toff += tot;
   }
@@ -958,13 +1137,13 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   const int job = blockIdx.x;
   const StreamDev& S = sd[job_s[job]];
   const int j = job_j[job];
-  const GAS uint32_t* c = (const GAS uint32_t*)S.cnt + (int64_t)j * S.C;
+  const GAS uint32_t* c = (const GAS uint32_t*)S.cnt + j;  // chunk-major: entry i at i * B
   GAS uint32_t* o = (GAS uint32_t*)S.idx + (int64_t)j * S.C;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint64_t carry = 0;
   for (int64_t base = 0; base < S.C; base += kThreads) {
     const int64_t i = base + threadIdx.x;
-    const uint32_t v = (i < S.C) ? c[i] : 0u;
+    const uint32_t v = (i < S.C) ? c[i * S.B] : 0u;
     const uint32_t incl = wave_incl_scan(v, lane);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
@@ -1012,7 +1191,7 @@ __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ 
   uint32_t cj = 0;
   int64_t Dj = 0;
   if (lane < S.B) {
-    cj = ((const GAS uint32_t*)S.cnt)[(int64_t)lane * S.C + chunk];
+    cj = ((const GAS uint32_t*)S.cnt)[chunk * S.B + lane];
     Dj = ((const GAS int64_t*)S.pso)[lane] * 64 + (int64_t)((const GAS uint32_t*)S.idx)[(int64_t)lane * S.C + chunk];
   }
   const uint32_t sbj = wave_incl_scan(cj, lane) - cj;
@@ -1292,6 +1471,10 @@ hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, h
 }
 template <typename Q>
 hipError_t launch_cd_inverse(const CDSeg* segs, int nseg, int64_t nblk, int a, int phase, hipStream_t s) {
+  if (phase == 2) {  // one pass over row tiles (v along rows)
+    if (a == 0) APC_LAUNCH((k_cd_inverse_tile<Q, 0>), nblk, segs, nseg, nblk);
+    APC_LAUNCH((k_cd_inverse_tile<Q, 1>), nblk, segs, nseg, nblk);
+  }
   if (phase == 0) {
     if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 0, 0>), nblk, segs, nseg, nblk);
     if (a == 1) APC_LAUNCH((k_cd_inverse<Q, 0, 1>), nblk, segs, nseg, nblk);
