@@ -1113,16 +1113,21 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     ptab[j * 64 + lane] = toff + incl - c;
     toff += tot;
   }
-  // sign bits, word by word in code order (each lane owns its cursor column)
+  // sign bits, word by word in code order (each lane owns its cursor column);
+  // cursors are taken 16 codes at a time so their LDS round trips overlap
 #pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    const uint32_t v = (lead[k >> 2] >> (8 * (k & 3))) & 0xffu;
-    if (v & 0x80u) {
-      const int j = (int)((v >> 1) & 63u);
-      if (j < MAXB) {
-        const uint32_t pos = atomicAdd(&ptab[j * 64 + lane], 1u);
-        if ((v & 1u) && pos < (uint32_t)kChunk) atomicOr(&sstage[pos >> 6], 1ull << (pos & 63));
-      }
+  for (int g = 0; g < 64; g += 16) {
+    uint32_t pos[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t v = (lead[(g + k) >> 2] >> (8 * ((g + k) & 3))) & 0xffu;
+      pos[k] = ~0u;
+      if (v & 0x80u) pos[k] = atomicAdd(&ptab[((v >> 1) & 63u) * 64 + lane], 1u);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t v = (lead[(g + k) >> 2] >> (8 * ((g + k) & 3))) & 0xffu;
+      if ((v & 0x81u) == 0x81u && pos[k] < (uint32_t)kChunk) atomicOr(&sstage[pos[k] >> 6], 1ull << (pos[k] & 63));
     }
   }
   __syncthreads();
@@ -1264,6 +1269,9 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
     const int j = B - 1 - b;
     P[b] = (b < B && j >= k0 && j < k1 && w < S.M) ? mag[(int64_t)j * S.M + w] : 0ull;
   }
+  // lane j: first sign bit of plane j's run for this chunk (all planes at once)
+  int64_t Dl = 0;
+  if (lane >= k0 && lane < k1) Dl = pso[lane] * 64 + (int64_t)idx[(int64_t)lane * S.C + chunk];
   // newcomer counts -> cursors; runs of sign words to fetch
   uint32_t woff = 0;
   int np = 0;
@@ -1276,7 +1284,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
     sig |= pw;
     const uint32_t incl = wave_incl_scan(c, lane);
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    const int64_t D = pso[j] * 64 + (int64_t)idx[(int64_t)j * S.C + chunk];
+    const int64_t D = readlane64(Dl, j);
     const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
     ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl - c;
     if (lane == 0) {
