@@ -741,11 +741,15 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     Tmp& t = tmp[f];
     t.goff.assign(g.L, 0);
     int64_t gtot = 0;
-    for (int l = 1; l < g.L; ++l) {
+    // compact level grids: per-level fields read the field at strides and
+    // only need the coarsest level here
+    const bool per_level = h->scheme.kind == APC_PER_LEVEL;
+    for (int l = per_level ? g.L - 1 : 1; l < g.L; ++l) {
+      if (l == 0) continue;
       t.goff[l] = gtot;
       gtot += (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
     }
-    APC_TRY(t.grids.alloc(sizeof(T) * (size_t)gtot));
+    APC_TRY(t.grids.alloc(sizeof(T) * (size_t)std::max<int64_t>(1, gtot)));
     APC_TRY(t.codes.alloc(sizeof(Q) * (size_t)h->code_n));
     if (h->cd_n) APC_TRY(t.cdc.alloc(sizeof(Q) * (size_t)h->cd_n));
     t.acc = nacc;
@@ -771,7 +775,13 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       if (h->scheme.kind != APC_PER_LEVEL) continue;
       for (int l = 0; l < h->geo.L - 1; ++l) {
         LevelSeg c = level_seg(h, l);
-        c.src = grid_ptr(f, l);
+        const Geo& g = h->geo;
+        c.src = X[f];
+        const int64_t sl = (int64_t)1 << l;
+        c.xs[0] = sl * g.N[1] * g.N[2];
+        c.xs[1] = sl * g.N[2];
+        c.xs[2] = sl;
+        if (mode == 0 && l == 0) c.racc = acc + tmp[f].acc;  // the field's range, in the same pass
         const int gi = group_of(h->meta, l, 0);
         c.gmax = acc + tmp[f].acc + 4 + gi;
         c.k_shift = h->meta.groups[gi].k_shift;
@@ -794,9 +804,11 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       s.src = X[f];
       s.n = H[f]->geo.n();
       s.acc = acc + tmp[f].acc;
-      rs.push_back(s);
       const Geo& g = H[f]->geo;
-      for (int l = 1; l < g.L; ++l) {
+      const bool per_level = H[f]->scheme.kind == APC_PER_LEVEL;
+      if (!per_level || g.L < 2) rs.push_back(s);  // per-level: the level-0 max pass finds the range
+      for (int l = per_level ? g.L - 1 : 1; l < g.L; ++l) {
+        if (l == 0) continue;
         FlatSeg q{};
         q.src = X[f];
         q.dst = tmp[f].grids.template as<T>() + tmp[f].goff[l];
@@ -816,8 +828,8 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     for (auto& s : gs) gb += 2.0 * sizeof(T) * s.n;
     const int64_t b1 = assign_blocks<FlatSeg>(rs, [](const FlatSeg& s) { return s.n; });
     const int64_t b2 = assign_blocks<FlatSeg>(gs, [](const FlatSeg& s) { return s.n; });
-    ls.push_back({K_RANGE, tb.add(rs), (int)rs.size(), b1, 0, nb, "range"});
-    ls.push_back({K_GATHER, tb.add(gs), (int)gs.size(), b2, 0, gb, "subsample"});
+    if (!rs.empty()) ls.push_back({K_RANGE, tb.add(rs), (int)rs.size(), b1, 0, nb, "range"});
+    if (!gs.empty()) ls.push_back({K_GATHER, tb.add(gs), (int)gs.size(), b2, 0, gb, "subsample"});
     {
       double by = 0;
       std::vector<LevelSeg> lv = level_segs(0, by);

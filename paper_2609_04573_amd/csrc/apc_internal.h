@@ -79,7 +79,9 @@ struct LevelSeg {
   int32_t nt1, nt2;      // tiles along axes 1 and 2
   int32_t final_out;     // reconstruction: out is the T output field
   int64_t blk_begin;     // first work block (tiles x runs) of this segment
-  const void* src;       // refactor: level grid (T); reconstruction: coarser level (double)
+  const void* src;       // refactor: the field (T), level grid at strides xs; reconstruction: coarser level (double)
+  int64_t xs[3];         // refactor: element strides of the level grid in src
+  unsigned long long* racc;  // max pass on level 0: range accumulators (min, max, max |x|, non-finite), or null
   void* out;             // reconstruction: level grid (double), or the T output field
   void* q[3];            // codes of regions 0, 1, 2 (Q*, lattice order)
   int32_t B[3], k[3];    // reconstruction: truncation of each region's codes

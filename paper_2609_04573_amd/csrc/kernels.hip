@@ -350,20 +350,53 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
   using V = typename std::conditional<MODE == 2, Q, T>::type;  // per-point input: code or value
   __shared__ double ctile[kC1 * kC2];
   __shared__ double u2[kC1 * kT2];
+  __shared__ int sbad;
   int cur = -1;
   double am = 0.0;
+  // range of the field (max pass over level 0): min, max, max |x|, non-finite seen
+  double rlo = INFINITY, rhi = -INFINITY, ram = 0.0;
+  bool rbad = false;
+  auto take = [&](double v) {
+    if (!isfinite(v)) {
+      rbad = true;
+    } else {
+      rlo = fmin(rlo, v);
+      rhi = fmax(rhi, v);
+      ram = fmax(ram, fabs(v));
+    }
+  };
+  auto flush = [&](int si) {
+    const double m = block_max(am);
+    if (threadIdx.x == 0) atomicMax(segs[si].gmax, (unsigned long long)__double_as_longlong(m));
+    unsigned long long* acc = segs[si].racc;
+    if (acc) {
+      const double l = -block_max(-rlo), h = block_max(rhi), a = block_max(ram);
+      if (threadIdx.x == 0) sbad = 0;
+      __syncthreads();
+      if (rbad) sbad = 1;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        if (l <= h) {
+          atomicMin(&acc[0], ordered_bits(l));
+          atomicMax(&acc[1], ordered_bits(h));
+        }
+        atomicMax(&acc[2], (unsigned long long)__double_as_longlong(a));
+        if (sbad) atomicOr(&acc[3], 1ull);
+      }
+    }
+  };
   const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     if (MODE == 0 && si != cur) {
-      if (cur >= 0) {
-        const double m = block_max(am);
-        if (tid == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
-      }
+      if (cur >= 0) flush(cur);
       cur = si;
       am = 0.0;
+      rlo = INFINITY, rhi = -INFINITY, ram = 0.0;
+      rbad = false;
     }
     const LevelSeg& S = segs[si];
+    unsigned long long* const racc = S.racc;
     const int m0 = S.m[0], m1 = S.m[1], m2 = S.m[2];
     const int mc0 = S.mc[0], mc1 = S.mc[1], mc2 = S.mc[2];
     const int deg = S.degree;
@@ -400,9 +433,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       const int c1 = c1s + r, c2 = c2s + kk;
       coff[k] = -1;
       if (e < kC1 * kC2 && c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2)
-        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * m2 + 2 * c2;
+        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * S.xs[1] + (int64_t)(2 * c2) * S.xs[2];
     }
-    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : (int64_t)2 * m1 * m2;  // coarse plane stride
+    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : 2 * S.xs[0];  // coarse plane stride
     double cpre[kCPer];
     auto fetch_tile = [&](int cc) {
 #pragma unroll
@@ -411,6 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         if (coff[k] >= 0) {
           const int64_t o = (int64_t)cc * cplane + coff[k];
           cpre[k] = MODE == 2 ? ((const GAS double*)S.src)[o] : (double)((const GAS T*)S.src)[o];
+          if (MODE == 0 && racc) take(cpre[k]);
         }
       }
     };
@@ -471,7 +505,10 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
           int64_t li, o;
           in[h * 4 + i] = (V)0;
           if (locate(2 * c + h, i, rr, li, o) && rr >= 0)
-            in[h * 4 + i] = MODE == 2 ? (V)qptr(rr)[li] : (V)((const GAS T*)S.src)[o];
+            in[h * 4 + i] = MODE == 2 ? (V)qptr(rr)[li]
+                                      : (V)((const GAS T*)S.src)[(int64_t)(2 * c + h) * S.xs[0] +
+                                                                  (int64_t)(t1 + 4 * rg + i) * S.xs[1] +
+                                                                  (int64_t)f2 * S.xs[2]];
         }
     };
     auto emit = [&](int f0, int i, double p, V v) {
@@ -491,6 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
           ((GAS double*)S.out)[o] = x;
       } else if (rr >= 0) {
         const double c = (double)v - p;
+        if (MODE == 0 && racc) take((double)v);
         if (MODE == 0)
           am = fmax(am, fabs(c));
         else
@@ -531,10 +569,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       }
     }
   }
-  if (MODE == 0 && cur >= 0) {
-    const double m = block_max(am);
-    if (tid == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
-  }
+  if (MODE == 0 && cur >= 0) flush(cur);
 }
 
 // Coarsest level: the values themselves are the coefficients.
