@@ -167,11 +167,17 @@ __device__ __forceinline__ int source_region(const RegionArgs& ra, const int i[3
 // "even" along this region's axis).
 __device__ __forceinline__ double predict_from_region(const RegionArgs& ra, int rp, const int i[3], int ax, int j,
                                                       int sk) {
-  const Lattice& PL = ra.prl[rp];
+  // rp differs between lanes: read both regions' (uniform) descriptors and
+  // select, rather than indexing the table per lane
+  const Lattice& P0 = ra.prl[0];
+  const Lattice& P1 = ra.prl[1];
+  const bool r1 = rp == 1;
   int tt[3];
-  for (int a = 0; a < 3; ++a) tt[a] = (a == ax) ? (j - 1) >> 1 : lat_of(i[a], PL.kind[a]);
-  const int64_t ls[3] = {(int64_t)PL.c[1] * PL.c[2], (int64_t)PL.c[2], 1};
-  const GAS double* pp = (const GAS double*)ra.pr[rp] + tt[0] * ls[0] + tt[1] * ls[1] + tt[2] * ls[2];
+  for (int a = 0; a < 3; ++a) tt[a] = (a == ax) ? (j - 1) >> 1 : lat_of(i[a], r1 ? P1.kind[a] : P0.kind[a]);
+  const int64_t c1 = r1 ? P1.c[1] : P0.c[1], c2 = r1 ? P1.c[2] : P0.c[2];
+  const int64_t ls[3] = {c1 * c2, c2, 1};
+  const GAS double* pp =
+      (const GAS double*)(r1 ? ra.pr[1] : ra.pr[0]) + tt[0] * ls[0] + tt[1] * ls[1] + tt[2] * ls[2];
   const int64_t st = ls[ax];
   return stencil_eval(sk, [&](int o) { return pp[((o + 1) / 2) * st]; });
 }
