@@ -22,6 +22,160 @@ if ROOT not in sys.path:
 HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s
 
 
+# Kernel symbol -> the launch category the library's event profiler reports.
+KERNEL_CATEGORY = [
+    ("k_level<", ", 0>", "coef_max"), ("k_level<", ", 1>", "coef_quant"), ("k_level<", ", 2>", "recon"),
+    ("k_coef<", ", 0>", "coef_max"), ("k_coef<", ", 1>", "coef_quant"), ("k_recon<", "", "recon"),
+    ("k_cd_forward", "", "cd_forward"), ("k_cd_inverse", "", "cd_inverse"), ("k_encode", "", "encode"),
+    ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_scan", "", "scan"),
+    ("k_range", "", "range"), ("k_gather", "", "subsample"), ("k_coarsest", "", "coarsest"),
+    ("k_coarse<", "", "coarse"), ("k_inject", "", "inject"),
+]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cubed_f32.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_04573_amd", "csrc", f) for f in ("kernels.hip", "apc_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short_kernel(name: str) -> str:
+    import re
+
+    m = re.search(r"(k_[a-z_]+(?:<[^()]*>)?)", name)
+    return m.group(1) if m else name.split("(")[0][-60:]
+
+
+def _category(kname: str):
+    for head, tail, cat in KERNEL_CATEGORY:
+        if kname.startswith(head) and (not tail or kname.endswith(tail)):
+            return cat
+    return None
+
+
+def _read_rows(path_dir: str, table: str):
+    """Rows of a rocprofv3 result: (kernel name, counter, value, dispatch, duration ns)."""
+    import csv
+    import glob
+    import sqlite3
+
+    rows = []
+    for f in glob.glob(os.path.join(path_dir, "**", "*_results.db"), recursive=True):
+        c = sqlite3.connect(f).cursor()
+        if table == "counters":
+            for k, cn, v, d, dur in c.execute(
+                    "select kernel_name, counter_name, value, dispatch_id, duration from counters_collection"):
+                rows.append((k, cn, float(v), int(d), float(dur or 0)))
+        else:
+            for k, dur in c.execute("select name, duration from kernels"):
+                rows.append((k, None, 0.0, 0, float(dur)))
+    for f in glob.glob(os.path.join(path_dir, "**", "*counter_collection.csv" if table == "counters"
+                                    else "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if table == "counters":
+                    rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]),
+                                 int(r.get("Dispatch_Id", 0)), 0.0))
+                else:
+                    dur = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+                    rows.append((r["Kernel_Name"], None, 0.0, 0, dur))
+    return rows
+
+
+def summarize_profiles(run_dir: str, steps: int, out_md: str, out_json: str, commands: list):
+    """Per-kernel time and HBM traffic from rocprofv3 runs of this benchmark.
+
+    run_dir holds three runs: kt/ (--kernel-trace), f/ (--pmc FETCH_SIZE) and
+    w/ (--pmc WRITE_SIZE).  Counter values (KiB per dispatch) are scaled by
+    what the same counters read for a plain copy of known size: the float32 ->
+    float64 conversion of the input field in the error check (reads n*4 B,
+    writes n*8 B)."""
+    import collections
+
+    trace = _read_rows(os.path.join(run_dir, "kt"), "trace")
+    fetch = _read_rows(os.path.join(run_dir, "f"), "counters")
+    write = _read_rows(os.path.join(run_dir, "w"), "counters")
+    n = 512 ** 3
+    cal = {}
+    for rows, cname, known in ((fetch, "FETCH_SIZE", 4.0 * n), (write, "WRITE_SIZE", 8.0 * n)):
+        vals = [v * 1024.0 for k, c, v, d, dur in rows if c == cname and "direct_copy_kernel" in k]
+        cal[cname] = {"known_bytes": known, "counter_bytes": vals[-1] if vals else None,
+                      "factor": (known / vals[-1]) if vals else 1.0}
+    per = collections.defaultdict(lambda: {"us": 0.0, "calls": 0, "fetch": 0.0, "write": 0.0, "fcalls": 0,
+                                           "wcalls": 0})
+    for k, _, _, _, dur in trace:
+        kn = _short_kernel(k)
+        if kn.startswith("k_"):
+            per[kn]["us"] += dur / 1e3
+            per[kn]["calls"] += 1
+    for rows, cname, key, ck in ((fetch, "FETCH_SIZE", "fetch", "fcalls"), (write, "WRITE_SIZE", "write", "wcalls")):
+        for k, c, v, d, dur in rows:
+            kn = _short_kernel(k)
+            if c == cname and kn.startswith("k_"):
+                per[kn][key] += v * 1024.0 * cal[cname]["factor"]
+                per[kn][ck] += 1
+    cats = collections.defaultdict(lambda: {"fetch": 0.0, "write": 0.0, "launches": 0, "us": 0.0, "calls": 0})
+    lines = ["| kernel | calls | total us | avg us | HBM read MB/launch | HBM write MB/launch | GB/s |",
+             "|---|---|---|---|---|---|---|"]
+    for kn, v in sorted(per.items(), key=lambda kv: -kv[1]["us"]):
+        fpl = v["fetch"] / max(1, v["fcalls"])
+        wpl = v["write"] / max(1, v["wcalls"])
+        avg = v["us"] / max(1, v["calls"])
+        gbs = (fpl + wpl) / (avg * 1e-6) / 1e9 if avg else 0.0
+        lines.append(f"| `{kn}` | {v['calls']} | {v['us']:.1f} | {avg:.1f} | {fpl / 1e6:.1f} | {wpl / 1e6:.1f} | {gbs:.0f} |")
+        cat = _category(kn)
+        if cat:
+            c = cats[cat]
+            c["fetch"] += v["fetch"]
+            c["write"] += v["write"]
+            c["launches"] += v["fcalls"]
+            c["us"] += v["us"]
+            c["calls"] += v["calls"]
+    traffic = {"kernel_source_hash": kernel_source_hash(), "workload": "512^3 float32, per-level cubic + CD axis 0, "
+               "rel 1e-4", "calibration": cal, "categories": {}}
+    for cat, c in cats.items():
+        traffic["categories"][cat] = {"bytes_per_launch": (c["fetch"] + c["write"]) / max(1, c["launches"]),
+                                      "read_bytes_per_launch": c["fetch"] / max(1, c["launches"]),
+                                      "write_bytes_per_launch": c["write"] / max(1, c["launches"]),
+                                      "launches": c["launches"], "avg_launch_us": c["us"] / max(1, c["calls"])}
+    with open(out_json, "w") as fh:
+        json.dump(traffic, fh, indent=1, sort_keys=True)
+    with open(out_md, "w") as fh:
+        fh.write("# Kernel time and HBM traffic: 512^3 float32 refactor + retrieve (rel 1e-4)\n\n")
+        fh.write("Commands (run from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):\n\n")
+        for cmd in commands:
+            fh.write(f"    {cmd}\n")
+        fh.write("\nCounter calibration against a plain copy of known size (the float32 -> float64 conversion "
+                 "of the 512^3 input: reads 512 MiB, writes 1 GiB):\n\n")
+        for cname, c in cal.items():
+            cb = c["counter_bytes"]
+            fh.write(f"- {cname}: counter {cb / 2**20 if cb else float('nan'):.1f} MiB for {c['known_bytes'] / 2**20:.0f} MiB "
+                     f"moved -> factor {c['factor']:.4f}\n")
+        fh.write(f"\nKernel trace over {steps} measured step(s) plus warm-up; traffic from one-step counter runs, "
+                 "scaled by the factors above.  Kernel source hash " + traffic["kernel_source_hash"] + ".\n\n")
+        fh.write("\n".join(lines) + "\n")
+
+
+def load_traffic(category: str):
+    """HBM bytes per launch of a kernel category from the committed counter
+    summary, or None when the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    c = t["categories"].get(category)
+    return None if c is None else c["bytes_per_launch"]
+
+
 def _pct(v, q):
     v = sorted(v)
     if not v:
@@ -167,7 +321,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--full", action="store_true", help="full-size batching and serving workloads")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="summarize rocprofv3 runs of this benchmark (DIR/kt, DIR/f, DIR/w) into profiles/")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        base = "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-systems"
+        cmds = [f"rocprofv3 --kernel-trace --stats -d {args.summarize_profiles}/kt -o kt -- {base}",
+                f"rocprofv3 --pmc FETCH_SIZE -d {args.summarize_profiles}/f -o f -- {base.replace('--steps 3', '--steps 1')}",
+                f"rocprofv3 --pmc WRITE_SIZE -d {args.summarize_profiles}/w -o w -- {base.replace('--steps 3', '--steps 1')}",
+                f"python3 bench.py --summarize-profiles {args.summarize_profiles}"]
+        summarize_profiles(args.summarize_profiles, 3, os.path.join(ROOT, "profiles", "kernels_512cubed_f32.md"),
+                           TRAFFIC_FILE, cmds)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by independent "
               "fields/blocks and is measured per GPU", file=sys.stderr)
@@ -255,7 +420,7 @@ def main():
     d = prof[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK / 1e9,
-                        "unit": "GB/s", "frac": achieved / (HBM_PEAK / 1e9), "traffic": None,
+                        "unit": "GB/s", "frac": achieved / (HBM_PEAK / 1e9), "traffic": load_traffic(dom),
                         "launches_per_step": d["count"] / args.steps,
                         "ms_per_step": d["ms"] / args.steps}
     line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4) for k, v in
