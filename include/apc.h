@@ -166,6 +166,26 @@ void apc_server_destroy(apc_server* sv);
 apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
                                int32_t mode, apc_scheme* out, void* hip_stream);
 
+/* Sweep-tile autotuner for batched per-level passes.  The per-level
+ * interpolation sweep (the tensor-product refinement of Section IV) runs on
+ * tiles of t2 columns (the fastest axis) by 1024/t2 rows, t2 in {32, 64,
+ * 128}.  apc_tune_tiles times the level's max pass with each width on the
+ * given device field (dims and dtype as apc_refactor; degree 1 or 3) for
+ * every level of at least 2^18 points, and records the fastest width for
+ * that level shape (dtype, log2 of the axis-1 and axis-2 extents) in a
+ * process-wide table that later refactors and retrievals of any field use.
+ * Outputs (optional): the width chosen for level 0 (0 if no level was
+ * timed) and the level-0 times in microseconds for widths 32, 64, 128
+ * (us0: 3 doubles).  The field is only read.  Tile widths never change
+ * results, only speed.
+ * apc_tile_override forces one width for every pass (0 restores the table);
+ * APC_E_INVALID for other values.  apc_tile_width reports the width used
+ * for a level of extents m1 x m2. */
+apc_status apc_tune_tiles(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim, int32_t degree,
+                          void* hip_stream, int32_t* tile0, double* us0);
+apc_status apc_tile_override(int32_t t2);
+apc_status apc_tile_width(int32_t dtype, int64_t m1, int64_t m2, int32_t* t2);
+
 void apc_free(apc_handle* h);
 const char* apc_strerror(apc_status s);
 const char* apc_last_error(void);

@@ -42,7 +42,7 @@ EXPORTED = [
     "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
-    "apc_server_destroy",
+    "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
 ]
 
 
@@ -100,11 +100,15 @@ _lib.apc_server_reset_stats.argtypes = [_vp]
 _lib.apc_server_destroy.argtypes = [_vp]
 _lib.apc_server_destroy.restype = None
 _lib.apc_profile_report.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
+_lib.apc_tune_tiles.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, _vp, ctypes.POINTER(_i32),
+                                ctypes.POINTER(ctypes.c_double)]
+_lib.apc_tile_override.argtypes = [_i32]
+_lib.apc_tile_width.argtypes = [_i32, _i64, _i64, ctypes.POINTER(_i32)]
 for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
               "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable",
               "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
-              "apc_server_reset_stats"):
+              "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -367,6 +371,30 @@ def select_pipeline(field, mode: str = "eb", stream=None) -> Scheme:
     _check(_lib.apc_select_pipeline(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(),
                                     MODES[mode], ctypes.byref(s), _stream_ptr(stream)))
     return Scheme._from_c(s, field.dim())
+
+
+def tune_tiles(field, degree: int = 3, stream=None) -> dict:
+    """Time the per-level sweep with every tile width on this field and keep
+    the fastest for its level shapes (a process-wide table)."""
+    assert field.is_cuda and field.is_contiguous()
+    dims = (ctypes.c_int64 * field.dim())(*field.shape)
+    t0 = ctypes.c_int32()
+    us = (ctypes.c_double * 3)()
+    _check(_lib.apc_tune_tiles(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(), degree,
+                               _stream_ptr(stream), ctypes.byref(t0), us))
+    return {"tile": t0.value, "us": {32: us[0], 64: us[1], 128: us[2]}}
+
+
+def tile_override(t2: int) -> None:
+    """Force one sweep tile width (32, 64 or 128) for every pass; 0 = tuned/default."""
+    _check(_lib.apc_tile_override(t2))
+
+
+def tile_width(dtype, m1: int, m2: int) -> int:
+    import torch
+    t = ctypes.c_int32()
+    _check(_lib.apc_tile_width(APC_F64 if dtype == torch.float64 else APC_F32, m1, m2, ctypes.byref(t)))
+    return t.value
 
 
 def axis_norms(n: int, L: int, degree: int) -> Tuple[List[float], List[float]]:

@@ -16,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -345,8 +346,29 @@ int64_t assign_blocks(std::vector<S>& segs, std::function<int64_t(const S&)> cou
   return b;
 }
 
-// Per-level pass geometry of level l (the coarser level is l + 1).
-LevelSeg level_seg(const apc_handle* h, int l) {
+// ------------------------------------------------ per-level sweep tile shapes
+// A tile is t2 columns (axis 2) by 1024 / t2 rows (axis 1).  The autotuner
+// records the fastest width per (dtype, log2 of the level's axis-1 and axis-2
+// extents); unseen shapes use a default.
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int>, int> g_tiles;
+int g_tile_override = 0;
+
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while (((int64_t)1 << b) < v) ++b;
+  return b;
+}
+int default_tile(int m2) { return m2 <= 32 ? 32 : 64; }
+int tile_for(int dtype, int m1, int m2) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  if (g_tile_override) return g_tile_override;
+  auto it = g_tiles.find(std::make_tuple(dtype, ceil_log2(m1), ceil_log2(m2)));
+  return it != g_tiles.end() ? it->second : default_tile(m2);
+}
+
+// Per-level pass geometry of level l (the coarser level is l + 1) for tiles t2 wide.
+LevelSeg level_seg(const apc_handle* h, int l, int t2) {
   const Geo& g = h->geo;
   LevelSeg s{};
   for (int a = 0; a < 3; ++a) {
@@ -354,8 +376,9 @@ LevelSeg level_seg(const apc_handle* h, int l) {
     s.mc[a] = g.m[l + 1][a];
   }
   s.degree = h->scheme.degree;
-  s.nt1 = (s.m[1] + kLvlT1 - 1) / kLvlT1;
-  s.nt2 = (s.m[2] + kLvlT2 - 1) / kLvlT2;
+  const int t1 = 1024 / t2;
+  s.nt1 = (s.m[1] + t1 - 1) / t1;
+  s.nt2 = (s.m[2] + t2 - 1) / t2;
   // runs along axis 0: as long as possible while the level still spreads
   // over enough blocks to fill the device
   s.ch = kLvlCH;
@@ -429,7 +452,7 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
       case K_LEVEL1:
       case K_LEVEL2:
         LAUNCH(l.name, l.bytes, st,
-               (launch_level<T, Q>((const LevelSeg*)p, l.nseg, l.nblk, l.kind - K_LEVEL0, st)));
+               (launch_level<T, Q>((const LevelSeg*)p, l.nseg, l.nblk, l.kind - K_LEVEL0, l.a, st)));
         break;
       default: return fail(APC_E_INVALID, "unknown launch kind");
     }
@@ -768,13 +791,29 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   unsigned long long* acc = accb.as<unsigned long long>();
   auto grid_ptr = [&](int f, int l) -> const T* { return l == 0 ? X[f] : tmp[f].grids.template as<T>() + tmp[f].goff[l]; };
   // per-level fields: one tensor-product pass per level (all levels in one launch)
+  // every segment of a launch shares one tile width: the one chosen for the
+  // largest level in the batch
+  int lvl_t2 = 64;
+  {
+    int64_t big = -1;
+    for (int f = 0; f < nf; ++f) {
+      const apc_handle* h = H[f];
+      if (h->scheme.kind != APC_PER_LEVEL || h->geo.L < 2) continue;
+      const Geo& g = h->geo;
+      const int64_t n = g.n();
+      if (n > big) {
+        big = n;
+        lvl_t2 = tile_for(h->dtype, (int)g.m[0][1], (int)g.m[0][2]);
+      }
+    }
+  }
   auto level_segs = [&](int mode, double& by) {
     std::vector<LevelSeg> ls2;
     for (int f = 0; f < nf; ++f) {
       const apc_handle* h = H[f];
       if (h->scheme.kind != APC_PER_LEVEL) continue;
       for (int l = 0; l < h->geo.L - 1; ++l) {
-        LevelSeg c = level_seg(h, l);
+        LevelSeg c = level_seg(h, l, lvl_t2);
         const Geo& g = h->geo;
         c.src = X[f];
         const int64_t sl = (int64_t)1 << l;
@@ -834,7 +873,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       double by = 0;
       std::vector<LevelSeg> lv = level_segs(0, by);
       const int64_t nbk = assign_level_blocks(lv);
-      if (!lv.empty()) ls.push_back({K_LEVEL0, tb.add(lv), (int)lv.size(), nbk, 0, by, "coef_max"});
+      if (!lv.empty()) ls.push_back({K_LEVEL0, tb.add(lv), (int)lv.size(), nbk, lvl_t2, by, "coef_max"});
     }
     for (int rho = 0; rho < 3; ++rho) {  // per-region fields: one pass per region
       std::vector<CoefSeg> cs;
@@ -907,7 +946,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     double by = 0;
     std::vector<LevelSeg> lv = level_segs(1, by);
     const int64_t nbk = assign_level_blocks(lv);
-    if (!lv.empty()) ls.push_back({K_LEVEL1, tb2.add(lv), (int)lv.size(), nbk, 0, by, "coef_quant"});
+    if (!lv.empty()) ls.push_back({K_LEVEL1, tb2.add(lv), (int)lv.size(), nbk, lvl_t2, by, "coef_quant"});
   }
   for (int rho = 0; rho < 3; ++rho) {
     std::vector<CoefSeg> cs;
@@ -1325,7 +1364,8 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     double* xout = l > 0 ? w.xb[l % 2] : nullptr;
     void* dst = l > 0 ? (void*)xout : (void*)out;
     if (per_level) {  // one tensor-product pass writes the whole level grid
-      LevelSeg c = level_seg(h, l);
+      const int t2 = tile_for(h->dtype, g.m[l][1], g.m[l][2]);
+      LevelSeg c = level_seg(h, l, t2);
       c.src = xin;
       c.out = dst;
       c.final_out = l == 0 ? 1 : 0;
@@ -1347,7 +1387,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       const int64_t nbk = assign_level_blocks(cs);
       const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
       const double by = (double)n * (sizeof(Q) + (l ? 8 : sizeof(T))) + 8.0 * c.mc[0] * c.mc[1] * c.mc[2];
-      ls.push_back({K_LEVEL2, tb.add(cs), 1, nbk, 0, by, "recon"});
+      ls.push_back({K_LEVEL2, tb.add(cs), 1, nbk, t2, by, "recon"});
       xin = xout;
       continue;
     }
@@ -1945,6 +1985,94 @@ apc_status select_impl(const T* field, int32_t dtype, const Geo& g, int mode, ap
 }
 
 }  // namespace
+
+// ------------------------------------------------------------- tile autotuner
+// Times the per-level max pass of every level of at least 2^18 points with
+// each tile width on the given field and records the fastest in the table.
+template <typename T>
+apc_status tune_impl(const T* field, int32_t dtype, const Geo& g, int degree, hipStream_t st, int32_t* tile0,
+                     double* us0) {
+  typedef typename std::conditional<sizeof(T) == 4, int32_t, int64_t>::type Q;
+  static const int kWidths[3] = {32, 64, 128};
+  DevBuf acc, tab;
+  APC_TRY(acc.alloc(64));
+  apc_handle probe;
+  probe.geo = g;
+  probe.scheme.degree = degree;
+  probe.dtype = dtype;
+  if (tile0) *tile0 = 0;
+  for (int l = 0; l + 1 < g.L; ++l) {
+    const int64_t n = (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
+    if (n < ((int64_t)1 << 18)) break;
+    double best = 1e300;
+    int bw = 64;
+    for (int k = 0; k < 3; ++k) {
+      LevelSeg c = level_seg(&probe, l, kWidths[k]);
+      c.src = field;
+      const int64_t sl = (int64_t)1 << l;
+      c.xs[0] = sl * g.N[1] * g.N[2];
+      c.xs[1] = sl * g.N[2];
+      c.xs[2] = sl;
+      c.gmax = acc.as<unsigned long long>();
+      std::vector<LevelSeg> cs{c};
+      const int64_t nbk = assign_level_blocks(cs);
+      APC_TRY(tab.alloc(sizeof(LevelSeg)));
+      HIP_TRY(hipMemcpyAsync(tab.p, cs.data(), sizeof(LevelSeg), hipMemcpyHostToDevice, st));
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      HIP_TRY((launch_level<T, Q>((const LevelSeg*)tab.p, 1, nbk, 0, kWidths[k], st)));  // warm
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) HIP_TRY((launch_level<T, Q>((const LevelSeg*)tab.p, 1, nbk, 0, kWidths[k], st)));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      const double us = ms * 1e3 / 3.0;
+      if (l == 0 && us0) us0[k] = us;
+      if (us < best) {
+        best = us;
+        bw = kWidths[k];
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_tile_mu);
+      g_tiles[std::make_tuple((int)dtype, ceil_log2(g.m[l][1]), ceil_log2(g.m[l][2]))] = bw;
+    }
+    if (l == 0 && tile0) *tile0 = bw;
+  }
+  return APC_OK;
+}
+
+extern "C" apc_status apc_tune_tiles(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
+                                     int32_t degree, void* hip_stream, int32_t* tile0, double* us0) {
+  if (!field_dev || !dims) return fail(APC_E_INVALID, "null argument");
+  apc_handle probe;
+  apc_scheme def{};
+  def.kind = APC_PER_LEVEL;
+  def.degree = degree;
+  def.cd_axis = -1;
+  APC_TRY(setup_geometry(&probe, dims, ndim, &def));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (dtype == APC_F32) return tune_impl<float>((const float*)field_dev, dtype, probe.geo, degree, st, tile0, us0);
+  if (dtype == APC_F64) return tune_impl<double>((const double*)field_dev, dtype, probe.geo, degree, st, tile0, us0);
+  return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
+}
+
+extern "C" apc_status apc_tile_override(int32_t t2) {
+  if (t2 != 0 && t2 != 32 && t2 != 64 && t2 != 128) return fail(APC_E_INVALID, "tile width must be 0, 32, 64 or 128");
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_override = t2;
+  return APC_OK;
+}
+
+extern "C" apc_status apc_tile_width(int32_t dtype, int64_t m1, int64_t m2, int32_t* t2) {
+  if (!t2) return fail(APC_E_INVALID, "null argument");
+  *t2 = tile_for(dtype, (int)m1, (int)m2);
+  return APC_OK;
+}
 
 extern "C" apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
                                           int32_t mode, apc_scheme* out, void* hip_stream) {

@@ -11,7 +11,7 @@ namespace apc {
 
 constexpr int kChunk = 4096;        // codes per chunk (sign index granularity)
 constexpr int kBlockElems = 4096;   // lattice elements per work block (16 per thread)
-constexpr int kLvlT1 = 16, kLvlT2 = 64, kLvlCH = 32;  // per-level pass: tile rows, columns, longest run
+constexpr int kLvlCH = 32;  // per-level pass: longest run of planes along axis 0
 
 enum AxisKind : int32_t { AX_ALL = 0, AX_ODD = 1, AX_EVEN = 2 };
 
@@ -70,8 +70,8 @@ struct ReconSeg {
   int32_t pad;
 };
 
-// Per-level tensor-product pass over one (field, level): tiles of 16 x 64
-// points of (axis 1, axis 2) by runs of ch planes along axis 0.
+// Per-level tensor-product pass over one (field, level): tiles of
+// (1024 / t2) x t2 points of (axis 1, axis 2) by runs of ch planes along axis 0.
 struct LevelSeg {
   int32_t m[3];          // level grid dims
   int32_t mc[3];         // coarser level grid dims
@@ -158,7 +158,7 @@ hipError_t launch_gather(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_
 template <typename T, typename Q>
 hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename T, typename Q>
-hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
+hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, int t2, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename Q>

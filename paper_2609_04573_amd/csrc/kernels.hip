@@ -347,12 +347,14 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // MODE 0: max |x - p| of the level.  MODE 1: codes q = rint(c * 2^k_shift)
 // into the three region lattices.  MODE 2: x = p + Delta * q' on the level
 // grid (coarse points are copied).
-constexpr int kT1 = kLvlT1, kT2 = kLvlT2;
-constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
-constexpr int kCPer = (kC1 * kC2 + kThreads - 1) / kThreads;  // coarse tile entries per thread
-
-template <typename T, typename Q, int MODE>
+// Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
+// every thread owns one column and four consecutive rows.
+template <typename T, typename Q, int MODE, int kT2>
 __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  constexpr int kNRG = kThreads / kT2;  // row groups
+  constexpr int kT1 = 4 * kNRG;
+  constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
+  constexpr int kCPer = (kC1 * kC2 + kThreads - 1) / kThreads;  // coarse tile entries per thread
   using V = typename std::conditional<MODE == 2, Q, T>::type;  // per-point input: code or value
   __shared__ double ctile[kC1 * kC2];
   __shared__ double u2[kC1 * kT2];
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       }
     }
   };
-  const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;
+  const int tid = threadIdx.x, col = tid % kT2, rg = tid / kT2;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     if (MODE == 0 && si != cur) {
@@ -465,8 +467,8 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       if (cc + 1 < mc0) fetch_tile(cc + 1);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int r = rg + 4 * k;
+      for (int k = 0; k < (kC1 + kNRG - 1) / kNRG; ++k) {
+        const int r = rg + kNRG * k;
         if (r < kC1) {
           const double* row = ctile + r * kC2 + tc2;
           u2[r * kT2 + col] = odd2 ? stencil_eval(sk2, [&](int o) { return row[(o + 1) / 2]; }) : row[0];
@@ -1501,11 +1503,17 @@ hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hi
   if (mode == 0) APC_LAUNCH((k_coef<T, Q, 0>), nblk, segs, nseg, nblk);
   APC_LAUNCH((k_coef<T, Q, 1>), nblk, segs, nseg, nblk);
 }
+template <typename T, typename Q, int MODE>
+hipError_t launch_level_mode(const LevelSeg* segs, int nseg, int64_t nblk, int t2, hipStream_t s) {
+  if (t2 == 32) APC_LAUNCH((k_level<T, Q, MODE, 32>), nblk, segs, nseg, nblk);
+  if (t2 == 128) APC_LAUNCH((k_level<T, Q, MODE, 128>), nblk, segs, nseg, nblk);
+  APC_LAUNCH((k_level<T, Q, MODE, 64>), nblk, segs, nseg, nblk);
+}
 template <typename T, typename Q>
-hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s) {
-  if (mode == 0) APC_LAUNCH((k_level<T, Q, 0>), nblk, segs, nseg, nblk);
-  if (mode == 1) APC_LAUNCH((k_level<T, Q, 1>), nblk, segs, nseg, nblk);
-  APC_LAUNCH((k_level<T, Q, 2>), nblk, segs, nseg, nblk);
+hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, int t2, hipStream_t s) {
+  if (mode == 0) return launch_level_mode<T, Q, 0>(segs, nseg, nblk, t2, s);
+  if (mode == 1) return launch_level_mode<T, Q, 1>(segs, nseg, nblk, t2, s);
+  return launch_level_mode<T, Q, 2>(segs, nseg, nblk, t2, s);
 }
 template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s) {
@@ -1579,8 +1587,8 @@ template hipError_t launch_gather<float>(const FlatSeg*, int, int64_t, hipStream
 template hipError_t launch_gather<double>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_coef<float, int32_t>(const CoefSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coef<double, int64_t>(const CoefSeg*, int, int64_t, int, hipStream_t);
-template hipError_t launch_level<float, int32_t>(const LevelSeg*, int, int64_t, int, hipStream_t);
-template hipError_t launch_level<double, int64_t>(const LevelSeg*, int, int64_t, int, hipStream_t);
+template hipError_t launch_level<float, int32_t>(const LevelSeg*, int, int64_t, int, int, hipStream_t);
+template hipError_t launch_level<double, int64_t>(const LevelSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_coarse<float, int32_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coarse<double, int64_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_cd_forward<int32_t>(const CDSeg*, int, int64_t, int, hipStream_t);

@@ -117,3 +117,34 @@ def test_select_pipeline_2d_matches_oracle():
     assert (got.kind, got.cd_axis) == (want.kind, want.cd_axis)
     if want.kind == "region":
         assert tuple(got.order) == tuple(want.order)
+
+
+def test_tile_widths_do_not_change_results(config1_field):
+    """Every sweep tile width gives the oracle's streams and reconstructions;
+    the autotuner picks one of them and records it for the level shape."""
+    apc = _apc()
+    fields = [config1_field, fieldgen.zonal_bands((130, 300), seed=5), fieldgen.power_law_field((33, 70, 150), seed=6)]
+    try:
+        for x in fields:
+            sc = oracle.Scheme(kind="level", cd_axis=0)
+            ref = oracle.refactor(x, sc)
+            want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", 1e-4)))
+            xd = torch.from_numpy(x).cuda()
+            for t2 in (32, 64, 128):
+                apc.tile_override(t2)
+                h = apc.refactor(xd, apc.Scheme(kind="level", cd_axis=0))
+                for s, st in enumerate(ref.streams):
+                    assert h.stream_blob(s) == st.blob, (x.shape, t2, s)
+                got, _ = h.retrieve(apc.Target("rel", 1e-4))
+                assert np.array_equal(got.cpu().numpy().view(np.uint32), want.view(np.uint32)), (x.shape, t2)
+                h.close()
+        apc.tile_override(0)
+        big = torch.from_numpy(fieldgen.power_law_field((64, 128, 256), seed=7)).cuda()
+        r = apc.tune_tiles(big)
+        assert r["tile"] in (32, 64, 128)
+        assert all(v > 0 for v in r["us"].values())
+        assert apc.tile_width(torch.float32, 128, 256) == r["tile"]
+        with pytest.raises(apc.ApcError):
+            apc.tile_override(48)
+    finally:
+        apc.tile_override(0)
