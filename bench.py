@@ -242,6 +242,10 @@ def batch_leg(apc, torch, fieldgen, full: bool):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, hs
 
+    # sweep tiles: time every width on one field of each shape class (not timed)
+    tiles = {}
+    for x in (xs[0], xs[n2], xs[-1]):
+        tiles["x".join(map(str, x.shape))] = apc.tune_tiles(x)["tile"]
     for fn in (per_field, batched):  # warm-up
         _, hs = fn()
         for h in hs:
@@ -255,7 +259,7 @@ def batch_leg(apc, torch, fieldgen, full: bool):
         h.close()
     return {"fields": len(xs), "GB": nbytes / 1e9, "per_field_s": tp, "batched_s": tb,
             "per_field_GBps": nbytes / tp / 1e9, "batched_GBps": nbytes / tb / 1e9, "speedup": tp / tb,
-            "identical_output": bool(same),
+            "identical_output": bool(same), "tuned_tiles": tiles,
             "workload": f"{n2} x 1800x3600 zonal bands + k^-3, {n3} x 100x500x500 and {nc} cubes 64..384 "
                         "k^-5/3, seed 2; per-level cubic + decomposition axis 0"}
 
@@ -364,6 +368,7 @@ def main():
         h.close()
         return t1 - t0, t2 - t1, info, streams
 
+    tune = apc.tune_tiles(xd)  # sweep tile width for this shape (setup, not timed)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -402,6 +407,7 @@ def main():
             "field_dtype": "float32",
             "points": int(x.size),
         },
+        "sweep_tile": {"chosen": tune["tile"], "level0_max_pass_us": tune["us"]},
         "refactor_GBps": nbytes / t_ref / 1e9,
         "refactor_hbm_frac": ref_alg / t_ref / HBM_PEAK,
         "retrieve_GBps": nbytes / t_ret / 1e9,
