@@ -222,6 +222,9 @@ apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out,
  * and write)} as JSON, then clears the records.  Not thread-safe. */
 apc_status apc_profile_enable(int32_t on);
 apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len);
+/* Restrict profiling to launches of one kernel name (as reported above);
+ * NULL or "" profiles every launch. */
+apc_status apc_profile_only(const char* name);
 
 #ifdef __cplusplus
 }

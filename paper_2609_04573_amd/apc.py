@@ -42,7 +42,7 @@ EXPORTED = [
     "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
-    "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
+    "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width", "apc_profile_only",
 ]
 
 
@@ -103,12 +103,14 @@ _lib.apc_profile_report.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_i64)]
 _lib.apc_tune_tiles.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, _vp, ctypes.POINTER(_i32),
                                 ctypes.POINTER(ctypes.c_double)]
 _lib.apc_tile_override.argtypes = [_i32]
+_lib.apc_profile_only.argtypes = [ctypes.c_char_p]
 _lib.apc_tile_width.argtypes = [_i32, _i64, _i64, ctypes.POINTER(_i32)]
 for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline",
               "apc_stream_info", "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable",
               "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
-              "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width"):
+              "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
+              "apc_profile_only"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -407,6 +409,11 @@ def axis_norms(n: int, L: int, degree: int) -> Tuple[List[float], List[float]]:
 
 def profile_enable(on: bool = True) -> None:
     _check(_lib.apc_profile_enable(1 if on else 0))
+
+
+def profile_only(name=None) -> None:
+    """Time only launches of this kernel name (None: every launch)."""
+    _check(_lib.apc_profile_only(name.encode() if name else None))
 
 
 def profile_report() -> dict:

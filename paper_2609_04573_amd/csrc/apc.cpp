@@ -64,6 +64,7 @@ struct ProfRec {
 };
 struct Profiler {
   bool on = false;
+  std::string only;  // if set, only launches of this name are timed
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get() {
@@ -84,6 +85,7 @@ struct ProfMark {
   hipStream_t st;
   ProfMark(const char* name, double bytes, hipStream_t s) : st(s) {
     if (!g_prof.on) return;
+    if (!g_prof.only.empty() && g_prof.only != name) return;
     ProfRec r{name, g_prof.get(), g_prof.get(), bytes};
     (void)hipEventRecord(r.a, st);
     g_prof.recs.push_back(r);
@@ -278,6 +280,48 @@ struct CDInfo {
   int64_t reg_off;   // offset of the region in the recomposition buffer
 };
 
+// Pinned host blocks for table uploads.  Pinning is slow (it dominates a
+// small retrieval), so blocks are pooled for the life of the process; each
+// carries an event recorded after the last copy queued out of it, and a
+// block is handed out again only once that event has completed.
+struct PinnedBlock {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+};
+struct PinnedPool {
+  std::mutex mu;
+  std::vector<PinnedBlock> free_;
+  apc_status get(size_t bytes, PinnedBlock& out) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      int best = -1;
+      for (int i = 0; i < (int)free_.size(); ++i)
+        if (free_[i].cap >= bytes && (best < 0 || free_[i].cap < free_[best].cap)) best = i;
+      if (best >= 0) {
+        out = free_[best];
+        free_.erase(free_.begin() + best);
+      }
+    }
+    if (out.p) return hipEventSynchronize(out.ev) == hipSuccess ? APC_OK : APC_E_HIP;
+    size_t cap = (size_t)1 << 16;
+    while (cap < bytes) cap <<= 1;
+    if (hipHostMalloc(&out.p, cap) != hipSuccess) return APC_E_OOM;
+    out.cap = cap;
+    if (hipEventCreateWithFlags(&out.ev, hipEventDisableTiming) != hipSuccess) return APC_E_HIP;
+    return APC_OK;
+  }
+  // return a block; st: the stream its last copy was queued on (null: none pending)
+  void put(PinnedBlock& b, hipStream_t st, bool pending) {
+    if (!b.p) return;
+    if (pending) (void)hipEventRecord(b.ev, st);
+    std::lock_guard<std::mutex> lk(mu);
+    free_.push_back(b);
+    b = PinnedBlock();
+  }
+};
+PinnedPool g_pinned;
+
 struct apc_handle {
   Meta meta;
   Geo geo;
@@ -296,13 +340,8 @@ struct apc_handle {
   std::vector<int> k_res;
   DevBuf xc, xb[2], pr[2], cdreg, tables;
   bool work_ready = false;
-  void* pinned = nullptr;  // staging of table uploads
-  size_t pinned_bytes = 0;
-  hipEvent_t upload_done = nullptr;
-  ~apc_handle() {
-    if (pinned) (void)hipHostFree(pinned);
-    if (upload_done) (void)hipEventDestroy(upload_done);
-  }
+  PinnedBlock pinned;  // staging of table uploads (its event follows the last upload)
+  ~apc_handle() { g_pinned.put(pinned, nullptr, false); }
 };
 
 namespace {
@@ -463,25 +502,23 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
 // Pinned staging that stays valid until the process ends; append-only
 // within one refactor call.
 struct Staging {
-  void* p = nullptr;
-  size_t cap = 0, used = 0;
-  ~Staging() {
-    if (p) (void)hipHostFree(p);
-  }
+  PinnedBlock b;
+  size_t used = 0;
+  hipStream_t last = nullptr;
+  ~Staging() { g_pinned.put(b, last, last != nullptr); }
   apc_status put(const std::vector<char>& bytes, void* dev, hipStream_t st) {
     if (bytes.empty()) return APC_OK;
-    if (used + bytes.size() > cap) {
-      // grow: the old buffer may still feed queued copies, so wait first
-      HIP_TRY(hipStreamSynchronize(st));
-      if (p) (void)hipHostFree(p);
-      cap = std::max<size_t>(bytes.size() * 2, (size_t)1 << 20);
-      HIP_TRY(hipHostMalloc(&p, cap));
+    if (used + bytes.size() > b.cap) {
+      // the old block may still feed queued copies: its event guards reuse
+      g_pinned.put(b, last, last != nullptr);
+      APC_TRY(g_pinned.get(std::max<size_t>(bytes.size() * 2, (size_t)1 << 20), b));
       used = 0;
     }
-    char* dst = (char*)p + used;
+    char* dst = (char*)b.p + used;
     memcpy(dst, bytes.data(), bytes.size());
     used += (bytes.size() + 255) & ~(size_t)255;
     HIP_TRY(hipMemcpyAsync(dev, dst, bytes.size(), hipMemcpyHostToDevice, st));
+    last = st;
     return APC_OK;
   }
 };
@@ -1250,7 +1287,6 @@ apc_status ensure_work(apc_handle* h) {
     }
     if (h->cdreg_n) APC_TRY(h->cdreg.alloc(qs * (size_t)h->cdreg_n));
   }
-  HIP_TRY(hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming));
   h->work_ready = true;
   return APC_OK;
 }
@@ -1442,20 +1478,16 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
 
 apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStream_t st) {
   if (bytes.empty()) return APC_OK;
-  if (h->pinned_bytes < bytes.size()) {
-    if (h->pinned) {
-      HIP_TRY(hipEventSynchronize(h->upload_done));
-      (void)hipHostFree(h->pinned);
-    }
-    h->pinned_bytes = std::max<size_t>(bytes.size() * 2, 1 << 16);
-    HIP_TRY(hipHostMalloc(&h->pinned, h->pinned_bytes));
+  if (h->pinned.cap < bytes.size()) {
+    g_pinned.put(h->pinned, nullptr, false);  // its event already follows its last upload
+    APC_TRY(g_pinned.get(bytes.size() * 2, h->pinned));
   } else {
-    HIP_TRY(hipEventSynchronize(h->upload_done));  // the previous copy has left the staging
+    HIP_TRY(hipEventSynchronize(h->pinned.ev));  // the previous copy has left the staging
   }
-  memcpy(h->pinned, bytes.data(), bytes.size());
+  memcpy(h->pinned.p, bytes.data(), bytes.size());
   APC_TRY(h->tables.alloc(bytes.size()));
-  HIP_TRY(hipMemcpyAsync(h->tables.p, h->pinned, bytes.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(h->upload_done, st));
+  HIP_TRY(hipMemcpyAsync(h->tables.p, h->pinned.p, bytes.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(h->pinned.ev, st));
   return APC_OK;
 }
 
@@ -1769,6 +1801,11 @@ apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out,
 
 apc_status apc_profile_enable(int32_t on) {
   g_prof.on = on != 0;
+  return APC_OK;
+}
+
+apc_status apc_profile_only(const char* name) {
+  g_prof.only = name ? name : "";
   return APC_OK;
 }
 
@@ -2118,33 +2155,25 @@ struct SrvRequest {
 
 struct SrvStaging {  // device table buffer fed from pinned memory
   DevBuf dev;
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t copied = nullptr;
-  bool used = false;
-  ~SrvStaging() {
-    if (pinned) (void)hipHostFree(pinned);
-    if (copied) (void)hipEventDestroy(copied);
-  }
+  PinnedBlock pinned;  // its event follows the last copy out of it
+  ~SrvStaging() { g_pinned.put(pinned, nullptr, false); }
   apc_status put(const std::vector<char>& b, hipStream_t st) {
     if (b.empty()) return APC_OK;
-    if (!copied) HIP_TRY(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
-    if (used) HIP_TRY(hipEventSynchronize(copied));
-    if (pinned_bytes < b.size()) {
-      if (pinned) (void)hipHostFree(pinned);
-      pinned_bytes = std::max<size_t>(2 * b.size(), 1 << 16);
-      HIP_TRY(hipHostMalloc(&pinned, pinned_bytes));
+    if (pinned.cap < b.size()) {
+      g_pinned.put(pinned, nullptr, false);
+      APC_TRY(g_pinned.get(2 * b.size(), pinned));
+    } else {
+      HIP_TRY(hipEventSynchronize(pinned.ev));
     }
-    memcpy(pinned, b.data(), b.size());
+    memcpy(pinned.p, b.data(), b.size());
     if (dev.bytes < b.size()) {
       // the old table may still be read by queued work on this stream: the
       // pool hands it out again only after the device has moved past it
       HIP_TRY(hipStreamSynchronize(st));
       APC_TRY(dev.alloc(b.size()));
     }
-    HIP_TRY(hipMemcpyAsync(dev.p, pinned, b.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(copied, st));
-    used = true;
+    HIP_TRY(hipMemcpyAsync(dev.p, pinned.p, b.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(pinned.ev, st));
     return APC_OK;
   }
 };
