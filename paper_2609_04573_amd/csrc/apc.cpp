@@ -292,7 +292,8 @@ struct PinnedBlock {
 struct PinnedPool {
   std::mutex mu;
   std::vector<PinnedBlock> free_;
-  apc_status get(size_t bytes, PinnedBlock& out) {
+  // a block of at least `bytes`; pooled blocks are idle (their copies done)
+  bool get(size_t bytes, PinnedBlock& out) {
     {
       std::lock_guard<std::mutex> lk(mu);
       int best = -1;
@@ -301,20 +302,31 @@ struct PinnedPool {
       if (best >= 0) {
         out = free_[best];
         free_.erase(free_.begin() + best);
+        return true;
       }
     }
-    if (out.p) return hipEventSynchronize(out.ev) == hipSuccess ? APC_OK : APC_E_HIP;
     size_t cap = (size_t)1 << 16;
     while (cap < bytes) cap <<= 1;
-    if (hipHostMalloc(&out.p, cap) != hipSuccess) return APC_E_OOM;
+    if (hipHostMalloc(&out.p, cap) != hipSuccess) {
+      out = PinnedBlock();
+      return false;
+    }
     out.cap = cap;
-    if (hipEventCreateWithFlags(&out.ev, hipEventDisableTiming) != hipSuccess) return APC_E_HIP;
-    return APC_OK;
+    if (hipEventCreateWithFlags(&out.ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(out.p);
+      out = PinnedBlock();
+      return false;
+    }
+    return true;
   }
-  // return a block; st: the stream its last copy was queued on (null: none pending)
+  // Return a block once the copies queued out of it are done (`pending`:
+  // the last one was queued on stream st and not yet marked by its event).
+  // Waiting here keeps pooled blocks free of events on streams that may be
+  // destroyed later.
   void put(PinnedBlock& b, hipStream_t st, bool pending) {
     if (!b.p) return;
     if (pending) (void)hipEventRecord(b.ev, st);
+    (void)hipEventSynchronize(b.ev);
     std::lock_guard<std::mutex> lk(mu);
     free_.push_back(b);
     b = PinnedBlock();
@@ -511,7 +523,8 @@ struct Staging {
     if (used + bytes.size() > b.cap) {
       // the old block may still feed queued copies: its event guards reuse
       g_pinned.put(b, last, last != nullptr);
-      APC_TRY(g_pinned.get(std::max<size_t>(bytes.size() * 2, (size_t)1 << 20), b));
+      if (!g_pinned.get(std::max<size_t>(bytes.size() * 2, (size_t)1 << 20), b))
+        return fail(APC_E_OOM, "pinned staging of %zu bytes", bytes.size());
       used = 0;
     }
     char* dst = (char*)b.p + used;
@@ -1480,7 +1493,7 @@ apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStrea
   if (bytes.empty()) return APC_OK;
   if (h->pinned.cap < bytes.size()) {
     g_pinned.put(h->pinned, nullptr, false);  // its event already follows its last upload
-    APC_TRY(g_pinned.get(bytes.size() * 2, h->pinned));
+    if (!g_pinned.get(bytes.size() * 2, h->pinned)) return fail(APC_E_OOM, "pinned staging of %zu bytes", bytes.size());
   } else {
     HIP_TRY(hipEventSynchronize(h->pinned.ev));  // the previous copy has left the staging
   }
@@ -2161,7 +2174,7 @@ struct SrvStaging {  // device table buffer fed from pinned memory
     if (b.empty()) return APC_OK;
     if (pinned.cap < b.size()) {
       g_pinned.put(pinned, nullptr, false);
-      APC_TRY(g_pinned.get(2 * b.size(), pinned));
+      if (!g_pinned.get(2 * b.size(), pinned)) return fail(APC_E_OOM, "pinned staging of %zu bytes", b.size());
     } else {
       HIP_TRY(hipEventSynchronize(pinned.ev));
     }
