@@ -8,6 +8,11 @@ decomposition (Section V-B, Algorithm 1), generic bitplane encoding
 reconstruction (Algorithm 2), plus target-driven pipeline selection
 (Section VI-A).
 
+Parity unpinned: ``select_pipeline``'s vote and the greedy order in which the
+interpreter takes planes.  The paper gives no example or closed form for
+either (only their inputs and guarantees are pinned: plan sizes, nesting,
+and the error bound of every plan).
+
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
 and never imports it; the two meet only on seeded inputs from ``fieldgen``.
