@@ -415,10 +415,18 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
     const int f0a = (lb / S.nt1) * S.ch;
     const int f0b = min(m0, f0a + S.ch);
     const int c1s = t1 / 2 - 1, c2s = t2 / 2 - 1;
-    // per-region operands, held in registers (a lane picks one by its region)
+    // segment operands, held in registers (stores through the segment's
+    // pointers must not force the table to be reloaded; a lane picks the
+    // operands of its region)
     Q* const qr[3] = {(Q*)S.q[0], (Q*)S.q[1], (Q*)S.q[2]};
     const int Br[3] = {S.B[0], S.B[1], S.B[2]}, kr[3] = {S.k[0], S.k[1], S.k[2]};
     auto qptr = [&](int rr) -> GAS Q* { return (GAS Q*)(rr == 0 ? qr[0] : (rr == 1 ? qr[1] : qr[2])); };
+    const void* const src = S.src;
+    void* const outp = S.out;
+    const int64_t xs0 = S.xs[0], xs1 = S.xs[1], xs2 = S.xs[2];
+    const bool fin = S.final_out != 0;
+    const double delta = S.delta;
+    const int kshift = S.k_shift;
 
     // in-plane geometry of this thread (constant along axis 0)
     const int f2 = t2 + col;
@@ -432,6 +440,35 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       sk1[i] = (f1 & 1) ? stencil_kind(f1, m1, deg) : 0;
       tr1[i] = (f1 & 1) ? ((f1 - 1) >> 1) - c1s : (f1 >> 1) - c1s;
     }
+    // offsets of the thread's four points, split into a per-plane part and a
+    // part fixed along axis 0 (all below 2^32: fields hold < 2^32 points):
+    // grid offset = f0 * m1 * m2 + rg2[i]; region lattice index = c * P + R
+    // with c = f0 / 2 (region 2 on odd planes; region 0 or 1, or a coarse
+    // point, on even planes); source offset = f0 * xs0 + rsrc[i]
+    const uint32_t pl2 = (uint32_t)m1 * (uint32_t)m2;
+    uint32_t rg2[4], re[4], pe[4], rsrc[4];
+    int rre[4];
+    bool okp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f1 = t1 + 4 * rg + i;
+      okp[i] = f1 < m1 && f2 < m2;
+      rg2[i] = (uint32_t)f1 * (uint32_t)m2 + (uint32_t)f2;
+      rsrc[i] = (uint32_t)((int64_t)f1 * xs1 + (int64_t)f2 * xs2);
+      if (f1 & 1) {
+        rre[i] = 1;
+        pe[i] = (uint32_t)(m1 >> 1) * (uint32_t)m2;
+        re[i] = (uint32_t)(f1 >> 1) * (uint32_t)m2 + (uint32_t)f2;
+      } else if (odd2) {
+        rre[i] = 0;
+        pe[i] = (uint32_t)((m1 + 1) >> 1) * (uint32_t)(m2 >> 1);
+        re[i] = (uint32_t)(f1 >> 1) * (uint32_t)(m2 >> 1) + (uint32_t)(f2 >> 1);
+      } else {
+        rre[i] = -1;
+        pe[i] = 0;
+        re[i] = 0;
+      }
+    }
     // coarse tile entries of this thread: global offsets within a plane (-1 = outside the grid)
     int64_t coff[kCPer];
 #pragma unroll
@@ -441,9 +478,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       const int c1 = c1s + r, c2 = c2s + kk;
       coff[k] = -1;
       if (e < kC1 * kC2 && c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2)
-        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * S.xs[1] + (int64_t)(2 * c2) * S.xs[2];
+        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * xs1 + (int64_t)(2 * c2) * xs2;
     }
-    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : 2 * S.xs[0];  // coarse plane stride
+    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
     double cpre[kCPer];
     auto fetch_tile = [&](int cc) {
 #pragma unroll
@@ -451,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         cpre[k] = 0.0;
         if (coff[k] >= 0) {
           const int64_t o = (int64_t)cc * cplane + coff[k];
-          cpre[k] = MODE == 2 ? ((const GAS double*)S.src)[o] : (double)((const GAS T*)S.src)[o];
+          cpre[k] = MODE == 2 ? ((const GAS double*)src)[o] : (double)((const GAS T*)src)[o];
           if (MODE == 0 && racc) take(cpre[k]);
         }
       }
@@ -482,65 +519,51 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       }
     };
 
-    // point (f0, i): region (-1 = a coarse point), lattice index, grid offset
-    auto locate = [&](int f0, int i, int& rr, int64_t& li, int64_t& o) -> bool {
-      const int f1 = t1 + 4 * rg + i;
-      if (f0 >= f0b || f1 >= m1 || f2 >= m2) return false;
-      o = ((int64_t)f0 * m1 + f1) * m2 + f2;
-      if (f0 & 1) {
-        rr = 2;
-        li = ((int64_t)(f0 >> 1) * m1 + f1) * m2 + f2;
-      } else if (f1 & 1) {
-        rr = 1;
-        li = ((int64_t)(f0 >> 1) * (m1 >> 1) + (f1 >> 1)) * m2 + f2;
-      } else if (odd2) {
-        rr = 0;
-        li = ((int64_t)(f0 >> 1) * ((m1 + 1) >> 1) + (f1 >> 1)) * (m2 >> 1) + (f2 >> 1);
-      } else {
-        rr = -1;
-        li = 0;
-      }
-      return true;
-    };
-    // inputs of the two fine planes 2c and 2c + 1
+    // inputs of the two fine planes 2c and 2c + 1 (codes, or the field's values)
     V in[8];
     auto fetch_points = [&](int c) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
+        const int f0 = 2 * c + h;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          int rr;
-          int64_t li, o;
           in[h * 4 + i] = (V)0;
-          if (locate(2 * c + h, i, rr, li, o) && rr >= 0)
-            in[h * 4 + i] = MODE == 2 ? (V)qptr(rr)[li]
-                                      : (V)((const GAS T*)S.src)[(int64_t)(2 * c + h) * S.xs[0] +
-                                                                  (int64_t)(t1 + 4 * rg + i) * S.xs[1] +
-                                                                  (int64_t)f2 * S.xs[2]];
+          const int rr = h ? 2 : rre[i];
+          if (f0 >= f0b || !okp[i] || rr < 0) continue;
+          if (MODE == 2) {
+            const uint32_t li = (uint32_t)c * (h ? pl2 : pe[i]) + (h ? rg2[i] : re[i]);
+            in[h * 4 + i] = (V)qptr(rr)[li];
+          } else {
+            in[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc[i]];
+          }
         }
+      }
     };
     auto emit = [&](int f0, int i, double p, V v) {
-      int rr;
-      int64_t li, o;
-      if (!locate(f0, i, rr, li, o)) return;
+      const int h = f0 & 1;
+      if (f0 >= f0b || !okp[i]) return;
+      const int rr = h ? 2 : rre[i];
       if (MODE == 2) {
         double x = p;  // a coarse point keeps its reconstructed value
         if (rr >= 0) {
           const int B = rr == 0 ? Br[0] : (rr == 1 ? Br[1] : Br[2]);
           const int k = rr == 0 ? kr[0] : (rr == 1 ? kr[1] : kr[2]);
-          x = p + (double)mask_code<Q>((Q)v, B, k) * S.delta;
+          x = p + (double)mask_code<Q>((Q)v, B, k) * delta;
         }
-        if (S.final_out)
-          ((GAS T*)S.out)[o] = (T)x;
+        const uint32_t o = (uint32_t)f0 * pl2 + rg2[i];
+        if (fin)
+          ((GAS T*)outp)[o] = (T)x;
         else
-          ((GAS double*)S.out)[o] = x;
+          ((GAS double*)outp)[o] = x;
       } else if (rr >= 0) {
         const double c = (double)v - p;
         if (MODE == 0 && racc) take((double)v);
-        if (MODE == 0)
+        if (MODE == 0) {
           am = fmax(am, fabs(c));
-        else
-          qptr(rr)[li] = (Q)(long long)rint(ldexp(c, S.k_shift));
+        } else {
+          const uint32_t li = (uint32_t)(f0 >> 1) * (h ? pl2 : pe[i]) + (h ? rg2[i] : re[i]);
+          qptr(rr)[li] = (Q)(long long)rint(ldexp(c, kshift));
+        }
       }
     };
 
