@@ -740,10 +740,12 @@ __device__ __forceinline__ W cd_combine(const CDNb& n, W h00, W h01, W h10, W h1
   return n.hr ? avgw<W>(a, b) : a;
 }
 
+// Row geometry.  A region lattice holds at most half of a field's points
+// (< 2^31), so offsets inside it are 32-bit.
 struct CDGeo {
   int t0, t1;          // row
   int Nu, Nv;
-  int64_t su, sv;      // lattice strides of u and v
+  int su, sv;          // lattice strides of u and v
   int64_t rowoff;      // lattice offset of (t0, t1, 0)
 };
 template <int A>
@@ -754,7 +756,7 @@ __device__ __forceinline__ CDGeo cd_geo(const CDSeg& S, uint32_t row) {
   g.t1 = (int)(row - (uint32_t)g.t0 * (uint32_t)S.c[1]);
   g.Nu = S.c[U];
   g.Nv = S.c[V];
-  const int64_t st[3] = {(int64_t)S.c[1] * S.c[2], (int64_t)S.c[2], 1};
+  const int st[3] = {S.c[1] * S.c[2], S.c[2], 1};
   g.su = st[U];
   g.sv = st[V];
   g.rowoff = (int64_t)row * S.c[2];
@@ -794,7 +796,8 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
                           (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, g.t0, g.t1),
                           (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, g.t0, g.t1)};
     const GAS Q* R = (const GAS Q*)S.R + g.rowoff;
-    for (int t2b = 0; t2b < S.c[2]; t2b += 64 * kCDBatch) {
+    const int c2 = S.c[2];
+    for (int t2b = 0; t2b < c2; t2b += 64 * kCDBatch) {
       W x[kCDBatch], h[kCDBatch][4];
       CDNb nb[kCDBatch];
       int cls[kCDBatch];
@@ -806,7 +809,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
         nb[i] = cls[i] == 1 ? cd_nb_s2(u, v, g.Nu, g.Nv) : cd_nb_s3(u, v, g.Nu, g.Nv);
         x[i] = 0;
         h[i][0] = h[i][1] = h[i][2] = h[i][3] = 0;
-        if (t2 < S.c[2]) {
+        if (t2 < c2) {
           const GAS Q* p = R + t2;
           x[i] = (W)p[0];
           if (cls[i] != 0) {
@@ -821,11 +824,11 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
 #pragma unroll
       for (int i = 0; i < kCDBatch; ++i) {
         const int t2 = t2b + lane + 64 * i;
-        if (t2 >= S.c[2]) continue;
+        if (t2 >= c2) continue;
         W res = x[i];
         if (cls[i] != 0) res -= cd_combine<W>(nb[i], h[i][0], h[i][1], h[i][2], h[i][3]);
         GAS Q* dst = cls[i] == 0 ? so[0] : (cls[i] == 1 ? so[1] : so[2]);
-        dst[cd_in_row<A>(cls[i], u, t2)] = (Q)res;
+        dst[(int)cd_in_row<A>(cls[i], u, t2)] = (Q)res;
         const UW mag = res < 0 ? (UW)(-res) : (UW)res;
         am[cls[i]] = am[cls[i]] > mag ? am[cls[i]] : mag;
       }
@@ -1125,7 +1128,10 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   const int64_t chunk = gch - S.chunk_begin;
   const GAS Q* src = (const GAS Q*)S.codes;
   GAS uint64_t* mag = (GAS uint64_t*)S.mag;
+  GAS uint32_t* cnt = (GAS uint32_t*)S.cnt;
+  GAS uint64_t* stg = (GAS uint64_t*)S.stage;
   const int B = S.B;
+  const int64_t M = S.M, n = S.n;
   const int64_t base = chunk * kChunk;
   const int64_t w = chunk * 64 + lane;
   sstage[lane] = 0ull;
@@ -1138,7 +1144,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   for (int i = 0; i < 16; ++i) lead[i] = 0u;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    stage_half<Q>(src, base, S.n, h, cst, lane);
+    stage_half<Q>(src, base, n, h, cst, lane);
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < QW; ++p) {
@@ -1170,12 +1176,12 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     if (b >= B) continue;
     const int j = B - 1 - b;
     const uint64_t pw = P[b];
-    if (w < S.M) mag[(int64_t)j * S.M + w] = pw;
+    if (w < M) mag[(int64_t)j * M + w] = pw;
     const uint32_t c = (uint32_t)__popcll(pw & ~sig);
     sig |= pw;
     const uint32_t incl = wave_incl_scan(c, lane);
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (lane == 0) ((GAS uint32_t*)S.cnt)[chunk * B + j] = tot;
+    if (lane == 0) cnt[chunk * B + j] = tot;
     ptab[j * 64 + lane] = toff + incl - c;
     toff += tot;
   }
@@ -1197,7 +1203,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
     }
   }
   __syncthreads();
-  ((GAS uint64_t*)S.stage)[chunk * 64 + lane] = sstage[lane];
+  stg[chunk * 64 + lane] = sstage[lane];
 }
 
 // Exclusive scan of the per-chunk counts of one (stream, plane): the index
@@ -1208,13 +1214,14 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   const int job = blockIdx.x;
   const StreamDev& S = sd[job_s[job]];
   const int j = job_j[job];
+  const int64_t C = S.C, B = S.B;
   const GAS uint32_t* c = (const GAS uint32_t*)S.cnt + j;  // chunk-major: entry i at i * B
-  GAS uint32_t* o = (GAS uint32_t*)S.idx + (int64_t)j * S.C;
+  GAS uint32_t* o = (GAS uint32_t*)S.idx + (int64_t)j * C;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint64_t carry = 0;
-  for (int64_t base = 0; base < S.C; base += kThreads) {
+  for (int64_t base = 0; base < C; base += kThreads) {
     const int64_t i = base + threadIdx.x;
-    const uint32_t v = (i < S.C) ? c[i * S.B] : 0u;
+    const uint32_t v = (i < C) ? c[i * B] : 0u;
     const uint32_t incl = wave_incl_scan(v, lane);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
@@ -1223,7 +1230,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
       if (w < wave) before += wsum[w];
       all += wsum[w];
     }
-    if (i < S.C) o[i] = (uint32_t)(carry + before + incl - v);
+    if (i < C) o[i] = (uint32_t)(carry + before + incl - v);
     carry += all;
     __syncthreads();
   }
@@ -1267,7 +1274,8 @@ __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ 
   }
   const uint32_t sbj = wave_incl_scan(cj, lane) - cj;
   __syncthreads();
-  for (int j = 0; j < S.B; ++j) {
+  const int B = S.B;
+  for (int j = 0; j < B; ++j) {
     const int64_t c = (uint32_t)__builtin_amdgcn_readlane((int)cj, j);
     if (c == 0) continue;
     const int64_t D = readlane64(Dj, j);
@@ -1313,6 +1321,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   const GAS int64_t* pso = (const GAS int64_t*)S.pso;
   const int B = S.B, k0 = S.k0, k1 = S.k1;
   const bool fresh = S.fresh != 0;
+  const int64_t M = S.M, C = S.C, n = S.n, sign_n = S.sign_n;
   const int64_t base = chunk * kChunk;
   const int64_t w = chunk * 64 + lane;
 
@@ -1321,7 +1330,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   if (!fresh) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      stage_half<Q>(dst, base, S.n, h, cst, lane);
+      stage_half<Q>(dst, base, n, h, cst, lane);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < 32; ++k)
@@ -1333,11 +1342,11 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = B - 1 - b;
-    P[b] = (b < B && j >= k0 && j < k1 && w < S.M) ? mag[(int64_t)j * S.M + w] : 0ull;
+    P[b] = (b < B && j >= k0 && j < k1 && w < M) ? mag[(int64_t)j * M + w] : 0ull;
   }
   // lane j: first sign bit of plane j's run for this chunk (all planes at once)
   int64_t Dl = 0;
-  if (lane >= k0 && lane < k1) Dl = pso[lane] * 64 + (int64_t)idx[(int64_t)lane * S.C + chunk];
+  if (lane >= k0 && lane < k1) Dl = pso[lane] * 64 + (int64_t)idx[(int64_t)lane * C + chunk];
   // newcomer counts -> cursors; runs of sign words to fetch
   uint32_t woff = 0;
   int np = 0;
@@ -1373,14 +1382,14 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
         hi = mid - 1;
     }
     const int64_t gw = pw0[lo] + (int64_t)(i - pwoff[lo]);
-    sw[i] = (gw >= 0 && gw < S.sign_n) ? sign[gw] : 0ull;
+    sw[i] = (gw >= 0 && gw < sign_n) ? sign[gw] : 0ull;
   }
   __syncthreads();
 
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (!fresh) {
-      stage_half<Q>(dst, base, S.n, h, cst, lane);
+      stage_half<Q>(dst, base, n, h, cst, lane);
       __syncthreads();
     }
     uint32_t nb[QW][32];
@@ -1406,7 +1415,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
       cst[lane * kRow + k] = neg ? (Q)(-(int64_t)mg) : (Q)mg;
     }
     __syncthreads();
-    unstage_half<Q>(dst, base, S.n, h, cst, lane);
+    unstage_half<Q>(dst, base, n, h, cst, lane);
     __syncthreads();
   }
 }
