@@ -326,7 +326,19 @@ struct PinnedPool {
   void put(PinnedBlock& b, hipStream_t st, bool pending) {
     if (!b.p) return;
     if (pending) (void)hipEventRecord(b.ev, st);
-    (void)hipEventSynchronize(b.ev);
+    if (hipEventSynchronize(b.ev) != hipSuccess) {
+      // the event is unusable (its stream is gone): replace it, and clear
+      // the error so it is not reported by an unrelated later call
+      (void)hipGetLastError();
+      (void)hipEventDestroy(b.ev);
+      b.ev = nullptr;
+      if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(b.p);
+        b = PinnedBlock();
+        return;
+      }
+    }
     std::lock_guard<std::mutex> lk(mu);
     free_.push_back(b);
     b = PinnedBlock();
@@ -2451,6 +2463,9 @@ void apc_server_destroy(apc_server* sv) {
   }
   sv->worker.join();
   (void)hipDeviceSynchronize();
+  // staging goes back to the pool while the streams its events name exist
+  for (auto& s : sv->slots) g_pinned.put(s->tab.pinned, nullptr, false);
+  for (auto& f : sv->fields) g_pinned.put(f->tab.pinned, nullptr, false);
   for (SrvRequest* r : [&] {
          std::vector<SrvRequest*> v;
          for (auto& kv : sv->reqs) v.push_back(kv.second.get());

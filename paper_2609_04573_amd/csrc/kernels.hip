@@ -987,25 +987,27 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const GAS Q* S1 = (const GAS Q*)S.S[0];
     const GAS Q* S2 = (const GAS Q*)S.S[1];
     const GAS Q* S3 = (const GAS Q*)S.S[2];
+    const int B0 = S.B[0], K0 = S.k[0], B1 = S.B[1], K1 = S.k[1], B2 = S.B[2], K2 = S.k[2];
+    GAS Q* const Rout = (GAS Q*)S.Rout;
     for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
       const int r = e / kCIHV, k = e - r * kCIHV;
       const int u = U0 + 2 * r, v = V0 + 2 * k;
       W val = 0;
       if (u < Nu && v < Nv) {
         auto s1 = [&](int du, int dv) -> W {
-          return (W)mask_code<Q>(S1[rb0[r + 1 + du / 2] + ((v + dv) >> 2)], S.B[0], S.k[0]);
+          return (W)mask_code<Q>(S1[rb0[r + 1 + du / 2] + ((v + dv) >> 2)], B0, K0);
         };
-        if (cd_class(u, v) == 0) {
-          val = s1(0, 0);
-        } else {
-          const CDNb n = cd_nb_s2(u, v, Nu, Nv);
-          const W x = (W)mask_code<Q>(S2[rb1[r] + cd_in_row<A>(1, u, v)], S.B[1], S.k[1]);
-          const W a0 = s1(n.r0, n.c0);
-          const W a1 = n.hc ? s1(n.r0, n.c1) : a0;
-          const W a2 = n.hr ? s1(n.r1, n.c0) : a0;
-          const W a3 = (n.hr && n.hc) ? s1(n.r1, n.c1) : a0;
-          val = x + cd_combine<W>(n, a0, a1, a2, a3);
-        }
+        // branch-free: an S1 point reads itself four times and skips the S2 term
+        const bool s2p = cd_class(u, v) != 0;
+        CDNb n = cd_nb_s2(u, v, Nu, Nv);
+        if (!s2p) n.r0 = n.r1 = n.c0 = n.c1 = 0, n.hr = n.hc = false;
+        const W a0 = s1(n.r0, n.c0);
+        const W a1 = s1(n.r0, n.hc ? n.c1 : n.c0);
+        const W a2 = s1(n.hr ? n.r1 : n.r0, n.c0);
+        const W a3 = s1(n.hr ? n.r1 : n.r0, n.hc ? n.c1 : n.c0);
+        const GAS Q* x2 = s2p ? S2 + rb1[r] + cd_in_row<A>(1, u, v) : S1 + rb0[r + 1] + (v >> 2);
+        const W x = (W)mask_code<Q>(*x2, s2p ? B1 : B0, s2p ? K1 : K0);
+        val = s2p ? x + cd_combine<W>(n, a0, a1, a2, a3) : a0;
       }
       h1[e] = val;
     }
@@ -1016,32 +1018,28 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       const int r = wave * (kCITU / 4) + rr;
       const int u = U0 + r;
       if (u >= Nu) continue;
-      GAS Q* out = (GAS Q*)S.Rout + rowoff(u);
-      const int64_t b2 = rb2[r];
+      GAS Q* out = Rout + rowoff(u);
+      const GAS Q* s3r = S3 + rb2[r];
       W xs[kCITV / 64];
 #pragma unroll
       for (int c = 0; c < kCITV / 64; ++c) {
         const int v = V0 + c * 64 + lane;
         xs[c] = 0;
-        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)mask_code<Q>(S3[b2 + cd_in_row<A>(2, u, v)], S.B[2], S.k[2]);
+        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)mask_code<Q>(s3r[(int)cd_in_row<A>(2, u, v)], B2, K2);
       }
 #pragma unroll
       for (int c = 0; c < kCITV / 64; ++c) {
         const int v = V0 + c * 64 + lane;
         if (v >= Nv) continue;
         auto h = [&](int du, int dv) -> W { return h1[((r + du) >> 1) * kCIHV + ((v + dv - V0) >> 1)]; };
-        W val;
-        if (!((u & 1) || (v & 1))) {
-          val = h(0, 0);
-        } else {
-          const CDNb n = cd_nb_s3(u, v, Nu, Nv);
-          const W a0 = h(n.r0, n.c0);
-          const W a1 = n.hc ? h(n.r0, n.c1) : a0;
-          const W a2 = n.hr ? h(n.r1, n.c0) : a0;
-          const W a3 = (n.hr && n.hc) ? h(n.r1, n.c1) : a0;
-          val = xs[c] + cd_combine<W>(n, a0, a1, a2, a3);
-        }
-        out[v] = (Q)val;
+        const bool s3p = (u & 1) || (v & 1);
+        CDNb n = cd_nb_s3(u, v, Nu, Nv);
+        if (!s3p) n.r0 = n.r1 = n.c0 = n.c1 = 0, n.hr = n.hc = false;
+        const W a0 = h(n.r0, n.c0);
+        const W a1 = h(n.r0, n.hc ? n.c1 : n.c0);
+        const W a2 = h(n.hr ? n.r1 : n.r0, n.c0);
+        const W a3 = h(n.hr ? n.r1 : n.r0, n.hc ? n.c1 : n.c0);
+        out[v] = (Q)(s3p ? xs[c] + cd_combine<W>(n, a0, a1, a2, a3) : a0);
       }
     }
   }
