@@ -119,12 +119,20 @@ __device__ __forceinline__ unsigned long long ordered_bits(double d) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes (zero shifted in), then the last
+// lane of row 0 is added to row 1 and of row 2 to row 3 (row_bcast:15), and
+// the last lane of row 1 to rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(v, off);
-    if (lane >= off) v += t;
-  }
-  return v;
+  (void)lane;
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 into rows 2, 3
+  return (uint32_t)x;
 }
 
 // Segment of global work block b (segments are sorted by blk_begin).
