@@ -135,6 +135,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
   return (uint32_t)x;
 }
 
+// The same prefix sum over N independent values per lane, one DPP step at a
+// time across all N, so consecutive DPP reads never wait on the VALU write
+// just before them.
+template <int CTRL, int ROWS, bool BC, int N>
+__device__ __forceinline__ void wave_scan_step(uint32_t (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x[i], CTRL, ROWS, 0xf, BC);
+}
+template <int N>
+__device__ __forceinline__ void wave_incl_scan_n(uint32_t (&x)[N]) {
+  wave_scan_step<0x111, 0xf, true>(x);
+  wave_scan_step<0x112, 0xf, true>(x);
+  wave_scan_step<0x114, 0xf, true>(x);
+  wave_scan_step<0x118, 0xf, true>(x);
+  wave_scan_step<0x142, 0xa, false>(x);
+  wave_scan_step<0x143, 0xc, false>(x);
+}
+
 // Segment of global work block b (segments are sorted by blk_begin).
 template <typename S>
 __device__ __forceinline__ int find_seg(const S* segs, int nseg, int64_t b) {
@@ -1066,48 +1084,61 @@ __device__ __forceinline__ int find_stream(const StreamDev* sd, int ns, int64_t 
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// Bit-matrix transpose of 32 words: afterwards bit k of a[p] is what bit p of
-// a[k] was (five rounds of block swaps, 2s x 2s blocks at round s).
-__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+// One round of the bit-matrix transpose: swap the off-diagonal S x S bit
+// blocks of every 2S x 2S block (M selects the low S bits of each 2S group).
+template <int S, uint32_t M>
+__device__ __forceinline__ void transpose_round(uint32_t (&a)[32]) {
 #pragma unroll
-  for (int s = 16; s >= 1; s >>= 1) {
-    const uint32_t m = s == 16 ? 0x0000FFFFu
-                     : s == 8  ? 0x00FF00FFu
-                     : s == 4  ? 0x0F0F0F0Fu
-                     : s == 2  ? 0x33333333u
-                               : 0x55555555u;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      if (k & s) continue;
-      const uint32_t t = ((a[k] >> s) ^ a[k + s]) & m;
-      a[k] ^= t << s;
-      a[k + s] ^= t;
-    }
+  for (int k = 0; k < 32; ++k) {
+    if (k & S) continue;
+    const uint32_t t = ((a[k] >> S) ^ a[k + S]) & M;
+    a[k] ^= t << S;
+    a[k + S] ^= t;
   }
+}
+
+// Bit-matrix transpose of 32 words: afterwards bit k of a[p] is what bit p of
+// a[k] was (five rounds of block swaps, 2s x 2s blocks at round s).  Each round
+// is its own instantiation so every register index is a compile-time constant.
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+  transpose_round<16, 0x0000FFFFu>(a);
+  transpose_round<8, 0x00FF00FFu>(a);
+  transpose_round<4, 0x0F0F0F0Fu>(a);
+  transpose_round<2, 0x33333333u>(a);
+  transpose_round<1, 0x55555555u>(a);
 }
 
 constexpr int kRow = 33;  // LDS row pitch (codes) of the half-word staging tile
 
 // Stage half h of every 64-code word of a chunk in LDS: row r holds codes
-// base + 64 r + 32 h + [0, 32) (zero past n).  Lane pairs of rows per load.
+// base + 64 r + 32 h + [0, 32) (zero past n).  Lane pairs of rows per load;
+// a chunk that lies wholly inside the stream takes the path without bounds
+// tests, and offsets inside a chunk are 32-bit.
 template <typename Q>
 __device__ __forceinline__ void stage_half(const GAS Q* src, int64_t base, int64_t n, int h, Q* cst, int lane) {
   const int k = lane & 31, rr = lane >> 5;
+  const GAS Q* s0 = src + base + 32 * h + k + 64 * rr;
+  if (base + kChunk <= n) {
 #pragma unroll 8
-  for (int it = 0; it < 32; ++it) {
-    const int r = 2 * it + rr;
-    const int64_t e = base + 64 * r + 32 * h + k;
-    cst[r * kRow + k] = e < n ? src[e] : (Q)0;
+    for (int it = 0; it < 32; ++it) cst[(2 * it + rr) * kRow + k] = s0[128 * it];
+  } else {
+    const int lim = (int)min<int64_t>(n - base, (int64_t)kChunk) - (32 * h + k + 64 * rr);
+#pragma unroll 8
+    for (int it = 0; it < 32; ++it) cst[(2 * it + rr) * kRow + k] = 128 * it < lim ? s0[128 * it] : (Q)0;
   }
 }
 template <typename Q>
 __device__ __forceinline__ void unstage_half(GAS Q* dst, int64_t base, int64_t n, int h, const Q* cst, int lane) {
   const int k = lane & 31, rr = lane >> 5;
+  GAS Q* d0 = dst + base + 32 * h + k + 64 * rr;
+  if (base + kChunk <= n) {
 #pragma unroll 8
-  for (int it = 0; it < 32; ++it) {
-    const int r = 2 * it + rr;
-    const int64_t e = base + 64 * r + 32 * h + k;
-    if (e < n) dst[e] = cst[r * kRow + k];
+    for (int it = 0; it < 32; ++it) d0[128 * it] = cst[(2 * it + rr) * kRow + k];
+  } else {
+    const int lim = (int)min<int64_t>(n - base, (int64_t)kChunk) - (32 * h + k + 64 * rr);
+#pragma unroll 8
+    for (int it = 0; it < 32; ++it)
+      if (128 * it < lim) d0[128 * it] = cst[(2 * it + rr) * kRow + k];
   }
 }
 
@@ -1124,7 +1155,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   constexpr int kStageBytes = 64 * kRow * (int)sizeof(Q);
   constexpr int kTabBytes = MAXB * 64 * 4;
   __shared__ __align__(16) unsigned char lds[kStageBytes > kTabBytes ? kStageBytes : kTabBytes];
-  __shared__ unsigned long long sstage[64];
+  __shared__ unsigned long long sstage[128];  // [64, 128): per-lane sinks of empty ORs
   Q* cst = (Q*)lds;                 // half-word staging tile
   uint32_t* ptab = (uint32_t*)lds;  // then: next staging position per (plane, word)
   const int lane = threadIdx.x;
@@ -1160,10 +1191,10 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
         const Q q = cst[lane * kRow + k];
         const uint64_t mg = absq(q);
         r[k] = (uint32_t)(mg >> (32 * p));
-        if (p == 0 && mg) {
+        if (p == 0) {
           const int kk = 32 * h + k;
           const uint32_t v = 0x80u | (((uint32_t)(B - bitlen64(mg)) & 63u) << 1) | (q < 0 ? 1u : 0u);
-          lead[kk >> 2] |= v << (8 * (kk & 3));
+          lead[kk >> 2] |= (mg ? v : 0u) << (8 * (kk & 3));
         }
       }
       transpose32(r);
@@ -1175,37 +1206,46 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   }
 
   // planes from the most significant: magnitude words, newcomer counts, cursors
+  uint32_t cc[MAXB], incl[MAXB];
   uint64_t sig = 0ull;
-  uint32_t toff = 0;
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    const uint64_t pw = P[b];
+    if (b < B && w < M) mag[(int64_t)(B - 1 - b) * M + w] = pw;
+    cc[b] = b < B ? (uint32_t)__popcll(pw & ~sig) : 0u;
+    incl[b] = cc[b];
+    sig |= pw;
+  }
+  wave_incl_scan_n<MAXB>(incl);
+  uint32_t toff = 0, mycnt = 0;
 #pragma unroll
   for (int b = MAXB - 1; b >= 0; --b) {
     if (b >= B) continue;
     const int j = B - 1 - b;
-    const uint64_t pw = P[b];
-    if (w < M) mag[(int64_t)j * M + w] = pw;
-    const uint32_t c = (uint32_t)__popcll(pw & ~sig);
-    sig |= pw;
-    const uint32_t incl = wave_incl_scan(c, lane);
-    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    if (lane == 0) cnt[chunk * B + j] = tot;
-    ptab[j * 64 + lane] = toff + incl - c;
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl[b], 63);
+    mycnt = lane == j ? tot : mycnt;
+    ptab[j * 64 + lane] = toff + incl[b] - cc[b];
     toff += tot;
   }
+  if (lane < B) cnt[chunk * B + lane] = mycnt;
   // sign bits, word by word in code order (each lane owns its cursor column);
-  // cursors are taken 16 codes at a time so their LDS round trips overlap
+  // cursors are taken 16 codes at a time so their LDS round trips overlap.
+  // Every lane issues every LDS operation: a zero code adds 0 to its own
+  // plane-0 cursor and a code with no sign bit to place ORs 0 into a word of
+  // its own past the staging, so no operation needs an exec-mask branch.
 #pragma unroll
   for (int g = 0; g < 64; g += 16) {
     uint32_t pos[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const uint32_t v = (lead[(g + k) >> 2] >> (8 * ((g + k) & 3))) & 0xffu;
-      pos[k] = ~0u;
-      if (v & 0x80u) pos[k] = atomicAdd(&ptab[((v >> 1) & 63u) * 64 + lane], 1u);
+      pos[k] = atomicAdd(&ptab[((v >> 1) & 63u) * 64 + lane], v >> 7);
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const uint32_t v = (lead[(g + k) >> 2] >> (8 * ((g + k) & 3))) & 0xffu;
-      if ((v & 0x81u) == 0x81u && pos[k] < (uint32_t)kChunk) atomicOr(&sstage[pos[k] >> 6], 1ull << (pos[k] & 63));
+      const bool put = (v & 0x81u) == 0x81u && pos[k] < (uint32_t)kChunk;
+      atomicOr(&sstage[put ? pos[k] >> 6 : 64 + lane], put ? 1ull << (pos[k] & 63) : 0ull);
     }
   }
   __syncthreads();
@@ -1354,26 +1394,35 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   int64_t Dl = 0;
   if (lane >= k0 && lane < k1) Dl = pso[lane] * 64 + (int64_t)idx[(int64_t)lane * C + chunk];
   // newcomer counts -> cursors; runs of sign words to fetch
+  uint32_t cc[MAXB], incl[MAXB];
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    const uint64_t pw = P[b];  // zero outside the decoded planes
+    cc[b] = (uint32_t)__popcll(pw & ~sig);
+    incl[b] = cc[b];
+    sig |= pw;
+  }
+  wave_incl_scan_n<MAXB>(incl);
   uint32_t woff = 0;
   int np = 0;
+  int64_t mypw0 = 0;
+  uint32_t mypwoff = 0;
 #pragma unroll
   for (int b = MAXB - 1; b >= 0; --b) {
     const int j = B - 1 - b;
     if (b >= B || j < k0 || j >= k1) continue;
-    const uint64_t pw = P[b];
-    const uint32_t c = (uint32_t)__popcll(pw & ~sig);
-    sig |= pw;
-    const uint32_t incl = wave_incl_scan(c, lane);
-    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl[b], 63);
     const int64_t D = readlane64(Dl, j);
     const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
-    ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl - c;
-    if (lane == 0) {
-      pw0[np] = D >> 6;
-      pwoff[np] = woff;
-    }
+    ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl[b] - cc[b];
+    mypw0 = lane == np ? (D >> 6) : mypw0;
+    mypwoff = lane == np ? woff : mypwoff;
     woff += nw;
     ++np;
+  }
+  if (lane < np) {
+    pw0[lane] = mypw0;
+    pwoff[lane] = mypwoff;
   }
   if (lane == 0) pwoff[np] = woff;
   __syncthreads();
@@ -1405,20 +1454,36 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
       for (int bb = 0; bb < 32; ++bb) nb[p][bb] = (32 * p + bb < MAXB) ? (uint32_t)(P[32 * p + bb] >> (32 * h)) : 0u;
       transpose32(nb[p]);
     }
+    // Every lane issues every cursor fetch-and-add (adding 0 to its own
+    // plane-0 cursor when the code takes no sign bit), 16 codes at a time.
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const Q old = fresh ? (Q)0 : cst[lane * kRow + k];
-      uint64_t mg = absq(old) | (uint64_t)nb[0][k];
-      if (QW == 2) mg |= (uint64_t)nb[QW - 1][k] << 32;
-      bool neg = old < 0;
-      if (old == (Q)0 && mg) {
+    for (int g = 0; g < 32; g += 16) {
+      uint64_t mgs[16];
+      uint32_t pos[16];
+      bool take[16], negs[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const Q old = fresh ? (Q)0 : cst[lane * kRow + g + k];
+        uint64_t mg = absq(old) | (uint64_t)nb[0][g + k];
+        if (QW == 2) mg |= (uint64_t)nb[QW - 1][g + k] << 32;
         const int j = B - bitlen64(mg);
-        if (j >= 0 && j < MAXB) {
-          const uint32_t pos = atomicAdd(&ptab[j * 64 + lane], 1u);
-          neg = pos < (uint32_t)(kSignWords * 64) && ((sw[pos >> 6] >> (pos & 63)) & 1ull);
-        }
+        take[k] = old == (Q)0 && mg != 0ull && j >= 0 && j < MAXB;
+        negs[k] = old < 0;
+        mgs[k] = mg;
+        pos[k] = atomicAdd(&ptab[(take[k] ? j : 0) * 64 + lane], take[k] ? 1u : 0u);
       }
-      cst[lane * kRow + k] = neg ? (Q)(-(int64_t)mg) : (Q)mg;
+      uint64_t wv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        take[k] = take[k] & (pos[k] < (uint32_t)(kSignWords * 64));
+        wv[k] = sw[(take[k] ? pos[k] : 0u) >> 6];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const bool sbit = (uint32_t)(wv[k] >> (pos[k] & 63)) & 1u;
+        const bool neg = (take[k] & sbit) | (!take[k] & negs[k]);
+        cst[lane * kRow + g + k] = neg ? (Q)(-(int64_t)mgs[k]) : (Q)mgs[k];
+      }
     }
     __syncthreads();
     unstage_half<Q>(dst, base, n, h, cst, lane);
