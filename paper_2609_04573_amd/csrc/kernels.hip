@@ -25,6 +25,36 @@ constexpr int kThreads = 256;
 // through them would compile to flat instructions (which also wait on LDS
 // traffic); every kernel re-types them into the global address space.
 #define GAS __attribute__((address_space(1)))
+
+// Raw buffer access: a wave-uniform base address and byte range held in
+// scalar registers plus a 32-bit per-lane byte offset.  The hardware range
+// check returns 0 for loads past the range and drops stores past it, which
+// stands in for per-lane bounds tests.  Dword 3 of the descriptor selects the
+// 32-bit data format (raw loads and stores ignore it, a zero format would mark
+// the buffer invalid).
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p, int64_t bytes) {
+  const int64_t b = bytes < 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)b, 0x00020000);
+}
+template <typename V>
+__device__ __forceinline__ V buf_load(BufRsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(V) == 4) {
+    const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    return __builtin_bit_cast(V, x);
+  } else {
+    const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    return __builtin_bit_cast(V, x);
+  }
+}
+template <typename V>
+__device__ __forceinline__ void buf_store(V v, BufRsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(V) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
 constexpr int kPerThread = kBlockElems / kThreads;  // 16
 constexpr unsigned kMaxGrid = 4096;
 
@@ -93,6 +123,29 @@ template <typename Q>
 __device__ __forceinline__ uint64_t absq(Q q) {
   return q < 0 ? (uint64_t)(-(int64_t)q) : (uint64_t)q;
 }
+
+// 32-bit part p of a code's magnitude (an int32 code's magnitude fits 32 bits).
+__device__ __forceinline__ uint32_t mag_part(int32_t q, int) { return q < 0 ? 0u - (uint32_t)q : (uint32_t)q; }
+__device__ __forceinline__ uint32_t mag_part(int64_t q, int p) { return (uint32_t)(absq(q) >> (32 * p)); }
+// Lead byte of a code for the sign pass: 0x80 | plane << 1 | negative, where
+// plane = B - bit length of the magnitude is where the code becomes
+// significant; 0 for a zero code.
+__device__ __forceinline__ uint32_t code_lead(int32_t q, int B) {
+  const uint32_t m = mag_part(q, 0);
+  const uint32_t v = 0x80u | (((uint32_t)(B - 32 + __clz((int)m)) & 63u) << 1) | ((uint32_t)q >> 31);
+  return m ? v : 0u;
+}
+__device__ __forceinline__ uint32_t code_lead(int64_t q, int B) {
+  const uint64_t m = absq(q);
+  const uint32_t v = 0x80u | (((uint32_t)(B - bitlen64(m)) & 63u) << 1) | (uint32_t)((uint64_t)q >> 63);
+  return m ? v : 0u;
+}
+
+// Unsigned type that holds a code's magnitude, and bit lengths.
+template <typename Q> struct MagOf { using type = uint64_t; };
+template <> struct MagOf<int32_t> { using type = uint32_t; };
+__device__ __forceinline__ int bitlen_of(uint32_t v) { return 32 - __clz((int)v); }
+__device__ __forceinline__ int bitlen_of(uint64_t v) { return bitlen64(v); }
 
 // Codes truncated to the first k of B planes (low B-k bits cleared).
 template <typename Q>
@@ -1111,35 +1164,31 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
 constexpr int kRow = 33;  // LDS row pitch (codes) of the half-word staging tile
 
 // Stage half h of every 64-code word of a chunk in LDS: row r holds codes
-// base + 64 r + 32 h + [0, 32) (zero past n).  Lane pairs of rows per load;
-// a chunk that lies wholly inside the stream takes the path without bounds
-// tests, and offsets inside a chunk are 32-bit.
+// 64 r + 32 h + [0, 32) of the chunk (zero past the stream's end, which is
+// where the chunk's buffer range ends).  Lane pairs of rows per load.
 template <typename Q>
-__device__ __forceinline__ void stage_half(const GAS Q* src, int64_t base, int64_t n, int h, Q* cst, int lane) {
-  const int k = lane & 31, rr = lane >> 5;
-  const GAS Q* s0 = src + base + 32 * h + k + 64 * rr;
-  if (base + kChunk <= n) {
+__device__ __forceinline__ void stage_half(BufRsrc rc, int h, Q* cst, int lane) {
+  const uint32_t k = lane & 31, rr = lane >> 5;
+  const uint32_t o = (32u * h + k + 64u * rr) * (uint32_t)sizeof(Q);
 #pragma unroll 8
-    for (int it = 0; it < 32; ++it) cst[(2 * it + rr) * kRow + k] = s0[128 * it];
-  } else {
-    const int lim = (int)min<int64_t>(n - base, (int64_t)kChunk) - (32 * h + k + 64 * rr);
-#pragma unroll 8
-    for (int it = 0; it < 32; ++it) cst[(2 * it + rr) * kRow + k] = 128 * it < lim ? s0[128 * it] : (Q)0;
-  }
+  for (uint32_t it = 0; it < 32; ++it) cst[(2 * it + rr) * kRow + k] = buf_load<Q>(rc, o, 128u * it * sizeof(Q));
 }
 template <typename Q>
-__device__ __forceinline__ void unstage_half(GAS Q* dst, int64_t base, int64_t n, int h, const Q* cst, int lane) {
-  const int k = lane & 31, rr = lane >> 5;
-  GAS Q* d0 = dst + base + 32 * h + k + 64 * rr;
-  if (base + kChunk <= n) {
+__device__ __forceinline__ void unstage_half(BufRsrc rc, int h, const Q* cst, int lane) {
+  const uint32_t k = lane & 31, rr = lane >> 5;
+  const uint32_t o = (32u * h + k + 64u * rr) * (uint32_t)sizeof(Q);
 #pragma unroll 8
-    for (int it = 0; it < 32; ++it) d0[128 * it] = cst[(2 * it + rr) * kRow + k];
-  } else {
-    const int lim = (int)min<int64_t>(n - base, (int64_t)kChunk) - (32 * h + k + 64 * rr);
-#pragma unroll 8
-    for (int it = 0; it < 32; ++it)
-      if (128 * it < lim) d0[128 * it] = cst[(2 * it + rr) * kRow + k];
-  }
+  for (uint32_t it = 0; it < 32; ++it) buf_store<Q>(cst[(2 * it + rr) * kRow + k], rc, o, 128u * it * sizeof(Q));
+}
+// A chunk's codes as a buffer: base + [0, min(n - base, chunk)).
+template <typename Q>
+__device__ __forceinline__ BufRsrc chunk_rsrc(const void* codes, int64_t base, int64_t n) {
+  return buf_rsrc((const Q*)codes + base, (n - base < kChunk ? n - base : (int64_t)kChunk) * (int64_t)sizeof(Q));
+}
+// Plane j's magnitude words of a chunk as a buffer (64 words, fewer at the end).
+__device__ __forceinline__ BufRsrc plane_rsrc(const void* mag, int64_t j, int64_t M, int64_t chunk) {
+  const int64_t w0 = chunk * 64;
+  return buf_rsrc((const uint64_t*)mag + j * M + w0, (M - w0 < 64 ? M - w0 : 64) * 8);
 }
 
 // One wave per 4096-code chunk, one lane per 64-code word.  Each lane
@@ -1150,7 +1199,7 @@ __device__ __forceinline__ void unstage_half(GAS Q* dst, int64_t base, int64_t n
 // LDS fetch-and-add per nonzero code on a (plane, word) cursor, visiting the
 // word's codes in order.
 template <typename Q, int MAXB>
-__global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd, int ns) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) == 4 ? 3 : 2))) void k_encode(const StreamDev* __restrict__ sd, int ns) {
   constexpr int QW = (int)sizeof(Q) / 4;
   constexpr int kStageBytes = 64 * kRow * (int)sizeof(Q);
   constexpr int kTabBytes = MAXB * 64 * 4;
@@ -1163,14 +1212,13 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  const GAS Q* src = (const GAS Q*)S.codes;
   GAS uint64_t* mag = (GAS uint64_t*)S.mag;
   GAS uint32_t* cnt = (GAS uint32_t*)S.cnt;
   GAS uint64_t* stg = (GAS uint64_t*)S.stage;
   const int B = S.B;
   const int64_t M = S.M, n = S.n;
   const int64_t base = chunk * kChunk;
-  const int64_t w = chunk * 64 + lane;
+  const BufRsrc rc = chunk_rsrc<Q>(S.codes, base, n);
   sstage[lane] = 0ull;
 
   uint64_t P[MAXB];   // P[b]: bit b of the word's 64 magnitudes
@@ -1181,7 +1229,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
   for (int i = 0; i < 16; ++i) lead[i] = 0u;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    stage_half<Q>(src, base, n, h, cst, lane);
+    stage_half<Q>(rc, h, cst, lane);
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < QW; ++p) {
@@ -1189,13 +1237,18 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
 #pragma unroll
       for (int k = 0; k < 32; ++k) {
         const Q q = cst[lane * kRow + k];
-        const uint64_t mg = absq(q);
-        r[k] = (uint32_t)(mg >> (32 * p));
+        r[k] = mag_part(q, p);
         if (p == 0) {
           const int kk = 32 * h + k;
-          const uint32_t v = 0x80u | (((uint32_t)(B - bitlen64(mg)) & 63u) << 1) | (q < 0 ? 1u : 0u);
-          lead[kk >> 2] |= (mg ? v : 0u) << (8 * (kk & 3));
+          lead[kk >> 2] |= code_lead(q, B) << (8 * (kk & 3));
         }
+      }
+      // Make the packed lead words opaque: otherwise the compiler sees
+      // through the byte packing and keeps every code's lead byte (or what
+      // it is made of) in a register of its own until the sign pass.
+      if (p == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) asm volatile("" : "+v"(lead[8 * h + i]));
       }
       transpose32(r);
 #pragma unroll
@@ -1211,7 +1264,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
 #pragma unroll
   for (int b = MAXB - 1; b >= 0; --b) {
     const uint64_t pw = P[b];
-    if (b < B && w < M) mag[(int64_t)(B - 1 - b) * M + w] = pw;
+    if (b < B) buf_store<uint64_t>(pw, plane_rsrc(S.mag, B - 1 - b, M, chunk), 8u * lane, 0u);
     cc[b] = b < B ? (uint32_t)__popcll(pw & ~sig) : 0u;
     incl[b] = cc[b];
     sig |= pw;
@@ -1244,8 +1297,7 @@ __global__ __launch_bounds__(64) void k_encode(const StreamDev* __restrict__ sd,
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const uint32_t v = (lead[(g + k) >> 2] >> (8 * ((g + k) & 3))) & 0xffu;
-      const bool put = (v & 0x81u) == 0x81u && pos[k] < (uint32_t)kChunk;
-      atomicOr(&sstage[put ? pos[k] >> 6 : 64 + lane], put ? 1ull << (pos[k] & 63) : 0ull);
+      if ((v & 0x81u) == 0x81u && pos[k] < (uint32_t)kChunk) atomicOr(&sstage[pos[k] >> 6], 1ull << (pos[k] & 63));
     }
   }
   __syncthreads();
@@ -1347,11 +1399,11 @@ __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ 
 // the chunk's run of plane-j sign bits, which starts at index[j][chunk]; the
 // sign words each plane needs are first copied into LDS.
 template <typename Q, int MAXB>
-__global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd, int ns) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) == 4 ? 3 : 1))) void k_decode(const StreamDev* __restrict__ sd, int ns) {
   constexpr int QW = (int)sizeof(Q) / 4;
   constexpr int kSignWords = 64 + 2 * MAXB;
   __shared__ Q cst[64 * kRow];
-  __shared__ uint32_t ptab[MAXB * 64];
+  __shared__ uint32_t ptab[MAXB / 2 * 64];  // cursors, two planes per word (16 bits each)
   __shared__ unsigned long long sw[kSignWords];
   __shared__ int64_t pw0[MAXB];     // first sign word of each decoded plane's run
   __shared__ uint32_t pwoff[MAXB + 1];  // its LDS offset (prefix over decoded planes)
@@ -1360,8 +1412,6 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
   const int64_t chunk = gch - S.chunk_begin;
-  GAS Q* dst = (GAS Q*)S.codes;
-  const GAS uint64_t* mag = (const GAS uint64_t*)S.mag;
   const GAS uint32_t* idx = (const GAS uint32_t*)S.idx;
   const GAS uint64_t* sign = (const GAS uint64_t*)S.sign;
   const GAS int64_t* pso = (const GAS int64_t*)S.pso;
@@ -1369,14 +1419,14 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
   const bool fresh = S.fresh != 0;
   const int64_t M = S.M, C = S.C, n = S.n, sign_n = S.sign_n;
   const int64_t base = chunk * kChunk;
-  const int64_t w = chunk * 64 + lane;
+  const BufRsrc rc = chunk_rsrc<Q>(S.codes, base, n);
 
   // significance before plane k0 = nonzero resident codes
   uint64_t sig = 0ull;
   if (!fresh) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      stage_half<Q>(dst, base, n, h, cst, lane);
+      stage_half<Q>(rc, h, cst, lane);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < 32; ++k)
@@ -1388,7 +1438,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = B - 1 - b;
-    P[b] = (b < B && j >= k0 && j < k1 && w < M) ? mag[(int64_t)j * M + w] : 0ull;
+    P[b] = (b < B && j >= k0 && j < k1) ? buf_load<uint64_t>(plane_rsrc(S.mag, j, M, chunk), 8u * lane, 0u) : 0ull;
   }
   // lane j: first sign bit of plane j's run for this chunk (all planes at once)
   int64_t Dl = 0;
@@ -1414,7 +1464,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl[b], 63);
     const int64_t D = readlane64(Dl, j);
     const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
-    ptab[j * 64 + lane] = woff * 64 + (uint32_t)(D & 63) + incl[b] - cc[b];
+    ((uint16_t*)ptab)[((j >> 1) * 64 + lane) * 2 + (j & 1)] = (uint16_t)(woff * 64 + (uint32_t)(D & 63) + incl[b] - cc[b]);
     mypw0 = lane == np ? (D >> 6) : mypw0;
     mypwoff = lane == np ? woff : mypwoff;
     woff += nw;
@@ -1444,7 +1494,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (!fresh) {
-      stage_half<Q>(dst, base, n, h, cst, lane);
+      stage_half<Q>(rc, h, cst, lane);
       __syncthreads();
     }
     uint32_t nb[QW][32];
@@ -1458,19 +1508,23 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
     // plane-0 cursor when the code takes no sign bit), 16 codes at a time.
 #pragma unroll
     for (int g = 0; g < 32; g += 16) {
-      uint64_t mgs[16];
+      typename MagOf<Q>::type mgs[16];
       uint32_t pos[16];
       bool take[16], negs[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const Q old = fresh ? (Q)0 : cst[lane * kRow + g + k];
-        uint64_t mg = absq(old) | (uint64_t)nb[0][g + k];
-        if (QW == 2) mg |= (uint64_t)nb[QW - 1][g + k] << 32;
-        const int j = B - bitlen64(mg);
-        take[k] = old == (Q)0 && mg != 0ull && j >= 0 && j < MAXB;
+        typename MagOf<Q>::type mg;
+        if constexpr (QW == 1)
+          mg = mag_part(old, 0) | nb[0][g + k];
+        else
+          mg = absq(old) | (uint64_t)nb[0][g + k] | (uint64_t)nb[QW - 1][g + k] << 32;
+        const int j = B - bitlen_of(mg);
+        take[k] = old == (Q)0 && mg != 0 && j >= 0 && j < MAXB;
         negs[k] = old < 0;
         mgs[k] = mg;
-        pos[k] = atomicAdd(&ptab[(take[k] ? j : 0) * 64 + lane], take[k] ? 1u : 0u);
+        const int jj = take[k] ? j : 0;
+        pos[k] = (atomicAdd(&ptab[(jj >> 1) * 64 + lane], take[k] ? 1u << (16 * (jj & 1)) : 0u) >> (16 * (jj & 1))) & 0xffffu;
       }
       uint64_t wv[16];
 #pragma unroll
@@ -1486,7 +1540,7 @@ __global__ __launch_bounds__(64) void k_decode(const StreamDev* __restrict__ sd,
       }
     }
     __syncthreads();
-    unstage_half<Q>(dst, base, n, h, cst, lane);
+    unstage_half<Q>(rc, h, cst, lane);
     __syncthreads();
   }
 }
