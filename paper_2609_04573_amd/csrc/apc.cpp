@@ -386,7 +386,7 @@ struct TableBuilder {
 
 enum LaunchKind {
   K_RANGE, K_GATHER, K_COEF0, K_COEF1, K_COARSE0, K_COARSE1, K_CDF, K_CDI0, K_CDI1,
-  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2, K_CDIT
+  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2, K_CDIT, K_CDFT
 };
 
 struct Launch {
@@ -493,7 +493,8 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
       case K_COARSE1:
         LAUNCH(l.name, l.bytes, st, (launch_coarse<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, 1, st)));
         break;
-      case K_CDF: LAUNCH(l.name, l.bytes, st, launch_cd_forward<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, st)); break;
+      case K_CDF: LAUNCH(l.name, l.bytes, st, launch_cd_forward<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 0, st)); break;
+      case K_CDFT: LAUNCH(l.name, l.bytes, st, launch_cd_forward<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 1, st)); break;
       case K_CDI0:
         LAUNCH(l.name, l.bytes, st, launch_cd_inverse<Q>((const CDSeg*)p, l.nseg, l.nblk, l.a, 0, st));
         break;
@@ -1071,8 +1072,13 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     }
     if (cs.empty()) continue;
     any_cd = true;
-    const int64_t nbk = assign_cd_blocks(cs);
-    ls.push_back({K_CDF, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
+    if (a3 < 2) {  // v runs along lattice rows: one pass over row tiles
+      const int64_t nbk = assign_cd_tile_blocks(cs, a3);
+      ls.push_back({K_CDFT, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
+    } else {
+      const int64_t nbk = assign_cd_blocks(cs);
+      ls.push_back({K_CDF, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
+    }
   }
   DevBuf tab2;
   APC_TRY(tab2.alloc(tb2.bytes.size()));

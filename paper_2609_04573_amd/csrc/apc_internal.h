@@ -162,7 +162,7 @@ hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, 
 template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s);
 template <typename Q>
-hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, hipStream_t s);
+hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, int tiled, hipStream_t s);
 template <typename Q>
 hipError_t launch_cd_inverse(const CDSeg* segs, int nseg, int64_t nblk, int a, int phase, hipStream_t s);
 template <typename Q>

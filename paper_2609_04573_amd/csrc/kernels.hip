@@ -1016,13 +1016,19 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
 // stores full-width (no partial-line writes).
 constexpr int kCITU = 8, kCITV = 256;
 constexpr int kCIHU = kCITU / 2 + 1, kCIHV = kCITV / 2 + 1;  // stride-2 rows/columns incl. halo
+// staged stream runs: S1 rows (3 x 65 points), S2 of the u = 0 mod 4 rows
+// (3 x 64) and of the u = 2 mod 4 rows (2 x 129)
+constexpr int kCIS1 = kCITV / 4 + 1, kCIS2C = kCITV / 4;
+constexpr int kCIN1 = 3 * kCIS1, kCIN2C = 3 * kCIS2C, kCIN = kCIN1 + kCIN2C + 2 * kCIHV;
+constexpr int kCIL = (kCIN + kThreads - 1) / kThreads;
 
 template <typename Q, int A>
 __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
   using W = LiftT<Q>;
   constexpr int U = A == 0 ? 1 : 0;
   __shared__ W h1[kCIHU * kCIHV];
-  __shared__ int64_t rb0[kCIHU + 2], rb1[kCIHU], rb2[kCITU];
+  __shared__ W lt[kCIN];
+  __shared__ int64_t rb0[3], rb1[kCIHU], rb2[kCITU];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
@@ -1045,11 +1051,11 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     };
     __syncthreads();  // LDS of the previous tile is free
     // stream offsets of the rows this tile touches
-    if (tid < kCIHU + 2) {  // S1 rows U0 - 2 + 2k
-      const int u = U0 - 2 + 2 * tid;
+    if (tid < 3) {  // S1 rows U0 + 4k
+      const int u = U0 + 4 * tid;
       int t0, t1;
       tt(u, t0, t1);
-      rb0[tid] = (u >= 0 && u < Nu) ? cd_row_base<A>(S, 0, t0, t1) : 0;
+      rb0[tid] = u < Nu ? cd_row_base<A>(S, 0, t0, t1) : 0;
     } else if (tid >= 16 && tid < 16 + kCIHU) {  // S2 rows U0 + 2k
       const int u = U0 + 2 * (tid - 16);
       int t0, t1;
@@ -1062,33 +1068,64 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       rb2[tid - 32] = (u < Nu) ? cd_row_base<A>(S, 2, t0, t1) : 0;
     }
     __syncthreads();
-    // stride-2 points (u, v even) of the tile and halo
     const GAS Q* S1 = (const GAS Q*)S.S[0];
     const GAS Q* S2 = (const GAS Q*)S.S[1];
     const GAS Q* S3 = (const GAS Q*)S.S[2];
     const int B0 = S.B[0], K0 = S.k[0], B1 = S.B[1], K1 = S.k[1], B2 = S.B[2], K2 = S.k[2];
     GAS Q* const Rout = (GAS Q*)S.Rout;
-    for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
-      const int r = e / kCIHV, k = e - r * kCIHV;
-      const int u = U0 + 2 * r, v = V0 + 2 * k;
-      W val = 0;
-      if (u < Nu && v < Nv) {
-        auto s1 = [&](int du, int dv) -> W {
-          return (W)mask_code<Q>(S1[rb0[r + 1 + du / 2] + ((v + dv) >> 2)], B0, K0);
-        };
-        // branch-free: an S1 point reads itself four times and skips the S2 term
-        const bool s2p = cd_class(u, v) != 0;
-        CDNb n = cd_nb_s2(u, v, Nu, Nv);
-        if (!s2p) n.r0 = n.r1 = n.c0 = n.c1 = 0, n.hr = n.hc = false;
-        const W a0 = s1(n.r0, n.c0);
-        const W a1 = s1(n.r0, n.hc ? n.c1 : n.c0);
-        const W a2 = s1(n.hr ? n.r1 : n.r0, n.c0);
-        const W a3 = s1(n.hr ? n.r1 : n.r0, n.hc ? n.c1 : n.c0);
-        const GAS Q* x2 = s2p ? S2 + rb1[r] + cd_in_row<A>(1, u, v) : S1 + rb0[r + 1] + (v >> 2);
-        const W x = (W)mask_code<Q>(*x2, s2p ? B1 : B0, s2p ? K1 : K0);
-        val = s2p ? x + cd_combine<W>(n, a0, a1, a2, a3) : a0;
+    // The tile's runs of the S1 and S2 streams, one coalesced load per point
+    // (in a row, each class's points of a column range are consecutive in its
+    // stream): S1 of rows U0 + 4i at v = V0 + 4l, S2 of those rows at
+    // v = V0 + 4l + 2, S2 of rows U0 + 2 + 4i at v = V0 + 2l.
+    {
+      W lv[kCIL];
+#pragma unroll
+      for (int i = 0; i < kCIL; ++i) {
+        const int e = tid + i * kThreads;
+        lv[i] = 0;
+        if (e < kCIN1) {
+          const int ii = e / kCIS1, l = e - ii * kCIS1;
+          if (U0 + 4 * ii < Nu && V0 + 4 * l < Nv) lv[i] = (W)mask_code<Q>(S1[rb0[ii] + (V0 >> 2) + l], B0, K0);
+        } else if (e < kCIN1 + kCIN2C) {
+          const int e2 = e - kCIN1, ii = e2 / kCIS2C, l = e2 - ii * kCIS2C;
+          if (U0 + 4 * ii < Nu && V0 + 4 * l + 2 < Nv)
+            lv[i] = (W)mask_code<Q>(S2[rb1[2 * ii] + (V0 >> 2) + l], B1, K1);
+        } else if (e < kCIN) {
+          const int e3 = e - kCIN1 - kCIN2C, ii = e3 / kCIHV, l = e3 - ii * kCIHV;
+          if (U0 + 2 + 4 * ii < Nu && V0 + 2 * l < Nv)
+            lv[i] = (W)mask_code<Q>(S2[rb1[2 * ii + 1] + (V0 >> 1) + l], B1, K1);
+        }
       }
-      h1[e] = val;
+#pragma unroll
+      for (int i = 0; i < kCIL; ++i)
+        if (tid + i * kThreads < kCIN) lt[tid + i * kThreads] = lv[i];
+    }
+    __syncthreads();
+    // stride-2 points (u, v even) of the tile and halo: S1 points as they are,
+    // S2 points plus their prediction from S1 (rows u -+ 2 and columns v -+ 2;
+    // an absent neighbour repeats the present one)
+    {
+      const W* s1t = lt;
+      const W* s2c = lt + kCIN1;
+      const W* s2b = lt + kCIN1 + kCIN2C;
+      for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
+        const int r = e / kCIHV, k = e - r * kCIHV;
+        const int u = U0 + 2 * r, v = V0 + 2 * k;
+        W val = 0;
+        if (u < Nu && v < Nv) {
+          const int c0 = k >> 1;
+          const int c1 = (k & 1) && v + 2 <= Nv - 1 ? c0 + 1 : c0;
+          if (!(r & 1)) {  // u = 0 mod 4
+            const W* row = s1t + (r >> 1) * kCIS1;
+            val = (k & 1) ? s2c[(r >> 1) * kCIS2C + c0] + avgw<W>(row[c0], row[c1]) : row[c0];
+          } else {  // u = 2 mod 4
+            const W* ra = s1t + (r >> 1) * kCIS1;
+            const W* rb = u + 2 <= Nu - 1 ? ra + kCIS1 : ra;
+            val = s2b[(r >> 1) * kCIHV + k] + avgw<W>(avgw<W>(ra[c0], ra[c1]), avgw<W>(rb[c0], rb[c1]));
+          }
+        }
+        h1[e] = val;
+      }
     }
     __syncthreads();
     // whole rows: stride-2 points from LDS, the rest from S3
@@ -1122,6 +1159,169 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       }
     }
   }
+}
+
+// Forward lifting in one pass when v runs along lattice rows (stacking axis
+// 0 or 1).  A block lifts a tile of 8 rows (u) x 256 columns (v) of one
+// slice: the tile's codes with a halo (the next row, two columns on each
+// side) are staged in LDS, then wave w lifts rows w and w + 4, which have
+// the same type (u = 0 mod 4, u = 2 mod 4, or odd), and writes each class of
+// a row as one run of its stream.  Each prediction is the column-then-row
+// average of four LDS values; an absent neighbour repeats the present one,
+// and since the floor average of a value with itself is that value this is
+// the same result as averaging only over the neighbours that exist.
+constexpr int kCFP = kCITV + 4;  // LDS row pitch: two halo columns each side
+
+template <typename Q, int A>
+__global__ __launch_bounds__(kThreads) void k_cd_forward_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using W = LiftT<Q>;
+  using UW = typename std::make_unsigned<W>::type;
+  constexpr int U = A == 0 ? 1 : 0;
+  __shared__ W L[(kCITU + 1) * kCFP];
+  int cur = -1;
+  UW am[3] = {0, 0, 0};
+  auto flush = [&](int si) {
+    for (int c = 0; c < 3; ++c) {
+      const double m = block_max((double)am[c]);
+      if (threadIdx.x == 0) atomicMax(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
+    }
+  };
+  auto upd = [&](int c, W res) {
+    const UW mag = res < 0 ? (UW)(-res) : (UW)res;
+    am[c] = am[c] > mag ? am[c] : mag;
+  };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int si = find_seg(segs, nseg, b);
+    if (si != cur) {
+      if (cur >= 0) flush(cur);
+      cur = si;
+      am[0] = am[1] = am[2] = 0;
+    }
+    const CDSeg& S = segs[si];
+    const int Nu = S.c[U], Nv = S.c[2];
+    const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
+    int lb = (int)(b - S.blk_begin);
+    const int V0 = (lb % nTv) * kCITV;
+    lb /= nTv;
+    const int U0 = (lb % nTu) * kCITU;
+    const int sa = lb / nTu;  // index along the stacking axis
+    auto tt = [&](int u, int& t0, int& t1) {
+      t0 = A == 0 ? sa : u;
+      t1 = A == 0 ? u : sa;
+    };
+    auto rowoff = [&](int u) -> int64_t {
+      int t0, t1;
+      tt(u, t0, t1);
+      return ((int64_t)t0 * S.c[1] + t1) * S.c[2];
+    };
+    __syncthreads();  // LDS of the previous tile is free
+    // all of a thread's loads are issued before the first LDS store
+    const GAS Q* R = (const GAS Q*)S.R;
+    constexpr int kFL = ((kCITU + 1) * kCFP + kThreads - 1) / kThreads;
+    W xv[kFL];
+#pragma unroll
+    for (int i = 0; i < kFL; ++i) {
+      const int e = tid + i * kThreads;
+      const int r = e / kCFP, c = e - r * kCFP;
+      const int u = U0 + r, v = V0 - 2 + c;
+      xv[i] = 0;
+      if (e < (kCITU + 1) * kCFP && u < Nu && v >= 0 && v < Nv) xv[i] = (W)R[rowoff(u) + v];
+    }
+#pragma unroll
+    for (int i = 0; i < kFL; ++i)
+      if (tid + i * kThreads < (kCITU + 1) * kCFP) L[tid + i * kThreads] = xv[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int r = wave + 4 * k;
+      const int u = U0 + r;
+      if (u >= Nu) continue;
+      int t0, t1;
+      tt(u, t0, t1);
+      const W* Lr = L + r * kCFP + 2;  // column v at Lr[v - V0]
+      if (wave == 0) {  // u = 0 mod 4: S1 at v = 0 mod 4, S2 at v = 2 mod 4, S3 at odd v
+        GAS Q* s1 = (GAS Q*)S.S[0] + cd_row_base<A>(S, 0, t0, t1) + (V0 >> 2);
+        GAS Q* s2 = (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, t0, t1) + (V0 >> 2);
+        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + (V0 >> 1);
+        {
+          const int j = 4 * lane;
+          if (V0 + j < Nv) {
+            const W x = Lr[j];
+            s1[lane] = (Q)x;
+            upd(0, x);
+          }
+        }
+        {
+          const int j = 4 * lane + 2;
+          if (V0 + j < Nv) {
+            const int j1 = V0 + j + 2 <= Nv - 1 ? j + 2 : j - 2;
+            const W res = Lr[j] - avgw<W>(Lr[j - 2], Lr[j1]);
+            s2[lane] = (Q)res;
+            upd(1, res);
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int l = lane + 64 * h, j = 2 * l + 1;
+          if (V0 + j < Nv) {
+            const int j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
+            const W res = Lr[j] - avgw<W>(Lr[j - 1], Lr[j1]);
+            s3[l] = (Q)res;
+            upd(2, res);
+          }
+        }
+      } else if (wave == 2) {  // u = 2 mod 4: S2 at even v (rows u -+ 2), S3 at odd v
+        const W* Ld = Lr - 2 * kCFP;
+        const W* Lu = u + 2 <= Nu - 1 ? Lr + 2 * kCFP : Ld;
+        GAS Q* s2 = (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, t0, t1) + (V0 >> 1);
+        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + (V0 >> 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int l = lane + 64 * h, j = 2 * l;
+          if (V0 + j < Nv) {
+            int j0 = j, j1 = j;
+            if (j & 2) {
+              j0 = j - 2;
+              j1 = V0 + j + 2 <= Nv - 1 ? j + 2 : j - 2;
+            }
+            const W res = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
+            s2[l] = (Q)res;
+            upd(1, res);
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int l = lane + 64 * h, j = 2 * l + 1;
+          if (V0 + j < Nv) {
+            const int j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
+            const W res = Lr[j] - avgw<W>(Lr[j - 1], Lr[j1]);
+            s3[l] = (Q)res;
+            upd(2, res);
+          }
+        }
+      } else {  // odd u: S3 everywhere, from rows u -+ 1
+        const W* Ld = Lr - kCFP;
+        const W* Lu = u + 1 <= Nu - 1 ? Lr + kCFP : Ld;
+        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + V0;
+#pragma unroll
+        for (int h = 0; h < kCITV / 64; ++h) {
+          const int j = lane + 64 * h;
+          if (V0 + j < Nv) {
+            int j0 = j, j1 = j;
+            if (j & 1) {
+              j0 = j - 1;
+              j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
+            }
+            const W res = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
+            s3[j] = (Q)res;
+            upd(2, res);
+          }
+        }
+      }
+    }
+  }
+  if (cur >= 0) flush(cur);
 }
 
 // ------------------------------------------------------------ bitplane codec
@@ -1678,7 +1878,11 @@ hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, 
   APC_LAUNCH((k_coarse<T, Q, 1>), nblk, segs, nseg, nblk);
 }
 template <typename Q>
-hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, hipStream_t s) {
+hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, int tiled, hipStream_t s) {
+  if (tiled) {  // row tiles (v along rows)
+    if (a == 0) APC_LAUNCH((k_cd_forward_tile<Q, 0>), nblk, segs, nseg, nblk);
+    APC_LAUNCH((k_cd_forward_tile<Q, 1>), nblk, segs, nseg, nblk);
+  }
   if (a == 0) APC_LAUNCH((k_cd_forward<Q, 0>), nblk, segs, nseg, nblk);
   if (a == 1) APC_LAUNCH((k_cd_forward<Q, 1>), nblk, segs, nseg, nblk);
   APC_LAUNCH((k_cd_forward<Q, 2>), nblk, segs, nseg, nblk);
@@ -1748,8 +1952,8 @@ template hipError_t launch_level<float, int32_t>(const LevelSeg*, int, int64_t, 
 template hipError_t launch_level<double, int64_t>(const LevelSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_coarse<float, int32_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
 template hipError_t launch_coarse<double, int64_t>(const FlatSeg*, int, int64_t, int, hipStream_t);
-template hipError_t launch_cd_forward<int32_t>(const CDSeg*, int, int64_t, int, hipStream_t);
-template hipError_t launch_cd_forward<int64_t>(const CDSeg*, int, int64_t, int, hipStream_t);
+template hipError_t launch_cd_forward<int32_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
+template hipError_t launch_cd_forward<int64_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_cd_inverse<int32_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_cd_inverse<int64_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_encode<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
