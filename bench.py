@@ -184,7 +184,7 @@ def _pct(v, q):
     return v[i]
 
 
-def cpu_baseline(x_full, rel: float, side: int = 256):
+def cpu_baseline(x_full, rel: float, side: int = 320):
     """The CPU oracle on a bounded sample of the same field: a side^3 block."""
     import numpy as np
 

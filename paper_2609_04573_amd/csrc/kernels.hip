@@ -263,6 +263,21 @@ __device__ __forceinline__ double predict_from_region(const RegionArgs& ra, int 
 
 inline unsigned grid_for(int64_t nblk) { return (unsigned)std::min<int64_t>(nblk, (int64_t)kMaxGrid); }
 
+// Running maximum / minimum / union of a value that only moves one way: the
+// current value is read first and the atomic is issued only when it would
+// change it, so the many blocks whose partial result is already covered do
+// not queue on one contended address.  A stale read only costs an atomic
+// that was not needed.
+__device__ __forceinline__ void max_u64(unsigned long long* p, unsigned long long v) {
+  if (v > *(volatile unsigned long long*)p) atomicMax(p, v);
+}
+__device__ __forceinline__ void min_u64(unsigned long long* p, unsigned long long v) {
+  if (v < *(volatile unsigned long long*)p) atomicMin(p, v);
+}
+__device__ __forceinline__ void or_u64(unsigned long long* p, unsigned long long v) {
+  if ((*(volatile unsigned long long*)p & v) != v) atomicOr(p, v);
+}
+
 // ------------------------------------------------------------- range pass
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
@@ -279,11 +294,11 @@ __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ 
     if (threadIdx.x == 0) {
       unsigned long long* acc = segs[si].acc;
       if (l <= h) {
-        atomicMin(&acc[0], ordered_bits(l));
-        atomicMax(&acc[1], ordered_bits(h));
+        min_u64(&acc[0], ordered_bits(l));
+        max_u64(&acc[1], ordered_bits(h));
       }
-      atomicMax(&acc[2], (unsigned long long)__double_as_longlong(a));
-      if (sbad) atomicOr(&acc[3], 1ull);
+      max_u64(&acc[2], (unsigned long long)__double_as_longlong(a));
+      if (sbad) or_u64(&acc[3], 1ull);
     }
   };
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -366,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
     if (MODE == 0 && si != cur) {
       if (cur >= 0) {
         const double m = block_max(am);
-        if (threadIdx.x == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
+        if (threadIdx.x == 0) max_u64(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
       }
       cur = si;
       am = 0.0;
@@ -408,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
   }
   if (MODE == 0 && cur >= 0) {
     const double m = block_max(am);
-    if (threadIdx.x == 0) atomicMax(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) max_u64(segs[cur].gmax, (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -454,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
   };
   auto flush = [&](int si) {
     const double m = block_max(am);
-    if (threadIdx.x == 0) atomicMax(segs[si].gmax, (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) max_u64(segs[si].gmax, (unsigned long long)__double_as_longlong(m));
     unsigned long long* acc = segs[si].racc;
     if (acc) {
       const double l = -block_max(-rlo), h = block_max(rhi), a = block_max(ram);
@@ -464,11 +479,11 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       __syncthreads();
       if (threadIdx.x == 0) {
         if (l <= h) {
-          atomicMin(&acc[0], ordered_bits(l));
-          atomicMax(&acc[1], ordered_bits(h));
+          min_u64(&acc[0], ordered_bits(l));
+          max_u64(&acc[1], ordered_bits(h));
         }
-        atomicMax(&acc[2], (unsigned long long)__double_as_longlong(a));
-        if (sbad) atomicOr(&acc[3], 1ull);
+        max_u64(&acc[2], (unsigned long long)__double_as_longlong(a));
+        if (sbad) or_u64(&acc[3], 1ull);
       }
     }
   };
@@ -692,7 +707,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
     if (MODE == 0 && si != cur) {
       if (cur >= 0) {
         const double m = block_max(am);
-        if (threadIdx.x == 0) atomicMax(segs[cur].acc, (unsigned long long)__double_as_longlong(m));
+        if (threadIdx.x == 0) max_u64(segs[cur].acc, (unsigned long long)__double_as_longlong(m));
       }
       cur = si;
       am = 0.0;
@@ -713,7 +728,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
   }
   if (MODE == 0 && cur >= 0) {
     const double m = block_max(am);
-    if (threadIdx.x == 0) atomicMax(segs[cur].acc, (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) max_u64(segs[cur].acc, (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -744,16 +759,18 @@ constexpr int kCDRowsPerBlock = kThreads / 64;
 // Elements of class cls before the start of row (t0, t1) in row-major
 // lattice order, i.e. the rank of (t0, t1, 0) in the class-cls stream.
 template <int A>
-__device__ __forceinline__ int64_t cd_row_base(const CDSeg& S, int cls, int t0, int t1) {
+__device__ __forceinline__ int64_t cd_row_base(int c1, int c2, int cls, int t0, int t1) {
   if (A == 0)  // (a, u, v) = (t0, t1, t2)
-    return (int64_t)t0 * cls_count(cls, rng_prefix(S.c[1]), rng_prefix(S.c[2])) +
-           cls_count(cls, rng_prefix(t1), rng_prefix(S.c[2]));
+    return (int64_t)t0 * cls_count(cls, rng_prefix(c1), rng_prefix(c2)) + cls_count(cls, rng_prefix(t1), rng_prefix(c2));
   if (A == 1)  // (u, a, v) = (t0, t1, t2)
-    return (int64_t)S.c[1] * cls_count(cls, rng_prefix(t0), rng_prefix(S.c[2])) +
-           (int64_t)t1 * cls_count(cls, rng_single(t0), rng_prefix(S.c[2]));
+    return (int64_t)c1 * cls_count(cls, rng_prefix(t0), rng_prefix(c2)) +
+           (int64_t)t1 * cls_count(cls, rng_single(t0), rng_prefix(c2));
   // (u, v, a) = (t0, t1, t2): whole rows belong to one class
-  return (int64_t)S.c[2] * (cls_count(cls, rng_prefix(t0), rng_prefix(S.c[1])) +
-                            cls_count(cls, rng_single(t0), rng_prefix(t1)));
+  return (int64_t)c2 * (cls_count(cls, rng_prefix(t0), rng_prefix(c1)) + cls_count(cls, rng_single(t0), rng_prefix(t1)));
+}
+template <int A>
+__device__ __forceinline__ int64_t cd_row_base(const CDSeg& S, int cls, int t0, int t1) {
+  return cd_row_base<A>(S.c[1], S.c[2], cls, t0, t1);
 }
 // Elements of class cls in the row before column t2 (u is the row's plane
 // coordinate when v runs along the row).
@@ -855,7 +872,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward(const CDSeg* __restrict
   auto flush = [&](int si) {
     for (int c = 0; c < 3; ++c) {
       const double m = block_max((double)am[c]);
-      if (threadIdx.x == 0) atomicMax(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
+      if (threadIdx.x == 0) max_u64(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
     }
   };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1183,7 +1200,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward_tile(const CDSeg* __res
   auto flush = [&](int si) {
     for (int c = 0; c < 3; ++c) {
       const double m = block_max((double)am[c]);
-      if (threadIdx.x == 0) atomicMax(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
+      if (threadIdx.x == 0) max_u64(segs[si].smax[c], (unsigned long long)__double_as_longlong(m));
     }
   };
   auto upd = [&](int c, W res) {
@@ -1191,17 +1208,28 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward_tile(const CDSeg* __res
     am[c] = am[c] > mag ? am[c] : mag;
   };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the current segment's fields, reloaded only when a tile of the next
+  // segment comes up (tiles of a block only move forward)
+  int64_t seg_end = -1, blk0 = 0;
+  int c0 = 0, c1 = 0, c2 = 0;
+  const GAS Q* R = nullptr;
+  GAS Q* Sp[3] = {nullptr, nullptr, nullptr};
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const int si = find_seg(segs, nseg, b);
-    if (si != cur) {
+    if (b >= seg_end) {
+      const int si = find_seg(segs, nseg, b);
       if (cur >= 0) flush(cur);
       cur = si;
       am[0] = am[1] = am[2] = 0;
+      const CDSeg& F = segs[si];
+      seg_end = si + 1 < nseg ? segs[si + 1].blk_begin : nblk;
+      blk0 = F.blk_begin;
+      c0 = F.c[0], c1 = F.c[1], c2 = F.c[2];
+      R = (const GAS Q*)F.R;
+      Sp[0] = (GAS Q*)F.S[0], Sp[1] = (GAS Q*)F.S[1], Sp[2] = (GAS Q*)F.S[2];
     }
-    const CDSeg& S = segs[si];
-    const int Nu = S.c[U], Nv = S.c[2];
+    const int Nu = A == 0 ? c1 : c0, Nv = c2;
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    int lb = (int)(b - S.blk_begin);
+    int lb = (int)(b - blk0);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
@@ -1213,111 +1241,100 @@ __global__ __launch_bounds__(kThreads) void k_cd_forward_tile(const CDSeg* __res
     auto rowoff = [&](int u) -> int64_t {
       int t0, t1;
       tt(u, t0, t1);
-      return ((int64_t)t0 * S.c[1] + t1) * S.c[2];
+      return ((int64_t)t0 * c1 + t1) * c2;
     };
     __syncthreads();  // LDS of the previous tile is free
-    // all of a thread's loads are issued before the first LDS store
-    const GAS Q* R = (const GAS Q*)S.R;
-    constexpr int kFL = ((kCITU + 1) * kCFP + kThreads - 1) / kThreads;
-    W xv[kFL];
+    // thread t loads column V0 + t of every row (row offsets are uniform),
+    // threads 0..35 one halo point each; all loads precede the LDS stores
+    static_assert(kCITV == kThreads && 4 * (kCITU + 1) <= kThreads, "tile shape");
+    W xv[kCITU + 1], xh = 0;
 #pragma unroll
-    for (int i = 0; i < kFL; ++i) {
-      const int e = tid + i * kThreads;
-      const int r = e / kCFP, c = e - r * kCFP;
-      const int u = U0 + r, v = V0 - 2 + c;
-      xv[i] = 0;
-      if (e < (kCITU + 1) * kCFP && u < Nu && v >= 0 && v < Nv) xv[i] = (W)R[rowoff(u) + v];
+    for (int r = 0; r < kCITU + 1; ++r) {
+      const int u = U0 + r;
+      xv[r] = 0;
+      if (u < Nu && V0 + tid < Nv) xv[r] = (W)R[rowoff(u) + V0 + tid];
+    }
+    const int hr = tid >> 2, hc = (tid & 3) < 2 ? (tid & 3) : kCITV + (tid & 3);
+    {
+      const int u = U0 + hr, v = V0 - 2 + hc;
+      if (tid < 4 * (kCITU + 1) && u < Nu && v >= 0 && v < Nv) xh = (W)R[rowoff(u) + v];
     }
 #pragma unroll
-    for (int i = 0; i < kFL; ++i)
-      if (tid + i * kThreads < (kCITU + 1) * kCFP) L[tid + i * kThreads] = xv[i];
+    for (int r = 0; r < kCITU + 1; ++r) L[r * kCFP + 2 + tid] = xv[r];
+    if (tid < 4 * (kCITU + 1)) L[hr * kCFP + hc] = xh;
     __syncthreads();
+    // Each wave computes the residuals of both its rows first (straight-line
+    // LDS reads, rows past the lattice read zeros), then stores what exists.
+    W res[2][kCITV / 64];
+    const int jc = 4 * lane;  // lane's column group in a u = 0 mod 4 row
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int r = wave + 4 * k;
       const int u = U0 + r;
-      if (u >= Nu) continue;
-      int t0, t1;
-      tt(u, t0, t1);
       const W* Lr = L + r * kCFP + 2;  // column v at Lr[v - V0]
       if (wave == 0) {  // u = 0 mod 4: S1 at v = 0 mod 4, S2 at v = 2 mod 4, S3 at odd v
-        GAS Q* s1 = (GAS Q*)S.S[0] + cd_row_base<A>(S, 0, t0, t1) + (V0 >> 2);
-        GAS Q* s2 = (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, t0, t1) + (V0 >> 2);
-        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + (V0 >> 1);
-        {
-          const int j = 4 * lane;
-          if (V0 + j < Nv) {
-            const W x = Lr[j];
-            s1[lane] = (Q)x;
-            upd(0, x);
-          }
-        }
-        {
-          const int j = 4 * lane + 2;
-          if (V0 + j < Nv) {
-            const int j1 = V0 + j + 2 <= Nv - 1 ? j + 2 : j - 2;
-            const W res = Lr[j] - avgw<W>(Lr[j - 2], Lr[j1]);
-            s2[lane] = (Q)res;
-            upd(1, res);
-          }
-        }
+        res[k][0] = Lr[jc];
+        res[k][1] = Lr[jc + 2] - avgw<W>(Lr[jc], Lr[V0 + jc + 4 <= Nv - 1 ? jc + 4 : jc]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int l = lane + 64 * h, j = 2 * l + 1;
-          if (V0 + j < Nv) {
-            const int j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
-            const W res = Lr[j] - avgw<W>(Lr[j - 1], Lr[j1]);
-            s3[l] = (Q)res;
-            upd(2, res);
-          }
+          const int j = 2 * (lane + 64 * h) + 1;
+          res[k][2 + h] = Lr[j] - avgw<W>(Lr[j - 1], Lr[V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1]);
         }
       } else if (wave == 2) {  // u = 2 mod 4: S2 at even v (rows u -+ 2), S3 at odd v
         const W* Ld = Lr - 2 * kCFP;
         const W* Lu = u + 2 <= Nu - 1 ? Lr + 2 * kCFP : Ld;
-        GAS Q* s2 = (GAS Q*)S.S[1] + cd_row_base<A>(S, 1, t0, t1) + (V0 >> 1);
-        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + (V0 >> 1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int l = lane + 64 * h, j = 2 * l;
-          if (V0 + j < Nv) {
-            int j0 = j, j1 = j;
-            if (j & 2) {
-              j0 = j - 2;
-              j1 = V0 + j + 2 <= Nv - 1 ? j + 2 : j - 2;
-            }
-            const W res = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
-            s2[l] = (Q)res;
-            upd(1, res);
-          }
+          const int j = 2 * (lane + 64 * h);
+          const int j0 = (j & 2) ? j - 2 : j;
+          const int j1 = (j & 2) ? (V0 + j + 2 <= Nv - 1 ? j + 2 : j - 2) : j;
+          res[k][h] = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int l = lane + 64 * h, j = 2 * l + 1;
-          if (V0 + j < Nv) {
-            const int j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
-            const W res = Lr[j] - avgw<W>(Lr[j - 1], Lr[j1]);
-            s3[l] = (Q)res;
-            upd(2, res);
-          }
+          const int j = 2 * (lane + 64 * h) + 1;
+          res[k][2 + h] = Lr[j] - avgw<W>(Lr[j - 1], Lr[V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1]);
         }
       } else {  // odd u: S3 everywhere, from rows u -+ 1
         const W* Ld = Lr - kCFP;
         const W* Lu = u + 1 <= Nu - 1 ? Lr + kCFP : Ld;
-        GAS Q* s3 = (GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + V0;
 #pragma unroll
         for (int h = 0; h < kCITV / 64; ++h) {
           const int j = lane + 64 * h;
-          if (V0 + j < Nv) {
-            int j0 = j, j1 = j;
-            if (j & 1) {
-              j0 = j - 1;
-              j1 = V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1;
-            }
-            const W res = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
-            s3[j] = (Q)res;
-            upd(2, res);
-          }
+          const int j0 = (j & 1) ? j - 1 : j;
+          const int j1 = (j & 1) ? (V0 + j + 1 <= Nv - 1 ? j + 1 : j - 1) : j;
+          res[k][h] = Lr[j] - avgw<W>(avgw<W>(Ld[j0], Ld[j1]), avgw<W>(Lu[j0], Lu[j1]));
         }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int u = U0 + wave + 4 * k;
+      if (u >= Nu) continue;
+      int t0, t1;
+      tt(u, t0, t1);
+      if (wave == 0) {
+        GAS Q* s1 = Sp[0] + cd_row_base<A>(c1, c2, 0, t0, t1) + (V0 >> 2);
+        GAS Q* s2 = Sp[1] + cd_row_base<A>(c1, c2, 1, t0, t1) + (V0 >> 2);
+        GAS Q* s3 = Sp[2] + cd_row_base<A>(c1, c2, 2, t0, t1) + (V0 >> 1);
+        if (V0 + jc < Nv) s1[lane] = (Q)res[k][0], upd(0, res[k][0]);
+        if (V0 + jc + 2 < Nv) s2[lane] = (Q)res[k][1], upd(1, res[k][1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (V0 + 2 * (lane + 64 * h) + 1 < Nv) s3[lane + 64 * h] = (Q)res[k][2 + h], upd(2, res[k][2 + h]);
+      } else if (wave == 2) {
+        GAS Q* s2 = Sp[1] + cd_row_base<A>(c1, c2, 1, t0, t1) + (V0 >> 1);
+        GAS Q* s3 = Sp[2] + cd_row_base<A>(c1, c2, 2, t0, t1) + (V0 >> 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (V0 + 2 * (lane + 64 * h) < Nv) s2[lane + 64 * h] = (Q)res[k][h], upd(1, res[k][h]);
+          if (V0 + 2 * (lane + 64 * h) + 1 < Nv) s3[lane + 64 * h] = (Q)res[k][2 + h], upd(2, res[k][2 + h]);
+        }
+      } else {
+        GAS Q* s3 = Sp[2] + cd_row_base<A>(c1, c2, 2, t0, t1) + V0;
+#pragma unroll
+        for (int h = 0; h < kCITV / 64; ++h)
+          if (V0 + lane + 64 * h < Nv) s3[lane + 64 * h] = (Q)res[k][h], upd(2, res[k][h]);
       }
     }
   }
@@ -1552,11 +1569,16 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 
 // Move each chunk's staged sign bits to their place in the stream's sign
 // section (dense, plane-major); one wave per chunk.  Lane j fetches plane j's
-// count and destination at once, a wave scan gives each plane's offset in
-// the staging, and the words are moved plane by plane.  Words shared with a
-// neighbouring chunk are combined with atomic OR; whole words are stored.
+// count and destination at once, wave scans give each plane's offset in the
+// staging and its first destination word, and the destination words of all
+// planes are spread over the lanes.  Words shared with a neighbouring chunk
+// are combined with atomic OR; whole words are stored.
 __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ sd, int ns) {
   __shared__ uint64_t st[64];
+  __shared__ int64_t pD[64];     // plane j: first bit of its run in the sign section
+  __shared__ uint32_t pc[64];    // plane j: sign bits of this chunk
+  __shared__ uint32_t ps[64];    // plane j: first bit of its run in the staging
+  __shared__ uint32_t pW[64];    // plane j: first of its destination words, counted over all planes
   const int64_t gch = blockIdx.x;
   const int u = find_stream(sd, ns, gch);
   const StreamDev& S = sd[u];
@@ -1570,25 +1592,37 @@ __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ 
     cj = ((const GAS uint32_t*)S.cnt)[chunk * S.B + lane];
     Dj = ((const GAS int64_t*)S.pso)[lane] * 64 + (int64_t)((const GAS uint32_t*)S.idx)[(int64_t)lane * S.C + chunk];
   }
-  const uint32_t sbj = wave_incl_scan(cj, lane) - cj;
+  const uint32_t nw = cj ? (uint32_t)(((Dj + cj - 1) >> 6) - (Dj >> 6) + 1) : 0u;
+  const uint32_t wincl = wave_incl_scan(nw, lane);
+  pD[lane] = Dj;
+  pc[lane] = cj;
+  ps[lane] = wave_incl_scan(cj, lane) - cj;
+  pW[lane] = wincl - nw;
+  const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)wincl, 63);
   __syncthreads();
-  const int B = S.B;
-  for (int j = 0; j < B; ++j) {
-    const int64_t c = (uint32_t)__builtin_amdgcn_readlane((int)cj, j);
-    if (c == 0) continue;
-    const int64_t D = readlane64(Dj, j);
-    const int sbit = __builtin_amdgcn_readlane((int)sbj, j);
-    const int64_t first = D >> 6, last = (D + c - 1) >> 6;
-    for (int64_t w = first + lane; w <= last; w += 64) {
-      const int64_t lo = max(w * 64, D), hi = min(w * 64 + 64, D + c);
-      const int nb = (int)(hi - lo);
-      const uint64_t bits = extract_bits(st, (int)(lo - D) + sbit, nb, 64);
-      const uint64_t val = bits << (lo - w * 64);
-      if (nb == 64)
-        ((GAS unsigned long long*)sign)[w] = val;
-      else if (val)
-        atomicOr(&sign[w], (unsigned long long)val);
+  // destination words of all planes, flattened, one per lane: the plane of
+  // word k is the last one whose first word is <= k (planes without bits
+  // share their first word with the next plane, and are passed over)
+  for (uint32_t k = lane; k < T; k += 64) {
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pW[mid] <= k)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
+    const int64_t D = pD[lo], c = pc[lo];
+    const int64_t w = (D >> 6) + (int64_t)(k - pW[lo]);
+    const int64_t blo = max(w * 64, D), bhi = min(w * 64 + 64, D + c);
+    const int nb = (int)(bhi - blo);
+    const uint64_t bits = extract_bits(st, (int)(blo - D) + (int)ps[lo], nb, 64);
+    const uint64_t val = bits << (blo - w * 64);
+    if (nb == 64)
+      ((GAS unsigned long long*)sign)[w] = val;
+    else if (val)
+      atomicOr(&sign[w], (unsigned long long)val);
   }
 }
 

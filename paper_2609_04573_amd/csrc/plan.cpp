@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
+#include <mutex>
 
 #include "host.h"
 
@@ -38,7 +40,7 @@ double to_double_scaled(__int128 num, int shift4) {
 // axis of n points.  Every weight is a multiple of 1/16, so each coarse unit
 // vector is prolonged level by level in integers scaled by 16 per level; its
 // support only grows by a few points per level.
-void axis_norms(int64_t n, int L, int degree, std::vector<double>& inf, std::vector<double>& one) {
+static void axis_norms_exact(int64_t n, int L, int degree, std::vector<double>& inf, std::vector<double>& one) {
   inf.assign(L, 1.0);
   one.assign(L, 1.0);
   std::vector<__int128> rows(n), cur, nxt;
@@ -87,6 +89,26 @@ void axis_norms(int64_t n, int L, int degree, std::vector<double>& inf, std::vec
     inf[l] = to_double_scaled(rowmax, l);
     one[l] = to_double_scaled(colmax, l);
   }
+}
+
+// The norms depend only on (n, L, degree) and every refactor of a field
+// needs them for each axis: they are computed once per shape and kept.
+void axis_norms(int64_t n, int L, int degree, std::vector<double>& inf, std::vector<double>& one) {
+  static std::mutex mu;
+  static std::map<std::array<int64_t, 3>, std::pair<std::vector<double>, std::vector<double>>> memo;
+  const std::array<int64_t, 3> key = {n, (int64_t)L, (int64_t)degree};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) {
+      inf = it->second.first;
+      one = it->second.second;
+      return;
+    }
+  }
+  axis_norms_exact(n, L, degree, inf, one);
+  std::lock_guard<std::mutex> lk(mu);
+  if (memo.size() < 4096) memo[key] = {inf, one};
 }
 
 Unit build_staircase(int group, const std::vector<std::vector<int>>& rs, const std::vector<Stream>& st) {
