@@ -591,7 +591,10 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
     // prediction of coarse plane cc (its tile is in cpre) on the thread's
     // four points; fetches the tile of cc + 1.  Block-uniform call.
     auto plane = [&](int cc, double (&u)[4]) {
-      __syncthreads();
+      // No barrier is needed before the tile is overwritten: its readers
+      // (the previous plane's axis-2 pass) all passed that plane's last
+      // barrier, and the readers of u2 (its axis-1 pass) pass the next one
+      // before u2 is written again.
 #pragma unroll
       for (int k = 0; k < kCPer; ++k)
         if (tid + k * kThreads < kC1 * kC2) ctile[tid + k * kThreads] = cpre[k];
