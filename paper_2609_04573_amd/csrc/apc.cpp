@@ -445,7 +445,7 @@ LevelSeg level_seg(const apc_handle* h, int l, int t2) {
   // runs along axis 0: as long as possible while the level still spreads
   // over enough blocks to fill the device
   s.ch = kLvlCH;
-  while (s.ch > 2 && (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch) < 2048) s.ch /= 2;
+  while (s.ch > 2 && (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch) < 1024) s.ch /= 2;
   return s;
 }
 int64_t assign_level_blocks(std::vector<LevelSeg>& segs) {

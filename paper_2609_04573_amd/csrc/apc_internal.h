@@ -11,7 +11,7 @@ namespace apc {
 
 constexpr int kChunk = 4096;        // codes per chunk (sign index granularity)
 constexpr int kBlockElems = 4096;   // lattice elements per work block (16 per thread)
-constexpr int kLvlCH = 32;  // per-level pass: longest run of planes along axis 0
+constexpr int kLvlCH = 128;  // per-level pass: longest run of planes along axis 0
 
 enum AxisKind : int32_t { AX_ALL = 0, AX_ODD = 1, AX_EVEN = 2 };
 
