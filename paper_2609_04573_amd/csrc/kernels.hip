@@ -1883,6 +1883,14 @@ __global__ __launch_bounds__(kThreads) void k_recon(const ReconSeg* __restrict__
     hipLaunchKernelGGL(kern, dim3(grid_for(nblk)), dim3(kThreads), 0, s, __VA_ARGS__); \
     return hipGetLastError();                                                          \
   } while (0)
+// The same with a kernel-specific cap on the grid (measured per kernel).
+#define APC_LAUNCH_CAP(kern, nblk, cap, ...)                                                         \
+  do {                                                                                               \
+    if ((nblk) <= 0) return hipSuccess;                                                              \
+    hipLaunchKernelGGL(kern, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)(cap))), dim3(kThreads), \
+                       0, s, __VA_ARGS__);                                                           \
+    return hipGetLastError();                                                                        \
+  } while (0)
 
 template <typename T>
 hipError_t launch_range(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s) {
@@ -1927,8 +1935,9 @@ hipError_t launch_cd_forward(const CDSeg* segs, int nseg, int64_t nblk, int a, i
 template <typename Q>
 hipError_t launch_cd_inverse(const CDSeg* segs, int nseg, int64_t nblk, int a, int phase, hipStream_t s) {
   if (phase == 2) {  // one pass over row tiles (v along rows)
-    if (a == 0) APC_LAUNCH((k_cd_inverse_tile<Q, 0>), nblk, segs, nseg, nblk);
-    APC_LAUNCH((k_cd_inverse_tile<Q, 1>), nblk, segs, nseg, nblk);
+    // one tile per block: measured faster than a grid-stride loop here
+    if (a == 0) APC_LAUNCH_CAP((k_cd_inverse_tile<Q, 0>), nblk, 1 << 20, segs, nseg, nblk);
+    APC_LAUNCH_CAP((k_cd_inverse_tile<Q, 1>), nblk, 1 << 20, segs, nseg, nblk);
   }
   if (phase == 0) {
     if (a == 0) APC_LAUNCH((k_cd_inverse<Q, 0, 0>), nblk, segs, nseg, nblk);
