@@ -325,11 +325,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--full", action="store_true", help="full-size batching and serving workloads")
+    ap.add_argument("--tile", type=int, default=0, choices=(0, 32, 64, 128),
+                    help="pin the sweep tile width instead of tuning it (profiling runs use this so that "
+                         "every run launches the same kernels and no tuning launches mix in)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarize rocprofv3 runs of this benchmark (DIR/kt, DIR/f, DIR/w) into profiles/")
     args = ap.parse_args()
     if args.summarize_profiles:
-        base = "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-systems"
+        base = "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-systems --tile 32"
         cmds = [f"rocprofv3 --kernel-trace --stats -d {args.summarize_profiles}/kt -o kt -- {base}",
                 f"rocprofv3 --pmc FETCH_SIZE -d {args.summarize_profiles}/f -o f -- {base.replace('--steps 3', '--steps 1')}",
                 f"rocprofv3 --pmc WRITE_SIZE -d {args.summarize_profiles}/w -o w -- {base.replace('--steps 3', '--steps 1')}",
@@ -368,7 +371,11 @@ def main():
         h.close()
         return t1 - t0, t2 - t1, info, streams
 
-    tune = apc.tune_tiles(xd)  # sweep tile width for this shape (setup, not timed)
+    if args.tile:
+        apc.tile_override(args.tile)
+        tune = {"tile": args.tile, "us": None}
+    else:
+        tune = apc.tune_tiles(xd)  # sweep tile width for this shape (setup, not timed)
     for _ in range(args.warmup):
         step()
     # untimed profiled steps: every launch bracketed by events -> per-kernel breakdown
