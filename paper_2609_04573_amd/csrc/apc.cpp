@@ -526,6 +526,21 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
 
 // Pinned staging that stays valid until the process ends; append-only
 // within one refactor call.
+// Device -> host copy on stream st through a pinned block, then wait for it:
+// a copy straight into pageable memory is staged by the runtime and costs
+// tens of microseconds of idle device time at every such read-back.
+apc_status read_back(void* host, const void* dev, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return APC_OK;
+  PinnedBlock b;
+  if (!g_pinned.get(bytes, b)) return fail(APC_E_OOM, "pinned read-back of %zu bytes", bytes);
+  hipError_t e = hipMemcpyAsync(b.p, dev, bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) memcpy(host, b.p, bytes);
+  g_pinned.put(b, st, e == hipSuccess ? false : true);
+  if (e != hipSuccess) return fail(APC_E_HIP, "read-back: %s", hipGetErrorString(e));
+  return APC_OK;
+}
+
 struct Staging {
   PinnedBlock b;
   size_t used = 0;
@@ -975,8 +990,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   APC_TRY(stage.put(tb.bytes, tab.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab.p, st)));
   std::vector<unsigned long long> hv((size_t)nacc);
-  HIP_TRY(hipMemcpyAsync(hv.data(), acc, 8 * hv.size(), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
   for (int f = 0; f < nf; ++f) {
     const unsigned long long* v = hv.data() + tmp[f].acc;
     if (v[3]) return fail(APC_E_NONFINITE, "field %d holds NaN or Inf", f);
@@ -1085,8 +1099,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   APC_TRY(stage.put(tb2.bytes, tab2.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab2.p, st)));
   if (any_cd) {
-    HIP_TRY(hipMemcpyAsync(hv.data(), acc, 8 * hv.size(), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
   }
   for (int f = 0; f < nf; ++f) {
     apc_handle* h = H[f];
@@ -1176,8 +1189,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
     LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
     LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
-    HIP_TRY(hipMemcpyAsync(tot.data(), totals.p, 8 * (size_t)njobs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    APC_TRY(read_back(tot.data(), totals.p, 8 * (size_t)njobs, st));
   }
   // ---- sign sections
   {
