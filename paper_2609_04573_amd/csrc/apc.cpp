@@ -901,7 +901,6 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         if (mode == 0 && l == 0) c.racc = acc + tmp[f].acc;  // the field's range, in the same pass
         const int gi = group_of(h->meta, l, 0);
         c.gmax = acc + tmp[f].acc + 4 + gi;
-        c.k_shift = h->meta.groups[gi].k_shift;
         for (int rho = 0; rho < h->geo.d; ++rho) c.q[rho] = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
         const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
         by += (double)n * (sizeof(T) + (mode == 1 ? sizeof(Q) : 0));
@@ -989,36 +988,14 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   APC_TRY(tab.alloc(tb.bytes.size()));
   APC_TRY(stage.put(tb.bytes, tab.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab.p, st)));
-  std::vector<unsigned long long> hv((size_t)nacc);
-  APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
-  for (int f = 0; f < nf; ++f) {
-    const unsigned long long* v = hv.data() + tmp[f].acc;
-    if (v[3]) return fail(APC_E_NONFINITE, "field %d holds NaN or Inf", f);
-    Meta& m = H[f]->meta;
-    m.xmin = unordered(v[0]);
-    m.xmax = unordered(v[1]);
-    m.A = bits_double(v[2]);
-    for (size_t gi = 0; gi < m.groups.size(); ++gi) {
-      Group& gr = m.groups[gi];
-      gr.M = bits_double(v[4 + gi]);
-      if (gr.M > 0.0) {
-        int E;
-        frexp(gr.M, &E);
-        gr.E = E;
-        gr.k_shift = P - E;
-        gr.delta = ldexp(1.0, E - P);
-      } else {
-        gr.E = 0;
-        gr.k_shift = 0;
-        gr.delta = 0.0;
-      }
-    }
-  }
 
-  // ---- second pass: codes, then coefficient decomposition
+  // ---- second pass: codes, then coefficient decomposition.  It is queued
+  // right behind the first: the quantization kernels derive each group's
+  // shift P - E from the group maximum the first pass left on the device, and
+  // the host reads the maxima (with the range and the decomposition maxima)
+  // once, after the decomposition.
   TableBuilder tb2;
   ls.clear();
-  bool any_cd = false;
   {
     double by = 0;
     std::vector<LevelSeg> lv = level_segs(1, by);
@@ -1038,7 +1015,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         if (lat_count(c.ra.lat) == 0) continue;
         c.G = grid_ptr(f, l);
         c.codes = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
-        c.k_shift = h->meta.groups[group_of(h->meta, l, rho)].k_shift;
+        c.gmax = acc + tmp[f].acc + 4 + group_of(h->meta, l, rho);
         by += (double)lat_count(c.ra.lat) * (sizeof(T) + sizeof(Q));
         cs.push_back(c);
       }
@@ -1054,7 +1031,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       s.src = grid_ptr(f, H[f]->geo.L - 1);
       s.dst = tmp[f].codes.p;
       s.n = H[f]->meta.streams[0].n;
-      s.k_shift = H[f]->meta.groups[0].k_shift;
+      s.acc = acc + tmp[f].acc + 4;  // the coarsest level's group (group 0)
       by += (double)(sizeof(T) + sizeof(Q)) * s.n;
       cs.push_back(s);
     }
@@ -1085,7 +1062,6 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       }
     }
     if (cs.empty()) continue;
-    any_cd = true;
     if (a3 < 2) {  // v runs along lattice rows: one pass over row tiles
       const int64_t nbk = assign_cd_tile_blocks(cs, a3);
       ls.push_back({K_CDFT, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
@@ -1098,8 +1074,30 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   APC_TRY(tab2.alloc(tb2.bytes.size()));
   APC_TRY(stage.put(tb2.bytes, tab2.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab2.p, st)));
-  if (any_cd) {
-    APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
+  std::vector<unsigned long long> hv((size_t)nacc);
+  APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
+  for (int f = 0; f < nf; ++f) {
+    const unsigned long long* v = hv.data() + tmp[f].acc;
+    if (v[3]) return fail(APC_E_NONFINITE, "field %d holds NaN or Inf", f);
+    Meta& m = H[f]->meta;
+    m.xmin = unordered(v[0]);
+    m.xmax = unordered(v[1]);
+    m.A = bits_double(v[2]);
+    for (size_t gi = 0; gi < m.groups.size(); ++gi) {
+      Group& gr = m.groups[gi];
+      gr.M = bits_double(v[4 + gi]);
+      if (gr.M > 0.0) {  // the shift the quantization kernels used (group_k_shift)
+        int E;
+        frexp(gr.M, &E);
+        gr.E = E;
+        gr.k_shift = P - E;
+        gr.delta = ldexp(1.0, E - P);
+      } else {
+        gr.E = 0;
+        gr.k_shift = 0;
+        gr.delta = 0.0;
+      }
+    }
   }
   for (int f = 0; f < nf; ++f) {
     apc_handle* h = H[f];

@@ -278,6 +278,21 @@ __device__ __forceinline__ void or_u64(unsigned long long* p, unsigned long long
   if ((*(volatile unsigned long long*)p & v) != v) atomicOr(p, v);
 }
 
+// Exponent alignment of a quantization group, P - E, where E is the binary
+// exponent of the group's largest |coefficient| M (M = m 2^E, 1/2 <= m < 1)
+// as the max pass left it in the group's accumulator (double bits); 0 for
+// an all-zero group.  P = 29 bits for float32 input, 52 for float64.  The
+// host derives the same value from the same accumulator for the metadata.
+template <typename T>
+__device__ __forceinline__ int group_k_shift(const unsigned long long* gmax) {
+  constexpr int P = sizeof(T) == 4 ? 29 : 52;
+  const double M = __longlong_as_double((long long)*gmax);
+  if (!(M > 0.0)) return 0;
+  int E;
+  (void)frexp(M, &E);
+  return P - E;
+}
+
 // ------------------------------------------------------------- range pass
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_range(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
@@ -376,6 +391,7 @@ template <typename T, typename Q, int MODE>
 __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ segs, int nseg, int64_t nblk) {
   int cur = -1;
   double am = 0.0;
+  int kq = 0, kseg = -1;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     if (MODE == 0 && si != cur) {
@@ -387,6 +403,10 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
       am = 0.0;
     }
     const CoefSeg& S = segs[si];
+    if (MODE == 1 && si != kseg) {  // the group's shift, read once per segment
+      kq = group_k_shift<T>(S.gmax);
+      kseg = si;
+    }
     const RegionArgs& ra = S.ra;
     const Lattice& L = ra.lat;
     const GAS T* G = (const GAS T*)S.G;
@@ -418,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
       if (MODE == 0)
         am = fmax(am, fabs(c));
       else
-        ((GAS Q*)S.codes)[e] = (Q)(long long)rint(ldexp(c, S.k_shift));
+        ((GAS Q*)S.codes)[e] = (Q)(long long)rint(ldexp(c, kq));
     }
   }
   if (MODE == 0 && cur >= 0) {
@@ -520,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
     const int64_t xs0 = S.xs[0], xs1 = S.xs[1], xs2 = S.xs[2];
     const bool fin = S.final_out != 0;
     const double delta = S.delta;
-    const int kshift = S.k_shift;
+    const int kshift = MODE == 1 ? group_k_shift<T>(S.gmax) : 0;
 
     // in-plane geometry of this thread (constant along axis 0)
     const int f2 = t2 + col;
@@ -705,6 +725,7 @@ template <typename T, typename Q, int MODE>
 __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
   int cur = -1;
   double am = 0.0;
+  int kq = 0, kseg = -1;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int si = find_seg(segs, nseg, b);
     if (MODE == 0 && si != cur) {
@@ -716,6 +737,10 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
       am = 0.0;
     }
     const FlatSeg& S = segs[si];
+    if (MODE == 1 && si != kseg) {  // the group's shift, read once per segment
+      kq = group_k_shift<T>(S.acc);
+      kseg = si;
+    }
     const GAS T* G = (const GAS T*)S.src;
     const int64_t e0 = (b - S.blk_begin) * kBlockElems;
 #pragma unroll 4
@@ -726,7 +751,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const FlatSeg* __restrict__
       if (MODE == 0)
         am = fmax(am, fabs(v));
       else
-        ((GAS Q*)S.dst)[e] = (Q)(long long)rint(ldexp(v, S.k_shift));
+        ((GAS Q*)S.dst)[e] = (Q)(long long)rint(ldexp(v, kq));
     }
   }
   if (MODE == 0 && cur >= 0) {
