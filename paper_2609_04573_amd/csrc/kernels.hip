@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
 // every thread owns one column and four consecutive rows.
 template <typename T, typename Q, int MODE, int kT2>
-__global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 || sizeof(T) == 8 ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
   constexpr int kNRG = kThreads / kT2;  // row groups
   constexpr int kT1 = 4 * kNRG;
   constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
@@ -547,42 +547,34 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
     const bool odd2 = f2 & 1;
     const int sk2 = odd2 ? stencil_kind(f2, m2, deg) : 0;
     const int tc2 = odd2 ? ((f2 - 1) >> 1) - c2s : (f2 >> 1) - c2s;  // coarse tile column of f2 (or left of it)
-    int sk1[4], tr1[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int f1 = t1 + 4 * rg + i;
-      sk1[i] = (f1 & 1) ? stencil_kind(f1, m1, deg) : 0;
-      tr1[i] = (f1 & 1) ? ((f1 - 1) >> 1) - c1s : (f1 >> 1) - c1s;
-    }
+    // The thread's four points are on rows f1b + i, i = 0..3, with f1b even
+    // (tiles start on even rows), so odd i means an odd row.  Everything
+    // about point i is a cheap function of i and a few per-thread values,
+    // recomputed where used instead of being held in registers.
+    const int f1b = t1 + 4 * rg;
+    const int sk1o[2] = {stencil_kind(f1b + 1, m1, deg), stencil_kind(f1b + 3, m1, deg)};
+    auto sk1 = [&](int i) { return (i & 1) ? sk1o[i >> 1] : 0; };
+    auto tr1 = [&](int i) { return (f1b >> 1) + (i >> 1) - c1s; };  // coarse tile row of the row (or above it)
     // offsets of the thread's four points, split into a per-plane part and a
     // part fixed along axis 0 (all below 2^32: fields hold < 2^32 points):
-    // grid offset = f0 * m1 * m2 + rg2[i]; region lattice index = c * P + R
+    // grid offset = f0 * m1 * m2 + rg2(i); region lattice index = c * P + R
     // with c = f0 / 2 (region 2 on odd planes; region 0 or 1, or a coarse
-    // point, on even planes); source offset = f0 * xs0 + rsrc[i]
+    // point, on even planes); source offset = f0 * xs0 + rsrc(i)
     const uint32_t pl2 = (uint32_t)m1 * (uint32_t)m2;
-    uint32_t rg2[4], re[4], pe[4], rsrc[4];
-    int rre[4];
-    bool okp[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int f1 = t1 + 4 * rg + i;
-      okp[i] = f1 < m1 && f2 < m2;
-      rg2[i] = (uint32_t)f1 * (uint32_t)m2 + (uint32_t)f2;
-      rsrc[i] = (uint32_t)((int64_t)f1 * xs1 + (int64_t)f2 * xs2);
-      if (f1 & 1) {
-        rre[i] = 1;
-        pe[i] = (uint32_t)(m1 >> 1) * (uint32_t)m2;
-        re[i] = (uint32_t)(f1 >> 1) * (uint32_t)m2 + (uint32_t)f2;
-      } else if (odd2) {
-        rre[i] = 0;
-        pe[i] = (uint32_t)((m1 + 1) >> 1) * (uint32_t)(m2 >> 1);
-        re[i] = (uint32_t)(f1 >> 1) * (uint32_t)(m2 >> 1) + (uint32_t)(f2 >> 1);
-      } else {
-        rre[i] = -1;
-        pe[i] = 0;
-        re[i] = 0;
-      }
-    }
+    const uint32_t rg2b = (uint32_t)f1b * (uint32_t)m2 + (uint32_t)f2;
+    const uint32_t rsrcb = (uint32_t)((int64_t)f1b * xs1 + (int64_t)f2 * xs2);
+    const uint32_t pe_odd = (uint32_t)(m1 >> 1) * (uint32_t)m2;                 // region 1 plane size
+    const uint32_t pe_even = (uint32_t)((m1 + 1) >> 1) * (uint32_t)(m2 >> 1);  // region 0 plane size
+    const uint32_t re_odd = (uint32_t)(f1b >> 1) * (uint32_t)m2 + (uint32_t)f2;
+    const uint32_t re_even = (uint32_t)(f1b >> 1) * (uint32_t)(m2 >> 1) + (uint32_t)(f2 >> 1);
+    auto okp = [&](int i) { return f1b + i < m1 && f2 < m2; };
+    auto rg2 = [&](int i) { return rg2b + (uint32_t)i * (uint32_t)m2; };
+    auto rsrc = [&](int i) { return rsrcb + (uint32_t)i * (uint32_t)xs1; };
+    auto rre = [&](int i) { return (i & 1) ? 1 : (odd2 ? 0 : -1); };  // region on even planes (-1: coarse point)
+    auto pe = [&](int i) { return (i & 1) ? pe_odd : pe_even; };
+    auto re = [&](int i) {
+      return (i & 1) ? re_odd + (uint32_t)(i >> 1) * (uint32_t)m2 : re_even + (uint32_t)(i >> 1) * (uint32_t)(m2 >> 1);
+    };
     // coarse tile entries of this thread: global offsets within a plane (-1 = outside the grid)
     int64_t coff[kCPer];
 #pragma unroll
@@ -631,8 +623,8 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double* cp = u2 + tr1[i] * kT2 + col;
-        u[i] = ((t1 + 4 * rg + i) & 1) ? stencil_eval(sk1[i], [&](int o) { return cp[((o + 1) / 2) * kT2]; }) : cp[0];
+        const double* cp = u2 + tr1(i) * kT2 + col;
+        u[i] = (i & 1) ? stencil_eval(sk1(i), [&](int o) { return cp[((o + 1) / 2) * kT2]; }) : cp[0];
       }
     };
 
@@ -645,21 +637,21 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           in[h * 4 + i] = (V)0;
-          const int rr = h ? 2 : rre[i];
-          if (f0 >= f0b || !okp[i] || rr < 0) continue;
+          const int rr = h ? 2 : rre(i);
+          if (f0 >= f0b || !okp(i) || rr < 0) continue;
           if (MODE == 2) {
-            const uint32_t li = (uint32_t)c * (h ? pl2 : pe[i]) + (h ? rg2[i] : re[i]);
+            const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
             in[h * 4 + i] = (V)qptr(rr)[li];
           } else {
-            in[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc[i]];
+            in[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc(i)];
           }
         }
       }
     };
     auto emit = [&](int f0, int i, double p, V v) {
       const int h = f0 & 1;
-      if (f0 >= f0b || !okp[i]) return;
-      const int rr = h ? 2 : rre[i];
+      if (f0 >= f0b || !okp(i)) return;
+      const int rr = h ? 2 : rre(i);
       if (MODE == 2) {
         double x = p;  // a coarse point keeps its reconstructed value
         if (rr >= 0) {
@@ -667,7 +659,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
           const int k = rr == 0 ? kr[0] : (rr == 1 ? kr[1] : kr[2]);
           x = p + (double)mask_code<Q>((Q)v, B, k) * delta;
         }
-        const uint32_t o = (uint32_t)f0 * pl2 + rg2[i];
+        const uint32_t o = (uint32_t)f0 * pl2 + rg2(i);
         if (fin)
           ((GAS T*)outp)[o] = (T)x;
         else
@@ -678,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const LevelSeg* __restrict__
         if (MODE == 0) {
           am = fmax(am, fabs(c));
         } else {
-          const uint32_t li = (uint32_t)(f0 >> 1) * (h ? pl2 : pe[i]) + (h ? rg2[i] : re[i]);
+          const uint32_t li = (uint32_t)(f0 >> 1) * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
           qptr(rr)[li] = (Q)(long long)rint(ldexp(c, kshift));
         }
       }
