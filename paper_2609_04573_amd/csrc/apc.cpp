@@ -1074,6 +1074,18 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   APC_TRY(tab2.alloc(tb2.bytes.size()));
   APC_TRY(stage.put(tb2.bytes, tab2.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab2.p, st)));
+  // Sign arenas, sized by a bound known before any count (each code takes at
+  // most one sign bit and each plane's run is rounded up to whole words) and
+  // cleared now, so that the clear is queued behind the passes above instead
+  // of between the count read-back and the sign placement.
+  std::vector<int64_t> sign_ub(nf, 0);
+  for (int f = 0; f < nf; ++f) {
+    apc_handle* h = H[f];
+    for (const Stream& S : h->meta.streams) sign_ub[f] += (S.n + 63) / 64 + 8 * (int64_t)sizeof(Q);
+    sign_ub[f] = std::max<int64_t>(1, sign_ub[f]);
+    APC_TRY(h->sign.alloc(8 * (size_t)sign_ub[f]));
+    HIP_TRY(hipMemsetAsync(h->sign.p, 0, 8 * (size_t)sign_ub[f], st));
+  }
   std::vector<unsigned long long> hv((size_t)nacc);
   APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
   for (int f = 0; f < nf; ++f) {
@@ -1219,9 +1231,8 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     }
     for (int f = 0; f < nf; ++f) {
       apc_handle* h = H[f];
-      APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_words[f])));
+      if (sign_words[f] > sign_ub[f]) return fail(APC_E_INVALID, "internal: sign section exceeds its bound");
       APC_TRY(h->pso.alloc(8 * std::max<size_t>(1, pso_host[f].size())));
-      HIP_TRY(hipMemsetAsync(h->sign.p, 0, 8 * (size_t)std::max<int64_t>(1, sign_words[f]), st));
       std::vector<char> b(8 * pso_host[f].size());
       if (!b.empty()) memcpy(b.data(), pso_host[f].data(), b.size());
       APC_TRY(stage.put(b, h->pso.p, st));
