@@ -529,15 +529,36 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
 // Device -> host copy on stream st through a pinned block, then wait for it:
 // a copy straight into pageable memory is staged by the runtime and costs
 // tens of microseconds of idle device time at every such read-back.
+// Waits by polling the block's event: a blocking wait puts the thread to
+// sleep and its wake-up alone costs tens of microseconds, during which the
+// device would idle.
 apc_status read_back(void* host, const void* dev, size_t bytes, hipStream_t st) {
   if (bytes == 0) return APC_OK;
   PinnedBlock b;
   if (!g_pinned.get(bytes, b)) return fail(APC_E_OOM, "pinned read-back of %zu bytes", bytes);
   hipError_t e = hipMemcpyAsync(b.p, dev, bytes, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipEventRecord(b.ev, st);
+  if (e == hipSuccess) {
+    while ((e = hipEventQuery(b.ev)) == hipErrorNotReady) {
+    }
+  }
   if (e == hipSuccess) memcpy(host, b.p, bytes);
-  g_pinned.put(b, st, e == hipSuccess ? false : true);
+  g_pinned.put(b, st, e != hipSuccess);
   if (e != hipSuccess) return fail(APC_E_HIP, "read-back: %s", hipGetErrorString(e));
+  return APC_OK;
+}
+
+// Wait for the work queued on st by polling an event (see read_back).
+apc_status spin_sync(hipStream_t st) {
+  hipEvent_t ev = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipError_t e = hipEventRecord(ev, st);
+  if (e == hipSuccess) {
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+  }
+  (void)hipEventDestroy(ev);
+  if (e != hipSuccess) return fail(APC_E_HIP, "stream wait: %s", hipGetErrorString(e));
   return APC_OK;
 }
 
@@ -1254,7 +1275,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       APC_TRY(stage.put(tb4.bytes, sdb2.p, st));
       LAUNCH("sign_move", sb, st,
              launch_sign_move((const StreamDev*)((const char*)sdb2.p + o_sd), (int)sds.size(), chunks, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      APC_TRY(spin_sync(st));
     }
   }
   for (int f = 0; f < nf; ++f) {
