@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
 // every thread owns one column and four consecutive rows.
 template <typename T, typename Q, int MODE, int kT2>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 || sizeof(T) == 8 ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
   constexpr int kNRG = kThreads / kT2;  // row groups
   constexpr int kT1 = 4 * kNRG;
   constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
@@ -475,10 +475,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE =
   __shared__ int sbad;
   int cur = -1;
   double am = 0.0;
-  // range of the field (max pass over level 0): min, max, max |x|, non-finite seen
-  double rlo = INFINITY, rhi = -INFINITY, ram = 0.0;
+  // range of the field (max pass over level 0): min, max, max |x|, non-finite
+  // seen; kept in the field's own type (exact: every value is one of the
+  // field's values), which for float32 fields halves their registers
+  T rlo = (T)INFINITY, rhi = (T)-INFINITY, ram = (T)0;
   bool rbad = false;
-  auto take = [&](double v) {
+  auto take = [&](T v) {
     if (!isfinite(v)) {
       rbad = true;
     } else {
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE =
     if (threadIdx.x == 0) max_u64(segs[si].gmax, (unsigned long long)__double_as_longlong(m));
     unsigned long long* acc = segs[si].racc;
     if (acc) {
-      const double l = -block_max(-rlo), h = block_max(rhi), a = block_max(ram);
+      const double l = -block_max(-(double)rlo), h = block_max((double)rhi), a = block_max((double)ram);
       if (threadIdx.x == 0) sbad = 0;
       __syncthreads();
       if (rbad) sbad = 1;
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE =
       if (cur >= 0) flush(cur);
       cur = si;
       am = 0.0;
-      rlo = INFINITY, rhi = -INFINITY, ram = 0.0;
+      rlo = (T)INFINITY, rhi = (T)-INFINITY, ram = (T)0;
       rbad = false;
     }
     const LevelSeg& S = segs[si];
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE =
         if (coff[k] >= 0) {
           const int64_t o = (int64_t)cc * cplane + coff[k];
           cpre[k] = MODE == 2 ? ((const GAS double*)src)[o] : (double)((const GAS T*)src)[o];
-          if (MODE == 0 && racc) take(cpre[k]);
+          if (MODE == 0 && racc) take((T)cpre[k]);
         }
       }
     };
@@ -666,7 +668,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MODE =
           ((GAS double*)outp)[o] = x;
       } else if (rr >= 0) {
         const double c = (double)v - p;
-        if (MODE == 0 && racc) take((double)v);
+        if (MODE == 0 && racc) take((T)v);
         if (MODE == 0) {
           am = fmax(am, fabs(c));
         } else {
