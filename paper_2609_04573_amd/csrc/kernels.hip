@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
 constexpr int kCFP = kCITV + 4;  // LDS row pitch: two halo columns each side
 
 template <typename Q, int A>
-__global__ __launch_bounds__(kThreads) void k_cd_forward_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(Q) == 4 ? 5 : 4))) void k_cd_forward_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
   using W = LiftT<Q>;
   using UW = typename std::make_unsigned<W>::type;
   constexpr int U = A == 0 ? 1 : 0;
