@@ -23,9 +23,12 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s
 
 
 # Kernel symbol -> the launch category the library's event profiler reports.
+# (name prefix, third template argument (the pass) or "", category); the
+# per-level sweep is k_level<T, Q, pass, tile width>, the per-region pass
+# k_coef<T, Q, pass>
 KERNEL_CATEGORY = [
-    ("k_level<", ", 0>", "coef_max"), ("k_level<", ", 1>", "coef_quant"), ("k_level<", ", 2>", "recon"),
-    ("k_coef<", ", 0>", "coef_max"), ("k_coef<", ", 1>", "coef_quant"), ("k_recon<", "", "recon"),
+    ("k_level<", "0", "coef_max"), ("k_level<", "1", "coef_quant"), ("k_level<", "2", "recon"),
+    ("k_coef<", "0", "coef_max"), ("k_coef<", "1", "coef_quant"), ("k_recon<", "", "recon"),
     ("k_cd_forward", "", "cd_forward"), ("k_cd_inverse", "", "cd_inverse"), ("k_encode", "", "encode"),
     ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_scan", "", "scan"),
     ("k_range", "", "range"), ("k_gather", "", "subsample"), ("k_coarsest", "", "coarsest"),
@@ -53,8 +56,9 @@ def _short_kernel(name: str) -> str:
 
 
 def _category(kname: str):
-    for head, tail, cat in KERNEL_CATEGORY:
-        if kname.startswith(head) and (not tail or kname.endswith(tail)):
+    args = kname[kname.find("<") + 1:kname.rfind(">")].split(",") if "<" in kname else []
+    for head, mode, cat in KERNEL_CATEGORY:
+        if kname.startswith(head) and (not mode or (len(args) > 2 and args[2].strip() == mode)):
             return cat
     return None
 
