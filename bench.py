@@ -24,10 +24,12 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s
 
 # Kernel symbol -> the launch category the library's event profiler reports.
 # (name prefix, third template argument (the pass) or "", category); the
-# per-level sweep is k_level<T, Q, pass, tile width>, the per-region pass
+# per-level sweep is k_level<T, Q, pass, tile width> (pass 2 reconstructs the
+# coarser levels, pass 3 level 0 into the output field), the per-region pass
 # k_coef<T, Q, pass>
 KERNEL_CATEGORY = [
-    ("k_level<", "0", "coef_max"), ("k_level<", "1", "coef_quant"), ("k_level<", "2", "recon"),
+    ("k_level<", "0", "coef_max"), ("k_level<", "1", "coef_quant"), ("k_level<", "2", "recon_coarse"),
+    ("k_level<", "3", "recon"),
     ("k_coef<", "0", "coef_max"), ("k_coef<", "1", "coef_quant"), ("k_recon<", "", "recon"),
     ("k_cd_forward", "", "cd_forward"), ("k_cd_inverse", "", "cd_inverse"), ("k_encode", "", "encode"),
     ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_scan", "", "scan"),
@@ -449,6 +451,13 @@ def main():
                         "unit": "GB/s", "frac": achieved / (HBM_PEAK / 1e9), "traffic": load_traffic(dom),
                         "launches_per_step": d["count"] / args.steps,
                         "ms_per_step": d["ms"] / args.steps}
+    # The same kernel in the single-stream profiled steps (no other kernel
+    # running beside it there): the timed steps retrieve on two streams, so a
+    # kernel timed there may share the device with the coarse-level chain.
+    b = breakdown[dom]
+    serial = b["bytes"] / (b["ms"] * 1e-3) / 1e9
+    line["roofline_single_stream"] = {"kernel": dom, "achieved": serial, "frac": serial / (HBM_PEAK / 1e9),
+                                      "unit": "GB/s", "ms_per_step": b["ms"] / 2}
     line["kernels_ms_per_step"] = {k: round(v["ms"] / 2, 4) for k, v in
                                    sorted(breakdown.items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_systems:

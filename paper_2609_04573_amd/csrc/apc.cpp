@@ -386,7 +386,11 @@ struct TableBuilder {
 
 enum LaunchKind {
   K_RANGE, K_GATHER, K_COEF0, K_COEF1, K_COARSE0, K_COARSE1, K_CDF, K_CDI0, K_CDI1,
-  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2, K_CDIT, K_CDFT
+  K_ENCODE, K_SIGN, K_DECODE, K_COARSEST, K_INJECT, K_RECON, K_LEVEL0, K_LEVEL1, K_LEVEL2, K_LEVEL3, K_CDIT, K_CDFT,
+  // two-stream retrieval: the helper stream starts after what the main one
+  // queued so far (FORK), marks its end (JOIN_REC), and the main one waits
+  // for that mark (JOIN_WAIT); without a helper stream these do nothing
+  K_FORK, K_JOIN_REC, K_JOIN_WAIT
 };
 
 struct Launch {
@@ -397,6 +401,7 @@ struct Launch {
   int a;          // stacking axis (decomposition kernels)
   double bytes;   // bytes the launch must move (profiling)
   const char* name;
+  int side = 0;   // 1: runs on the helper stream, when there is one
 };
 
 template <typename S>
@@ -479,10 +484,24 @@ int64_t assign_cd_tile_blocks(std::vector<CDSeg>& segs, int a) {
 }
 
 template <typename T, typename Q>
-apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st) {
+apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st0, hipStream_t aux = nullptr,
+                 hipEvent_t ev_fork = nullptr, hipEvent_t ev_join = nullptr) {
   for (const Launch& l : ls) {
     const void* p = base + l.off;
+    const hipStream_t st = aux && l.side ? aux : st0;
     switch (l.kind) {
+      case K_FORK:
+        if (aux) {
+          HIP_TRY(hipEventRecord(ev_fork, st0));
+          HIP_TRY(hipStreamWaitEvent(aux, ev_fork, 0));
+        }
+        break;
+      case K_JOIN_REC:
+        if (aux) HIP_TRY(hipEventRecord(ev_join, aux));
+        break;
+      case K_JOIN_WAIT:
+        if (aux) HIP_TRY(hipStreamWaitEvent(st0, ev_join, 0));
+        break;
       case K_RANGE: LAUNCH(l.name, l.bytes, st, launch_range<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_GATHER: LAUNCH(l.name, l.bytes, st, launch_gather<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_COEF0: LAUNCH(l.name, l.bytes, st, (launch_coef<T, Q>((const CoefSeg*)p, l.nseg, l.nblk, 0, st))); break;
@@ -515,6 +534,7 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
       case K_LEVEL0:
       case K_LEVEL1:
       case K_LEVEL2:
+      case K_LEVEL3:
         LAUNCH(l.name, l.bytes, st,
                (launch_level<T, Q>((const LevelSeg*)p, l.nseg, l.nblk, l.kind - K_LEVEL0, l.a, st)));
         break;
@@ -524,8 +544,6 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
   return APC_OK;
 }
 
-// Pinned staging that stays valid until the process ends; append-only
-// within one refactor call.
 // Device -> host copy on stream st through a pinned block, then wait for it:
 // a copy straight into pageable memory is staged by the runtime and costs
 // tens of microseconds of idle device time at every such read-back.
@@ -562,6 +580,8 @@ apc_status spin_sync(hipStream_t st) {
   return APC_OK;
 }
 
+// Pinned staging that stays valid until the process ends; append-only
+// within one refactor call.
 struct Staging {
   PinnedBlock b;
   size_t used = 0;
@@ -1378,20 +1398,28 @@ WorkPtrs handle_work(apc_handle* h) {
 // Tables and launches of one retrieval; kres tracks the planes resident
 // after it (incremental decode).  The decode part and the reconstruction
 // part can be built separately (a server runs them on different streams).
+// `split`: queue the levels coarser than level 0 (their decode, the coarsest
+// level and their reconstruction) so that they can run on a helper stream
+// beside the level-0 decode and recomposition (per-level fields with a
+// decomposition and at least three levels; the launches carry fork and join
+// marks, which do nothing when issued on one stream).
 template <typename T, typename Q>
 void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::vector<int>& kres,
                     TableBuilder& tb, std::vector<Launch>& ls, int64_t* fetched, const WorkPtrs& w,
-                    bool with_decode = true, bool with_recon = true) {
+                    bool with_decode = true, bool with_recon = true, bool split = false) {
   Meta& m = h->meta;
   const Geo& g = h->geo;
   const int d = g.d, L = g.L;
   const bool per_level = h->scheme.kind == APC_PER_LEVEL;
-  std::vector<StreamDev> sds;
-  int64_t chunks = 0, fb = 0;
-  double db = 0.0;
+  const bool split_on = split && with_decode && with_recon && per_level && !h->cd.empty() && L >= 3;
+  const size_t base = ls.size();
+  std::vector<StreamDev> sds, sds_fine;
+  int64_t chunks = 0, chunks_fine = 0, fb = 0;
+  double db = 0.0, db_fine = 0.0;
   for (int s = 0; s < (int)m.streams.size() && with_decode; ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
+    const bool fine = split_on && S.level == 0 && S.kind != S_COARSE;
     StreamDev sd{};
     sd.codes = (S.use_cd ? h->cd_codes.as<Q>() : h->codes.as<Q>()) + S.code_off;
     sd.mag = h->mag.as<uint64_t>() + S.mag_off;
@@ -1402,22 +1430,26 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     sd.n = S.n;
     sd.M = S.words();
     sd.C = S.chunks();
-    sd.chunk_begin = chunks;
+    sd.chunk_begin = fine ? chunks_fine : chunks;
     sd.B = S.B;
     sd.k0 = kres[s];
     sd.k1 = planes[s];
     sd.fresh = kres[s] == 0 ? 1 : 0;
+    double b = 0.0;
     for (int j = sd.k0; j < sd.k1; ++j) {
       fb += S.plane_bytes(j);
-      db += 8.0 * ((S.nsig[j] + 63) / 64);
+      b += 8.0 * ((S.nsig[j] + 63) / 64);
     }
-    db += (double)(sd.k1 - sd.k0) * (8.0 * sd.M + 4.0 * sd.C) + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
-    chunks += sd.C;
-    sds.push_back(sd);
+    b += (double)(sd.k1 - sd.k0) * (8.0 * sd.M + 4.0 * sd.C) + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
+    (fine ? chunks_fine : chunks) += sd.C;
+    (fine ? db_fine : db) += b;
+    (fine ? sds_fine : sds).push_back(sd);
     kres[s] = planes[s];
   }
   if (fetched) *fetched = fb;
   if (!sds.empty()) ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, 0, db, "decode"});
+  if (!sds_fine.empty())  // `a` = 1 marks the level-0 decode for the reordering below
+    ls.push_back({K_DECODE, tb.add(sds_fine), (int)sds_fine.size(), chunks_fine, 1, db_fine, "decode"});
   if (!with_recon) return;
   // inverse decomposition of every level-0 region
   if (!h->cd.empty() && L >= 2) {
@@ -1496,7 +1528,8 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       const int64_t nbk = assign_level_blocks(cs);
       const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
       const double by = (double)n * (sizeof(Q) + (l ? 8 : sizeof(T))) + 8.0 * c.mc[0] * c.mc[1] * c.mc[2];
-      ls.push_back({K_LEVEL2, tb.add(cs), 1, nbk, t2, by, "recon"});
+      // level 0 writes the output field: its own kernel and profile name
+      ls.push_back({l == 0 ? K_LEVEL3 : K_LEVEL2, tb.add(cs), 1, nbk, t2, by, l == 0 ? "recon" : "recon_coarse"});
       xin = xout;
       continue;
     }
@@ -1547,6 +1580,34 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     }
     xin = xout;
   }
+  if (split_on) {
+    // queued as: coarse decode | fork | coarsest, levels L-2..1 (helper) |
+    // join mark | level-0 decode, recomposition | join wait | level 0
+    std::vector<Launch> dec_c, dec_f, cdi, chain, lev0;
+    for (size_t i = base; i < ls.size(); ++i) {
+      Launch x = ls[i];
+      if (x.kind == K_DECODE)
+        (x.a ? dec_f : dec_c).push_back(x);
+      else if (x.kind == K_CDIT || x.kind == K_CDI0 || x.kind == K_CDI1)
+        cdi.push_back(x);
+      else if (x.kind == K_LEVEL3)
+        lev0.push_back(x);
+      else {
+        x.side = 1;
+        chain.push_back(x);
+      }
+    }
+    ls.resize(base);
+    auto mark = [&](int kind) { ls.push_back({kind, 0, 0, 0, 0, 0.0, "mark"}); };
+    for (const Launch& x : dec_c) ls.push_back(x);
+    mark(K_FORK);
+    for (const Launch& x : chain) ls.push_back(x);
+    mark(K_JOIN_REC);
+    for (const Launch& x : dec_f) ls.push_back(x);
+    for (const Launch& x : cdi) ls.push_back(x);
+    mark(K_JOIN_WAIT);
+    for (const Launch& x : lev0) ls.push_back(x);
+  }
 }
 
 apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStream_t st) {
@@ -1564,15 +1625,71 @@ apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStrea
   return APC_OK;
 }
 
+// Helper streams (with a fork and a join event) for two-stream retrievals,
+// checked out per call and returned as soon as the work is queued: later
+// users queue behind it, and the events are read when a wait is queued, so
+// re-recording them afterwards is safe.  Created on first use on a device
+// (default priority, non-blocking) and kept until the process ends.
+struct AuxStream {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+struct AuxPool {
+  std::mutex mu;
+  std::vector<AuxStream> free_;
+  bool get(AuxStream& out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].dev == dev) {
+          out = free_[i];
+          free_.erase(free_.begin() + (long)i);
+          return true;
+        }
+    }
+    out = AuxStream();
+    out.dev = dev;
+    if (hipStreamCreateWithFlags(&out.s, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&out.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&out.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;  // the stream is kept (never destroyed)
+    }
+    return true;
+  }
+  void put(const AuxStream& a) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_.push_back(a);
+  }
+};
+AuxPool g_aux;
+
 template <typename T, typename Q>
 apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, hipStream_t st, int64_t* fetched) {
   APC_TRY(ensure_work(h));
   TableBuilder tb;
   std::vector<Launch> ls;
   std::vector<int> kres = h->k_res;
-  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched, handle_work(h));
+  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched, handle_work(h), true, true, true);
   APC_TRY(upload_tables(h, tb.bytes, st));
-  APC_TRY((issue<T, Q>(ls, (const char*)h->tables.p, st)));
+  // two streams, except while every launch is timed (the per-kernel
+  // breakdown is taken on one stream so that no kernel's time includes
+  // another's running beside it)
+  bool split = !(g_prof.on && g_prof.only.empty());
+  bool marks = false;
+  for (const Launch& l : ls) marks = marks || l.kind == K_FORK;
+  split = split && marks;
+  AuxStream aux;
+  if (split && g_aux.get(aux)) {
+    const apc_status r = issue<T, Q>(ls, (const char*)h->tables.p, st, aux.s, aux.fork, aux.join);
+    g_aux.put(aux);
+    APC_TRY(r);
+  } else {
+    APC_TRY((issue<T, Q>(ls, (const char*)h->tables.p, st)));
+  }
   h->k_res = kres;
   return APC_OK;
 }

@@ -460,7 +460,8 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // LDS passes.
 // MODE 0: max |x - p| of the level.  MODE 1: codes q = rint(c * 2^k_shift)
 // into the three region lattices.  MODE 2: x = p + Delta * q' on the level
-// grid (coarse points are copied).
+// grid (coarse points are copied), written as float64 for the next level;
+// MODE 3: the same for level 0, written as the output field (type T).
 // Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
 // every thread owns one column and four consecutive rows.
 template <typename T, typename Q, int MODE, int kT2>
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
   constexpr int kT1 = 4 * kNRG;
   constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
   constexpr int kCPer = (kC1 * kC2 + kThreads - 1) / kThreads;  // coarse tile entries per thread
-  using V = typename std::conditional<MODE == 2, Q, T>::type;  // per-point input: code or value
+  using V = typename std::conditional<MODE >= 2, Q, T>::type;  // per-point input: code or value
   __shared__ double ctile[kC1 * kC2];
   __shared__ double u2[kC1 * kT2];
   __shared__ int sbad;
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     const void* const src = S.src;
     void* const outp = S.out;
     const int64_t xs0 = S.xs[0], xs1 = S.xs[1], xs2 = S.xs[2];
-    const bool fin = S.final_out != 0;
+    constexpr bool fin = MODE == 3;  // level 0: the T output field
     const double delta = S.delta;
     const int kshift = MODE == 1 ? group_k_shift<T>(S.gmax) : 0;
 
@@ -586,9 +587,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       const int c1 = c1s + r, c2 = c2s + kk;
       coff[k] = -1;
       if (e < kC1 * kC2 && c1 >= 0 && c1 < mc1 && c2 >= 0 && c2 < mc2)
-        coff[k] = MODE == 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * xs1 + (int64_t)(2 * c2) * xs2;
+        coff[k] = MODE >= 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * xs1 + (int64_t)(2 * c2) * xs2;
     }
-    const int64_t cplane = MODE == 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
+    const int64_t cplane = MODE >= 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
     double cpre[kCPer];
     auto fetch_tile = [&](int cc) {
 #pragma unroll
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
         cpre[k] = 0.0;
         if (coff[k] >= 0) {
           const int64_t o = (int64_t)cc * cplane + coff[k];
-          cpre[k] = MODE == 2 ? ((const GAS double*)src)[o] : (double)((const GAS T*)src)[o];
+          cpre[k] = MODE >= 2 ? ((const GAS double*)src)[o] : (double)((const GAS T*)src)[o];
           if (MODE == 0 && racc) take((T)cpre[k]);
         }
       }
@@ -641,7 +642,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
           in[h * 4 + i] = (V)0;
           const int rr = h ? 2 : rre(i);
           if (f0 >= f0b || !okp(i) || rr < 0) continue;
-          if (MODE == 2) {
+          if (MODE >= 2) {
             const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
             in[h * 4 + i] = (V)qptr(rr)[li];
           } else {
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       const int h = f0 & 1;
       if (f0 >= f0b || !okp(i)) return;
       const int rr = h ? 2 : rre(i);
-      if (MODE == 2) {
+      if (MODE >= 2) {
         double x = p;  // a coarse point keeps its reconstructed value
         if (rr >= 0) {
           const int B = rr == 0 ? Br[0] : (rr == 1 ? Br[1] : Br[2]);
@@ -1934,7 +1935,8 @@ template <typename T, typename Q>
 hipError_t launch_level(const LevelSeg* segs, int nseg, int64_t nblk, int mode, int t2, hipStream_t s) {
   if (mode == 0) return launch_level_mode<T, Q, 0>(segs, nseg, nblk, t2, s);
   if (mode == 1) return launch_level_mode<T, Q, 1>(segs, nseg, nblk, t2, s);
-  return launch_level_mode<T, Q, 2>(segs, nseg, nblk, t2, s);
+  if (mode == 2) return launch_level_mode<T, Q, 2>(segs, nseg, nblk, t2, s);
+  return launch_level_mode<T, Q, 3>(segs, nseg, nblk, t2, s);
 }
 template <typename T, typename Q>
 hipError_t launch_coarse(const FlatSeg* segs, int nseg, int64_t nblk, int mode, hipStream_t s) {
