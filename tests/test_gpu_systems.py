@@ -148,3 +148,32 @@ def test_tile_widths_do_not_change_results(config1_field):
             apc.tile_override(48)
     finally:
         apc.tile_override(0)
+
+
+def test_two_stream_retrieval_equals_one_stream():
+    """A retrieval of a per-level field with a decomposition runs its coarse
+    levels on a helper stream beside the level-0 work; with every launch
+    profiled it runs on one stream.  Both give the oracle's values, for a
+    fresh decode and for an incremental one on the same handle."""
+    apc = _apc()
+    x = fieldgen.power_law_field((40, 72, 300), seed=9)
+    sc = oracle.Scheme(kind="level", cd_axis=0)
+    ref = oracle.refactor(x, sc)
+    xd = torch.from_numpy(x).cuda()
+    outs = {}
+    for one_stream in (False, True):
+        h = apc.refactor(xd, apc.Scheme(kind="level", cd_axis=0))
+        apc.apc.profile_enable(one_stream)
+        try:
+            for rel in (1e-2, 1e-5):
+                got, _ = h.retrieve(apc.Target("rel", rel))
+                torch.cuda.synchronize()
+                outs[(one_stream, rel)] = got.cpu().numpy().view(np.uint32)
+        finally:
+            apc.apc.profile_enable(False)
+            apc.apc.profile_report()
+        h.close()
+    for rel in (1e-2, 1e-5):
+        want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", rel))).view(np.uint32)
+        assert np.array_equal(outs[(False, rel)], want), rel
+        assert np.array_equal(outs[(True, rel)], want), rel
