@@ -1581,7 +1581,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     xin = xout;
   }
   if (split_on) {
-    // queued as: coarse decode | fork | coarsest, levels L-2..1 (helper) |
+    // queued as: fork | coarse decode, coarsest, levels L-2..1 (helper) |
     // join mark | level-0 decode, recomposition | join wait | level 0
     std::vector<Launch> dec_c, dec_f, cdi, chain, lev0;
     for (size_t i = base; i < ls.size(); ++i) {
@@ -1599,8 +1599,11 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     }
     ls.resize(base);
     auto mark = [&](int kind) { ls.push_back({kind, 0, 0, 0, 0, 0.0, "mark"}); };
-    for (const Launch& x : dec_c) ls.push_back(x);
     mark(K_FORK);
+    for (Launch x : dec_c) {
+      x.side = 1;
+      ls.push_back(x);
+    }
     for (const Launch& x : chain) ls.push_back(x);
     mark(K_JOIN_REC);
     for (const Launch& x : dec_f) ls.push_back(x);
