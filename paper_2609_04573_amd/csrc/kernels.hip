@@ -147,13 +147,30 @@ template <> struct MagOf<int32_t> { using type = uint32_t; };
 __device__ __forceinline__ int bitlen_of(uint32_t v) { return 32 - __clz((int)v); }
 __device__ __forceinline__ int bitlen_of(uint64_t v) { return bitlen64(v); }
 
-// Codes truncated to the first k of B planes (low B-k bits cleared).
+// Codes truncated to the first k of B planes (magnitude bits below plane k
+// cleared, sign kept), through a mask on the magnitude computed once per
+// segment: all ones when k >= B, zero when k <= 0.
+template <typename Q> struct UOf { using type = uint64_t; };
+template <> struct UOf<int32_t> { using type = uint32_t; };
+template <typename Q>
+__device__ __forceinline__ typename UOf<Q>::type code_mask(int B, int k) {
+  using U = typename UOf<Q>::type;
+  if (k >= B) return ~(U)0;
+  if (k <= 0) return (U)0;
+  return ~(U)0 << (B - k);  // 1 <= B - k < bits of U
+}
+// Apply a magnitude mask to a sign-magnitude code held in two's complement
+// (branch-free: s is 0 or all ones, (x ^ s) - s negates when s is set).
+template <typename Q>
+__device__ __forceinline__ Q apply_mask(Q q, typename UOf<Q>::type m) {
+  using U = typename UOf<Q>::type;
+  const U s = (U)(q >> (8 * sizeof(Q) - 1));
+  const U mag = ((U)q ^ s) - s;
+  return (Q)(((mag & m) ^ s) - s);
+}
 template <typename Q>
 __device__ __forceinline__ Q mask_code(Q q, int B, int k) {
-  if (k >= B) return q;
-  if (k <= 0) return 0;
-  const uint64_t m = absq(q) & ~((1ull << (B - k)) - 1ull);
-  return q < 0 ? (Q)(-(int64_t)m) : (Q)m;
+  return apply_mask<Q>(q, code_mask<Q>(B, k));
 }
 
 __device__ __forceinline__ double block_max(double v) {
@@ -536,7 +553,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     // pointers must not force the table to be reloaded; a lane picks the
     // operands of its region)
     Q* const qr[3] = {(Q*)S.q[0], (Q*)S.q[1], (Q*)S.q[2]};
-    const int Br[3] = {S.B[0], S.B[1], S.B[2]}, kr[3] = {S.k[0], S.k[1], S.k[2]};
+    using UM = typename UOf<Q>::type;
+    const UM Mr[3] = {code_mask<Q>(S.B[0], S.k[0]), code_mask<Q>(S.B[1], S.k[1]), code_mask<Q>(S.B[2], S.k[2])};
     auto qptr = [&](int rr) -> GAS Q* { return (GAS Q*)(rr == 0 ? qr[0] : (rr == 1 ? qr[1] : qr[2])); };
     const void* const src = S.src;
     void* const outp = S.out;
@@ -658,9 +676,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       if (MODE >= 2) {
         double x = p;  // a coarse point keeps its reconstructed value
         if (rr >= 0) {
-          const int B = rr == 0 ? Br[0] : (rr == 1 ? Br[1] : Br[2]);
-          const int k = rr == 0 ? kr[0] : (rr == 1 ? kr[1] : kr[2]);
-          x = p + (double)mask_code<Q>((Q)v, B, k) * delta;
+          const UM m = rr == 0 ? Mr[0] : (rr == 1 ? Mr[1] : Mr[2]);
+          x = p + (double)apply_mask<Q>((Q)v, m) * delta;
         }
         const uint32_t o = (uint32_t)f0 * pl2 + rg2(i);
         if (fin)
@@ -1111,7 +1128,8 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const GAS Q* S1 = (const GAS Q*)S.S[0];
     const GAS Q* S2 = (const GAS Q*)S.S[1];
     const GAS Q* S3 = (const GAS Q*)S.S[2];
-    const int B0 = S.B[0], K0 = S.k[0], B1 = S.B[1], K1 = S.k[1], B2 = S.B[2], K2 = S.k[2];
+    using UM = typename UOf<Q>::type;
+    const UM M0 = code_mask<Q>(S.B[0], S.k[0]), M1 = code_mask<Q>(S.B[1], S.k[1]), M2 = code_mask<Q>(S.B[2], S.k[2]);
     GAS Q* const Rout = (GAS Q*)S.Rout;
     // The tile's runs of the S1 and S2 streams, one coalesced load per point
     // (in a row, each class's points of a column range are consecutive in its
@@ -1125,15 +1143,15 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
         lv[i] = 0;
         if (e < kCIN1) {
           const int ii = e / kCIS1, l = e - ii * kCIS1;
-          if (U0 + 4 * ii < Nu && V0 + 4 * l < Nv) lv[i] = (W)mask_code<Q>(S1[rb0[ii] + (V0 >> 2) + l], B0, K0);
+          if (U0 + 4 * ii < Nu && V0 + 4 * l < Nv) lv[i] = (W)apply_mask<Q>(S1[rb0[ii] + (V0 >> 2) + l], M0);
         } else if (e < kCIN1 + kCIN2C) {
           const int e2 = e - kCIN1, ii = e2 / kCIS2C, l = e2 - ii * kCIS2C;
           if (U0 + 4 * ii < Nu && V0 + 4 * l + 2 < Nv)
-            lv[i] = (W)mask_code<Q>(S2[rb1[2 * ii] + (V0 >> 2) + l], B1, K1);
+            lv[i] = (W)apply_mask<Q>(S2[rb1[2 * ii] + (V0 >> 2) + l], M1);
         } else if (e < kCIN) {
           const int e3 = e - kCIN1 - kCIN2C, ii = e3 / kCIHV, l = e3 - ii * kCIHV;
           if (U0 + 2 + 4 * ii < Nu && V0 + 2 * l < Nv)
-            lv[i] = (W)mask_code<Q>(S2[rb1[2 * ii + 1] + (V0 >> 1) + l], B1, K1);
+            lv[i] = (W)apply_mask<Q>(S2[rb1[2 * ii + 1] + (V0 >> 1) + l], M1);
         }
       }
 #pragma unroll
@@ -1181,7 +1199,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       for (int c = 0; c < kCITV / 64; ++c) {
         const int v = V0 + c * 64 + lane;
         xs[c] = 0;
-        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)mask_code<Q>(s3r[(int)cd_in_row<A>(2, u, v)], B2, K2);
+        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v)], M2);
       }
 #pragma unroll
       for (int c = 0; c < kCITV / 64; ++c) {
