@@ -1581,8 +1581,10 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     xin = xout;
   }
   if (split_on) {
-    // queued as: fork | coarse decode, coarsest, levels L-2..1 (helper) |
-    // join mark | level-0 decode, recomposition | join wait | level 0
+    // queued as: fork | level-0 decode, recomposition | coarse decode,
+    // coarsest, levels L-2..1 (helper) | join mark | join wait | level 0.
+    // The critical path is queued first, so the device starts on it while
+    // the host is still queueing the helper's many small launches.
     std::vector<Launch> dec_c, dec_f, cdi, chain, lev0;
     for (size_t i = base; i < ls.size(); ++i) {
       Launch x = ls[i];
@@ -1600,14 +1602,14 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     ls.resize(base);
     auto mark = [&](int kind) { ls.push_back({kind, 0, 0, 0, 0, 0.0, "mark"}); };
     mark(K_FORK);
+    for (const Launch& x : dec_f) ls.push_back(x);
+    for (const Launch& x : cdi) ls.push_back(x);
     for (Launch x : dec_c) {
       x.side = 1;
       ls.push_back(x);
     }
     for (const Launch& x : chain) ls.push_back(x);
     mark(K_JOIN_REC);
-    for (const Launch& x : dec_f) ls.push_back(x);
-    for (const Launch& x : cdi) ls.push_back(x);
     mark(K_JOIN_WAIT);
     for (const Launch& x : lev0) ls.push_back(x);
   }
