@@ -481,8 +481,17 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // MODE 3: the same for level 0, written as the output field (type T).
 // Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
 // every thread owns one column and four consecutive rows.
+// With 4-byte per-point inputs (float32 fields; codes of float32 fields),
+// the quantization and reconstruction passes fetch a step's inputs one
+// whole step ahead, at four waves per SIMD (the extra registers cost the
+// fifth wave, which the max pass keeps: there the early fetch does not pay).
+template <typename T, typename Q, int MODE>
+constexpr bool level_ahead() {
+  return MODE != 0 && (MODE >= 2 ? sizeof(Q) : sizeof(T)) == 4;
+}
 template <typename T, typename Q, int MODE, int kT2>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    (level_ahead<T, Q, MODE>() || sizeof(T) == 8) ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
   constexpr int kNRG = kThreads / kT2;  // row groups
   constexpr int kT1 = 4 * kNRG;
   constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
@@ -649,9 +658,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       }
     };
 
-    // inputs of the two fine planes 2c and 2c + 1 (codes, or the field's values)
-    V in[8];
-    auto fetch_points = [&](int c) {
+    // inputs of the two fine planes 2c and 2c + 1 (codes, or the field's
+    // values); fetched a whole step ahead (kAhead) into two buffers used in
+    // turn, their latency is hidden behind a plane's LDS passes and the
+    // emission of the current step
+    constexpr bool kAhead = level_ahead<T, Q, MODE>();
+    V in[8], nx[8];
+    auto fetch_points = [&](int c, V (&dst)[8]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f0 = 2 * c + h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          dst[h * 4 + i] = (V)0;
+          const int rr = h ? 2 : rre(i);
+          if (f0 >= f0b || !okp(i) || rr < 0) continue;
+          if (MODE >= 2) {
+            const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
+            dst[h * 4 + i] = (V)qptr(rr)[li];
+          } else {
+            dst[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc(i)];
+          }
+        }
+      }
+    };
+    // the same into in[] (a separate copy: sharing the one above costs the
+    // max pass registers)
+    auto fetch_in = [&](int c) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int f0 = 2 * c + h;
@@ -701,12 +734,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     fetch_tile(max(cb - 1, 0));
     if (cb - 1 >= 0) plane(cb - 1, w0);
     plane(cb, w1);
-    fetch_points(cb);
+    fetch_in(cb);
     if (cb + 1 < mc0) plane(cb + 1, w2);
     if (cb + 2 < mc0) plane(cb + 2, w3);
-    for (int c = cb; 2 * c < f0b; ++c) {
+    // one step: fine planes 2c and 2c + 1 from the inputs in cur
+    auto step = [&](int c, V (&cur)[8], V (&nxt)[8]) {
+      fetch_points(c + 1, nxt);  // planes at or past f0b are not read
       if (c > cb) {
-        fetch_points(c);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           w0[i] = w1[i];
@@ -716,7 +750,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
         if (c + 2 < mc0) plane(c + 2, w3);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) emit(2 * c, i, w1[i], in[i]);
+      for (int i = 0; i < 4; ++i) emit(2 * c, i, w1[i], cur[i]);
       if (2 * c + 1 < f0b) {
         const int sk0 = stencil_kind(2 * c + 1, m0, deg);
 #pragma unroll
@@ -724,7 +758,38 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
           const double p = stencil_eval(sk0, [&](int o) {
             return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
           });
-          emit(2 * c + 1, i, p, in[4 + i]);
+          emit(2 * c + 1, i, p, cur[4 + i]);
+        }
+      }
+    };
+    if constexpr (kAhead) {
+      for (int c = cb; 2 * c < f0b; c += 2) {
+        step(c, in, nx);
+        if (2 * (c + 1) < f0b) step(c + 1, nx, in);
+      }
+    } else {
+      for (int c = cb; 2 * c < f0b; ++c) {
+        if (c > cb) {
+          fetch_in(c);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            w0[i] = w1[i];
+            w1[i] = w2[i];
+            w2[i] = w3[i];
+          }
+          if (c + 2 < mc0) plane(c + 2, w3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) emit(2 * c, i, w1[i], in[i]);
+        if (2 * c + 1 < f0b) {
+          const int sk0 = stencil_kind(2 * c + 1, m0, deg);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double p = stencil_eval(sk0, [&](int o) {
+              return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
+            });
+            emit(2 * c + 1, i, p, in[4 + i]);
+          }
         }
       }
     }
