@@ -32,7 +32,8 @@ KERNEL_CATEGORY = [
     ("k_level<", "3", "recon"),
     ("k_coef<", "0", "coef_max"), ("k_coef<", "1", "coef_quant"), ("k_recon<", "", "recon"),
     ("k_cd_forward", "", "cd_forward"), ("k_cd_inverse", "", "cd_inverse"), ("k_encode", "", "encode"),
-    ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_scan", "", "scan"),
+    ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_sign_layout", "", "sign_layout"),
+    ("k_scan", "", "scan"),
     ("k_range", "", "range"), ("k_gather", "", "subsample"), ("k_coarsest", "", "coarsest"),
     ("k_coarse<", "", "coarse"), ("k_inject", "", "inject"),
 ]

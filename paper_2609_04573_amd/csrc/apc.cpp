@@ -566,6 +566,39 @@ apc_status read_back(void* host, const void* dev, size_t bytes, hipStream_t st) 
   return APC_OK;
 }
 
+// A read-back in two halves: start() queues the copy, finish() waits for it
+// (polling, as read_back does) and copies the result out, so the host can
+// queue more work in between.
+struct PendingRead {
+  PinnedBlock b;
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipStream_t st = nullptr;
+  bool queued = false;
+  ~PendingRead() { g_pinned.put(b, st, queued); }
+  apc_status start(void* h, const void* dev, size_t n, hipStream_t s) {
+    host = h;
+    bytes = n;
+    st = s;
+    if (n == 0) return APC_OK;
+    if (!g_pinned.get(n, b)) return fail(APC_E_OOM, "pinned read-back of %zu bytes", n);
+    HIP_TRY(hipMemcpyAsync(b.p, dev, n, hipMemcpyDeviceToHost, s));
+    queued = true;
+    HIP_TRY(hipEventRecord(b.ev, s));
+    return APC_OK;
+  }
+  apc_status finish() {
+    if (bytes == 0) return APC_OK;
+    hipError_t e;
+    while ((e = hipEventQuery(b.ev)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) return fail(APC_E_HIP, "read-back: %s", hipGetErrorString(e));
+    queued = false;
+    memcpy(host, b.p, bytes);
+    return APC_OK;
+  }
+};
+
 // Wait for the work queued on st by polling an event (see read_back).
 apc_status spin_sync(hipStream_t st) {
   hipEvent_t ev = nullptr;
@@ -1229,6 +1262,8 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       }
   }
   std::vector<int64_t> tot((size_t)njobs);
+  PendingRead rd_tot;
+  DevBuf layout, prefix, errb;
   if (!sds.empty()) {
     TableBuilder tb3;
     const size_t o_sd = tb3.add(sds);
@@ -1240,68 +1275,108 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
     LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
     LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
-    APC_TRY(read_back(tot.data(), totals.p, 8 * (size_t)njobs, st));
+    APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
   }
-  // ---- sign sections
+  // ---- sign sections: laid out on the device from the plane totals
+  // (k_sign_layout), then placed; the totals come back to the host meanwhile
+  // and the host repeats the layout for the metadata
   {
-    size_t jb = 0, i = 0;
-    std::vector<std::vector<int64_t>> pso_host(nf);
+    size_t i = 0;
+    std::vector<int> nplanes(nf, 0);
+    for (int f = 0; f < nf; ++f) H[f]->psb.assign(H[f]->meta.streams.size(), 0);
+    std::vector<SignJob> sj((size_t)njobs);
+    std::vector<SignStream> ss(sds.size());
+    std::vector<int32_t> f_first(nf, 0);
+    {
+      int k = 0, prev_f = -1;
+      for (i = 0; i < sds.size(); ++i) {
+        const int f = sd_of[i].first, s = sd_of[i].second;
+        if (f != prev_f) {
+          f_first[f] = k;
+          prev_f = f;
+        }
+        H[f]->psb[s] = nplanes[f];
+        ss[i].first = k;
+        ss[i].njob = sds[i].B;
+        ss[i].f_first = f_first[f];
+        ss[i].ub = sign_ub[f];
+        for (int j = 0; j < sds[i].B; ++j, ++k) {
+          sj[k].pso_dst = (int64_t*)(intptr_t)(nplanes[f] + j);  // rebased below
+          sj[k].s_first = ss[i].first;
+        }
+        nplanes[f] += sds[i].B;
+      }
+    }
+    for (int f = 0; f < nf; ++f) APC_TRY(H[f]->pso.alloc(8 * std::max<size_t>(1, (size_t)nplanes[f])));
+    for (int k = 0; k < njobs; ++k) {
+      const int f = sd_of[job[k]].first;
+      sj[k].pso_dst = H[f]->pso.as<int64_t>() + (intptr_t)sj[k].pso_dst;
+    }
+    double sb = 0;
+    for (i = 0; i < sds.size(); ++i) {
+      const int f = sd_of[i].first, s = sd_of[i].second;
+      sds[i].sign = H[f]->sign.as<uint64_t>();  // the stream's offset is added on the device
+      sds[i].pso = H[f]->pso.as<int64_t>() + H[f]->psb[s];
+      sds[i].sign_n = 0;
+      sb += 512.0 * sds[i].C + 8.0 * (sds[i].n / 64 + sds[i].B);
+    }
+    if (!sds.empty()) {
+      TableBuilder tb4;
+      const size_t o_sd = tb4.add(sds);
+      const size_t o_sj = tb4.add(sj);
+      const size_t o_ss = tb4.add(ss);
+      APC_TRY(layout.alloc(tb4.bytes.size()));
+      APC_TRY(prefix.alloc(8 * ((size_t)njobs + 1)));
+      APC_TRY(errb.alloc(4));
+      HIP_TRY(hipMemsetAsync(errb.p, 0, 4, st));
+      APC_TRY(stage.put(tb4.bytes, layout.p, st));
+      StreamDev* sdd = (StreamDev*)((char*)layout.p + o_sd);
+      LAUNCH("sign_layout", 16.0 * njobs, st,
+             launch_sign_layout(totals.as<int64_t>(), njobs, (const SignJob*)((const char*)layout.p + o_sj),
+                                (int)sds.size(), (const SignStream*)((const char*)layout.p + o_ss), sdd,
+                                prefix.as<int64_t>(), errb.as<int32_t>(), st));
+      LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
+    }
+    // the same layout on the host, for the metadata
+    APC_TRY(rd_tot.finish());
     std::vector<int64_t> sign_words(nf, 0);
-    for (int f = 0; f < nf; ++f) {
-      H[f]->psb.assign(H[f]->meta.streams.size(), 0);
+    for (int f = 0; f < nf; ++f)
       for (Stream& S : H[f]->meta.streams) {
         S.nsig.clear();
         S.pso.clear();
       }
-    }
+    size_t jb = 0;
     for (i = 0; i < sds.size(); ++i) {
       const int f = sd_of[i].first, s = sd_of[i].second;
       Stream& S = H[f]->meta.streams[s];
       S.nsig.assign(S.B, 0);
       S.pso.assign(S.B, 0);
       S.sign_off = sign_words[f];
-      H[f]->psb[s] = (int)pso_host[f].size();
       int64_t w = 0;
       for (int j = 0; j < S.B; ++j, ++jb) {
         S.nsig[j] = tot[jb];
         S.pso[j] = w;
-        pso_host[f].push_back(w);
         w += (tot[jb] + 63) / 64;
       }
       sign_words[f] += w;
     }
-    for (int f = 0; f < nf; ++f) {
-      apc_handle* h = H[f];
+    for (int f = 0; f < nf; ++f)
       if (sign_words[f] > sign_ub[f]) return fail(APC_E_INVALID, "internal: sign section exceeds its bound");
-      APC_TRY(h->pso.alloc(8 * std::max<size_t>(1, pso_host[f].size())));
-      std::vector<char> b(8 * pso_host[f].size());
-      if (!b.empty()) memcpy(b.data(), pso_host[f].data(), b.size());
-      APC_TRY(stage.put(b, h->pso.p, st));
-    }
-    double sb = 0;
-    for (i = 0; i < sds.size(); ++i) {
-      const int f = sd_of[i].first, s = sd_of[i].second;
-      const Stream& S = H[f]->meta.streams[s];
-      sds[i].sign = H[f]->sign.as<uint64_t>() + S.sign_off;
-      sds[i].pso = H[f]->pso.as<int64_t>() + H[f]->psb[s];
-      sds[i].sign_n = S.sign_words();
-      sb += 512.0 * sds[i].C + 8.0 * sds[i].sign_n;
-    }
-    if (!sds.empty()) {
-      TableBuilder tb4;
-      const size_t o_sd = tb4.add(sds);
-      DevBuf sdb2;
-      APC_TRY(sdb2.alloc(tb4.bytes.size()));
-      APC_TRY(stage.put(tb4.bytes, sdb2.p, st));
-      LAUNCH("sign_move", sb, st,
-             launch_sign_move((const StreamDev*)((const char*)sdb2.p + o_sd), (int)sds.size(), chunks, st));
-      APC_TRY(spin_sync(st));
-    }
   }
+  // The rest of the metadata is host work on counts already read back; it
+  // runs while the sign placement is on the device, and so does the
+  // interpreter's greedy sequence for error-bound targets (kept in the
+  // handle for its first retrieval).
   for (int f = 0; f < nf; ++f) {
     assign_weights(H[f]);
     finalize_units(H[f]);
     H[f]->k_res.assign(H[f]->meta.streams.size(), 0);
+    ensure_sequence(H[f]->meta, 0);
+  }
+  if (!sds.empty()) {  // waits for the sign placement: the temporaries above are released on return
+    int32_t err = 0;
+    APC_TRY(read_back(&err, errb.p, 4, st));
+    if (err) return fail(APC_E_INVALID, "internal: sign section exceeds its bound");
   }
   return APC_OK;
 }

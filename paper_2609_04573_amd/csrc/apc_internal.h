@@ -138,6 +138,21 @@ struct StreamDev {
   int32_t fresh;        // decode: resident codes are all zero (skip reading them)
 };
 
+// Sign-section layout, computed on the device from the per-(stream, plane)
+// sign counts.  Jobs are the (stream, plane) pairs in stream order, planes
+// most significant first; streams are the encode table's entries.
+struct SignJob {
+  int64_t* pso_dst;  // where the plane's word offset within its stream goes
+  int32_t s_first;   // first job of the plane's stream
+  int32_t pad;
+};
+struct SignStream {
+  int32_t first, njob;  // its jobs
+  int32_t f_first;      // first job of its field
+  int32_t pad;
+  int64_t ub;           // words of the field's sign arena
+};
+
 inline FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;
   f.d = d;
@@ -169,6 +184,8 @@ template <typename Q>
 hipError_t launch_encode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 hipError_t launch_scan(const StreamDev* sd, const int32_t* job_s, const int32_t* job_j, int njobs, int64_t* totals,
                        hipStream_t s);
+hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* jobs, int ns, const SignStream* ss,
+                              StreamDev* sd, int64_t* prefix, int32_t* err, hipStream_t s);
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
 hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);

@@ -1658,6 +1658,56 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   if (threadIdx.x == 0) totals[job] = (int64_t)carry;
 }
 
+// Sign-section layout from the plane totals (one block of kLayoutThreads).
+// Job k takes ceil(totals[k] / 64) words; prefix[] is their exclusive prefix
+// sum over all jobs (prefix[njobs] = the sum).  A plane's run starts
+// prefix[k] - prefix[first job of its stream] words into its stream's run,
+// and a stream's run starts prefix[first] - prefix[first job of its field]
+// words into its field's sign arena.  A stream whose run would end past the
+// arena is not placed (its plane count is set to zero, so the sign placement
+// skips it) and err is set.
+constexpr int kLayoutThreads = 1024;
+__global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* __restrict__ totals, int njobs,
+                                                                const SignJob* __restrict__ jobs, int ns,
+                                                                const SignStream* __restrict__ ss, StreamDev* sd,
+                                                                int64_t* prefix, int32_t* err) {
+  __shared__ int64_t part[kLayoutThreads];
+  const int t = threadIdx.x;
+  // each thread sums a contiguous range of jobs, a block scan of the range
+  // sums gives each range's start, and the range is written out in order
+  const int per = (njobs + kLayoutThreads - 1) / kLayoutThreads;
+  const int k0 = min(njobs, t * per), k1 = min(njobs, k0 + per);
+  int64_t sum = 0;
+  for (int k = k0; k < k1; ++k) sum += (totals[k] + 63) >> 6;
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kLayoutThreads; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;  // exclusive
+  for (int k = k0; k < k1; ++k) {
+    prefix[k] = run;
+    run += (totals[k] + 63) >> 6;
+  }
+  if (t == kLayoutThreads - 1) prefix[njobs] = part[t];
+  __syncthreads();  // prefix[] is read below by other threads of the block
+  for (int k = t; k < njobs; k += kLayoutThreads) *jobs[k].pso_dst = prefix[k] - prefix[jobs[k].s_first];
+  for (int i = t; i < ns; i += kLayoutThreads) {
+    const SignStream& S = ss[i];
+    const int64_t off = prefix[S.first] - prefix[S.f_first];
+    const int64_t end = prefix[S.first + S.njob] - prefix[S.f_first];
+    if (end > S.ub) {
+      sd[i].B = 0;
+      atomicOr(err, 1);
+    } else {
+      sd[i].sign += off;
+    }
+  }
+}
+
 // Bits [pos, pos + nb) of a little-endian bit string held in words w.
 __device__ __forceinline__ uint64_t extract_bits(const uint64_t* w, int pos, int nb, int nwords) {
   const int w0 = pos >> 6, sh = pos & 63;
@@ -2063,6 +2113,12 @@ hipError_t launch_scan(const StreamDev* sd, const int32_t* job_s, const int32_t*
                        hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan, dim3(njobs), dim3(kThreads), 0, s, sd, job_s, job_j, totals);
+  return hipGetLastError();
+}
+hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* jobs, int ns, const SignStream* ss,
+                              StreamDev* sd, int64_t* prefix, int32_t* err, hipStream_t s) {
+  if (njobs <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sign_layout, dim3(1), dim3(kLayoutThreads), 0, s, totals, njobs, jobs, ns, ss, sd, prefix, err);
   return hipGetLastError();
 }
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
