@@ -1251,7 +1251,13 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       }
     }
     __syncthreads();
-    // whole rows: stride-2 points from LDS, the rest from S3
+    // whole rows: stride-2 points from LDS, the rest from S3.  A lane takes
+    // column pairs (v0 = V0 + 2p, v1 = v0 + 1), which share their stride-2
+    // neighbours: on an even row, v0 is a stride-2 point and v1 averages its
+    // left and right neighbours; on an odd row, v0 averages the rows above
+    // and below, v1 the four diagonal neighbours (columns first, as the
+    // lifting predicts).  A missing right or lower neighbour repeats the
+    // present one, which leaves that average equal to it.
 #pragma unroll
     for (int rr = 0; rr < kCITU / 4; ++rr) {
       const int r = wave * (kCITU / 4) + rr;
@@ -1259,26 +1265,31 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       if (u >= Nu) continue;
       GAS Q* out = Rout + rowoff(u);
       const GAS Q* s3r = S3 + rb2[r];
-      W xs[kCITV / 64];
+      const bool uodd = u & 1;
+      W x0[kCITV / 128], x1[kCITV / 128];
 #pragma unroll
-      for (int c = 0; c < kCITV / 64; ++c) {
-        const int v = V0 + c * 64 + lane;
-        xs[c] = 0;
-        if (v < Nv && ((u & 1) || (v & 1))) xs[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v)], M2);
+      for (int c = 0; c < kCITV / 128; ++c) {
+        const int v0 = V0 + 2 * (c * 64 + lane), v1 = v0 + 1;
+        x0[c] = x1[c] = 0;
+        if (uodd && v0 < Nv) x0[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v0)], M2);
+        if (v1 < Nv) x1[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v1)], M2);
       }
+      const W* ht = h1 + (r >> 1) * kCIHV;                         // row u (even u) or u - 1
+      const W* hb = (uodd && u + 1 <= Nu - 1) ? ht + kCIHV : ht;  // row u + 1 (odd u)
 #pragma unroll
-      for (int c = 0; c < kCITV / 64; ++c) {
-        const int v = V0 + c * 64 + lane;
-        if (v >= Nv) continue;
-        auto h = [&](int du, int dv) -> W { return h1[((r + du) >> 1) * kCIHV + ((v + dv - V0) >> 1)]; };
-        const bool s3p = (u & 1) || (v & 1);
-        CDNb n = cd_nb_s3(u, v, Nu, Nv);
-        if (!s3p) n.r0 = n.r1 = n.c0 = n.c1 = 0, n.hr = n.hc = false;
-        const W a0 = h(n.r0, n.c0);
-        const W a1 = h(n.r0, n.hc ? n.c1 : n.c0);
-        const W a2 = h(n.hr ? n.r1 : n.r0, n.c0);
-        const W a3 = h(n.hr ? n.r1 : n.r0, n.hc ? n.c1 : n.c0);
-        out[v] = (Q)(s3p ? xs[c] + cd_combine<W>(n, a0, a1, a2, a3) : a0);
+      for (int c = 0; c < kCITV / 128; ++c) {
+        const int p = c * 64 + lane, v0 = V0 + 2 * p, v1 = v0 + 1;
+        if (v0 >= Nv) continue;
+        const bool hc = v1 + 1 <= Nv - 1;
+        const W t0 = ht[p], t1 = hc ? ht[p + 1] : t0;
+        if (!uodd) {
+          out[v0] = (Q)t0;
+          if (v1 < Nv) out[v1] = (Q)(x1[c] + avgw<W>(t0, t1));
+        } else {
+          const W b0 = hb[p], b1 = hc ? hb[p + 1] : b0;
+          out[v0] = (Q)(x0[c] + avgw<W>(t0, b0));
+          if (v1 < Nv) out[v1] = (Q)(x1[c] + avgw<W>(avgw<W>(t0, t1), avgw<W>(b0, b1)));
+        }
       }
     }
   }
