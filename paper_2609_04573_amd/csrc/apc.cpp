@@ -1263,23 +1263,13 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   }
   std::vector<int64_t> tot((size_t)njobs);
   PendingRead rd_tot;
-  DevBuf layout, prefix, errb;
-  if (!sds.empty()) {
-    TableBuilder tb3;
-    const size_t o_sd = tb3.add(sds);
-    const size_t o_job = tb3.add(job);
-    APC_TRY(sdb.alloc(tb3.bytes.size()));
-    APC_TRY(totals.alloc(8 * (size_t)njobs));
-    APC_TRY(stage.put(tb3.bytes, sdb.p, st));
-    const StreamDev* sdd = (const StreamDev*)((const char*)sdb.p + o_sd);
-    const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
-    LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
-    LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
-    APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
-  }
+  DevBuf prefix, errb;
   // ---- sign sections: laid out on the device from the plane totals
   // (k_sign_layout), then placed; the totals come back to the host meanwhile
-  // and the host repeats the layout for the metadata
+  // and the host repeats the layout for the metadata.  The layout tables
+  // (each plane's offset slot, each stream's jobs) travel with the encode
+  // table, and the layout kernel adds each stream's offset to its sign
+  // pointer in that table, which the sign placement then reads.
   {
     size_t i = 0;
     std::vector<int> nplanes(nf, 0);
@@ -1321,19 +1311,24 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       sb += 512.0 * sds[i].C + 8.0 * (sds[i].n / 64 + sds[i].B);
     }
     if (!sds.empty()) {
-      TableBuilder tb4;
-      const size_t o_sd = tb4.add(sds);
-      const size_t o_sj = tb4.add(sj);
-      const size_t o_ss = tb4.add(ss);
-      APC_TRY(layout.alloc(tb4.bytes.size()));
+      TableBuilder tb3;
+      const size_t o_sd = tb3.add(sds);
+      const size_t o_job = tb3.add(job);
+      const size_t o_sj = tb3.add(sj);
+      const size_t o_ss = tb3.add(ss);
+      APC_TRY(sdb.alloc(tb3.bytes.size()));
+      APC_TRY(totals.alloc(8 * (size_t)njobs));
       APC_TRY(prefix.alloc(8 * ((size_t)njobs + 1)));
       APC_TRY(errb.alloc(4));
-      HIP_TRY(hipMemsetAsync(errb.p, 0, 4, st));
-      APC_TRY(stage.put(tb4.bytes, layout.p, st));
-      StreamDev* sdd = (StreamDev*)((char*)layout.p + o_sd);
+      APC_TRY(stage.put(tb3.bytes, sdb.p, st));
+      StreamDev* sdd = (StreamDev*)((char*)sdb.p + o_sd);
+      const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
+      LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
+      LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
+      APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
       LAUNCH("sign_layout", 16.0 * njobs, st,
-             launch_sign_layout(totals.as<int64_t>(), njobs, (const SignJob*)((const char*)layout.p + o_sj),
-                                (int)sds.size(), (const SignStream*)((const char*)layout.p + o_ss), sdd,
+             launch_sign_layout(totals.as<int64_t>(), njobs, (const SignJob*)((const char*)sdb.p + o_sj),
+                                (int)sds.size(), (const SignStream*)((const char*)sdb.p + o_ss), sdd,
                                 prefix.as<int64_t>(), errb.as<int32_t>(), st));
       LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
     }

@@ -1676,7 +1676,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
 // and a stream's run starts prefix[first] - prefix[first job of its field]
 // words into its field's sign arena.  A stream whose run would end past the
 // arena is not placed (its plane count is set to zero, so the sign placement
-// skips it) and err is set.
+// skips it) and err is set (it is cleared first).
 constexpr int kLayoutThreads = 1024;
 __global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* __restrict__ totals, int njobs,
                                                                 const SignJob* __restrict__ jobs, int ns,
@@ -1684,6 +1684,7 @@ __global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* _
                                                                 int64_t* prefix, int32_t* err) {
   __shared__ int64_t part[kLayoutThreads];
   const int t = threadIdx.x;
+  if (t == 0) *err = 0;  // set below, after the barriers
   // each thread sums a contiguous range of jobs, a block scan of the range
   // sums gives each range's start, and the range is written out in order
   const int per = (njobs + kLayoutThreads - 1) / kLayoutThreads;
