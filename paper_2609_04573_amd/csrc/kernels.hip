@@ -1800,7 +1800,9 @@ __global__ __launch_bounds__(64) void k_sign_move(const StreamDev* __restrict__ 
 // significant at plane j takes the next bit of its (plane, word) cursor in
 // the chunk's run of plane-j sign bits, which starts at index[j][chunk]; the
 // sign words each plane needs are first copied into LDS.
-template <typename Q, int MAXB>
+// FRESH: every stream of the launch starts from zero codes (its first
+// decode), so no resident code is read.
+template <typename Q, int MAXB, bool FRESH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) == 4 ? 3 : 1))) void k_decode(const StreamDev* __restrict__ sd, int ns) {
   constexpr int QW = (int)sizeof(Q) / 4;
   constexpr int kSignWords = 64 + 2 * MAXB;
@@ -1818,7 +1820,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) ==
   const GAS uint64_t* sign = (const GAS uint64_t*)S.sign;
   const GAS int64_t* pso = (const GAS int64_t*)S.pso;
   const int B = S.B, k0 = S.k0, k1 = S.k1;
-  const bool fresh = S.fresh != 0;
+  const bool fresh = FRESH || S.fresh != 0;
   const int64_t M = S.M, C = S.C, n = S.n, sign_n = S.sign_n;
   const int64_t base = chunk * kChunk;
   const BufRsrc rc = chunk_rsrc<Q>(S.codes, base, n);
@@ -2139,10 +2141,13 @@ hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStre
   return hipGetLastError();
 }
 template <typename Q>
-hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
+hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
-  hipLaunchKernelGGL((k_decode<Q, MAXB>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  if (all_fresh)
+    hipLaunchKernelGGL((k_decode<Q, MAXB, true>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  else
+    hipLaunchKernelGGL((k_decode<Q, MAXB, false>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   return hipGetLastError();
 }
 template <typename T, typename Q>
@@ -2176,8 +2181,8 @@ template hipError_t launch_cd_inverse<int32_t>(const CDSeg*, int, int64_t, int, 
 template hipError_t launch_cd_inverse<int64_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_encode<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
 template hipError_t launch_encode<int64_t>(const StreamDev*, int, int64_t, hipStream_t);
-template hipError_t launch_decode<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
-template hipError_t launch_decode<int64_t>(const StreamDev*, int, int64_t, hipStream_t);
+template hipError_t launch_decode<int32_t>(const StreamDev*, int, int64_t, bool, hipStream_t);
+template hipError_t launch_decode<int64_t>(const StreamDev*, int, int64_t, bool, hipStream_t);
 template hipError_t launch_coarsest<float, int32_t>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_coarsest<double, int64_t>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_inject<float>(const FlatSeg*, int, int64_t, hipStream_t);
