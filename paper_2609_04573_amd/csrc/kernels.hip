@@ -113,6 +113,17 @@ __device__ __forceinline__ double stencil_eval(int kind, F tap) {
   }
 }
 
+// The same stencils with all four taps given, every form evaluated and the
+// one of `kind` selected: no branches where the kind varies across a wave
+// (each form keeps its own operation order, so results are bit-equal).
+__device__ __forceinline__ double stencil_select(int kind, double a, double b, double c, double e) {
+  const double cub = (9.0 * (b + c) - (a + e)) * 0.0625;
+  const double lq = ((3.0 * b + 6.0 * c) - e) * 0.125;
+  const double rq = ((6.0 * b + 3.0 * c) - a) * 0.125;
+  const double lin = (b + c) * 0.5;
+  return kind == ST_CUBIC ? cub : (kind == ST_LQUAD ? lq : (kind == ST_RQUAD ? rq : (kind == ST_LINEAR ? lin : b)));
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -646,15 +657,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       for (int k = 0; k < (kC1 + kNRG - 1) / kNRG; ++k) {
         const int r = rg + kNRG * k;
         if (r < kC1) {
-          const double* row = ctile + r * kC2 + tc2;
-          u2[r * kT2 + col] = odd2 ? stencil_eval(sk2, [&](int o) { return row[(o + 1) / 2]; }) : row[0];
+          const double* row = ctile + r * kC2 + tc2;  // taps row[-1..2] lie inside the tile row
+          const double b0 = row[0];
+          u2[r * kT2 + col] = odd2 ? stencil_select(sk2, row[-1], b0, row[1], row[2]) : b0;
         }
       }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double* cp = u2 + tr1(i) * kT2 + col;
-        u[i] = (i & 1) ? stencil_eval(sk1(i), [&](int o) { return cp[((o + 1) / 2) * kT2]; }) : cp[0];
+        const double* cp = u2 + tr1(i) * kT2 + col;  // taps cp[-1..2 rows] lie inside the tile
+        u[i] = (i & 1) ? stencil_select(sk1(i), cp[-kT2], cp[0], cp[kT2], cp[2 * kT2]) : cp[0];
       }
     };
 
