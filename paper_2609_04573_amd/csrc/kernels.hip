@@ -741,7 +741,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       }
     };
 
-    double w0[4], w1[4], w2[4], w3[4];  // predictions of coarse planes c-1, c, c+1, c+2
+    double w0[4] = {}, w1[4] = {}, w2[4] = {}, w3[4] = {};  // predictions of coarse planes c-1, c, c+1, c+2
     const int cb = f0a >> 1;
     fetch_tile(max(cb - 1, 0));
     if (cb - 1 >= 0) plane(cb - 1, w0);
@@ -767,9 +767,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         const int sk0 = stencil_kind(2 * c + 1, m0, deg);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double p = stencil_eval(sk0, [&](int o) {
-            return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
-          });
+          const double p = stencil_select(sk0, w0[i], w1[i], w2[i], w3[i]);
           emit(2 * c + 1, i, p, cur[4 + i]);
         }
       }
@@ -797,9 +795,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
           const int sk0 = stencil_kind(2 * c + 1, m0, deg);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const double p = stencil_eval(sk0, [&](int o) {
-              return o == -3 ? w0[i] : (o == -1 ? w1[i] : (o == 1 ? w2[i] : w3[i]));
-            });
+            const double p = stencil_select(sk0, w0[i], w1[i], w2[i], w3[i]);
             emit(2 * c + 1, i, p, in[4 + i]);
           }
         }
@@ -1243,23 +1239,22 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       const W* s1t = lt;
       const W* s2c = lt + kCIN1;
       const W* s2b = lt + kCIN1 + kCIN2C;
+      // branch-free: every lane reads the S1 values around it and both S2
+      // candidates (indices kept inside the staged runs) and selects
       for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
         const int r = e / kCIHV, k = e - r * kCIHV;
         const int u = U0 + 2 * r, v = V0 + 2 * k;
-        W val = 0;
-        if (u < Nu && v < Nv) {
-          const int c0 = k >> 1;
-          const int c1 = (k & 1) && v + 2 <= Nv - 1 ? c0 + 1 : c0;
-          if (!(r & 1)) {  // u = 0 mod 4
-            const W* row = s1t + (r >> 1) * kCIS1;
-            val = (k & 1) ? s2c[(r >> 1) * kCIS2C + c0] + avgw<W>(row[c0], row[c1]) : row[c0];
-          } else {  // u = 2 mod 4
-            const W* ra = s1t + (r >> 1) * kCIS1;
-            const W* rb = u + 2 <= Nu - 1 ? ra + kCIS1 : ra;
-            val = s2b[(r >> 1) * kCIHV + k] + avgw<W>(avgw<W>(ra[c0], ra[c1]), avgw<W>(rb[c0], rb[c1]));
-          }
-        }
-        h1[e] = val;
+        const int rh = r >> 1, c0 = k >> 1;
+        const int c1 = (k & 1) && v + 2 <= Nv - 1 ? c0 + 1 : c0;
+        const bool r2 = r & 1;  // u = 2 mod 4 (else 0 mod 4)
+        const W* ra = s1t + rh * kCIS1;
+        const W* rb = r2 && u + 2 <= Nu - 1 ? ra + kCIS1 : ra;
+        const W a0 = ra[c0], a1 = ra[c1], b0 = rb[c0], b1 = rb[c1];
+        const W sc = s2c[rh * kCIS2C + c0];          // inside the staging for every lane
+        const W sb = s2b[(r2 ? rh : 0) * kCIHV + k];  // row 0 for u = 0 mod 4 (not used)
+        const W v2 = sb + avgw<W>(avgw<W>(a0, a1), avgw<W>(b0, b1));
+        const W v0 = (k & 1) ? sc + avgw<W>(a0, a1) : a0;
+        h1[e] = (u < Nu && v < Nv) ? (r2 ? v2 : v0) : (W)0;
       }
     }
     __syncthreads();
