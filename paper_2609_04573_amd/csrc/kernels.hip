@@ -1657,11 +1657,19 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
   const GAS uint32_t* c = (const GAS uint32_t*)S.cnt + j;  // chunk-major: entry i at i * B
   GAS uint32_t* o = (GAS uint32_t*)S.idx + (int64_t)j * C;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // kScanPer consecutive chunks per thread and turn: a long stream takes a
+  // quarter of the barrier-separated turns
+  constexpr int kScanPer = 4;
   uint64_t carry = 0;
-  for (int64_t base = 0; base < C; base += kThreads) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t v = (i < C) ? c[i * B] : 0u;
-    const uint32_t incl = wave_incl_scan(v, lane);
+  for (int64_t base = 0; base < C; base += kThreads * kScanPer) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer], t = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      v[q] = (i0 + q < C) ? c[(i0 + q) * B] : 0u;
+      t += v[q];
+    }
+    const uint32_t incl = wave_incl_scan(t, lane);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     uint32_t before = 0, all = 0;
@@ -1669,7 +1677,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(const StreamDev* __restrict__
       if (w < wave) before += wsum[w];
       all += wsum[w];
     }
-    if (i < C) o[i] = (uint32_t)(carry + before + incl - v);
+    uint32_t run = (uint32_t)carry + before + incl - t;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      if (i0 + q < C) o[i0 + q] = run;
+      run += v[q];
+    }
     carry += all;
     __syncthreads();
   }
