@@ -629,15 +629,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     }
     const int64_t cplane = MODE >= 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
     double cpre[kCPer];
+    // Loads are issued on every lane, a lane without a point reading a
+    // harmless address (the segment table) and dropping the value: branches
+    // around per-lane loads cost more than the loads.
+    const void* const safe = (const void*)segs;
     auto fetch_tile = [&](int cc) {
 #pragma unroll
       for (int k = 0; k < kCPer; ++k) {
-        cpre[k] = 0.0;
-        if (coff[k] >= 0) {
-          const int64_t o = (int64_t)cc * cplane + coff[k];
-          cpre[k] = MODE >= 2 ? ((const GAS double*)src)[o] : (double)((const GAS T*)src)[o];
-          if (MODE == 0 && racc) take((T)cpre[k]);
+        const bool ok = coff[k] >= 0;
+        const int64_t o = (int64_t)cc * cplane + coff[k];
+        if (MODE == 0) {  // as in fetch_in
+          cpre[k] = 0.0;
+          if (ok) {
+            cpre[k] = (double)((const GAS T*)src)[o];
+            if (racc) take((T)cpre[k]);
+          }
+          continue;
         }
+        double x;
+        if (MODE >= 2)
+          x = *(ok ? (const GAS double*)src + o : (const GAS double*)safe);
+        else
+          x = (double)*(ok ? (const GAS T*)src + o : (const GAS T*)safe);
+        cpre[k] = ok ? x : 0.0;
+        if (MODE == 0 && racc && ok) take((T)cpre[k]);
       }
     };
 
@@ -682,15 +697,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         const int f0 = 2 * c + h;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          dst[h * 4 + i] = (V)0;
           const int rr = h ? 2 : rre(i);
-          if (f0 >= f0b || !okp(i) || rr < 0) continue;
+          const bool ok = f0 < f0b && okp(i) && rr >= 0;
+          V x;
           if (MODE >= 2) {
+            const int rho = h ? 2 : (i & 1);  // the region of this row (rr, where there is a point)
             const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
-            dst[h * 4 + i] = (V)qptr(rr)[li];
+            x = (V) * (ok ? (const GAS Q*)qr[rho] + li : (const GAS Q*)safe);
           } else {
-            dst[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc(i)];
+            x = (V) * (ok ? (const GAS T*)src + (int64_t)f0 * xs0 + rsrc(i) : (const GAS T*)safe);
           }
+          dst[h * 4 + i] = ok ? x : (V)0;
         }
       }
     };
@@ -702,15 +719,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         const int f0 = 2 * c + h;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          in[h * 4 + i] = (V)0;
           const int rr = h ? 2 : rre(i);
-          if (f0 >= f0b || !okp(i) || rr < 0) continue;
-          if (MODE >= 2) {
-            const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
-            in[h * 4 + i] = (V)qptr(rr)[li];
-          } else {
-            in[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc(i)];
+          const bool ok = f0 < f0b && okp(i) && rr >= 0;
+          if (MODE == 0) {  // the max pass keeps branches here (its registers are tight)
+            in[h * 4 + i] = (V)0;
+            if (ok) in[h * 4 + i] = (V)((const GAS T*)src)[(int64_t)f0 * xs0 + rsrc(i)];
+            continue;
           }
+          V x;
+          if (MODE >= 2) {
+            const int rho = h ? 2 : (i & 1);  // the region of this row (rr, where there is a point)
+            const uint32_t li = (uint32_t)c * (h ? pl2 : pe(i)) + (h ? rg2(i) : re(i));
+            x = (V) * (ok ? (const GAS Q*)qr[rho] + li : (const GAS Q*)safe);
+          } else {
+            x = (V) * (ok ? (const GAS T*)src + (int64_t)f0 * xs0 + rsrc(i) : (const GAS T*)safe);
+          }
+          in[h * 4 + i] = ok ? x : (V)0;
         }
       }
     };
