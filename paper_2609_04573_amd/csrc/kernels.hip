@@ -1233,23 +1233,25 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     // stream): S1 of rows U0 + 4i at v = V0 + 4l, S2 of those rows at
     // v = V0 + 4l + 2, S2 of rows U0 + 2 + 4i at v = V0 + 2l.
     {
+      // every lane loads (one of the three runs, by its slot), a slot
+      // without a point reading a harmless address and dropping the value
       W lv[kCIL];
 #pragma unroll
       for (int i = 0; i < kCIL; ++i) {
         const int e = tid + i * kThreads;
-        lv[i] = 0;
-        if (e < kCIN1) {
-          const int ii = e / kCIS1, l = e - ii * kCIS1;
-          if (U0 + 4 * ii < Nu && V0 + 4 * l < Nv) lv[i] = (W)apply_mask<Q>(S1[rb0[ii] + (V0 >> 2) + l], M0);
-        } else if (e < kCIN1 + kCIN2C) {
-          const int e2 = e - kCIN1, ii = e2 / kCIS2C, l = e2 - ii * kCIS2C;
-          if (U0 + 4 * ii < Nu && V0 + 4 * l + 2 < Nv)
-            lv[i] = (W)apply_mask<Q>(S2[rb1[2 * ii] + (V0 >> 2) + l], M1);
-        } else if (e < kCIN) {
-          const int e3 = e - kCIN1 - kCIN2C, ii = e3 / kCIHV, l = e3 - ii * kCIHV;
-          if (U0 + 2 + 4 * ii < Nu && V0 + 2 * l < Nv)
-            lv[i] = (W)apply_mask<Q>(S2[rb1[2 * ii + 1] + (V0 >> 1) + l], M1);
-        }
+        const bool s1 = e < kCIN1, s2c = !s1 && e < kCIN1 + kCIN2C;
+        const int e2 = e - kCIN1, e3 = e - kCIN1 - kCIN2C;
+        const int i1 = e / kCIS1, i2 = e2 / kCIS2C, i3 = e3 / kCIHV;
+        const int ii = s1 ? i1 : (s2c ? i2 : i3);
+        const int l = s1 ? e - i1 * kCIS1 : (s2c ? e2 - i2 * kCIS2C : e3 - i3 * kCIHV);
+        const int uu = U0 + 4 * ii + (s1 || s2c ? 0 : 2);
+        const int vv = s1 ? V0 + 4 * l : (s2c ? V0 + 4 * l + 2 : V0 + 2 * l);
+        const bool ok = e < kCIN && uu < Nu && vv < Nv;
+        // run start: rb0[ii] (S1), rb1[2 ii] or rb1[2 ii + 1] (S2); index kept inside the tables
+        const int64_t rb = s1 ? rb0[min(ii, 2)] : rb1[min(s2c ? 2 * ii : 2 * ii + 1, kCIHU - 1)];
+        const int64_t o = rb + (s1 || s2c ? (V0 >> 2) : (V0 >> 1)) + l;
+        const Q q = *(ok ? (s1 ? S1 : S2) + o : (const GAS Q*)segs);
+        lv[i] = ok ? (W)apply_mask<Q>(q, s1 ? M0 : M1) : (W)0;
       }
 #pragma unroll
       for (int i = 0; i < kCIL; ++i)
@@ -1301,9 +1303,11 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
 #pragma unroll
       for (int c = 0; c < kCITV / 128; ++c) {
         const int v0 = V0 + 2 * (c * 64 + lane), v1 = v0 + 1;
-        x0[c] = x1[c] = 0;
-        if (uodd && v0 < Nv) x0[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v0)], M2);
-        if (v1 < Nv) x1[c] = (W)apply_mask<Q>(s3r[(int)cd_in_row<A>(2, u, v1)], M2);
+        const bool ok0 = uodd && v0 < Nv, ok1 = v1 < Nv;
+        const Q q0 = *(ok0 ? s3r + (int)cd_in_row<A>(2, u, v0) : (const GAS Q*)segs);
+        const Q q1 = *(ok1 ? s3r + (int)cd_in_row<A>(2, u, v1) : (const GAS Q*)segs);
+        x0[c] = ok0 ? (W)apply_mask<Q>(q0, M2) : (W)0;
+        x1[c] = ok1 ? (W)apply_mask<Q>(q1, M2) : (W)0;
       }
       const W* ht = h1 + (r >> 1) * kCIHV;                         // row u (even u) or u - 1
       const W* hb = (uodd && u + 1 <= Nu - 1) ? ht + kCIHV : ht;  // row u + 1 (odd u)
