@@ -1657,9 +1657,12 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   }
   if (split_on) {
     // queued as: fork | level-0 decode, recomposition | coarse decode,
-    // coarsest, levels L-2..1 (helper) | join mark | join wait | level 0.
-    // The critical path is queued first, so the device starts on it while
-    // the host is still queueing the helper's many small launches.
+    // coarsest, levels L-2..2 (helper) | join mark | join wait | level 1,
+    // level 0.  The critical path is queued first, so the device starts on
+    // it while the host is still queueing the helper's many small launches;
+    // level 1, the largest of the coarse levels, runs on the main stream,
+    // where it has the device to itself instead of sharing it with the
+    // recomposition.
     std::vector<Launch> dec_c, dec_f, cdi, chain, lev0;
     for (size_t i = base; i < ls.size(); ++i) {
       Launch x = ls[i];
@@ -1674,6 +1677,12 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
         chain.push_back(x);
       }
     }
+    std::vector<Launch> lev1;
+    if (!chain.empty() && chain.back().kind == K_LEVEL2) {  // levels run coarse to fine: the last is level 1
+      lev1.push_back(chain.back());
+      lev1.back().side = 0;
+      chain.pop_back();
+    }
     ls.resize(base);
     auto mark = [&](int kind) { ls.push_back({kind, 0, 0, 0, 0, 0.0, "mark"}); };
     mark(K_FORK);
@@ -1686,6 +1695,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     for (const Launch& x : chain) ls.push_back(x);
     mark(K_JOIN_REC);
     mark(K_JOIN_WAIT);
+    for (const Launch& x : lev1) ls.push_back(x);
     for (const Launch& x : lev0) ls.push_back(x);
   }
 }
