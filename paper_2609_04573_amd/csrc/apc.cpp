@@ -525,8 +525,10 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
         break;
       case K_ENCODE: LAUNCH(l.name, l.bytes, st, launch_encode<Q>((const StreamDev*)p, l.nseg, l.nblk, st)); break;
       case K_SIGN: LAUNCH(l.name, l.bytes, st, launch_sign_move((const StreamDev*)p, l.nseg, l.nblk, st)); break;
-      case K_DECODE:  // a: bit 0 marks the level-0 decode, bit 1 a launch of first decodes only
-        LAUNCH(l.name, l.bytes, st, launch_decode<Q>((const StreamDev*)p, l.nseg, l.nblk, (l.a & 2) != 0, st));
+      case K_DECODE:  // a: bit 0 marks the level-0 decode, bit 1 a launch of first decodes only,
+                      // bit 2 one whose streams add at most 16 planes each
+        LAUNCH(l.name, l.bytes, st,
+               launch_decode<Q>((const StreamDev*)p, l.nseg, l.nblk, (l.a & 2) != 0, (l.a & 4) ? 16 : 64, st));
         break;
       case K_COARSEST:
         LAUNCH(l.name, l.bytes, st, (launch_coarsest<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, st)));
@@ -1489,6 +1491,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   int64_t chunks = 0, chunks_fine = 0, fb = 0;
   double db = 0.0, db_fine = 0.0;
   bool fresh = true, fresh_fine = true;  // every stream of the launch decodes from zero
+  int maxk = 0, maxk_fine = 0;             // most planes a stream of the launch adds
   for (int s = 0; s < (int)m.streams.size() && with_decode; ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
@@ -1518,13 +1521,16 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     (fine ? db_fine : db) += b;
     (fine ? sds_fine : sds).push_back(sd);
     (fine ? fresh_fine : fresh) &= sd.fresh != 0;
+    (fine ? maxk_fine : maxk) = std::max(fine ? maxk_fine : maxk, sd.k1 - sd.k0);
     kres[s] = planes[s];
   }
   if (fetched) *fetched = fb;
-  if (!sds.empty()) ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, fresh ? 2 : 0, db, "decode"});
-  if (!sds_fine.empty())  // bit 0 of `a` marks the level-0 decode for the reordering below
-    ls.push_back({K_DECODE, tb.add(sds_fine), (int)sds_fine.size(), chunks_fine, fresh_fine ? 3 : 1, db_fine,
+  if (!sds.empty())
+    ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, (fresh ? 2 : 0) | (maxk <= 16 ? 4 : 0), db,
                   "decode"});
+  if (!sds_fine.empty())  // bit 0 of `a` marks the level-0 decode for the reordering below
+    ls.push_back({K_DECODE, tb.add(sds_fine), (int)sds_fine.size(), chunks_fine,
+                  1 | (fresh_fine ? 2 : 0) | (maxk_fine <= 16 ? 4 : 0), db_fine, "decode"});
   if (!with_recon) return;
   // inverse decomposition of every level-0 region
   if (!h->cd.empty() && L >= 2) {

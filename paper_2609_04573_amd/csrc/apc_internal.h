@@ -188,7 +188,7 @@ hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* j
                               StreamDev* sd, int64_t* prefix, int32_t* err, hipStream_t s);
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
-hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, hipStream_t s);
+hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, int max_planes, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T>

@@ -1508,10 +1508,10 @@ __device__ __forceinline__ int find_stream(const StreamDev* sd, int ns, int64_t 
 
 // One round of the bit-matrix transpose: swap the off-diagonal S x S bit
 // blocks of every 2S x 2S block (M selects the low S bits of each 2S group).
-template <int S, uint32_t M>
-__device__ __forceinline__ void transpose_round(uint32_t (&a)[32]) {
+template <int S, uint32_t M, int N = 32>
+__device__ __forceinline__ void transpose_round(uint32_t (&a)[N]) {
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
+  for (int k = 0; k < N; ++k) {
     if (k & S) continue;
     const uint32_t t = ((a[k] >> S) ^ a[k + S]) & M;
     a[k] ^= t << S;
@@ -1528,6 +1528,16 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
   transpose_round<4, 0x0F0F0F0Fu>(a);
   transpose_round<2, 0x33333333u>(a);
   transpose_round<1, 0x55555555u>(a);
+}
+
+// Two 16 x 16 bit-matrix transposes at once, one in each half of 16 words:
+// afterwards bit k of the low (high) half of a[p] is what bit p of the low
+// (high) half of a[k] was.  The masks of the four rounds keep the halves apart.
+__device__ __forceinline__ void transpose16x2(uint32_t (&a)[16]) {
+  transpose_round<8, 0x00FF00FFu, 16>(a);
+  transpose_round<4, 0x0F0F0F0Fu, 16>(a);
+  transpose_round<2, 0x33333333u, 16>(a);
+  transpose_round<1, 0x55555555u, 16>(a);
 }
 
 constexpr int kRow = 33;  // LDS row pitch (codes) of the half-word staging tile
@@ -1997,6 +2007,127 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) ==
   }
 }
 
+// First decode of 32-bit codes whose plans take at most kDW planes (every
+// stream of the launch): the algorithm of k_decode with the decoded planes
+// held in a window of kDW bit positions [lo, lo + kDW) (half the registers)
+// and the codes staged through LDS a quarter word (16 codes) at a time (half
+// the LDS), so that more waves fit a CU.
+constexpr int kDW = 16;
+constexpr int kRowQ = 17;  // LDS row pitch (codes) of the quarter-word staging tile
+__device__ __forceinline__ void unstage_quarter(BufRsrc rc, int qi, const int32_t* cst, int lane) {
+  const uint32_t k = lane & 15, rr = lane >> 4;  // four rows per store
+  const uint32_t o = (16u * qi + k + 64u * rr) * 4u;
+#pragma unroll 8
+  for (uint32_t it = 0; it < 16; ++it) buf_store<int32_t>(cst[(4 * it + rr) * kRowQ + k], rc, o, 1024u * it);
+}
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_decode_w16(const StreamDev* __restrict__ sd, int ns) {
+  constexpr int kSignWords = 64 + 2 * kDW;
+  __shared__ int32_t cst[64 * kRowQ];
+  __shared__ uint32_t ptab[kDW / 2 * 64];  // cursors of planes j < kDW, two per word (16 bits each)
+  __shared__ unsigned long long sw[kSignWords];
+  __shared__ int64_t pw0[kDW];
+  __shared__ uint32_t pwoff[kDW + 1];
+  const int lane = threadIdx.x;
+  const int64_t gch = blockIdx.x;
+  const int u = find_stream(sd, ns, gch);
+  const StreamDev& S = sd[u];
+  const int64_t chunk = gch - S.chunk_begin;
+  const GAS uint32_t* idx = (const GAS uint32_t*)S.idx;
+  const GAS uint64_t* sign = (const GAS uint64_t*)S.sign;
+  const GAS int64_t* pso = (const GAS int64_t*)S.pso;
+  const int B = S.B, k1 = S.k1;  // planes [0, k1), k1 <= kDW
+  const int64_t M = S.M, C = S.C, n = S.n, sign_n = S.sign_n;
+  const BufRsrc rc = chunk_rsrc<int32_t>(S.codes, chunk * kChunk, n);
+  // plane j is bit position B - 1 - j >= B - k1 >= B - kDW: window from lo
+  const int lo = B > kDW ? B - kDW : 0;
+  uint64_t P[kDW];
+#pragma unroll
+  for (int r = 0; r < kDW; ++r) {
+    const int j = B - 1 - lo - r;
+    P[r] = (j >= 0 && j < k1) ? buf_load<uint64_t>(plane_rsrc(S.mag, j, M, chunk), 8u * lane, 0u) : 0ull;
+  }
+  int64_t Dl = 0;
+  if (lane < k1) Dl = pso[lane] * 64 + (int64_t)idx[(int64_t)lane * C + chunk];
+  uint32_t cc[kDW], incl[kDW];
+  uint64_t sig = 0ull;
+#pragma unroll
+  for (int r = kDW - 1; r >= 0; --r) {
+    const uint64_t pw = P[r];
+    cc[r] = (uint32_t)__popcll(pw & ~sig);
+    incl[r] = cc[r];
+    sig |= pw;
+  }
+  wave_incl_scan_n<kDW>(incl);
+  uint32_t woff = 0;
+  int np = 0;
+  int64_t mypw0 = 0;
+  uint32_t mypwoff = 0;
+#pragma unroll
+  for (int r = kDW - 1; r >= 0; --r) {
+    const int j = B - 1 - lo - r;
+    if (j < 0 || j >= k1) continue;
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl[r], 63);
+    const int64_t D = readlane64(Dl, j);
+    const uint32_t nw = tot ? (uint32_t)(((D + tot - 1) >> 6) - (D >> 6) + 1) : 0u;
+    ((uint16_t*)ptab)[((j >> 1) * 64 + lane) * 2 + (j & 1)] = (uint16_t)(woff * 64 + (uint32_t)(D & 63) + incl[r] - cc[r]);
+    mypw0 = lane == np ? (D >> 6) : mypw0;
+    mypwoff = lane == np ? woff : mypwoff;
+    woff += nw;
+    ++np;
+  }
+  if (lane < np) {
+    pw0[lane] = mypw0;
+    pwoff[lane] = mypwoff;
+  }
+  if (lane == 0) pwoff[np] = woff;
+  __syncthreads();
+  // the sign words of every run (woff <= 64 + 2 * planes by construction)
+  for (uint32_t i = lane; i < woff && i < (uint32_t)kSignWords; i += 64) {
+    int lo2 = 0;
+#pragma unroll
+    for (int st = kDW / 2; st >= 1; st >>= 1)
+      if (lo2 + st < np && pwoff[lo2 + st] <= i) lo2 += st;
+    const int64_t gw = pw0[lo2] + (int64_t)(i - pwoff[lo2]);
+    sw[i] = (gw >= 0 && gw < sign_n) ? sign[gw] : 0ull;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint32_t x[kDW];
+#pragma unroll
+    for (int r = 0; r < kDW; ++r) x[r] = (uint32_t)(P[r] >> (32 * h));
+    transpose16x2(x);  // low half of x[k]: code 32h + k; high half: code 32h + 16 + k
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      uint32_t mgs[16], pos[16];
+      bool take[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t mg = (g ? (x[k] >> 16) : (x[k] & 0xffffu)) << lo;
+        const int j = B - (mg ? 32 - __clz((int)mg) : 0);
+        take[k] = mg != 0u;
+        mgs[k] = mg;
+        const int jj = take[k] ? j : 0;
+        pos[k] = (atomicAdd(&ptab[(jj >> 1) * 64 + lane], take[k] ? 1u << (16 * (jj & 1)) : 0u) >> (16 * (jj & 1))) & 0xffffu;
+      }
+      uint64_t wv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        take[k] = take[k] & (pos[k] < (uint32_t)(kSignWords * 64));
+        wv[k] = sw[(take[k] ? pos[k] : 0u) >> 6];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const bool neg = take[k] & ((uint32_t)(wv[k] >> (pos[k] & 63)) & 1u);
+        cst[lane * kRowQ + k] = neg ? -(int32_t)mgs[k] : (int32_t)mgs[k];
+      }
+      __syncthreads();
+      unstage_quarter(rc, 2 * h + g, cst, lane);
+      __syncthreads();
+    }
+  }
+}
+
 // ----------------------------------------------------------- reconstruction
 template <typename T, typename Q>
 __global__ __launch_bounds__(kThreads) void k_coarsest(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
@@ -2189,10 +2320,12 @@ hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStre
   return hipGetLastError();
 }
 template <typename Q>
-hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, hipStream_t s) {
+hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, int max_planes, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
-  if (all_fresh)
+  if (sizeof(Q) == 4 && all_fresh && max_planes <= kDW)
+    hipLaunchKernelGGL(k_decode_w16, dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  else if (all_fresh)
     hipLaunchKernelGGL((k_decode<Q, MAXB, true>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   else
     hipLaunchKernelGGL((k_decode<Q, MAXB, false>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
@@ -2229,8 +2362,8 @@ template hipError_t launch_cd_inverse<int32_t>(const CDSeg*, int, int64_t, int, 
 template hipError_t launch_cd_inverse<int64_t>(const CDSeg*, int, int64_t, int, int, hipStream_t);
 template hipError_t launch_encode<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
 template hipError_t launch_encode<int64_t>(const StreamDev*, int, int64_t, hipStream_t);
-template hipError_t launch_decode<int32_t>(const StreamDev*, int, int64_t, bool, hipStream_t);
-template hipError_t launch_decode<int64_t>(const StreamDev*, int, int64_t, bool, hipStream_t);
+template hipError_t launch_decode<int32_t>(const StreamDev*, int, int64_t, bool, int, hipStream_t);
+template hipError_t launch_decode<int64_t>(const StreamDev*, int, int64_t, bool, int, hipStream_t);
 template hipError_t launch_coarsest<float, int32_t>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_coarsest<double, int64_t>(const FlatSeg*, int, int64_t, hipStream_t);
 template hipError_t launch_inject<float>(const FlatSeg*, int, int64_t, hipStream_t);
