@@ -54,7 +54,7 @@ def kernel_source_hash() -> str:
 def _short_kernel(name: str) -> str:
     import re
 
-    m = re.search(r"(k_[a-z_]+(?:<[^()]*>)?)", name)
+    m = re.search(r"(k_[a-z0-9_]+(?:<[^()]*>)?)", name)
     return m.group(1) if m else name.split("(")[0][-60:]
 
 
