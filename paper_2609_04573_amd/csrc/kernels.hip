@@ -48,6 +48,12 @@ __device__ __forceinline__ V buf_load(BufRsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(V, x);
   }
 }
+// A wave-uniform 64-bit value (held in vector registers) moved to scalar ones.
+__device__ __forceinline__ int64_t readfirst64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 template <typename V>
 __device__ __forceinline__ void buf_store(V v, BufRsrc r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(V) == 4)
@@ -1180,8 +1186,9 @@ template <typename Q, int A>
 __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __restrict__ segs, int nseg, int64_t nblk) {
   using W = LiftT<Q>;
   constexpr int U = A == 0 ? 1 : 0;
-  __shared__ W h1[kCIHU * kCIHV];
-  __shared__ W lt[kCIN];
+  // both padded to whole turns of the block, so every thread writes every turn
+  __shared__ W h1[(kCIHU * kCIHV + kThreads - 1) / kThreads * kThreads];
+  __shared__ W lt[kCIL * kThreads];
   __shared__ int64_t rb0[3], rb1[kCIHU], rb2[kCITU];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -1255,7 +1262,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       }
 #pragma unroll
       for (int i = 0; i < kCIL; ++i)
-        if (tid + i * kThreads < kCIN) lt[tid + i * kThreads] = lv[i];
+        lt[tid + i * kThreads] = lv[i];  // zero past the runs
     }
     __syncthreads();
     // stride-2 points (u, v even) of the tile and halo: S1 points as they are,
@@ -1267,7 +1274,9 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       const W* s2b = lt + kCIN1 + kCIN2C;
       // branch-free: every lane reads the S1 values around it and both S2
       // candidates (indices kept inside the staged runs) and selects
-      for (int e = tid; e < kCIHU * kCIHV; e += kThreads) {
+      // whole turns: entries past the last (padding) take values from reads
+      // that stay inside the staging and are never used
+      for (int e = tid; e < (kCIHU * kCIHV + kThreads - 1) / kThreads * kThreads; e += kThreads) {
         const int r = e / kCIHV, k = e - r * kCIHV;
         const int u = U0 + 2 * r, v = V0 + 2 * k;
         const int rh = r >> 1, c0 = k >> 1;
@@ -1296,35 +1305,32 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
       const int r = wave * (kCITU / 4) + rr;
       const int u = U0 + r;
       if (u >= Nu) continue;
-      GAS Q* out = Rout + rowoff(u);
-      const GAS Q* s3r = S3 + rb2[r];
       const bool uodd = u & 1;
+      // the row's S3 run and its output row as buffers: a column past the
+      // row is out of their range, so its load reads zero and its store is
+      // dropped (no per-lane branches)
+      const BufRsrc s3b = buf_rsrc((const void*)(S3 + readfirst64(rb2[r])), (int64_t)(uodd ? Nv : Nv >> 1) * (int64_t)sizeof(Q));
+      const BufRsrc ob = buf_rsrc((const void*)(Rout + rowoff(u)), (int64_t)Nv * (int64_t)sizeof(Q));
       W x0[kCITV / 128], x1[kCITV / 128];
 #pragma unroll
       for (int c = 0; c < kCITV / 128; ++c) {
         const int v0 = V0 + 2 * (c * 64 + lane), v1 = v0 + 1;
-        const bool ok0 = uodd && v0 < Nv, ok1 = v1 < Nv;
-        const Q q0 = *(ok0 ? s3r + (int)cd_in_row<A>(2, u, v0) : (const GAS Q*)segs);
-        const Q q1 = *(ok1 ? s3r + (int)cd_in_row<A>(2, u, v1) : (const GAS Q*)segs);
-        x0[c] = ok0 ? (W)apply_mask<Q>(q0, M2) : (W)0;
-        x1[c] = ok1 ? (W)apply_mask<Q>(q1, M2) : (W)0;
+        x0[c] = 0;
+        if (uodd) x0[c] = (W)apply_mask<Q>(buf_load<Q>(s3b, (uint32_t)cd_in_row<A>(2, u, v0) * sizeof(Q), 0u), M2);
+        x1[c] = (W)apply_mask<Q>(buf_load<Q>(s3b, (uint32_t)cd_in_row<A>(2, u, v1) * sizeof(Q), 0u), M2);
       }
       const W* ht = h1 + (r >> 1) * kCIHV;                         // row u (even u) or u - 1
       const W* hb = (uodd && u + 1 <= Nu - 1) ? ht + kCIHV : ht;  // row u + 1 (odd u)
 #pragma unroll
       for (int c = 0; c < kCITV / 128; ++c) {
-        const int p = c * 64 + lane, v0 = V0 + 2 * p, v1 = v0 + 1;
-        if (v0 >= Nv) continue;
+        const int p = c * 64 + lane, v0 = V0 + 2 * p, v1 = v0 + 1;  // p + 1 <= kCIHV - 1
         const bool hc = v1 + 1 <= Nv - 1;
         const W t0 = ht[p], t1 = hc ? ht[p + 1] : t0;
-        if (!uodd) {
-          out[v0] = (Q)t0;
-          if (v1 < Nv) out[v1] = (Q)(x1[c] + avgw<W>(t0, t1));
-        } else {
-          const W b0 = hb[p], b1 = hc ? hb[p + 1] : b0;
-          out[v0] = (Q)(x0[c] + avgw<W>(t0, b0));
-          if (v1 < Nv) out[v1] = (Q)(x1[c] + avgw<W>(avgw<W>(t0, t1), avgw<W>(b0, b1)));
-        }
+        const W b0 = hb[p], b1 = hc ? hb[p + 1] : b0;
+        const W o0 = uodd ? x0[c] + avgw<W>(t0, b0) : t0;
+        const W o1 = x1[c] + (uodd ? avgw<W>(avgw<W>(t0, t1), avgw<W>(b0, b1)) : avgw<W>(t0, t1));
+        buf_store<Q>((Q)o0, ob, (uint32_t)v0 * sizeof(Q), 0u);
+        buf_store<Q>((Q)o1, ob, (uint32_t)v1 * sizeof(Q), 0u);
       }
     }
   }
