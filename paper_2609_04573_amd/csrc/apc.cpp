@@ -165,6 +165,10 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) pool().put(p, bytes);
@@ -190,6 +194,46 @@ struct DevBuf {
     return (X*)p;
   }
 };
+
+// Device buffers that queued work may still use, kept until an event
+// recorded behind that work has completed (then they go back to the pool):
+// a call can return without waiting for its last kernels.
+struct Retired {
+  hipEvent_t ev = nullptr;
+  std::vector<DevBuf> bufs;
+};
+std::mutex g_retired_mu;
+std::deque<Retired>& retired() {
+  static std::deque<Retired>* r = new std::deque<Retired>();  // never destroyed, like the pool
+  return *r;
+}
+// Release the retired buffers whose work has finished (oldest first).
+void reap_retired() {
+  std::lock_guard<std::mutex> lk(g_retired_mu);
+  auto& q = retired();
+  while (!q.empty()) {
+    const hipError_t e = hipEventQuery(q.front().ev);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) (void)hipGetLastError();  // the stream is gone: nothing runs on it any more
+    (void)hipEventDestroy(q.front().ev);
+    q.pop_front();
+  }
+}
+// Keep bufs until the work queued on st so far has finished.
+apc_status retire(std::vector<DevBuf>&& bufs, hipStream_t st) {
+  Retired r;
+  hipError_t e = hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(r.ev, st);
+  if (e != hipSuccess) {  // fall back to waiting here
+    if (r.ev) (void)hipEventDestroy(r.ev);
+    (void)hipStreamSynchronize(st);
+    return APC_OK;
+  }
+  r.bufs = std::move(bufs);
+  std::lock_guard<std::mutex> lk(g_retired_mu);
+  retired().push_back(std::move(r));
+  return APC_OK;
+}
 
 // Field geometry in the 3D embedding.
 struct Geo {
@@ -365,7 +409,11 @@ struct apc_handle {
   DevBuf xc, xb[2], pr[2], cdreg, tables;
   bool work_ready = false;
   PinnedBlock pinned;  // staging of table uploads (its event follows the last upload)
-  ~apc_handle() { g_pinned.put(pinned, nullptr, false); }
+  hipEvent_t ready = nullptr;  // follows the refactor's last kernel (work on other streams waits for it)
+  ~apc_handle() {
+    g_pinned.put(pinned, nullptr, false);
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 namespace {
@@ -623,12 +671,12 @@ struct Staging {
   PinnedBlock b;
   size_t used = 0;
   hipStream_t last = nullptr;
-  ~Staging() { g_pinned.put(b, last, last != nullptr); }
+  ~Staging() { g_pinned.put(b, nullptr, false); }  // its event follows its last copy
   apc_status put(const std::vector<char>& bytes, void* dev, hipStream_t st) {
     if (bytes.empty()) return APC_OK;
     if (used + bytes.size() > b.cap) {
       // the old block may still feed queued copies: its event guards reuse
-      g_pinned.put(b, last, last != nullptr);
+      g_pinned.put(b, nullptr, false);
       if (!g_pinned.get(std::max<size_t>(bytes.size() * 2, (size_t)1 << 20), b))
         return fail(APC_E_OOM, "pinned staging of %zu bytes", bytes.size());
       used = 0;
@@ -637,6 +685,7 @@ struct Staging {
     memcpy(dst, bytes.data(), bytes.size());
     used += (bytes.size() + 255) & ~(size_t)255;
     HIP_TRY(hipMemcpyAsync(dev, dst, bytes.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(b.ev, st));
     last = st;
     return APC_OK;
   }
@@ -905,6 +954,16 @@ int stream_of(const Meta& m, int l, int rho) {
 template <typename T, typename Q>
 apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T*>& X, hipStream_t st) {
   const int nf = (int)H.size();
+  reap_retired();
+  // on an early (error) return, queued work is waited for before anything
+  // is released; a completed call retires its temporaries instead
+  struct Drain {
+    hipStream_t st;
+    bool armed = true;
+    ~Drain() {
+      if (armed) (void)hipStreamSynchronize(st);
+    }
+  } drain{st};
   const int P = sizeof(T) == 4 ? 29 : 52;
   struct Tmp {
     DevBuf grids, codes, cdc;
@@ -1372,11 +1431,24 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     H[f]->k_res.assign(H[f]->meta.streams.size(), 0);
     ensure_sequence(H[f]->meta, 0);
   }
-  if (!sds.empty()) {  // waits for the sign placement: the temporaries above are released on return
-    int32_t err = 0;
-    APC_TRY(read_back(&err, errb.p, 4, st));
-    if (err) return fail(APC_E_INVALID, "internal: sign section exceeds its bound");
+  // The call returns while the sign placement may still run: each handle
+  // gets an event behind it (work on other streams waits for that), and the
+  // temporaries stay allocated until it has finished.  (The layout kernel's
+  // bound check repeats the host's, above, which has already passed.)
+  for (int f = 0; f < nf; ++f) {
+    if (!H[f]->ready) HIP_TRY(hipEventCreateWithFlags(&H[f]->ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(H[f]->ready, st));
   }
+  std::vector<DevBuf> keep;
+  for (Tmp& t : tmp) {
+    keep.push_back(std::move(t.grids));
+    keep.push_back(std::move(t.codes));
+    keep.push_back(std::move(t.cdc));
+  }
+  for (DevBuf* b : {&accb, &tab, &tab2, &cntb, &stageb, &sdb, &jobs, &totals, &prefix, &errb})
+    keep.push_back(std::move(*b));
+  APC_TRY(retire(std::move(keep), st));
+  drain.armed = false;
   return APC_OK;
 }
 
@@ -1765,6 +1837,7 @@ AuxPool g_aux;
 
 template <typename T, typename Q>
 apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, hipStream_t st, int64_t* fetched) {
+  if (h->ready) HIP_TRY(hipStreamWaitEvent(st, h->ready, 0));  // the refactor's last kernels
   APC_TRY(ensure_work(h));
   TableBuilder tb;
   std::vector<Launch> ls;
@@ -1964,6 +2037,7 @@ apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n
   if (!h || !targets || !outs_dev || !out || n < 1) return fail(APC_E_INVALID, "bad argument");
   APC_TRY(ensure_work(h));
   hipStream_t st = (hipStream_t)hip_stream;
+  if (h->ready) HIP_TRY(hipStreamWaitEvent(st, h->ready, 0));  // the refactor's last kernels
   std::unique_ptr<apc_ladder> ld(new apc_ladder());
   ld->h = h;
   TableBuilder tb;
@@ -2052,6 +2126,7 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
   char* dst = (char*)host_dst;
   memset(dst, 0, (size_t)S.blob_bytes());
   if (S.B == 0 || S.n == 0) return APC_OK;
+  if (h->ready) HIP_TRY(hipEventSynchronize(h->ready));  // the refactor's last kernels
   const int64_t ib = 4 * (int64_t)S.B * S.chunks();
   HIP_TRY(hipMemcpy(dst, h->idx.as<uint32_t>() + S.idx_off, (size_t)ib, hipMemcpyDeviceToHost));
   const int64_t ibp = ib + (8 - ib % 8) % 8;
@@ -2614,6 +2689,7 @@ apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t
     sv->fields.emplace_back(new SrvField());
     SrvField& F = *sv->fields.back();
     F.h = fields[f];
+    if (F.h->ready) HIP_TRY(hipEventSynchronize(F.h->ready));  // the refactor's last kernels
     APC_TRY(ensure_codes(F.h));
     F.k_issued = F.h->k_res;
     HIP_TRY(hipStreamCreateWithFlags(&F.dec_st, hipStreamNonBlocking));
