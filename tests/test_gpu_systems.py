@@ -177,3 +177,25 @@ def test_two_stream_retrieval_equals_one_stream():
         want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", rel))).view(np.uint32)
         assert np.array_equal(outs[(False, rel)], want), rel
         assert np.array_equal(outs[(True, rel)], want), rel
+
+
+def test_refactor_returns_before_its_last_kernels():
+    """The refactor returns while its sign placement may still run; a
+    retrieval on another stream and a blob export right after it wait for
+    the handle's ready event, so both see the finished representation: the
+    retrieval equals the oracle's and the blobs equal those exported after
+    a full device synchronization."""
+    apc = _apc()
+    x = fieldgen.power_law_field((48, 96, 256), seed=12)
+    sc = oracle.Scheme(kind="level", cd_axis=0)
+    ref = oracle.refactor(x, sc)
+    xd = torch.from_numpy(x).cuda()
+    side = torch.cuda.Stream()
+    h = apc.refactor(xd, apc.Scheme(kind="level", cd_axis=0))
+    got, _ = h.retrieve(apc.Target("rel", 1e-4), stream=side)
+    blobs = [h.stream_blob(s) for s in range(h.num_streams)]
+    torch.cuda.synchronize()
+    want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", 1e-4))).view(np.uint32)
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
+    assert blobs == [h.stream_blob(s) for s in range(h.num_streams)]
+    h.close()
