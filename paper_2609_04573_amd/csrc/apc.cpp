@@ -2102,6 +2102,7 @@ void apc_free(apc_handle* h) {
   // back to the shared pool only once the device is idle.
   (void)hipDeviceSynchronize();
   delete h;
+  reap_retired();  // the device is idle: every retired buffer goes back to the pool
 }
 
 int32_t apc_num_streams(const apc_handle* h) { return h ? (int32_t)h->meta.streams.size() : 0; }
