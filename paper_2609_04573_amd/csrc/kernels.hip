@@ -2030,7 +2030,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   constexpr int kSignWords = 64 + 2 * kDW;
   __shared__ int32_t cst[64 * kRowQ];
   __shared__ uint32_t ptab[kDW / 2 * 64];  // cursors of planes j < kDW, two per word (16 bits each)
-  __shared__ unsigned long long sw[kSignWords];
+  __shared__ unsigned long long sw[128];  // kSignWords, padded to two whole turns
   __shared__ int64_t pw0[kDW];
   __shared__ uint32_t pwoff[kDW + 1];
   const int lane = threadIdx.x;
@@ -2087,14 +2087,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   if (lane == 0) pwoff[np] = woff;
   __syncthreads();
-  // the sign words of every run (woff <= 64 + 2 * planes by construction)
-  for (uint32_t i = lane; i < woff && i < (uint32_t)kSignWords; i += 64) {
+  // the sign words of every run (woff <= 64 + 2 * planes by construction),
+  // two whole turns; the sign section as a buffer, so a word past it (or a
+  // slot past the runs) reads zero without a branch
+  const BufRsrc sb = buf_rsrc((const void*)S.sign, sign_n * 8);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const uint32_t i = lane + 64 * t;
     int lo2 = 0;
 #pragma unroll
     for (int st = kDW / 2; st >= 1; st >>= 1)
       if (lo2 + st < np && pwoff[lo2 + st] <= i) lo2 += st;
     const int64_t gw = pw0[lo2] + (int64_t)(i - pwoff[lo2]);
-    sw[i] = (gw >= 0 && gw < sign_n) ? sign[gw] : 0ull;
+    const bool ok = i < woff && i < (uint32_t)kSignWords && gw >= 0 && gw < sign_n;
+    sw[i] = buf_load<uint64_t>(sb, ok ? (uint32_t)gw * 8u : 0x80000000u, 0u);
   }
   __syncthreads();
 #pragma unroll
