@@ -412,7 +412,10 @@ struct apc_handle {
   hipEvent_t ready = nullptr;  // follows the refactor's last kernel (work on other streams waits for it)
   ~apc_handle() {
     g_pinned.put(pinned, nullptr, false);
-    if (ready) (void)hipEventDestroy(ready);
+    if (ready) {  // the buffers go back to the shared pool only after the refactor's last kernels
+      (void)hipEventSynchronize(ready);
+      (void)hipEventDestroy(ready);
+    }
   }
 };
 
