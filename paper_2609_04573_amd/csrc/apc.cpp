@@ -1562,15 +1562,18 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   const bool per_level = h->scheme.kind == APC_PER_LEVEL;
   const bool split_on = split && with_decode && with_recon && per_level && !h->cd.empty() && L >= 3;
   const size_t base = ls.size();
-  std::vector<StreamDev> sds, sds_fine;
-  int64_t chunks = 0, chunks_fine = 0, fb = 0;
-  double db = 0.0, db_fine = 0.0;
-  bool fresh = true, fresh_fine = true;  // every stream of the launch decodes from zero
-  int maxk = 0, maxk_fine = 0;             // most planes a stream of the launch adds
+  // decode launches by (level 0 or not) x (first decode adding at most 16
+  // planes, which the windowed kernel takes, or any other)
+  std::vector<StreamDev> sdv[4];
+  int64_t chv[4] = {0, 0, 0, 0}, fb = 0;
+  double dbv[4] = {0, 0, 0, 0};
+  bool frv[4] = {true, true, true, true};  // every stream of the launch decodes from zero
   for (int s = 0; s < (int)m.streams.size() && with_decode; ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
     const bool fine = split_on && S.level == 0 && S.kind != S_COARSE;
+    const bool win = kres[s] == 0 && planes[s] <= 16;
+    const int cat = (fine ? 2 : 0) + (win ? 1 : 0);
     StreamDev sd{};
     sd.codes = (S.use_cd ? h->cd_codes.as<Q>() : h->codes.as<Q>()) + S.code_off;
     sd.mag = h->mag.as<uint64_t>() + S.mag_off;
@@ -1581,7 +1584,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     sd.n = S.n;
     sd.M = S.words();
     sd.C = S.chunks();
-    sd.chunk_begin = fine ? chunks_fine : chunks;
+    sd.chunk_begin = chv[cat];
     sd.B = S.B;
     sd.k0 = kres[s];
     sd.k1 = planes[s];
@@ -1592,20 +1595,19 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       b += 8.0 * ((S.nsig[j] + 63) / 64);
     }
     b += (double)(sd.k1 - sd.k0) * (8.0 * sd.M + 4.0 * sd.C) + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
-    (fine ? chunks_fine : chunks) += sd.C;
-    (fine ? db_fine : db) += b;
-    (fine ? sds_fine : sds).push_back(sd);
-    (fine ? fresh_fine : fresh) &= sd.fresh != 0;
-    (fine ? maxk_fine : maxk) = std::max(fine ? maxk_fine : maxk, sd.k1 - sd.k0);
+    chv[cat] += sd.C;
+    dbv[cat] += b;
+    sdv[cat].push_back(sd);
+    frv[cat] = frv[cat] && sd.fresh != 0;
     kres[s] = planes[s];
   }
   if (fetched) *fetched = fb;
-  if (!sds.empty())
-    ls.push_back({K_DECODE, tb.add(sds), (int)sds.size(), chunks, (fresh ? 2 : 0) | (maxk <= 16 ? 4 : 0), db,
-                  "decode"});
-  if (!sds_fine.empty())  // bit 0 of `a` marks the level-0 decode for the reordering below
-    ls.push_back({K_DECODE, tb.add(sds_fine), (int)sds_fine.size(), chunks_fine,
-                  1 | (fresh_fine ? 2 : 0) | (maxk_fine <= 16 ? 4 : 0), db_fine, "decode"});
+  // `a`: bit 0 marks a level-0 decode (for the reordering below), bit 1 a
+  // launch of first decodes only, bit 2 one whose streams add at most 16 planes
+  for (int cat = 0; cat < 4; ++cat)
+    if (!sdv[cat].empty())
+      ls.push_back({K_DECODE, tb.add(sdv[cat]), (int)sdv[cat].size(), chv[cat],
+                    ((cat & 2) ? 1 : 0) | (frv[cat] ? 2 : 0) | ((cat & 1) ? 4 : 0), dbv[cat], "decode"});
   if (!with_recon) return;
   // inverse decomposition of every level-0 region
   if (!h->cd.empty() && L >= 2) {
