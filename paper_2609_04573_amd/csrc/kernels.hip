@@ -485,13 +485,16 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // Per-level interpolation predicts every point of level l from the coarser
 // level by one-dimensional stencils along axis 2, then axis 1, then axis 0,
 // each pass reading the predictions of the previous one (tensor product).
-// A block owns a 16 x 64 tile of (axis 1, axis 2) and walks a run of up to
-// 32 planes along axis 0 (shorter runs on small levels, for parallelism): each coarse plane is upsampled in-plane through LDS
-// (axis 2, then axis 1) into registers, a four-plane register window gives
-// the axis-0 stencil, and every point of the level is visited once.  The
-// coarse tile of the next plane and the point values (or codes) of the
-// current planes are fetched one step ahead, so their latency overlaps the
-// LDS passes.
+// A block owns a kT1 x kT2 tile of (axis 1, axis 2) and walks a run of up
+// to 128 planes along axis 0 (shorter runs on small levels, for
+// parallelism): each coarse plane is upsampled in-plane through LDS (axis 2,
+// then axis 1) into registers, a four-plane register window gives the
+// axis-0 stencil, and every point of the level is visited once.  The coarse
+// tile of the next plane is fetched one step ahead and the point values (or
+// codes) of the current planes before the plane's LDS passes (a whole step
+// ahead in the quantization and reconstruction passes of 4-byte inputs), so
+// their latency overlaps the LDS passes.  Stencils are selected without
+// branches, and outside the max pass the loads are issued on every lane.
 // MODE 0: max |x - p| of the level.  MODE 1: codes q = rint(c * 2^k_shift)
 // into the three region lattices.  MODE 2: x = p + Delta * q' on the level
 // grid (coarse points are copied), written as float64 for the next level;
