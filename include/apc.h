@@ -82,10 +82,15 @@ typedef struct apc_handle apc_handle;
 /* Refactor a device-resident field (Algorithm 1).  field_dev: n elements of
  * dtype (caller owned, read only, must stay valid until the stream passes
  * this call).  On success *out owns every plane stream (device memory) and
- * the host metadata; release it with apc_free.  The call synchronizes
- * hip_stream (the quantization steps depend on global coefficient maxima).
+ * the host metadata; release it with apc_free.  The call waits for the
+ * coefficient maxima and plane counts (the quantization steps depend on
+ * global group maxima, the metadata on the counts) and returns while its
+ * last kernels (the sign placement) may still run on hip_stream: the handle
+ * carries an event behind them, and retrieval, ladders, the server,
+ * serialization and blob export on any stream wait for that event first.
  * Errors: APC_E_INVALID (dims/scheme), APC_E_DTYPE, APC_E_NONFINITE,
- * APC_E_OOM, APC_E_HIP; *out is untouched on error. */
+ * APC_E_OOM, APC_E_HIP; *out is untouched on error (queued work is waited
+ * for before the call's temporaries are released). */
 apc_status apc_refactor(const void* field_dev, int32_t dtype, const int64_t* dims, int32_t ndim,
                         const apc_scheme* scheme, void* hip_stream, apc_handle** out);
 

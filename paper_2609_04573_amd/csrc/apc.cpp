@@ -159,6 +159,11 @@ Pool& pool() {
 }
 
 // Device allocation owned by a host object.
+struct DevBuf;
+// While set (by a DrainScope), buffers released on this thread are parked
+// in this list instead of going back to the pool.
+thread_local std::vector<DevBuf>* g_park = nullptr;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -171,6 +176,10 @@ struct DevBuf {
   }
   ~DevBuf() { release(); }
   void release() {
+    if (p && g_park) {
+      g_park->emplace_back(std::move(*this));
+      return;
+    }
     if (p) pool().put(p, bytes);
     p = nullptr;
     bytes = 0;
@@ -234,6 +243,35 @@ apc_status retire(std::vector<DevBuf>&& bufs, hipStream_t st) {
   retired().push_back(std::move(r));
   return APC_OK;
 }
+
+// Scope of a call that queues work on stream st and may return early: every
+// device buffer released on this thread while the scope lives is parked
+// instead of going back to the pool.  When the scope ends, an armed scope
+// (an error return) waits for the stream before the parked buffers are
+// released; a disarmed one (the call completed) retires them behind an event
+// on st.  Buffers released by destructors that run before the scope's own
+// (locals declared after it) are therefore never handed out while queued
+// kernels may still use them.
+struct DrainScope {
+  hipStream_t st;
+  bool armed = true;
+  std::vector<DevBuf> parked;
+  std::vector<DevBuf>* prev;
+  explicit DrainScope(hipStream_t s) : st(s), prev(g_park) { g_park = &parked; }
+  DrainScope(const DrainScope&) = delete;
+  DrainScope& operator=(const DrainScope&) = delete;
+  ~DrainScope() {
+    g_park = prev;
+    if (parked.empty()) return;
+    if (armed) {
+      (void)hipStreamSynchronize(st);
+      (void)hipGetLastError();
+      parked.clear();
+    } else {
+      (void)retire(std::move(parked), st);
+    }
+  }
+};
 
 // Field geometry in the 3D embedding.
 struct Geo {
@@ -410,8 +448,13 @@ struct apc_handle {
   bool work_ready = false;
   PinnedBlock pinned;  // staging of table uploads (its event follows the last upload)
   hipEvent_t ready = nullptr;  // follows the refactor's last kernel (work on other streams waits for it)
+  hipEvent_t tab_ev = nullptr;  // follows the last retrieval that read `tables`
   ~apc_handle() {
     g_pinned.put(pinned, nullptr, false);
+    if (tab_ev) {
+      (void)hipEventSynchronize(tab_ev);
+      (void)hipEventDestroy(tab_ev);
+    }
     if (ready) {  // the buffers go back to the shared pool only after the refactor's last kernels
       (void)hipEventSynchronize(ready);
       (void)hipEventDestroy(ready);
@@ -958,15 +1001,9 @@ template <typename T, typename Q>
 apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T*>& X, hipStream_t st) {
   const int nf = (int)H.size();
   reap_retired();
-  // on an early (error) return, queued work is waited for before anything
-  // is released; a completed call retires its temporaries instead
-  struct Drain {
-    hipStream_t st;
-    bool armed = true;
-    ~Drain() {
-      if (armed) (void)hipStreamSynchronize(st);
-    }
-  } drain{st};
+  // on an early (error) return, queued work is waited for before any
+  // buffer is released; a completed call retires its temporaries instead
+  DrainScope drain(st);
   const int P = sizeof(T) == 4 ? 29 : 52;
   struct Tmp {
     DevBuf grids, codes, cdc;
@@ -1042,8 +1079,11 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         const int gi = group_of(h->meta, l, 0);
         c.gmax = acc + tmp[f].acc + 4 + gi;
         for (int rho = 0; rho < h->geo.d; ++rho) c.q[rho] = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
-        const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
-        by += (double)n * (sizeof(T) + (mode == 1 ? sizeof(Q) : 0));
+        // bytes the method moves: each fine point of the level read once (and
+        // its code written in the quantization pass); coarse points are
+        // counted at their own, coarser level, the coarsest by its own pass
+        const int64_t nfine = (int64_t)c.m[0] * c.m[1] * c.m[2] - (int64_t)c.mc[0] * c.mc[1] * c.mc[2];
+        by += (double)nfine * (sizeof(T) + (mode == 1 ? sizeof(Q) : 0));
         ls2.push_back(c);
       }
     }
@@ -1684,8 +1724,10 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       }
       std::vector<LevelSeg> cs{c};
       const int64_t nbk = assign_level_blocks(cs);
-      const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2];
-      const double by = (double)n * (sizeof(Q) + (l ? 8 : sizeof(T))) + 8.0 * c.mc[0] * c.mc[1] * c.mc[2];
+      // codes of the level's fine points and the coarser grid read, every
+      // point of the level written
+      const int64_t n = (int64_t)c.m[0] * c.m[1] * c.m[2], nc = (int64_t)c.mc[0] * c.mc[1] * c.mc[2];
+      const double by = (double)(n - nc) * sizeof(Q) + (double)n * (l ? 8 : sizeof(T)) + 8.0 * nc;
       // level 0 writes the output field: its own kernel and profile name
       ls.push_back({l == 0 ? K_LEVEL3 : K_LEVEL2, tb.add(cs), 1, nbk, t2, by, l == 0 ? "recon" : "recon_coarse"});
       xin = xout;
@@ -1792,6 +1834,11 @@ apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStrea
     HIP_TRY(hipEventSynchronize(h->pinned.ev));  // the previous copy has left the staging
   }
   memcpy(h->pinned.p, bytes.data(), bytes.size());
+  if (h->tables.bytes < bytes.size() && h->tab_ev) {
+    // a larger table: the previous retrieval (on any stream) may still read
+    // the old one, which goes back to the shared pool only after it
+    HIP_TRY(hipEventSynchronize(h->tab_ev));
+  }
   APC_TRY(h->tables.alloc(bytes.size()));
   HIP_TRY(hipMemcpyAsync(h->tables.p, h->pinned.p, bytes.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(h->pinned.ev, st));
@@ -1864,6 +1911,8 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   } else {
     APC_TRY((issue<T, Q>(ls, (const char*)h->tables.p, st)));
   }
+  if (!h->tab_ev) HIP_TRY(hipEventCreateWithFlags(&h->tab_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(h->tab_ev, st));  // the helper stream, if any, has joined st
   h->k_res = kres;
   return APC_OK;
 }

@@ -166,14 +166,15 @@ __device__ __forceinline__ int bitlen_of(uint64_t v) { return bitlen64(v); }
 
 // Codes truncated to the first k of B planes (magnitude bits below plane k
 // cleared, sign kept), through a mask on the magnitude computed once per
-// segment: all ones when k >= B, zero when k <= 0.
+// segment: zero when k <= 0 or B <= 0 (a stream without planes is never
+// decoded, so its code buffer may hold anything), all ones when k >= B.
 template <typename Q> struct UOf { using type = uint64_t; };
 template <> struct UOf<int32_t> { using type = uint32_t; };
 template <typename Q>
 __device__ __forceinline__ typename UOf<Q>::type code_mask(int B, int k) {
   using U = typename UOf<Q>::type;
+  if (k <= 0 || B <= 0) return (U)0;
   if (k >= B) return ~(U)0;
-  if (k <= 0) return (U)0;
   return ~(U)0 << (B - k);  // 1 <= B - k < bits of U
 }
 // Apply a magnitude mask to a sign-magnitude code held in two's complement
