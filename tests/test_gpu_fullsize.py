@@ -1,17 +1,17 @@
 """GPU checks at the full benchmark size: the 512^3 float32 k^-5/3 field with
 the benchmark's scheme (per-level cubic + decomposition on axis 0), in the
-launch configuration bench.py times, plus its float64 256^3 copy.
+launch configuration bench.py times (sweep tiles from the autotuner), plus
+its float64 256^3 copy, and 64x512x512 slabs whose level 0 is swept in runs
+of 16 planes along axis 0 (the multi-step register window of the sweep).
 
-The oracle cannot refactor 512^3 in test time (about two minutes), so:
-- levels 1 and up are compared bit for bit: per-level refactoring of level l
-  reads only the stride-2^l grid, so the oracle run on x[::2, ::2, ::2]
-  without decomposition yields exactly the streams (and group maxima) of the
-  full field's levels 1..L-1 and its coarsest level;
-- level 0 and the whole retrieval path are checked by properties that hold
-  at any size: the max-error bound at every step of the relative-eb ladder
-  1e-1..1e-7, the PSNR guarantee at 40..120 dB, incremental == fresh
-  retrieval bit for bit, nested plans, and the full-plane reconstruction
-  within the model bound."""
+Bit parity with the oracle: every stream's bytes and the metadata of the
+whole 512^3 refactor, and the reconstructions at rel 1e-2, 1e-4, 1e-6 and
+PSNR 60, 100 dB (the oracle needs about two minutes for the refactor and
+half a minute per retrieval).  Properties that hold at any size cover the
+rest of the ladders: the max-error bound at every step of the relative-eb
+ladder 1e-1..1e-7, the PSNR guarantee at 40..120 dB, incremental == fresh
+retrieval bit for bit, nested plans, and the full-plane reconstruction within
+the model bound."""
 import math
 
 import numpy as np
@@ -44,6 +44,61 @@ def _max_err(out, xd):
 def _psnr(out, xd, rng):
     mse = float(((out.double() - xd.double()) ** 2).mean().item())
     return math.inf if mse == 0 else 20 * math.log10(rng / math.sqrt(mse))
+
+
+def _bits(a):
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def _compare_with_oracle(apc, x, sc_gpu, sc_or, targets, tune=False):
+    from test_gpu_parity import _check_metadata
+
+    xd = torch.from_numpy(x).cuda()
+    if tune:
+        apc.tune_tiles(xd)  # the launch configuration the benchmark times
+    h = apc.refactor(xd, sc_gpu)
+    ref = oracle.refactor(x, sc_or)
+    _check_metadata(h, ref)
+    for s, st in enumerate(ref.streams):
+        assert h.stream_blob(s) == st.blob, f"stream {s} bytes differ"
+    for kind, val in targets:
+        pl = oracle.plan(ref, oracle.Target(kind, val))
+        planes, info = h.plan(apc.Target(kind, val))
+        assert planes == pl.planes and info["bound"] == pl.bound and info["bytes_total"] == pl.bytes
+        out, _ = h.retrieve(apc.Target(kind, val))
+        want = oracle.retrieve(ref, pl)
+        got = out.cpu().numpy()
+        assert np.array_equal(_bits(got), _bits(want)), (kind, val, float(np.abs(got - want).max()))
+        del want, got
+    h.close()
+    apc.tile_override(0)
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_512_matches_oracle(field512):
+    """The benchmark's field, scheme and launch configuration, bit for bit."""
+    apc = _apc()
+    _compare_with_oracle(apc, field512, apc.Scheme(kind="level", cd_axis=0), oracle.Scheme(kind="level", cd_axis=0),
+                         [("rel", 1e-2), ("rel", 1e-4), ("rel", 1e-6), ("psnr", 60), ("psnr", 100)], tune=True)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype,scheme", [
+    (np.float32, ("level", 3, None, 0)),
+    (np.float64, ("level", 3, None, 0)),
+    (np.float32, ("level", 1, None, 1)),
+    (np.float32, ("region", 3, (2, 1, 0), None)),
+], ids=str)
+def test_slab_16_plane_runs_match_oracle(dtype, scheme):
+    """64x512x512: level 0 of the per-level sweep runs 16 planes per block
+    along axis 0 (the run is shortened from 128 only as far as 1024 blocks
+    per level need), so every pass of the sweep takes its multi-step path."""
+    apc = _apc()
+    x = fieldgen.power_law_field((64, 512, 512), seed=31, dtype=dtype)
+    kind, degree, order, cd = scheme
+    _compare_with_oracle(apc, x, apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
+                         oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
+                         [("rel", 1e-3), ("rel", 1e-6), ("psnr", 80)])
 
 
 def test_fullsize_coarse_levels_match_oracle(field512):

@@ -1,0 +1,152 @@
+"""Pins of the oracle's interpreter and tuner against hand-worked examples
+(tests/golden/*.json, each with its derivation and citation): the greedy
+retrieval order and its bounds (Section V-C, Algorithm 2), the max ordering
+of level-0 regions (Section V-C), the tuning vote and its tie-breaks, and the
+positions of the ~1% sample blocks (Section VI-A).  The expected values were
+worked out by hand from the rules stated in the paper and the readings, not
+by running the oracle, so a flipped tie-break, a staircase that advances one
+region per segment, or a shifted sample would fail here."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bitplane, pipeline
+from oracle.plan import BelowFloor, Unit, build_staircase, greedy_sequence, make_plan
+from oracle.scheme import Scheme
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+def _meta(d):
+    return bitplane.StreamMeta(n=d["n"], B=d["B"], maxabs=d["maxabs"], nsig=list(d["nsig"]))
+
+
+def _toy_ref(g):
+    """A refactored-field object holding only what the interpreter reads."""
+    ref = pipeline.Refactored(shape=(64,), dtype=np.dtype(np.float32), scheme=Scheme(), L=1, P=29, xmin=0.0,
+                              xmax=1.0, A=1.0, sigma=(0,))
+    for i, u in enumerate(g["units"]):
+        grp = pipeline.Group(key=("toy", i), n=u["n"], M=0.0, E=0, delta=0.0, w=u["wd"], rho=u["wd"])
+        grp.wd_inf = u["wd"]
+        grp.wd_2 = u["wd"]
+        ref.groups.append(grp)
+        m = _meta(u)
+        ref.streams.append(pipeline.Stream(key=("toy", i), group=i, meta=m, blob=b"", codes=np.zeros(0, np.int64)))
+        ref.units.append(Unit(group=i, kind="plane", stream=i, meta=m))
+        ref.group_units[i] = [i]
+        ref.group_order.append(i)
+    ref.eps_fp = g["eps_fp"]
+    ref.meta_bytes = g["meta_bytes"]
+    return ref
+
+
+def test_greedy_order_and_bounds_match_the_hand_worked_toy():
+    g = _gold("greedy_toy.json")
+    ref = _toy_ref(g)
+    E0, seq = greedy_sequence(ref, "inf")
+    assert E0 == g["E0"]
+    assert [u for u, _ in seq] == g["sequence"]
+    assert [E for _, E in seq] == g["bounds"]
+
+
+def test_greedy_plans_match_the_hand_worked_toy():
+    g = _gold("greedy_toy.json")
+    ref = _toy_ref(g)
+    for p in g["plans"]:
+        pl = make_plan(ref, p["tau"], "inf")
+        assert pl.planes == p["planes"]
+        assert pl.nsteps == p["nsteps"]
+        assert pl.bound == p["bound"]
+        assert pl.bytes == p["bytes"]
+    with pytest.raises(BelowFloor):
+        make_plan(ref, g["below_floor_tau"], "inf")
+
+
+def test_greedy_tie_goes_to_the_lower_unit():
+    """Swapping the two tied units' order in the table flips which goes first
+    at the tie (step 2 of the toy), so the rule, not the data, decides it."""
+    g = _gold("greedy_toy.json")
+    g2 = dict(g)
+    g2["units"] = [g["units"][1], g["units"][0], g["units"][2]]
+    ref = _toy_ref(g2)
+    _, seq = greedy_sequence(ref, "inf")
+    # by hand: step 1 unit 1 (the old unit 0, 1*2/20 = 0.1); step 2 a tie at
+    # 0.05 between unit 0 (0.5*2/20) and unit 1 (1*1/20): the lower index,
+    # unit 0, now goes first; step 3 unit 0 (0.5*2/12); step 4 unit 1 (0.05 >
+    # 0.025); step 5 unit 0 (0.025 > 0.0125); then unit 2 twice
+    assert [u for u, _ in seq] == [1, 0, 0, 1, 0, 2, 2]
+
+
+def test_staircase_matches_the_hand_worked_toy():
+    g = _gold("staircase_toy.json")
+    metas, trips = [], []
+    for r, region in enumerate(g["regions"]):
+        trips.append([3 * r + t for t in range(3)])
+        metas.extend(_meta(d) for d in region)
+    u = build_staircase(7, trips, metas)
+    assert u.kind == "stair" and u.group == 7
+    assert u.levels == g["levels"]
+    assert u.seg_bytes == g["seg_bytes"]
+    assert [[list(st) for st in seg] for seg in u.seg_steps] == g["seg_steps"]
+
+
+def test_vote_tables_and_tie_breaks(monkeypatch):
+    g = _gold("vote_toy.json")
+    tols = list(pipeline.TUNING_TOLERANCES)
+    for table, winner in ((g["table1"], g["table1_winner"]), (g["table2"], g["table2_winner"])):
+        monkeypatch.setattr(pipeline, "_sample_bytes", lambda blocks, c, tol, rng, mode, t=table: t[c][tols.index(tol)])
+        cands = ["A", "B", "C"]
+        assert cands[pipeline._vote([], cands, 1.0, "eb")] == winner
+
+
+def test_select_pipeline_two_stages(monkeypatch):
+    """Stage 1 votes among the interpolation candidates with decomposition
+    off, stage 2 among that winner with decomposition none / axis 0..d-1."""
+    seen = []
+
+    def sizes(blocks, c, tol, rng, mode):
+        seen.append(c)
+        if c.cd_axis is None:
+            return 10 if (c.kind == "region" and c.order == (1, 2, 0)) else 20
+        return 5 if c.cd_axis == 2 else 30
+
+    monkeypatch.setattr(pipeline, "_sample_bytes", sizes)
+    x = np.zeros((16, 16, 16), np.float32)
+    best = pipeline.select_pipeline(x, "eb")
+    assert best == Scheme(kind="region", order=(1, 2, 0), cd_axis=2)
+    stage1 = [c for c in seen if c.cd_axis is None and c.kind == "level"]
+    assert stage1, "per-level is a candidate in error-bound mode"
+    seen.clear()
+    best = pipeline.select_pipeline(x, "psnr")
+    assert best == Scheme(kind="region", order=(1, 2, 0), cd_axis=2)
+    assert all(c.kind == "region" for c in seen), "PSNR mode has no per-level candidate"
+    # 6 per-region orders, then 4 decomposition options, at 9 tolerances each
+    assert len(seen) == 9 * (6 + 4)
+
+
+@pytest.mark.parametrize("case", _gold("sample_blocks.json")["cases"], ids=lambda c: "x".join(map(str, c["shape"])))
+def test_sample_block_positions(case):
+    shape = tuple(case["shape"])
+    d = len(shape)
+    starts = set()
+    blocks = []
+    # one coordinate array per axis (broadcast views: no full-size copy)
+    for a in range(d):
+        idx = np.arange(shape[a], dtype=np.int64).reshape([-1 if b == a else 1 for b in range(d)])
+        blocks.append(pipeline.sample_blocks(np.broadcast_to(idx, shape)))
+    assert len(blocks[0]) == case["count"]
+    for parts in zip(*blocks):
+        assert all(p.shape == tuple(case["block"]) for p in parts)
+        starts.add(tuple(int(p.flat[0]) for p in parts))
+    want = set()
+    import itertools
+    for s in itertools.product(*case["starts"]):
+        want.add(tuple(s))
+    assert starts == want
