@@ -122,6 +122,27 @@ apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev,
  * clamped to the stream's plane count). */
 apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream);
 
+/* Retrieval that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same plan and same output bytes as apc_retrieve with
+ * the same target, but every plane of the plan is decoded from zero (the
+ * handle's resident planes are neither used nor updated, so
+ * info.bytes_fetched counts every plane of the plan), and every device
+ * buffer the retrieval needs (decoded codes, float64 coarse grids, the
+ * recomposition buffer, launch tables) is carved from one static device
+ * array of 256 MiB per device, held from module load until the process
+ * ends.  The call issues no hipMalloc, hipFree or other allocating routine;
+ * its launch tables are copied from pageable host memory with
+ * hipMemcpyAsync on hip_stream, and all work runs on hip_stream (no helper
+ * stream).  The array keeps the last call's contents; nothing in it needs
+ * to start at zero.  All calls on one device share the array: calls queued
+ * on one stream are ordered, calls that overlap on different streams race.
+ * Errors: APC_E_INVALID if the field's buffers exceed the array (float32
+ * fields need about 13 bytes per point with a decomposition, so 256^3 fits
+ * and 320^3 does not), APC_E_BELOW_FLOOR as apc_retrieve. */
+apc_status apc_retrieve_static(apc_handle* h, const apc_target* target, void* out_dev, apc_retrieve_info* info,
+                               void* hip_stream);
+
 /* Retrieval ladder as one HIP graph: the plans of targets[0..n) are made
  * now, their decode / recompose / reconstruct launches are captured once,
  * and apc_ladder_launch replays them on any stream, writing step i to

@@ -43,6 +43,7 @@ EXPORTED = [
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
     "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width", "apc_profile_only",
+    "apc_retrieve_static",
 ]
 
 
@@ -68,6 +69,7 @@ _lib.apc_refactor.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, ctypes.POIN
 _lib.apc_plan.argtypes = [_vp, ctypes.POINTER(_Target), ctypes.POINTER(_i32), ctypes.POINTER(_Info)]
 _lib.apc_retrieve.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
 _lib.apc_retrieve_planes.argtypes = [_vp, ctypes.POINTER(_i32), _vp, _vp]
+_lib.apc_retrieve_static.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
 _lib.apc_select_pipeline.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, ctypes.POINTER(_Scheme), _vp]
 _lib.apc_free.argtypes = [_vp]
 _lib.apc_free.restype = None
@@ -110,7 +112,7 @@ for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes",
               "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
               "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
-              "apc_profile_only"):
+              "apc_profile_only", "apc_retrieve_static"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -226,6 +228,19 @@ class Handle:
         inf = _Info()
         _check(_lib.apc_retrieve(self._h, ctypes.byref(target._c()), ctypes.c_void_p(out.data_ptr()),
                                  ctypes.byref(inf), _stream_ptr(stream)))
+        return out, _info_dict(inf)
+
+    def retrieve_static(self, target: Target, out=None, stream=None):
+        """apc_retrieve_static: the same output as retrieve(), decoded from no
+        resident planes into the library's static device scratch (no device
+        allocation by the library)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        assert out.is_contiguous() and out.dtype == self.dtype and tuple(out.shape) == self.shape
+        inf = _Info()
+        _check(_lib.apc_retrieve_static(self._h, ctypes.byref(target._c()), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.byref(inf), _stream_ptr(stream)))
         return out, _info_dict(inf)
 
     def retrieve_planes(self, planes: Sequence[int], out=None, stream=None):

@@ -1502,6 +1502,10 @@ struct WorkPtrs {
   double* xb[2] = {nullptr, nullptr};
   double* pr[2] = {nullptr, nullptr};
   void* cdreg = nullptr;
+  // decoded codes (region codes, decomposition codes); null = the handle's
+  // resident buffers
+  void* codes = nullptr;
+  void* cd_codes = nullptr;
 };
 
 // Bytes of work buffers a retrieval of this handle needs (layout of carve_work).
@@ -1602,6 +1606,8 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   const bool per_level = h->scheme.kind == APC_PER_LEVEL;
   const bool split_on = split && with_decode && with_recon && per_level && !h->cd.empty() && L >= 3;
   const size_t base = ls.size();
+  Q* const codes = w.codes ? (Q*)w.codes : h->codes.as<Q>();
+  Q* const cd_codes = w.cd_codes ? (Q*)w.cd_codes : h->cd_codes.as<Q>();
   // decode launches by (level 0 or not) x (first decode adding at most 16
   // planes, which the windowed kernel takes, or any other)
   std::vector<StreamDev> sdv[4];
@@ -1615,7 +1621,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     const bool win = kres[s] == 0 && planes[s] <= 16;
     const int cat = (fine ? 2 : 0) + (win ? 1 : 0);
     StreamDev sd{};
-    sd.codes = (S.use_cd ? h->cd_codes.as<Q>() : h->codes.as<Q>()) + S.code_off;
+    sd.codes = (S.use_cd ? cd_codes : codes) + S.code_off;
     sd.mag = h->mag.as<uint64_t>() + S.mag_off;
     sd.idx = h->idx.as<uint32_t>() + S.idx_off;
     sd.sign = h->sign.as<uint64_t>() + S.sign_off;
@@ -1661,7 +1667,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       c.f1 = make_fastdiv((uint32_t)std::max(1, c.c[1]));
       c.Rout = (Q*)w.cdreg + ci.reg_off;
       for (int t = 0; t < 3; ++t) {
-        c.S[t] = h->cd_codes.as<Q>() + ci.s_off[t];
+        c.S[t] = cd_codes + ci.s_off[t];
         c.B[t] = m.streams[ci.s_idx[t]].B;
         c.k[t] = planes[ci.s_idx[t]];
       }
@@ -1687,7 +1693,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   {
     const Stream& s0 = m.streams[0];
     FlatSeg c{};
-    c.src = h->codes.as<Q>();
+    c.src = codes;
     c.dst = L == 1 ? (void*)out : (void*)w.xc;
     c.n = s0.n;
     c.B = s0.B;
@@ -1717,7 +1723,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
           c.B[rho] = 64;
           c.k[rho] = 64;
         } else {
-          c.q[rho] = h->codes.as<Q>() + h->region_off[l * 3 + rho];
+          c.q[rho] = codes + h->region_off[l * 3 + rho];
           c.B[rho] = m.streams[s].B;
           c.k[rho] = planes[s];
         }
@@ -1766,7 +1772,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       } else {
         const int s = stream_of(m, l, rho);
         const Stream& S = m.streams[s];
-        r.q = h->codes.as<Q>() + h->region_off[l * 3 + rho];
+        r.q = codes + h->region_off[l * 3 + rho];
         r.B = S.B;
         r.k = planes[s];
         r.delta = m.groups[S.group].delta;
@@ -1999,6 +2005,73 @@ apc_status refactor_many(const void* const* fields, int32_t dtype, const int64_t
   return refactor_batch<double, int64_t>(hs, xs, st);
 }
 
+// ------------------------------------------------ retrieval without allocation
+// Every device buffer of apc_retrieve_static (decoded codes, the float64
+// coarse grids, the recomposition buffer, the launch tables) is carved from
+// this array, which each device holds from module load until the process
+// ends.  Host code never passes the array's name to the device: its address
+// on the current device is looked up once per device (static_scratch) and
+// kept.
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+apc_status static_scratch(char** base) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(APC_E_INVALID, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(APC_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *base = g_scratch_ptr[dev];
+  return APC_OK;
+}
+
+// One retrieval from no resident planes with every buffer in the static
+// scratch: [region codes | decomposition codes | work grids | tables].
+template <typename T, typename Q>
+apc_status retrieve_static_impl(apc_handle* h, const std::vector<int>& planes, T* out, hipStream_t st,
+                                int64_t* fetched) {
+  char* base = nullptr;
+  APC_TRY(static_scratch(&base));
+  auto up = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  size_t off = 0;
+  const size_t o_codes = off;
+  off += up(sizeof(Q) * (size_t)std::max<int64_t>(1, h->code_n));
+  const size_t o_cd = off;
+  off += up(sizeof(Q) * (size_t)std::max<int64_t>(1, h->cd_n));
+  const size_t o_work = off;
+  off += up(work_bytes(h));
+  if (off > kStaticScratchBytes)
+    return fail(APC_E_INVALID, "field needs %zu bytes of retrieval buffers; the static scratch holds %zu", off,
+                kStaticScratchBytes);
+  WorkPtrs w = carve_work(h, base + o_work);
+  w.codes = base + o_codes;
+  w.cd_codes = base + o_cd;
+  TableBuilder tb;
+  std::vector<Launch> ls;
+  std::vector<int> kres(h->meta.streams.size(), 0);  // every plane of the plan is decoded from zero
+  build_retrieve<T, Q>(h, planes, out, kres, tb, ls, fetched, w, true, true, false);
+  const size_t o_tab = off;
+  off += up(tb.bytes.size());
+  if (off > kStaticScratchBytes)
+    return fail(APC_E_INVALID, "field needs %zu bytes of retrieval buffers; the static scratch holds %zu", off,
+                kStaticScratchBytes);
+  if (h->ready) HIP_TRY(hipStreamWaitEvent(st, h->ready, 0));  // the refactor's last kernels
+  // from pageable memory: the runtime has consumed the source when the call returns
+  if (!tb.bytes.empty())
+    HIP_TRY(hipMemcpyAsync(base + o_tab, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, st));
+  APC_TRY((issue<T, Q>(ls, base + o_tab, st)));
+  return APC_OK;
+}
+
 }  // namespace
 
 // Retrieval ladder captured as one HIP graph (a sequence of targets, each
@@ -2084,6 +2157,23 @@ apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_d
   std::vector<int> p(h->meta.streams.size());
   for (size_t s = 0; s < p.size(); ++s) p[s] = std::max(0, std::min<int>(planes[s], h->meta.streams[s].B));
   return do_retrieve(h, p, out_dev, hip_stream, nullptr);
+}
+
+apc_status apc_retrieve_static(apc_handle* h, const apc_target* target, void* out_dev, apc_retrieve_info* info,
+                               void* hip_stream) {
+  if (!h || !target || !out_dev) return fail(APC_E_INVALID, "null argument");
+  std::vector<int> planes;
+  apc_retrieve_info inf{};
+  APC_TRY(plan_for(h, target, planes, &inf));
+  int64_t fetched = 0;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (h->dtype == APC_F32)
+    APC_TRY((retrieve_static_impl<float, int32_t>(h, planes, (float*)out_dev, st, &fetched)));
+  else
+    APC_TRY((retrieve_static_impl<double, int64_t>(h, planes, (double*)out_dev, st, &fetched)));
+  inf.bytes_fetched = fetched;
+  if (info) *info = inf;
+  return APC_OK;
 }
 
 apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n, void* const* outs_dev,
