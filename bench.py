@@ -191,8 +191,33 @@ def _pct(v, q):
     return v[i]
 
 
+def log(msg: str) -> None:
+    """Progress of the long legs, on stderr (stdout carries the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """Model name of the host CPU, the logical CPUs it has and the ones this
+    process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "allowed_cpus": allowed}
+
+
 def cpu_baseline(x_full, rel: float, side: int = 320):
-    """The CPU oracle on a bounded sample of the same field: a side^3 block."""
+    """The CPU oracle on a bounded sample of the same field: a side^3 block.
+    The oracle is NumPy elementwise work and runs on one thread."""
     import numpy as np
 
     import oracle
@@ -213,26 +238,28 @@ def cpu_baseline(x_full, rel: float, side: int = 320):
         "cores": 1,
         "kind": "oracle",
         "sample": f"{side}^3 corner block of the same field, refactor + retrieve at rel 1e-4, single-threaded NumPy",
+        "host": host_cpu(),
         "refactor_s": t1 - t0,
         "retrieve_s": t2 - t1,
     }
 
 
-def batch_leg(apc, torch, fieldgen, full: bool):
-    """Uneven fields refactored in one batched call vs one call per field."""
+def batch_leg(apc, torch, fieldgen, quick: bool):
+    """Uneven fields refactored in one batched call vs one call per field:
+    32 fields 1800x3600 (zonal bands + k^-3), 32 of 100x500x500 and 32 cubes
+    of side 64..384 (k^-5/3), seed 2; drawn on the device."""
     import numpy as np
 
     rng = np.random.default_rng(2)
-    n2, n3, nc = (32, 32, 32) if full else (4, 4, 8)
-    fields = []
+    n2, n3, nc = (4, 4, 8) if quick else (32, 32, 32)
+    xs = []
     for i in range(n2):
-        fields.append(fieldgen.zonal_bands((1800, 3600), seed=1000 + i))
+        xs.append(fieldgen.zonal_bands_torch((1800, 3600), seed=1000 + i))
     for i in range(n3):
-        fields.append(fieldgen.power_law_field((100, 500, 500), seed=2000 + i))
+        xs.append(fieldgen.power_law_field_torch((100, 500, 500), seed=2000 + i))
     for i in range(nc):
         m = int(rng.integers(64, 385))
-        fields.append(fieldgen.power_law_field((m, m, m), seed=3000 + i))
-    xs = [torch.from_numpy(f).cuda() for f in fields]
+        xs.append(fieldgen.power_law_field_torch((m, m, m), seed=3000 + i))
     schemes = [apc.Scheme(kind="level", cd_axis=0) for _ in xs]
     nbytes = sum(x.numel() * x.element_size() for x in xs)
     torch.cuda.synchronize()
@@ -257,34 +284,47 @@ def batch_leg(apc, torch, fieldgen, full: bool):
         _, hs = fn()
         for h in hs:
             h.close()
-    tp, hp = per_field()
-    tb, hb = batched()
-    same = all(a.metadata() == b.metadata() for a, b in zip(hp, hb))
-    same = same and all(hp[i].stream_blob(s) == hb[i].stream_blob(s)
-                        for i in (0, len(hp) - 1) for s in range(hp[i].num_streams))
-    for h in hp + hb:
-        h.close()
-    return {"fields": len(xs), "GB": nbytes / 1e9, "per_field_s": tp, "batched_s": tb,
+    tp, tb = [], []
+    same = True
+    for rep in range(3):
+        t, hp = per_field()
+        tp.append(t)
+        t, hb = batched()
+        tb.append(t)
+        if rep == 0:
+            same = all(a.metadata() == b.metadata() for a, b in zip(hp, hb))
+            same = same and all(hp[i].stream_blob(s) == hb[i].stream_blob(s)
+                                for i in (0, n2, len(hp) - 1) for s in range(hp[i].num_streams))
+            stream_bytes = sum(h.stream_info(s)["blob_bytes"] for h in hb for s in range(h.num_streams))
+        for h in hp + hb:
+            h.close()
+    tp, tb = sorted(tp)[1], sorted(tb)[1]
+    del xs
+    torch.cuda.empty_cache()
+    return {"fields": n2 + n3 + nc, "GB": nbytes / 1e9, "per_field_s": tp, "batched_s": tb,
             "per_field_GBps": nbytes / tp / 1e9, "batched_GBps": nbytes / tb / 1e9, "speedup": tp / tb,
+            "batched_hbm_frac": (nbytes + stream_bytes) / tb / HBM_PEAK,
             "identical_output": bool(same), "tuned_tiles": tiles,
             "workload": f"{n2} x 1800x3600 zonal bands + k^-3, {n3} x 100x500x500 and {nc} cubes 64..384 "
-                        "k^-5/3, seed 2; per-level cubic + decomposition axis 0"}
+                        "k^-5/3 (seed 2, drawn on the device); per-level cubic + decomposition axis 0; "
+                        "median of 3"}
 
 
-def serve_leg(apc, torch, fieldgen, full: bool):
+def serve_leg(apc, torch, fieldgen, quick: bool):
     """Poisson request stream over resident fields: continuous batching vs
     one request at a time."""
     import numpy as np
 
-    side = 256 if full else 128
-    xs = [torch.from_numpy(fieldgen.power_law_field((side,) * 3, seed=3 + i)).cuda() for i in range(16)]
+    side = 128 if quick else 256
+    xs = [fieldgen.power_law_field_torch((side,) * 3, seed=3 + i) for i in range(16)]
     schemes = [apc.Scheme(kind="level", cd_axis=0) for _ in xs]
-    rates = (100, 200, 500, 1000, 2000, 5000) if full else (500, 2000)
-    nreq = 2000 if full else 300
+    rates = (500, 2000) if quick else (100, 200, 500, 1000, 2000, 5000)
+    nreq = 300 if quick else 2000
     eb = (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
     psnr = (40, 50, 60, 70, 80, 90, 100)
-    out = {"workload": f"16 resident {side}^3 float32 k^-5/3 fields (seeds 3-18), Poisson arrivals, "
-                       "targets uniform over eb 1e-2..1e-6 and PSNR 40..100 dB, incremental planes",
+    out = {"workload": f"16 resident {side}^3 float32 k^-5/3 fields (seeds 3-18, drawn on the device), Poisson "
+                       f"arrivals, {nreq} requests per rate, targets uniform over eb 1e-2..1e-6 and PSNR 40..100 dB, "
+                       "incremental planes, 4 GiB work budget",
            "rates": {}}
     for ri, rate in enumerate(rates):
         res = {}
@@ -319,7 +359,188 @@ def serve_leg(apc, torch, fieldgen, full: bool):
             res[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
                          "req_per_s": nreq / wall, "max_concurrent": st["max_running"]}
         out["rates"][str(rate)] = res
+        log(f"serve: {rate} req/s done")
     return out
+
+
+def _time_pipeline(apc, torch, xd, scheme, targets, reps: int = 5):
+    """Median refactor time (up to the end of its last kernel) and, per
+    target, the median time of the first retrieval from a fresh handle."""
+    nbytes = xd.numel() * xd.element_size()
+    xf = xd.double()
+    rng = float(xf.max() - xf.min())
+    out = torch.empty_like(xd)
+    tr, tt = [], {t: [] for t in targets}
+    infos = {}
+    for rep in range(reps + 1):
+        for t in targets:
+            t0 = time.perf_counter()
+            h = apc.refactor(xd, scheme)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = h.retrieve(t, out=out)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep:  # the first pass warms up
+                tr.append(t1 - t0)
+                tt[t].append(t2 - t1)
+            else:
+                infos[t] = info
+                err = (out.double() - xf).abs()
+                if t.kind == "rel":
+                    infos[t]["max_error"] = float(err.max())
+                    assert infos[t]["max_error"] <= t.value * rng, "retrieval violated its error bound"
+                else:
+                    mse = float((err ** 2).mean())
+                    infos[t]["psnr_db"] = math.inf if mse == 0 else 20 * math.log10(rng / math.sqrt(mse))
+                    assert infos[t]["psnr_db"] >= t.value, "retrieval missed its PSNR target"
+                streams = sum(h.stream_info(s)["blob_bytes"] for s in range(h.num_streams))
+            h.close()
+    t_ref = sorted(tr)[len(tr) // 2]
+    res = {"refactor_ms": t_ref * 1e3, "refactor_GBps": nbytes / t_ref / 1e9,
+           "refactor_hbm_frac": (nbytes + streams) / t_ref / HBM_PEAK, "stream_bytes": streams, "retrieve": {}}
+    for t in targets:
+        tm = sorted(tt[t])[len(tt[t]) // 2]
+        inf = infos[t]
+        r = {"ms": tm * 1e3, "GBps": nbytes / tm / 1e9, "hbm_frac": (inf["bytes_total"] + nbytes) / tm / HBM_PEAK,
+             "plan_bytes": inf["bytes_total"], "bitrate": inf["bitrate"]}
+        for k in ("max_error", "psnr_db"):
+            if k in inf:
+                r[k] = inf[k]
+        res["retrieve"][f"{t.kind} {t.value:g}"] = r
+    return res
+
+
+def region_and_f64_legs(apc, torch, x512):
+    """The per-region (PSNR-mode) pipeline on the 512^3 float32 field, and
+    the float64 256^3 copy x[::2, ::2, ::2] with the benchmark's scheme."""
+    import numpy as np
+
+    xd = torch.from_numpy(x512).cuda()
+    reg = _time_pipeline(apc, torch, xd, apc.Scheme(kind="region", order=(2, 1, 0)),
+                         [apc.Target("psnr", 80), apc.Target("rel", 1e-4)])
+    reg["workload"] = ("512^3 float32 k^-5/3 (seed 1); per-region cubic, pass order axis 2, 1, 0, no decomposition "
+                       "(the PSNR-mode scheme family); first retrieval from a fresh handle")
+    x64 = torch.from_numpy(np.ascontiguousarray(x512[::2, ::2, ::2]).astype(np.float64)).cuda()
+    f64 = _time_pipeline(apc, torch, x64, apc.Scheme(kind="level", cd_axis=0),
+                         [apc.Target("rel", 1e-4), apc.Target("psnr", 100)])
+    f64["workload"] = "float64 256^3 copy x[::2,::2,::2] of the 512^3 field; per-level cubic + decomposition axis 0"
+    del xd, x64
+    torch.cuda.empty_cache()
+    return reg, f64
+
+
+def scale_leg(apc, torch, fieldgen, quick: bool):
+    """1024^3 float32 k^-5/3 field with ~1% sharp-front spheres (seed 4):
+    target-driven selection in both modes, refactor with the error-bound
+    choice, the 7-step relative-eb ladder 1e-1..1e-7 as one graph ladder, and
+    a batch of mixed eb / PSNR requests through the server."""
+    import numpy as np
+
+    n = 256 if quick else 1024
+    x = fieldgen.sharp_fronts_torch((n,) * 3, seed=4)
+    torch.cuda.synchronize()
+    nbytes = x.numel() * 4
+    xf_min, xf_max = float(x.min()), float(x.max())
+    rng = xf_max - xf_min
+    res = {"workload": f"{n}^3 float32 k^-5/3 + 1% sharp-front spheres (tanh, width 2 cells), seed 4, drawn on the "
+                       "device"}
+    sel = {}
+    for mode in ("eb", "psnr"):
+        apc.select_pipeline(x, mode)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc = apc.select_pipeline(x, mode)
+        torch.cuda.synchronize()
+        sel[mode] = {"ms": (time.perf_counter() - t0) * 1e3, "scheme": {"kind": sc.kind, "order": sc.order,
+                                                                        "cd_axis": sc.cd_axis}}
+        if mode == "eb":
+            sc_eb = sc
+    res["select_pipeline"] = sel
+    apc.tune_tiles(x)
+    tr = []
+    for rep in range(4):
+        t0 = time.perf_counter()
+        h = apc.refactor(x, sc_eb)
+        torch.cuda.synchronize()
+        if rep:
+            tr.append(time.perf_counter() - t0)
+        if rep < 3:
+            h.close()
+    t_ref = sorted(tr)[len(tr) // 2]
+    streams = sum(h.stream_info(s)["blob_bytes"] for s in range(h.num_streams))
+    res["refactor"] = {"ms": t_ref * 1e3, "GBps": nbytes / t_ref / 1e9,
+                       "hbm_frac": (nbytes + streams) / t_ref / HBM_PEAK, "stream_bytes": streams}
+    # the ladder: every relative bound of 1e-1..1e-7 that the representation reaches
+    targets, skipped = [], []
+    for k in range(1, 8):
+        t = apc.Target("rel", 10.0 ** -k)
+        try:
+            h.plan(t)
+            targets.append(t)
+        except apc.BelowFloor:
+            skipped.append(t.value)
+    outs = [torch.empty_like(x) for _ in targets]
+    t0 = time.perf_counter()
+    lad = apc.Ladder(h, targets, outs)
+    t_create = time.perf_counter() - t0
+    lad.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lad.launch()
+    torch.cuda.synchronize()
+    t_lad = time.perf_counter() - t0
+    steps = []
+    for t, o in zip(targets, outs):
+        _, info = h.plan(t)
+        err = float((o.double() - x.double()).abs().max())
+        assert err <= t.value * rng, "ladder step violated its error bound"
+        steps.append({"rel": t.value, "max_error": err, "tau": t.value * rng, "plan_bytes": info["bytes_total"],
+                      "bitrate": info["bitrate"]})
+    lad.close()
+    del outs
+    torch.cuda.empty_cache()
+    res["ladder"] = {"graph_create_ms": t_create * 1e3, "replay_ms": t_lad * 1e3,
+                     "replay_GBps_out": len(targets) * nbytes / t_lad / 1e9, "steps": steps,
+                     "below_floor": skipped}
+    # a batch of mixed requests submitted together to the server
+    reqs = [apc.Target("rel", 1e-2), apc.Target("psnr", 60), apc.Target("rel", 1e-4), apc.Target("psnr", 80),
+            apc.Target("rel", 1e-3), apc.Target("psnr", 100), apc.Target("rel", 1e-5), apc.Target("psnr", 40)]
+    outs = [torch.empty_like(x) for _ in reqs]
+    h2 = apc.refactor(x, sc_eb)  # nothing resident yet
+    torch.cuda.synchronize()
+    srv = apc.Server([h2], budget_bytes=96 << 30, max_slots=4)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(0, t, o) for t, o in zip(reqs, outs)]
+    infos = [srv.wait(tk) for tk in tickets]
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    h2.close()
+    checks = []
+    xd = x.double()
+    for t, o, inf in zip(reqs, outs, infos):
+        err = (o.double() - xd).abs()
+        if t.kind == "rel":
+            e = float(err.max())
+            assert e <= t.value * rng
+            checks.append({"target": f"rel {t.value:g}", "max_error": e, "plan_bytes": inf["bytes_total"]})
+        else:
+            mse = float((err ** 2).mean())
+            p = math.inf if mse == 0 else 20 * math.log10(rng / math.sqrt(mse))
+            assert p >= t.value
+            checks.append({"target": f"psnr {t.value:g}", "psnr_db": p, "plan_bytes": inf["bytes_total"]})
+    # the same request alone gives the same bytes
+    alone, _ = h.retrieve(reqs[2])
+    same = bool(torch.equal(alone.view(torch.int32), outs[2].view(torch.int32)))
+    res["mixed_batch"] = {"requests": len(reqs), "wall_ms": t_batch * 1e3, "p50_ms": st["p50_ms"],
+                          "p99_ms": st["p99_ms"], "max_concurrent": st["max_running"], "results": checks,
+                          "equal_to_alone": same}
+    h.close()
+    del outs, x, xd
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -331,7 +552,8 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true", help="skip the batching and serving legs")
-    ap.add_argument("--full", action="store_true", help="full-size batching and serving workloads")
+    ap.add_argument("--quick", action="store_true",
+                    help="reduced systems legs (4+4+8 batched fields, 128^3 served fields, 256^3 scale field)")
     ap.add_argument("--tile", type=int, default=0, choices=(0, 32, 64, 128),
                     help="pin the sweep tile width instead of tuning it (profiling runs use this so that "
                          "every run launches the same kernels and no tuning launches mix in)")
@@ -370,6 +592,7 @@ def main():
     def step(with_sizes=False):
         t0 = time.perf_counter()
         h = apc.refactor(xd, scheme)
+        torch.cuda.synchronize()  # up to the refactor's last kernel (the call returns before it ends)
         t1 = time.perf_counter()
         _, info = h.retrieve(target, out=out)
         torch.cuda.synchronize()
@@ -462,15 +685,22 @@ def main():
                                       "unit": "GB/s", "ms_per_step": b["ms"] / 2}
     line["kernels_ms_per_step"] = {k: round(v["ms"] / 2, 4) for k, v in
                                    sorted(breakdown.items(), key=lambda kv: -kv[1]["ms"])}
+    log(f"main steps done: {line['ms_per_step']:.3f} ms per step")
     if not args.no_systems:
-        line["batch"] = batch_leg(apc, torch, fieldgen, args.full)
-        line["serve"] = serve_leg(apc, torch, fieldgen, args.full)
+        line["region_512"], line["f64_256"] = region_and_f64_legs(apc, torch, x)
+        log("per-region 512^3 and float64 256^3 legs done")
+        line["batch"] = batch_leg(apc, torch, fieldgen, args.quick)
+        log("batch leg done")
+        line["config5"] = scale_leg(apc, torch, fieldgen, args.quick)
+        log("scale leg done")
+        line["serve"] = serve_leg(apc, torch, fieldgen, args.quick)
         top = line["serve"]["rates"][max(line["serve"]["rates"], key=int)]["continuous"]
         line["retrieve_ms_p50"] = top["p50_ms"]
         line["retrieve_ms_p99"] = top["p99_ms"]
         line["retrieve_latency_source"] = "serving leg, highest arrival rate, continuous batching"
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, args.rel)
+        log("cpu baseline done")
     print(json.dumps(line))
 
 

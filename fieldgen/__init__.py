@@ -152,3 +152,88 @@ def config1_field() -> np.ndarray:
 def config2_field(n: int = 512, dtype=np.float32) -> np.ndarray:
     """n^3 k^-5/3 Gaussian random field, seed 1."""
     return power_law_field((n, n, n), alpha=5.0 / 3.0, seed=1, dtype=dtype)
+
+
+# --------------------------------------------------------------------------
+# Device-side variants of the same recipes (torch on the current GPU), for
+# benchmark workloads too large to draw on the host in reasonable time.  They
+# follow the recipes above step by step but draw from torch's generator and
+# use torch's FFT, so their values differ from the NumPy versions; nothing
+# compares them with the oracle.
+# --------------------------------------------------------------------------
+
+def power_law_field_torch(shape, alpha: float = 5.0 / 3.0, seed: int = 1, dtype=None, device="cuda"):
+    """``power_law_field`` drawn on the device (float64 math, cast once)."""
+    import torch
+
+    dtype = dtype or torch.float32
+    shape = tuple(int(s) for s in shape)
+    d = len(shape)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    w = torch.randn(shape, generator=g, dtype=torch.float64, device=device)
+    F = torch.fft.rfftn(w)
+    del w
+    expo = -(alpha + d - 1) / 2.0
+    k2 = None
+    for ax, n in enumerate(shape):
+        f = torch.fft.rfftfreq(n, dtype=torch.float64, device=device) if ax == d - 1 else \
+            torch.fft.fftfreq(n, dtype=torch.float64, device=device)
+        shp = [1] * d
+        shp[ax] = f.numel()
+        t = (f ** 2).reshape(shp)
+        k2 = t if k2 is None else k2 + t
+    for i0 in range(F.shape[0]):  # slab by slab along axis 0 (bounded memory)
+        kk = k2[i0] if d > 1 else k2[i0:i0 + 1]
+        amp = torch.where(kk > 0, kk.clamp_min(1e-300) ** (expo / 2.0), torch.zeros_like(kk))
+        F[i0] *= amp
+    v = torch.fft.irfftn(F, s=shape)
+    del F
+    v -= v.mean()
+    v /= v.std(unbiased=False)
+    return v.to(dtype)
+
+
+def zonal_bands_torch(shape=(1800, 3600), seed: int = 2, dtype=None, device="cuda"):
+    """``zonal_bands`` drawn on the device."""
+    import torch
+
+    dtype = dtype or torch.float32
+    rng = np.random.default_rng(seed)
+    n0, n1 = shape
+    i = torch.arange(n0, dtype=torch.float64, device=device)[:, None]
+    v = torch.zeros(shape, dtype=torch.float64, device=device)
+    for m in (2, 5, 9):
+        a = rng.uniform(0.5, 1.0)
+        phi = rng.uniform(0.0, 2 * np.pi)
+        v += a * torch.cos(2 * np.pi * m * i / n0 + phi)
+    sub_seed = int(rng.integers(0, 2**31 - 1))
+    v += 0.3 * power_law_field_torch(shape, alpha=3.0, seed=sub_seed, dtype=torch.float64, device=device)
+    return v.to(dtype)
+
+
+def sharp_fronts_torch(shape, seed: int = 4, frac: float = 0.01, radius: float = 32.0, dtype=None, device="cuda"):
+    """``sharp_fronts`` drawn on the device (sphere centres and normals from
+    the same NumPy draws as the host version)."""
+    import torch
+
+    dtype = dtype or torch.float32
+    base = power_law_field_torch(shape, seed=seed, dtype=torch.float64, device=device)
+    rng = np.random.default_rng(seed + 1000)
+    vol = float(np.prod(shape))
+    nsph = max(1, int(round(frac * vol / (4.0 / 3.0 * np.pi * radius ** 3))))
+    sd = float(base.std(unbiased=False))
+    for _ in range(nsph):
+        c = rng.uniform(0.0, 1.0, size=3) * np.asarray(shape, dtype=np.float64)
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        lo = [max(0, int(c[a] - radius - 8)) for a in range(3)]
+        hi = [min(shape[a], int(c[a] + radius + 8) + 1) for a in range(3)]
+        z = torch.arange(lo[0], hi[0], dtype=torch.float64, device=device)[:, None, None]
+        y = torch.arange(lo[1], hi[1], dtype=torch.float64, device=device)[None, :, None]
+        x = torch.arange(lo[2], hi[2], dtype=torch.float64, device=device)[None, None, :]
+        rc = torch.sqrt((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2)
+        dp = (z - c[0]) * nrm[0] + (y - c[1]) * nrm[1] + (x - c[2]) * nrm[2]
+        bump = 2.0 * sd * torch.tanh(dp / 2.0) * 0.5 * (1.0 - torch.tanh((rc - radius) / 2.0))
+        base[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] += bump
+    return base.to(dtype)

@@ -236,6 +236,36 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
 /* Metadata as a JSON text (groups, streams, staircase, bounds). */
 apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_t* len);
 
+/* Shape and dtype of a handle's field: dims (3 int64, the first ndim set),
+ * ndim, dtype (APC_F32 / APC_F64); any output may be NULL. */
+apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int32_t* dtype);
+
+/* Serialization of the refactored representation (Section III-B: the data
+ * are refactored once and stored; retrievals happen later from what was
+ * stored).  The byte string holds the geometry and scheme, the metadata the
+ * interpreter needs (range, group maxima, per-stream plane counts and
+ * new-significant counts) and every stream's blob in the apc_stream_blob
+ * layout, each section with its length and a 64-bit checksum:
+ *   [0,8) magic "APCREP01"; [8,16) total length; [16,24) metadata length;
+ *   [24,32) metadata checksum; metadata (int32 dtype, ndim; int64 dims[3];
+ *   int32 kind, degree, order[3], cd_axis, levels, L, P, 0; float64 xmin,
+ *   xmax, A; uint32 group and stream counts; float64 M per group; per
+ *   stream int64 n, maxabs, int32 B, 0, int64 nsig[B]); then per stream
+ *   uint64 blob length, uint64 blob checksum, blob.  Little endian.
+ * apc_serialize: with host_dst NULL only *len is set (the size needed);
+ *   otherwise host_dst (caller owned, cap >= *len bytes) receives the
+ *   bytes.  Waits for the handle's refactor to finish.  APC_E_INVALID if
+ *   cap is too small.
+ * apc_deserialize: checks every field (magic, lengths, checksums, the
+ *   geometry and layout they imply, plane and index counts) and returns
+ *   APC_E_CORRUPT, with a message naming the first failed check, for
+ *   truncated, padded or altered bytes.  With out NULL it only checks (host
+ *   only, no device needed).  Otherwise *out is a new handle (release with
+ *   apc_free) whose streams are uploaded on hip_stream; the call returns
+ *   after the upload.  The handle retrieves exactly as the serialized one. */
+apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64_t* len);
+apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_handle** out);
+
 /* Host-only helper (no device needed): exact chain norms of the 1D
  * interpolation chain on an axis of length n for levels 0..L-1, rounded to
  * float64 (max row / column abs sums).  inf_out, one_out: L doubles. */

@@ -43,7 +43,7 @@ EXPORTED = [
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
     "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width", "apc_profile_only",
-    "apc_retrieve_static",
+    "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize",
 ]
 
 
@@ -70,6 +70,9 @@ _lib.apc_plan.argtypes = [_vp, ctypes.POINTER(_Target), ctypes.POINTER(_i32), ct
 _lib.apc_retrieve.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
 _lib.apc_retrieve_planes.argtypes = [_vp, ctypes.POINTER(_i32), _vp, _vp]
 _lib.apc_retrieve_static.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
+_lib.apc_field_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.apc_serialize.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_i64)]
+_lib.apc_deserialize.argtypes = [ctypes.c_char_p, _i64, _vp, ctypes.POINTER(_vp)]
 _lib.apc_select_pipeline.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, ctypes.POINTER(_Scheme), _vp]
 _lib.apc_free.argtypes = [_vp]
 _lib.apc_free.restype = None
@@ -112,7 +115,7 @@ for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes",
               "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
               "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
-              "apc_profile_only", "apc_retrieve_static"):
+              "apc_profile_only", "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -263,6 +266,14 @@ class Handle:
         _check(_lib.apc_stream_blob(self._h, s, buf, max(1, nb)))
         return buf.raw[:nb]
 
+    def serialize(self) -> bytes:
+        """The stored representation as bytes (apc_serialize)."""
+        ln = _i64()
+        _check(_lib.apc_serialize(self._h, None, 0, ctypes.byref(ln)))
+        buf = ctypes.create_string_buffer(max(1, ln.value))
+        _check(_lib.apc_serialize(self._h, buf, ln.value, ctypes.byref(ln)))
+        return buf.raw[:ln.value]
+
     def metadata(self) -> dict:
         ln = _i64()
         _check(_lib.apc_metadata_json(self._h, None, 0, ctypes.byref(ln)))
@@ -279,6 +290,24 @@ def refactor(field, scheme: Scheme = Scheme(), stream=None) -> Handle:
     _check(_lib.apc_refactor(ctypes.c_void_p(field.data_ptr()), _dtype_code(field), dims, field.dim(),
                              ctypes.byref(scheme._c(field.dim())), _stream_ptr(stream), ctypes.byref(out)))
     return Handle(out.value, tuple(field.shape), field.dtype)
+
+
+def check_serialized(data: bytes) -> None:
+    """Check serialized bytes without a device (raises ApcError, status
+    APC_E_CORRUPT, naming the first failed check)."""
+    _check(_lib.apc_deserialize(data, len(data), None, None))
+
+
+def deserialize(data: bytes, stream=None) -> Handle:
+    """A handle from apc_serialize bytes (streams uploaded on the stream)."""
+    import torch
+    out = ctypes.c_void_p()
+    _check(_lib.apc_deserialize(data, len(data), _stream_ptr(stream), ctypes.byref(out)))
+    dims = (ctypes.c_int64 * 3)()
+    nd, dt = _i32(), _i32()
+    _check(_lib.apc_field_info(out, dims, ctypes.byref(nd), ctypes.byref(dt)))
+    return Handle(out.value, tuple(dims[i] for i in range(nd.value)),
+                  torch.float32 if dt.value == APC_F32 else torch.float64)
 
 
 def refactor_batch(fields, schemes, stream=None) -> List[Handle]:

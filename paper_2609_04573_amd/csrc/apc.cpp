@@ -2,6 +2,8 @@
 // (Algorithm 2) on one gfx950 device.  Metadata (group maxima, plane
 // counts) is computed on the device and read back; planning is host-side.
 #include <math.h>
+
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -2074,6 +2076,253 @@ apc_status retrieve_static_impl(apc_handle* h, const std::vector<int>& planes, T
 
 }  // namespace
 
+// ------------------------------------------------------------ serialization
+// The stored representation as one byte string (all integers little endian):
+//   [0, 8)    magic "APCREP01"
+//   [8, 16)   total length in bytes
+//   [16, 24)  length of the metadata section
+//   [24, 32)  checksum of the metadata section
+//   metadata  dtype, ndim (int32); dims[3] (int64, unused ones 0); scheme:
+//             kind, degree, order[3] (the pass order; unused entries 0),
+//             cd_axis, levels (= L) (int32); L, P, 0 (int32); xmin, xmax, A
+//             (float64); group and stream counts (uint32); M per group
+//             (float64); per stream: n, max |code| (int64), B, 0 (int32),
+//             new-significant counts of its B planes (int64)
+//   streams   per stream in stream order: blob length, blob checksum
+//             (uint64), then the blob in the layout of apc_stream_blob
+// Every section is a multiple of 8 bytes long.
+namespace {
+
+constexpr char kRepMagic[8] = {'A', 'P', 'C', 'R', 'E', 'P', '0', '1'};
+
+// 64-bit checksum of a byte range: the length, then every little-endian
+// 64-bit word (the last one zero padded), each folded in by xor, a multiply
+// by an odd constant and an xor-shift.  It catches truncation and stray
+// changes; it is not a cryptographic hash.
+uint64_t rep_hash(const unsigned char* p, size_t n) {
+  uint64_t h = 0x6a09e667f3bcc909ull ^ (uint64_t)n;
+  auto mix = [&](uint64_t w) {
+    h ^= w;
+    h *= 0x9e3779b97f4a7c15ull;
+    h ^= h >> 32;
+  };
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    memcpy(&w, p + i, 8);
+    mix(w);
+  }
+  if (i < n) {
+    uint64_t w = 0;
+    memcpy(&w, p + i, n - i);
+    mix(w);
+  }
+  return h;
+}
+
+template <typename V>
+void put(std::vector<unsigned char>& b, V v) {
+  const size_t at = b.size();
+  b.resize(at + sizeof(V));
+  memcpy(b.data() + at, &v, sizeof(V));
+}
+
+void rep_meta(const apc_handle* h, std::vector<unsigned char>& b) {
+  const Geo& g = h->geo;
+  const Meta& m = h->meta;
+  put<int32_t>(b, h->dtype);
+  put<int32_t>(b, g.d);
+  for (int a = 0; a < 3; ++a) put<int64_t>(b, a < g.d ? g.N[3 - g.d + a] : 0);
+  put<int32_t>(b, h->scheme.kind);
+  put<int32_t>(b, h->scheme.degree);
+  for (int j = 0; j < 3; ++j) put<int32_t>(b, j < g.d ? g.sigma_user[j] : 0);
+  put<int32_t>(b, h->scheme.cd_axis);
+  put<int32_t>(b, g.L);
+  put<int32_t>(b, g.L);
+  put<int32_t>(b, m.P);
+  put<int32_t>(b, 0);
+  put<double>(b, m.xmin);
+  put<double>(b, m.xmax);
+  put<double>(b, m.A);
+  put<uint32_t>(b, (uint32_t)m.groups.size());
+  put<uint32_t>(b, (uint32_t)m.streams.size());
+  for (const Group& gr : m.groups) put<double>(b, gr.M);
+  for (const Stream& S : m.streams) {
+    put<int64_t>(b, S.n);
+    put<int64_t>(b, S.maxabs);
+    put<int32_t>(b, S.B);
+    put<int32_t>(b, 0);
+    for (int j = 0; j < S.B; ++j) put<int64_t>(b, S.nsig[j]);
+  }
+}
+
+struct RepReader {
+  const unsigned char* p;
+  size_t n, at = 0;
+  bool ok = true;
+  template <typename V>
+  V get() {
+    V v{};
+    if (!ok || n - at < sizeof(V)) {
+      ok = false;
+      return v;
+    }
+    memcpy(&v, p + at, sizeof(V));
+    at += sizeof(V);
+    return v;
+  }
+};
+
+#define REP_CHECK(cond, ...)                         \
+  do {                                               \
+    if (!(cond)) return fail(APC_E_CORRUPT, __VA_ARGS__); \
+  } while (0)
+
+// Check a serialized representation and rebuild the host side of its handle
+// (geometry, layout, metadata, the interpreter's sequence); blobs[s] points
+// at stream s's blob inside src.  No device work.
+apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_handle>& out,
+                     std::vector<const unsigned char*>& blobs) {
+  REP_CHECK(len >= 32, "%lld bytes: shorter than the header", (long long)len);
+  REP_CHECK(memcmp(src, kRepMagic, 8) == 0, "bad magic");
+  uint64_t tl, ml, mh;
+  memcpy(&tl, src + 8, 8);
+  memcpy(&ml, src + 16, 8);
+  memcpy(&mh, src + 24, 8);
+  REP_CHECK(tl == (uint64_t)len, "length field %llu, %lld bytes given (truncated or padded)",
+            (unsigned long long)tl, (long long)len);
+  REP_CHECK(ml <= (uint64_t)len - 32 && ml % 8 == 0, "metadata length %llu out of range", (unsigned long long)ml);
+  REP_CHECK(rep_hash(src + 32, (size_t)ml) == mh, "metadata checksum mismatch");
+  RepReader r{src + 32, (size_t)ml};
+  const int32_t dtype = r.get<int32_t>(), ndim = r.get<int32_t>();
+  int64_t dims[3];
+  for (int a = 0; a < 3; ++a) dims[a] = r.get<int64_t>();
+  apc_scheme sc{};
+  sc.kind = r.get<int32_t>();
+  sc.degree = r.get<int32_t>();
+  for (int j = 0; j < 3; ++j) sc.order[j] = r.get<int32_t>();
+  sc.cd_axis = r.get<int32_t>();
+  sc.levels = r.get<int32_t>();
+  const int32_t L = r.get<int32_t>(), P = r.get<int32_t>();
+  (void)r.get<int32_t>();
+  const double xmin = r.get<double>(), xmax = r.get<double>(), A = r.get<double>();
+  const uint32_t ng = r.get<uint32_t>(), ns = r.get<uint32_t>();
+  REP_CHECK(r.ok, "metadata truncated");
+  REP_CHECK(dtype == APC_F32 || dtype == APC_F64, "dtype %d", dtype);
+  REP_CHECK(P == (dtype == APC_F32 ? 29 : 52), "precision %d does not match the dtype", P);
+  std::unique_ptr<apc_handle> h(new apc_handle());
+  h->dtype = dtype;
+  if (setup_geometry(h.get(), dims, ndim, &sc) != APC_OK)
+    return fail(APC_E_CORRUPT, "geometry or scheme: %s", g_last_error.c_str());
+  REP_CHECK(h->geo.L == L, "level count %d, the geometry gives %d", L, h->geo.L);
+  build_layout(h.get(), P);
+  Meta& m = h->meta;
+  REP_CHECK(ng == m.groups.size() && ns == m.streams.size(), "%u groups / %u streams, the layout has %zu / %zu", ng,
+            ns, m.groups.size(), m.streams.size());
+  REP_CHECK(std::isfinite(xmin) && std::isfinite(xmax) && xmin <= xmax && A == std::max(fabs(xmin), fabs(xmax)),
+            "range fields inconsistent");
+  m.xmin = xmin;
+  m.xmax = xmax;
+  m.A = A;
+  for (Group& gr : m.groups) {
+    gr.M = r.get<double>();
+    REP_CHECK(r.ok && std::isfinite(gr.M) && gr.M >= 0.0, "group maximum out of range");
+    if (gr.M > 0.0) {
+      int E;
+      frexp(gr.M, &E);
+      gr.E = E;
+      gr.k_shift = P - E;
+      gr.delta = ldexp(1.0, E - P);
+    }
+  }
+  const int maxB = dtype == APC_F32 ? 31 : 62;
+  for (Stream& S : m.streams) {
+    const int64_t n = r.get<int64_t>(), mx = r.get<int64_t>();
+    const int32_t B = r.get<int32_t>();
+    (void)r.get<int32_t>();
+    REP_CHECK(r.ok, "metadata truncated");
+    REP_CHECK(n == S.n, "stream length %lld, the layout gives %lld", (long long)n, (long long)S.n);
+    REP_CHECK(mx >= 0 && B == bitlen(mx) && B <= maxB, "stream maximum / plane count inconsistent");
+    const Group& gr = m.groups[S.group];
+    if (!S.use_cd) {
+      const int64_t want = gr.M > 0.0 ? (int64_t)rint(ldexp(gr.M, gr.k_shift)) : 0;
+      REP_CHECK(S.n == 0 || mx == want, "stream maximum does not follow its group maximum");
+    } else {
+      REP_CHECK(gr.M > 0.0 || mx == 0, "decomposition stream of an all-zero group");
+    }
+    S.maxabs = mx;
+    S.B = B;
+    S.nsig.assign(B, 0);
+    int64_t tot = 0;
+    for (int j = 0; j < B; ++j) {
+      S.nsig[j] = r.get<int64_t>();
+      REP_CHECK(r.ok && S.nsig[j] >= 0 && S.nsig[j] <= S.n, "plane counts out of range");
+      tot += S.nsig[j];
+    }
+    REP_CHECK(tot <= S.n, "more new-significant codes than codes");
+    REP_CHECK(B == 0 || S.nsig[0] > 0, "the top plane holds no new-significant code");
+  }
+  REP_CHECK(r.at == r.n, "metadata section has %zu trailing bytes", r.n - r.at);
+  // stream blobs
+  size_t at = 32 + (size_t)ml;
+  blobs.assign(m.streams.size(), nullptr);
+  int64_t mag_w = 0, idx_n = 0, sign_w = 0, nplanes = 0;
+  h->psb.assign(m.streams.size(), 0);
+  for (int s = 0; s < (int)m.streams.size(); ++s) {
+    Stream& S = m.streams[s];
+    REP_CHECK((uint64_t)len - at >= 16, "stream %d header truncated", s);
+    uint64_t bl, bh;
+    memcpy(&bl, src + at, 8);
+    memcpy(&bh, src + at + 8, 8);
+    REP_CHECK(bl == (uint64_t)S.blob_bytes(), "stream %d: %llu blob bytes, its metadata gives %lld", s,
+              (unsigned long long)bl, (long long)S.blob_bytes());
+    REP_CHECK((uint64_t)len - at - 16 >= bl, "stream %d blob truncated", s);
+    const unsigned char* b = src + at + 16;
+    REP_CHECK(rep_hash(b, (size_t)bl) == bh, "stream %d checksum mismatch", s);
+    blobs[s] = b;
+    at += 16 + (size_t)bl;
+    S.mag_off = mag_w;
+    S.idx_off = idx_n;
+    S.sign_off = sign_w;
+    S.pso.assign(S.B, 0);
+    if (S.B == 0 || S.n == 0) continue;
+    // index entries: per plane, counts before each chunk, starting at zero,
+    // non-decreasing by at most a chunk, and within the plane's total
+    const int64_t C = S.chunks();
+    for (int j = 0; j < S.B; ++j) {
+      uint32_t prev = 0;
+      for (int64_t c = 0; c < C; ++c) {
+        uint32_t v;
+        memcpy(&v, b + 4 * ((int64_t)j * C + c), 4);
+        REP_CHECK((c == 0 ? v == 0 : (v >= prev && v - prev <= 4096)) && v <= (uint64_t)S.nsig[j],
+                  "stream %d plane %d: index entry %lld out of order", s, j, (long long)c);
+        prev = v;
+      }
+    }
+    int64_t w = 0;
+    for (int j = 0; j < S.B; ++j) {
+      S.pso[j] = w;
+      w += (S.nsig[j] + 63) / 64;
+    }
+    h->psb[s] = (int)nplanes;
+    mag_w += (int64_t)S.B * S.words();
+    idx_n += (int64_t)S.B * C;
+    sign_w += w;
+    nplanes += S.B;
+  }
+  REP_CHECK(at == (size_t)len, "%lld trailing bytes", (long long)(len - (int64_t)at));
+  assign_weights(h.get());
+  finalize_units(h.get());
+  h->k_res.assign(m.streams.size(), 0);
+  ensure_sequence(m, 0);
+  out = std::move(h);
+  return APC_OK;
+}
+
+#undef REP_CHECK
+
+}  // namespace
+
 // Retrieval ladder captured as one HIP graph (a sequence of targets, each
 // written to its own output).
 struct apc_ladder {
@@ -2290,6 +2539,91 @@ apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_
     if (cap < (int64_t)js.size() + 1) return fail(APC_E_INVALID, "buffer too small");
     memcpy(buf, js.c_str(), js.size() + 1);
   }
+  return APC_OK;
+}
+
+apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int32_t* dtype) {
+  if (!h) return fail(APC_E_INVALID, "null handle");
+  const Geo& g = h->geo;
+  if (ndim) *ndim = g.d;
+  if (dtype) *dtype = h->dtype;
+  if (dims)
+    for (int a = 0; a < g.d; ++a) dims[a] = g.N[3 - g.d + a];
+  return APC_OK;
+}
+
+apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64_t* len) {
+  if (!h || !len) return fail(APC_E_INVALID, "null argument");
+  std::vector<unsigned char> meta;
+  rep_meta(h, meta);
+  int64_t total = 32 + (int64_t)meta.size();
+  for (const Stream& S : h->meta.streams) total += 16 + S.blob_bytes();
+  *len = total;
+  if (!host_dst) return APC_OK;
+  if (cap < total) return fail(APC_E_INVALID, "buffer of %lld bytes, the representation needs %lld", (long long)cap,
+                               (long long)total);
+  if (h->ready) HIP_TRY(hipEventSynchronize(h->ready));  // the refactor's last kernels
+  unsigned char* d = (unsigned char*)host_dst;
+  memcpy(d, kRepMagic, 8);
+  const uint64_t tl = (uint64_t)total, ml = (uint64_t)meta.size(), mh = rep_hash(meta.data(), meta.size());
+  memcpy(d + 8, &tl, 8);
+  memcpy(d + 16, &ml, 8);
+  memcpy(d + 24, &mh, 8);
+  memcpy(d + 32, meta.data(), meta.size());
+  int64_t at = 32 + (int64_t)meta.size();
+  for (int s = 0; s < (int)h->meta.streams.size(); ++s) {
+    const Stream& S = h->meta.streams[s];
+    const uint64_t bl = (uint64_t)S.blob_bytes();
+    unsigned char* blob = d + at + 16;
+    if (bl) APC_TRY(apc_stream_blob(h, s, blob, (int64_t)bl));
+    const uint64_t bh = rep_hash(blob, (size_t)bl);
+    memcpy(d + at, &bl, 8);
+    memcpy(d + at + 8, &bh, 8);
+    at += 16 + (int64_t)bl;
+  }
+  return APC_OK;
+}
+
+apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_handle** out) {
+  if (!src || len < 0) return fail(APC_E_INVALID, "null argument");
+  std::unique_ptr<apc_handle> h;
+  std::vector<const unsigned char*> blobs;
+  APC_TRY(rep_parse((const unsigned char*)src, len, h, blobs));
+  if (!out) return APC_OK;  // checked only
+  hipStream_t st = (hipStream_t)hip_stream;
+  Meta& m = h->meta;
+  int64_t mag_w = 0, idx_n = 0, sign_w = 0, nplanes = 0;
+  for (const Stream& S : m.streams) {
+    if (S.B == 0 || S.n == 0) continue;
+    mag_w += (int64_t)S.B * S.words();
+    idx_n += (int64_t)S.B * S.chunks();
+    sign_w += S.sign_words();
+    nplanes += S.B;
+  }
+  APC_TRY(h->mag.alloc(8 * (size_t)std::max<int64_t>(1, mag_w)));
+  APC_TRY(h->idx.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
+  APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_w)));
+  APC_TRY(h->pso.alloc(8 * (size_t)std::max<int64_t>(1, nplanes)));
+  std::vector<int64_t> pso((size_t)std::max<int64_t>(1, nplanes), 0);
+  // copies from pageable memory: the runtime has consumed each source when
+  // the call returns, and the stream is synchronized before returning
+  for (int s = 0; s < (int)m.streams.size(); ++s) {
+    const Stream& S = m.streams[s];
+    if (S.B == 0 || S.n == 0) continue;
+    const unsigned char* b = blobs[s];
+    const int64_t ib = 4 * (int64_t)S.B * S.chunks();
+    const int64_t ibp = ib + (8 - ib % 8) % 8;
+    const int64_t mb = 8 * (int64_t)S.B * S.words();
+    const int64_t sb = 8 * S.sign_words();
+    HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, (size_t)ib, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
+    if (sb)
+      HIP_TRY(hipMemcpyAsync(h->sign.as<uint64_t>() + S.sign_off, b + ibp + mb, (size_t)sb, hipMemcpyHostToDevice, st));
+    for (int j = 0; j < S.B; ++j) pso[(size_t)h->psb[s] + j] = S.pso[j];
+  }
+  HIP_TRY(hipMemcpyAsync(h->pso.p, pso.data(), 8 * pso.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = h.release();
   return APC_OK;
 }
 
