@@ -328,9 +328,9 @@ def serve_leg(apc, torch, fieldgen, quick: bool):
            "rates": {}}
     for ri, rate in enumerate(rates):
         res = {}
-        for slots, name in ((4, "continuous"), (1, "fifo")):
+        for slots, batch, name in ((4, 16, "continuous"), (1, 1, "fifo")):
             hs = apc.refactor_batch(xs, schemes)
-            srv = apc.Server(hs, budget_bytes=4 << 30, max_slots=slots)
+            srv = apc.Server(hs, budget_bytes=4 << 30, max_slots=slots, max_batch=batch)
             rng = np.random.default_rng(100 + ri)
             gaps = rng.exponential(1.0 / rate, size=nreq)
             reqs = []
@@ -339,7 +339,7 @@ def serve_leg(apc, torch, fieldgen, quick: bool):
                 t = apc.Target("rel", float(rng.choice(eb))) if rng.random() < 0.5 else \
                     apc.Target("psnr", float(rng.choice(psnr)))
                 reqs.append((f, t))
-            outs = [torch.empty_like(xs[0]) for _ in range(8)]
+            outs = [torch.empty_like(xs[0]) for _ in range(64)]  # more than can be in flight at once
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             due = t0

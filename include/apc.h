@@ -157,25 +157,34 @@ apc_status apc_ladder_launch(apc_ladder* ladder, void* hip_stream);
 void apc_ladder_free(apc_ladder* ladder);
 
 /* Serving: a request loop over resident refactored fields with continuous
- * batching.  Requests are admitted in arrival order whenever one of
- * max_slots slot streams is free and the request's work buffers fit in
- * hbm_budget_bytes (the decoded-code buffers of the fields are resident and
- * not counted); admitted requests run concurrently.  Only planes no earlier
- * request has fetched are decoded (per field, on the field's own stream);
- * each request reads the resident codes truncated to its own plan, so its
- * output equals that of the same request made alone.  The server owns the
+ * batching.  Requests queue in arrival order.  Whenever one of max_slots
+ * slot streams is free, the server's worker thread takes the queued
+ * requests (up to max_batch of them, in order, while their work buffers fit
+ * in hbm_budget_bytes; the decoded-code buffers of the fields are resident
+ * and not counted) as one batch: the planes no earlier batch decoded are
+ * decoded for each field up to the largest plan of the batch on that field
+ * (all fields in shared launches, on the server's decode stream), then the
+ * recomposition and reconstruction of every request of the batch run as
+ * merged launches on the slot stream.  Batches on different slots overlap
+ * on the device, and requests that arrive meanwhile join the next batch.
+ * Each request reads the resident codes truncated to its own plan, so its
+ * output equals that of the same request made alone.  max_slots = 1 and
+ * max_batch = 1 give a one-at-a-time (FIFO) server.  The server owns the
  * fields' retrieval state until apc_server_destroy (which lets queued work
  * finish); handles stay owned by the caller and must outlive the server.
- *   submit: plans on the host and queues; APC_E_BELOW_FLOOR for an
+ *   submit: plans on the calling thread and queues; APC_E_BELOW_FLOOR for an
  *           unreachable target; APC_E_BUSY if the queue is full or the
  *           request alone exceeds the budget.  out_dev (caller owned, n
- *           elements of the field's dtype) is written asynchronously.
- *   poll / wait: completion of a ticket (wait also returns the plan info and
- *           forgets the ticket).
- *   stats: latency from submit to completion over completed requests. */
+ *           elements of the field's dtype) is written asynchronously and
+ *           must not be shared with another request in flight.
+ *   poll / wait: completion of a ticket (wait also returns the plan info,
+ *           whose bytes_fetched counts the planes the request added in
+ *           arrival order, and forgets the ticket).
+ *   stats: latency from submit to completion over completed requests, and
+ *           the most requests on the device at once. */
 typedef struct apc_server apc_server;
 apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t hbm_budget_bytes,
-                             int32_t max_slots, apc_server** out);
+                             int32_t max_slots, int32_t max_batch, apc_server** out);
 apc_status apc_server_submit(apc_server* sv, int32_t field, const apc_target* target, void* out_dev,
                              int64_t* ticket);
 apc_status apc_server_poll(apc_server* sv, int64_t ticket, int32_t* done);

@@ -18,6 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libapc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
 
+# torch first: its bundled HIP runtime is then the one the library binds to
+# (both carry the soname libamdhip64.so.7), so device memory and streams
+# from torch and the library's own calls share one runtime instance
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 APC_OK = 0
@@ -96,7 +101,7 @@ _lib.apc_ladder_create.argtypes = [_vp, ctypes.POINTER(_Target), _i32, ctypes.PO
 _lib.apc_ladder_launch.argtypes = [_vp, _vp]
 _lib.apc_ladder_free.argtypes = [_vp]
 _lib.apc_ladder_free.restype = None
-_lib.apc_server_create.argtypes = [ctypes.POINTER(_vp), _i32, _i64, _i32, ctypes.POINTER(_vp)]
+_lib.apc_server_create.argtypes = [ctypes.POINTER(_vp), _i32, _i64, _i32, _i32, ctypes.POINTER(_vp)]
 _lib.apc_server_submit.argtypes = [_vp, _i32, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_i64)]
 _lib.apc_server_poll.argtypes = [_vp, _i64, ctypes.POINTER(_i32)]
 _lib.apc_server_wait.argtypes = [_vp, _i64, ctypes.POINTER(_Info)]
@@ -362,11 +367,14 @@ class Ladder:
 class Server:
     """Continuous-batching retrieval server over resident refactored fields."""
 
-    def __init__(self, handles: Sequence[Handle], budget_bytes: int, max_slots: int = 4):
+    def __init__(self, handles: Sequence[Handle], budget_bytes: int, max_slots: int = 4, max_batch: int = 16):
+        """max_slots batches in flight, up to max_batch requests per batch
+        (max_slots = max_batch = 1: one request at a time)."""
         self.handles = list(handles)
         arr = (ctypes.c_void_p * len(self.handles))(*[h._h.value for h in self.handles])
         out = ctypes.c_void_p()
-        _check(_lib.apc_server_create(arr, len(self.handles), int(budget_bytes), int(max_slots), ctypes.byref(out)))
+        _check(_lib.apc_server_create(arr, len(self.handles), int(budget_bytes), int(max_slots), int(max_batch),
+                                      ctypes.byref(out)))
         self._p = out
 
     def submit(self, field: int, target: Target, out) -> int:

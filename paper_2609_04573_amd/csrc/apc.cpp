@@ -473,9 +473,12 @@ struct TableBuilder {
   std::vector<char> bytes;
   template <typename S>
   size_t add(const std::vector<S>& v) {
+    return add_raw(v.data(), sizeof(S) * v.size());
+  }
+  size_t add_raw(const void* p, size_t n) {
     size_t off = (bytes.size() + 255) & ~(size_t)255;
-    bytes.resize(off + sizeof(S) * v.size());
-    if (!v.empty()) memcpy(bytes.data() + off, v.data(), sizeof(S) * v.size());
+    bytes.resize(off + n);
+    if (n) memcpy(bytes.data() + off, p, n);
     return off;
   }
 };
@@ -498,7 +501,15 @@ struct Launch {
   double bytes;   // bytes the launch must move (profiling)
   const char* name;
   int side = 0;   // 1: runs on the helper stream, when there is one
+  int stage = 0;  // retrieval: dependency order (launches of one stage are independent)
 };
+
+// Dependency stage of a retrieval launch: decodes, the inverse
+// decomposition, the coarsest level, then levels from coarse to fine
+// (per-region levels: injection, then regions in order).  Launches of
+// several retrievals with the same stage, kind and argument can be merged
+// into one launch over all their segments.
+int level_stage(int l, int sub) { return 100 + 10 * (64 - l) + sub; }
 
 template <typename S>
 int64_t assign_blocks(std::vector<S>& segs, std::function<int64_t(const S&)> count) {
@@ -1683,11 +1694,14 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       if (a3 < 2) {  // v runs along lattice rows: one pass over row tiles
         const int64_t nbk = assign_cd_tile_blocks(cs, a3);
         ls.push_back({K_CDIT, tb.add(cs), (int)cs.size(), nbk, a3, by, "cd_inverse"});
+        ls.back().stage = 1;
       } else {
         const int64_t nbk = assign_cd_blocks(cs);
         const size_t off = tb.add(cs);
         ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+        ls.back().stage = 1;
         ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+        ls.back().stage = 2;
       }
     }
   }
@@ -1705,6 +1719,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     std::vector<FlatSeg> cs{c};
     const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
     ls.push_back({K_COARSEST, tb.add(cs), 1, nbk, 0, (8.0 + sizeof(Q)) * s0.n, "coarsest"});
+    ls.back().stage = 3;
   }
   const double* xin = w.xc;
   for (int l = L - 2; l >= 0; --l) {
@@ -1738,6 +1753,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       const double by = (double)(n - nc) * sizeof(Q) + (double)n * (l ? 8 : sizeof(T)) + 8.0 * nc;
       // level 0 writes the output field: its own kernel and profile name
       ls.push_back({l == 0 ? K_LEVEL3 : K_LEVEL2, tb.add(cs), 1, nbk, t2, by, l == 0 ? "recon" : "recon_coarse"});
+      ls.back().stage = level_stage(l, 0);
       xin = xout;
       continue;
     }
@@ -1755,6 +1771,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       std::vector<FlatSeg> cs{c};
       const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
       ls.push_back({K_INJECT, tb.add(cs), 1, nbk, 0, (8.0 + (l ? 8 : sizeof(T))) * c.n, "inject"});
+      ls.back().stage = level_stage(l, 0);
     }
     for (int rho = 0; rho < d; ++rho) {
       ReconSeg r{};
@@ -1785,6 +1802,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       const int64_t nbk = assign_blocks<ReconSeg>(cs, [](const ReconSeg& s) { return lat_count(s.ra.lat); });
       const double by = (double)cnt * (sizeof(Q) + (l ? 8 : sizeof(T)) + (r.ra.pr_out ? 8 : 0));
       ls.push_back({K_RECON, tb.add(cs), 1, nbk, 0, by, "recon"});
+      ls.back().stage = level_stage(l, 1 + rho);
     }
     xin = xout;
   }
@@ -1831,6 +1849,91 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     for (const Launch& x : lev1) ls.push_back(x);
     for (const Launch& x : lev0) ls.push_back(x);
   }
+}
+
+// Segment size of each retrieval launch kind, and the shift of a segment's
+// first work block (first chunk for decodes).
+size_t seg_size_of(int kind) {
+  switch (kind) {
+    case K_DECODE: return sizeof(StreamDev);
+    case K_CDIT:
+    case K_CDI0:
+    case K_CDI1: return sizeof(CDSeg);
+    case K_COARSEST:
+    case K_INJECT: return sizeof(FlatSeg);
+    case K_RECON: return sizeof(ReconSeg);
+    case K_LEVEL2:
+    case K_LEVEL3: return sizeof(LevelSeg);
+    default: return 0;
+  }
+}
+void rebase_seg(int kind, char* seg, int64_t add) {
+  switch (kind) {
+    case K_DECODE: ((StreamDev*)seg)->chunk_begin += add; break;
+    case K_CDIT:
+    case K_CDI0:
+    case K_CDI1: ((CDSeg*)seg)->blk_begin += add; break;
+    case K_COARSEST:
+    case K_INJECT: ((FlatSeg*)seg)->blk_begin += add; break;
+    case K_RECON: ((ReconSeg*)seg)->blk_begin += add; break;
+    case K_LEVEL2:
+    case K_LEVEL3: ((LevelSeg*)seg)->blk_begin += add; break;
+    default: break;
+  }
+}
+
+// The launches of several retrievals (each list with its own table) merged:
+// launches with equal (stage, kind, argument) become one launch over the
+// concatenated segments, work blocks (chunks for decodes) numbered on from
+// the previous list's, in stage order.  Launches of one stage never depend
+// on each other, and every retrieval's own order is kept.
+struct LaunchPart {
+  const TableBuilder* tb;
+  const std::vector<Launch>* ls;
+};
+void merge_launches(const std::vector<LaunchPart>& parts, TableBuilder& tb, std::vector<Launch>& out) {
+  struct Acc {
+    Launch l{};
+    std::vector<char> segs;
+  };
+  std::map<std::tuple<int, int, int>, Acc> acc;
+  for (const LaunchPart& p : parts)
+    for (const Launch& l : *p.ls) {
+      const size_t sz = seg_size_of(l.kind);
+      auto key = std::make_tuple(l.stage, l.kind, l.a);
+      auto it = acc.find(key);
+      if (it == acc.end()) {
+        Acc a;
+        a.l = l;
+        a.l.nseg = 0;
+        a.l.nblk = 0;
+        a.l.bytes = 0.0;
+        it = acc.emplace(key, std::move(a)).first;
+      }
+      Acc& a = it->second;
+      const size_t at = a.segs.size();
+      a.segs.resize(at + sz * (size_t)l.nseg);
+      memcpy(a.segs.data() + at, p.tb->bytes.data() + l.off, sz * (size_t)l.nseg);
+      for (int i = 0; i < l.nseg; ++i) rebase_seg(l.kind, a.segs.data() + at + sz * (size_t)i, a.l.nblk);
+      a.l.nseg += l.nseg;
+      a.l.nblk += l.nblk;
+      a.l.bytes += l.bytes;
+    }
+  for (auto& kv : acc) {
+    Launch l = kv.second.l;
+    l.off = tb.add_raw(kv.second.segs.data(), kv.second.segs.size());
+    out.push_back(l);
+  }
+}
+
+// Plane bytes of planes [kcur[s], planes[s]) of every stream; kcur advances.
+int64_t fetch_bytes(const Meta& m, std::vector<int>& kcur, const std::vector<int>& planes) {
+  int64_t b = 0;
+  for (size_t s = 0; s < planes.size(); ++s) {
+    for (int j = kcur[s]; j < planes[s]; ++j) b += m.streams[s].plane_bytes(j);
+    kcur[s] = std::max(kcur[s], planes[s]);
+  }
+  return b;
 }
 
 apc_status upload_tables(apc_handle* h, const std::vector<char>& bytes, hipStream_t st) {
@@ -2968,14 +3071,23 @@ extern "C" apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, 
 }
 
 // ------------------------------------------------------------------ serving
-// A request loop over resident refactored fields with continuous batching:
-// requests are admitted in arrival order whenever a slot stream is free and
-// their work buffers fit the HBM budget, so new requests start while earlier
-// ones are still on the device.  Missing planes of a field are decoded on
-// that field's own stream (decodes of one field are serialized and only add
-// planes); each request then recomposes and reconstructs on its slot stream
-// after the decode that covers its plan, reading the shared codes truncated
-// to its own plan, so its result does not depend on what else is in flight.
+// A request loop over resident refactored fields with continuous batching.
+// Requests queue in arrival order; whenever one of max_slots slot streams is
+// free, the worker thread takes the queued requests (up to max_batch, in
+// order, as long as their work buffers fit the HBM budget) as one batch:
+//  - the planes the batch needs that no earlier batch decoded are decoded
+//    for each field up to the largest plan of the batch on that field, every
+//    field in the same launches, on the server's decode stream (decodes are
+//    serialized there: each one only adds planes to the resident codes);
+//  - on the slot stream, after that decode, the recomposition and
+//    reconstruction of every request of the batch run as one set of merged
+//    launches, each request reading the resident codes truncated to its own
+//    plan into its own work buffers and output.
+// Batches on different slots overlap on the device; requests that arrive
+// while batches run are admitted into the next one.  A request's output
+// therefore depends only on its own plan.  Plans are made at submission, on
+// the caller's thread; the worker builds tables without holding the server
+// lock and watches its batches' completion events without sleeping.
 namespace {
 
 struct SrvRequest {
@@ -2985,12 +3097,10 @@ struct SrvRequest {
   std::vector<int> planes;
   apc_retrieve_info info{};
   size_t footprint = 0;
-  int slot = -1;
   int state = 0;  // 0 pending, 1 running, 2 done, 3 failed
   apc_status status = APC_OK;
   double t_submit = 0, t_start = 0, t_done = 0;
   DevBuf work;
-  hipEvent_t done_ev = nullptr;
 };
 
 struct SrvStaging {  // device table buffer fed from pinned memory
@@ -3010,7 +3120,7 @@ struct SrvStaging {  // device table buffer fed from pinned memory
       // the old table may still be read by queued work on this stream: the
       // pool hands it out again only after the device has moved past it
       HIP_TRY(hipStreamSynchronize(st));
-      APC_TRY(dev.alloc(b.size()));
+      APC_TRY(dev.alloc(2 * b.size()));
     }
     HIP_TRY(hipMemcpyAsync(dev.p, pinned.p, b.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(pinned.ev, st));
@@ -3020,17 +3130,14 @@ struct SrvStaging {  // device table buffer fed from pinned memory
 
 struct SrvSlot {
   hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
   SrvStaging tab;
-  int64_t req = -1;
+  std::vector<int64_t> batch;  // tickets of the batch in flight (empty: free)
 };
 
 struct SrvField {
   apc_handle* h = nullptr;
-  hipStream_t dec_st = nullptr;
-  hipEvent_t dec_ev = nullptr;
-  bool has_dec = false;
-  std::vector<int> k_issued;
-  SrvStaging tab;
+  std::vector<int> k_issued;  // planes decoded (or queued for decoding) per stream
 };
 
 double now_s() {
@@ -3043,48 +3150,92 @@ struct apc_server {
   int device = 0;
   std::vector<std::unique_ptr<SrvField>> fields;
   std::vector<std::unique_ptr<SrvSlot>> slots;
+  hipStream_t dec_st = nullptr;
+  hipEvent_t dec_ev = nullptr;
+  bool has_dec = false;
+  SrvStaging dec_tab;
   std::map<int64_t, std::unique_ptr<SrvRequest>> reqs;
   std::deque<int64_t> pending;
   std::vector<double> lat_ms;
   int64_t next_ticket = 1;
   size_t budget = 0, in_use = 0;
+  int max_batch = 1;
   int max_queue = 1 << 16;
-  int64_t completed = 0, failed = 0, max_running = 0;
+  int64_t completed = 0, failed = 0, max_running = 0, running = 0;
   std::mutex mu;
   std::condition_variable cv, done_cv;
   std::thread worker;
   bool stop = false;
 
+  // Queue the work of one batch (called without the lock; only the worker
+  // touches the fields' decode state and the slots).
   template <typename T, typename Q>
-  apc_status start(SrvRequest& r, SrvSlot& sl) {
-    SrvField& f = *fields[r.field];
-    apc_handle* h = f.h;
-    // decode of the planes no request has asked for yet, on the field's stream
-    TableBuilder tbd;
-    std::vector<Launch> ld;
-    int64_t fetched = 0;
-    build_retrieve<T, Q>(h, r.planes, (T*)r.out, f.k_issued, tbd, ld, &fetched, WorkPtrs(), true, false);
-    r.info.bytes_fetched = fetched;
-    if (!ld.empty()) {
-      APC_TRY(f.tab.put(tbd.bytes, f.dec_st));
-      APC_TRY((issue<T, Q>(ld, (const char*)f.tab.dev.p, f.dec_st)));
-      HIP_TRY(hipEventRecord(f.dec_ev, f.dec_st));
-      f.has_dec = true;
+  apc_status start(const std::vector<SrvRequest*>& batch, SrvSlot& sl) {
+    // decodes: per field, up to the largest plan of the batch; each request
+    // is credited with the planes it adds in arrival order
+    std::map<int, std::vector<int>> want;
+    for (SrvRequest* r : batch) {
+      SrvField& f = *fields[r->field];
+      auto it = want.find(r->field);
+      if (it == want.end()) it = want.emplace(r->field, f.k_issued).first;
+      std::vector<int>& u = it->second;
+      r->info.bytes_fetched = fetch_bytes(f.h->meta, u, r->planes);
     }
-    // recomposition and reconstruction on the slot stream, after the decode
-    // that covers this plan
-    if (f.has_dec) HIP_TRY(hipStreamWaitEvent(sl.st, f.dec_ev, 0));
-    APC_TRY(r.work.alloc(r.footprint));
-    const WorkPtrs w = carve_work(h, r.work.p);
-    TableBuilder tbr;
-    std::vector<Launch> lr;
-    std::vector<int> kdone = f.k_issued;  // no decode in this part
-    build_retrieve<T, Q>(h, r.planes, (T*)r.out, kdone, tbr, lr, nullptr, w, false, true);
-    APC_TRY(sl.tab.put(tbr.bytes, sl.st));
-    APC_TRY((issue<T, Q>(lr, (const char*)sl.tab.dev.p, sl.st)));
-    if (!r.done_ev) HIP_TRY(hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(r.done_ev, sl.st));
+    std::vector<TableBuilder> dtb(want.size());
+    std::vector<std::vector<Launch>> dls(want.size());
+    std::vector<LaunchPart> parts;
+    size_t i = 0;
+    for (auto& kv : want) {
+      SrvField& f = *fields[kv.first];
+      build_retrieve<T, Q>(f.h, kv.second, nullptr, f.k_issued, dtb[i], dls[i], nullptr, WorkPtrs(), true, false);
+      if (!dls[i].empty()) parts.push_back({&dtb[i], &dls[i]});
+      ++i;
+    }
+    if (!parts.empty()) {
+      TableBuilder tb;
+      std::vector<Launch> ls;
+      merge_launches(parts, tb, ls);
+      APC_TRY(dec_tab.put(tb.bytes, dec_st));
+      APC_TRY((issue<T, Q>(ls, (const char*)dec_tab.dev.p, dec_st)));
+      HIP_TRY(hipEventRecord(dec_ev, dec_st));
+      has_dec = true;
+    }
+    // recomposition and reconstruction of every request, merged, on the
+    // slot stream after the decode that covers the batch
+    if (has_dec) HIP_TRY(hipStreamWaitEvent(sl.st, dec_ev, 0));
+    std::vector<TableBuilder> rtb(batch.size());
+    std::vector<std::vector<Launch>> rls(batch.size());
+    parts.clear();
+    for (size_t j = 0; j < batch.size(); ++j) {
+      SrvRequest* r = batch[j];
+      apc_handle* h = fields[r->field]->h;
+      APC_TRY(r->work.alloc(r->footprint));
+      const WorkPtrs w = carve_work(h, r->work.p);
+      std::vector<int> kdone = fields[r->field]->k_issued;  // no decode in this part
+      build_retrieve<T, Q>(h, r->planes, (T*)r->out, kdone, rtb[j], rls[j], nullptr, w, false, true);
+      parts.push_back({&rtb[j], &rls[j]});
+    }
+    TableBuilder tb;
+    std::vector<Launch> ls;
+    merge_launches(parts, tb, ls);
+    APC_TRY(sl.tab.put(tb.bytes, sl.st));
+    APC_TRY((issue<T, Q>(ls, (const char*)sl.tab.dev.p, sl.st)));
+    HIP_TRY(hipEventRecord(sl.done, sl.st));
     return APC_OK;
+  }
+
+  void finish(SrvRequest& r, double t, bool ok, apc_status s) {
+    r.t_done = t;
+    r.state = ok ? 2 : 3;
+    if (!ok) {
+      r.status = s;
+      ++failed;
+    }
+    lat_ms.push_back((r.t_done - r.t_submit) * 1e3);
+    ++completed;
+    r.work.release();
+    in_use -= r.footprint;
+    --running;
   }
 
   void loop() {
@@ -3092,63 +3243,77 @@ struct apc_server {
     std::unique_lock<std::mutex> lk(mu);
     while (!stop) {
       bool busy = false;
-      int running = 0;
       for (auto& slp : slots) {
         SrvSlot& sl = *slp;
-        if (sl.req < 0) continue;
-        SrvRequest& r = *reqs[sl.req];
-        const hipError_t q = hipEventQuery(r.done_ev);
+        if (sl.batch.empty()) continue;
+        const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) {
           busy = true;
-          ++running;
           continue;
         }
-        r.t_done = now_s();
-        r.state = q == hipSuccess ? 2 : 3;
-        if (q != hipSuccess) r.status = APC_E_HIP;
-        lat_ms.push_back((r.t_done - r.t_submit) * 1e3);
-        ++completed;
-        r.work.release();
-        in_use -= r.footprint;
-        sl.req = -1;
+        const double t = now_s();
+        for (int64_t tk : sl.batch) finish(*reqs[tk], t, q == hipSuccess, APC_E_HIP);
+        sl.batch.clear();
         done_cv.notify_all();
       }
       while (!pending.empty()) {
-        SrvRequest& r = *reqs[pending.front()];
-        int free_slot = -1;
-        for (size_t i = 0; i < slots.size(); ++i)
-          if (slots[i]->req < 0) {
-            free_slot = (int)i;
+        SrvSlot* free_slot = nullptr;
+        for (auto& slp : slots)
+          if (slp->batch.empty()) {
+            free_slot = slp.get();
             break;
           }
-        if (free_slot < 0 || in_use + r.footprint > budget) break;
-        pending.pop_front();
-        SrvSlot& sl = *slots[free_slot];
-        r.slot = free_slot;
-        r.t_start = now_s();
-        const apc_status s = fields[r.field]->h->dtype == APC_F32 ? start<float, int32_t>(r, sl)
-                                                                : start<double, int64_t>(r, sl);
-        if (s != APC_OK) {
-          r.state = 3;
-          r.status = s;
-          ++failed;
-          r.work.release();
+        if (!free_slot) break;
+        // the queued requests in arrival order, as many as fit
+        std::vector<SrvRequest*> batch;
+        size_t fp = 0;
+        while (!pending.empty() && (int)batch.size() < max_batch) {
+          SrvRequest& r = *reqs[pending.front()];
+          if (in_use + fp + r.footprint > budget) break;
+          fp += r.footprint;
+          batch.push_back(&r);
+          pending.pop_front();
+        }
+        if (batch.empty()) break;  // the head waits for running batches to free memory
+        const double t = now_s();
+        for (SrvRequest* r : batch) {
+          r->state = 1;
+          r->t_start = t;
+          free_slot->batch.push_back(r->ticket);
+        }
+        in_use += fp;
+        running += (int64_t)batch.size();
+        max_running = std::max(max_running, running);
+        lk.unlock();
+        const bool f32 = fields[batch[0]->field]->h->dtype == APC_F32;
+        apc_status st = APC_OK;
+        // a batch holds one dtype: split off the requests of the other one
+        std::vector<SrvRequest*> same, other;
+        for (SrvRequest* r : batch) ((fields[r->field]->h->dtype == APC_F32) == f32 ? same : other).push_back(r);
+        st = f32 ? start<float, int32_t>(same, *free_slot) : start<double, int64_t>(same, *free_slot);
+        if (st == APC_OK && !other.empty())
+          st = f32 ? start<double, int64_t>(other, *free_slot) : start<float, int32_t>(other, *free_slot);
+        lk.lock();
+        if (st != APC_OK) {
+          // nothing of a failed batch is trusted: wait for what was queued, fail every request
+          (void)hipStreamSynchronize(free_slot->st);
+          (void)hipStreamSynchronize(dec_st);
+          const double t2 = now_s();
+          for (int64_t tk : free_slot->batch) finish(*reqs[tk], t2, false, st);
+          free_slot->batch.clear();
           done_cv.notify_all();
           continue;
         }
-        r.state = 1;
-        in_use += r.footprint;
-        sl.req = r.ticket;
         busy = true;
-        ++running;
       }
-      max_running = std::max<int64_t>(max_running, running);
       if (busy) {
+        // batches in flight: watch their events without sleeping (a sleep
+        // or a blocking wait costs tens of microseconds of latency)
         lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        std::this_thread::yield();
         lk.lock();
       } else {
-        cv.wait_for(lk, std::chrono::milliseconds(50));
+        cv.wait(lk, [&] { return stop || !pending.empty(); });
       }
     }
   }
@@ -3157,12 +3322,14 @@ struct apc_server {
 extern "C" {
 
 apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t hbm_budget_bytes, int32_t max_slots,
-                             apc_server** out) {
-  if (!fields || nfields < 1 || max_slots < 1 || max_slots > 64 || hbm_budget_bytes <= 0 || !out)
+                             int32_t max_batch, apc_server** out) {
+  if (!fields || nfields < 1 || max_slots < 1 || max_slots > 64 || max_batch < 1 || max_batch > 1024 ||
+      hbm_budget_bytes <= 0 || !out)
     return fail(APC_E_INVALID, "bad argument");
   std::unique_ptr<apc_server> sv(new apc_server());
   HIP_TRY(hipGetDevice(&sv->device));
   sv->budget = (size_t)hbm_budget_bytes;
+  sv->max_batch = max_batch;
   for (int f = 0; f < nfields; ++f) {
     if (!fields[f]) return fail(APC_E_INVALID, "null field handle %d", f);
     sv->fields.emplace_back(new SrvField());
@@ -3170,13 +3337,18 @@ apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t
     F.h = fields[f];
     if (F.h->ready) HIP_TRY(hipEventSynchronize(F.h->ready));  // the refactor's last kernels
     APC_TRY(ensure_codes(F.h));
+    // both greedy sequences now: later plans only read the metadata, so
+    // submissions plan without any lock
+    ensure_sequence(F.h->meta, 0);
+    ensure_sequence(F.h->meta, 1);
     F.k_issued = F.h->k_res;
-    HIP_TRY(hipStreamCreateWithFlags(&F.dec_st, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&F.dec_ev, hipEventDisableTiming));
   }
+  HIP_TRY(hipStreamCreateWithFlags(&sv->dec_st, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&sv->dec_ev, hipEventDisableTiming));
   for (int i = 0; i < max_slots; ++i) {
     sv->slots.emplace_back(new SrvSlot());
     HIP_TRY(hipStreamCreateWithFlags(&sv->slots.back()->st, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&sv->slots.back()->done, hipEventDisableTiming));
   }
   HIP_TRY(hipDeviceSynchronize());
   apc_server* raw = sv.get();
@@ -3188,19 +3360,19 @@ apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t
 apc_status apc_server_submit(apc_server* sv, int32_t field, const apc_target* target, void* out_dev,
                              int64_t* ticket) {
   if (!sv || !target || !out_dev || !ticket) return fail(APC_E_INVALID, "null argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
   if (field < 0 || field >= (int32_t)sv->fields.size()) return fail(APC_E_INVALID, "bad field %d", field);
-  if ((int)sv->pending.size() >= sv->max_queue) return fail(APC_E_BUSY, "request queue full");
   std::unique_ptr<SrvRequest> r(new SrvRequest());
   r->field = field;
   r->out = out_dev;
+  r->t_submit = now_s();
   apc_handle* h = sv->fields[field]->h;
-  APC_TRY(plan_for(h, target, r->planes, &r->info));
+  APC_TRY(plan_for(h, target, r->planes, &r->info));  // read-only: the sequences exist
   r->footprint = work_bytes(h);
   if (r->footprint > sv->budget)
     return fail(APC_E_BUSY, "request needs %zu bytes of work buffers, budget is %zu", r->footprint, sv->budget);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if ((int)sv->pending.size() >= sv->max_queue) return fail(APC_E_BUSY, "request queue full");
   r->ticket = sv->next_ticket++;
-  r->t_submit = now_s();
   *ticket = r->ticket;
   sv->pending.push_back(r->ticket);
   sv->reqs[r->ticket] = std::move(r);
@@ -3217,7 +3389,6 @@ apc_status apc_server_wait(apc_server* sv, int64_t ticket, apc_retrieve_info* in
   sv->done_cv.wait(lk, [&] { return r->state >= 2; });
   const apc_status s = r->status;
   if (info) *info = r->info;
-  if (r->done_ev) (void)hipEventDestroy(r->done_ev);
   sv->reqs.erase(it);
   if (s != APC_OK) return fail(s, "request %lld failed", (long long)ticket);
   return APC_OK;
@@ -3259,7 +3430,7 @@ apc_status apc_server_reset_stats(apc_server* sv) {
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->lat_ms.clear();
   sv->completed = 0;
-  sv->max_running = 0;
+  sv->max_running = sv->running;
   return APC_OK;
 }
 
@@ -3271,7 +3442,7 @@ void apc_server_destroy(apc_server* sv) {
     sv->done_cv.wait(lk, [&] {
       if (!sv->pending.empty()) return false;
       for (const auto& s : sv->slots)
-        if (s->req >= 0) return false;
+        if (!s->batch.empty()) return false;
       return true;
     });
     sv->stop = true;
@@ -3281,20 +3452,14 @@ void apc_server_destroy(apc_server* sv) {
   (void)hipDeviceSynchronize();
   // staging goes back to the pool while the streams its events name exist
   for (auto& s : sv->slots) g_pinned.put(s->tab.pinned, nullptr, false);
-  for (auto& f : sv->fields) g_pinned.put(f->tab.pinned, nullptr, false);
-  for (SrvRequest* r : [&] {
-         std::vector<SrvRequest*> v;
-         for (auto& kv : sv->reqs) v.push_back(kv.second.get());
-         return v;
-       }())
-    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
-  for (auto& s : sv->slots)
+  g_pinned.put(sv->dec_tab.pinned, nullptr, false);
+  for (auto& s : sv->slots) {
+    if (s->done) (void)hipEventDestroy(s->done);
     if (s->st) (void)hipStreamDestroy(s->st);
-  for (auto& f : sv->fields) {
-    f->h->k_res = f->k_issued;
-    if (f->dec_ev) (void)hipEventDestroy(f->dec_ev);
-    if (f->dec_st) (void)hipStreamDestroy(f->dec_st);
   }
+  if (sv->dec_ev) (void)hipEventDestroy(sv->dec_ev);
+  if (sv->dec_st) (void)hipStreamDestroy(sv->dec_st);
+  for (auto& f : sv->fields) f->h->k_res = f->k_issued;
   delete sv;
 }
 

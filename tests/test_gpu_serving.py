@@ -1,11 +1,13 @@
 """GPU tests of the continuous-batching retrieval server: every result in a
-concurrent mix equals the same request made alone (bit for bit), work of
-several requests overlaps on the device, only missing planes are fetched,
-and admission respects the HBM budget."""
+concurrent mix equals the same request made alone and the oracle's
+reconstruction for its plan (bit for bit), several requests are on the
+device at once (merged into batches), only missing planes are fetched, and
+admission respects the HBM budget."""
 import numpy as np
 import pytest
 
 import fieldgen
+import oracle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,11 +42,20 @@ def _requests(nreq, nf, seed):
     return reqs
 
 
+def _oracle_refs(xs, schemes):
+    refs = []
+    for x, s in zip(xs, schemes):
+        refs.append(oracle.refactor(x.cpu().numpy(), oracle.Scheme(kind=s.kind, degree=s.degree, order=s.order,
+                                                                    cd_axis=s.cd_axis)))
+    return refs
+
+
+@pytest.mark.timeout(600)
 def test_server_mix_equals_alone():
     apc = _apc()
     xs, schemes = _setup()
     served = apc.refactor_batch(xs, schemes)
-    srv = apc.Server(served, budget_bytes=4 << 30, max_slots=4)
+    srv = apc.Server(served, budget_bytes=4 << 30, max_slots=4, max_batch=8)
     reqs = _requests(80, len(xs), seed=100)
     outs = [torch.empty_like(xs[f]) for f, _ in reqs]
     tickets = [srv.submit(f, t, o) for (f, t), o in zip(reqs, outs)]
@@ -57,10 +68,39 @@ def test_server_mix_equals_alone():
     fetched = sum(i["bytes_fetched"] for i in infos)
     total = sum(i["bytes_total"] for i in infos)
     assert fetched < total  # later requests reuse planes fetched by earlier ones
+    refs = _oracle_refs(xs, schemes)
     for k, ((f, t), o) in enumerate(zip(reqs, outs)):
         want, _ = alone[f].retrieve(t)
         assert torch.equal(o.view(torch.int32), want.view(torch.int32)), (k, f, t)
+        pl = oracle.plan(refs[f], oracle.Target(t.kind, t.value))
+        assert infos[k]["bytes_total"] == pl.bytes
+        ow = oracle.retrieve(refs[f], pl)
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), ow.view(np.uint32)), (k, f, t)
     for h in alone + served:
+        h.close()
+
+
+def test_server_batches_requests_submitted_together():
+    """Requests queued while a batch runs join the next batch: with one slot,
+    a burst of submissions is served in merged batches (several requests on
+    the device at once) and every output still equals the oracle's."""
+    apc = _apc()
+    xs, schemes = _setup(n=64, nf=4)
+    served = apc.refactor_batch(xs, schemes)
+    srv = apc.Server(served, budget_bytes=4 << 30, max_slots=1, max_batch=16)
+    reqs = _requests(40, len(xs), seed=11)
+    outs = [torch.empty_like(xs[f]) for f, _ in reqs]
+    tickets = [srv.submit(f, t, o) for (f, t), o in zip(reqs, outs)]
+    for tk in tickets:
+        srv.wait(tk)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["max_running"] >= 2, st
+    refs = _oracle_refs(xs, schemes)
+    for (f, t), o in zip(reqs, outs):
+        ow = oracle.retrieve(refs[f], oracle.plan(refs[f], oracle.Target(t.kind, t.value)))
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), ow.view(np.uint32)), (f, t)
+    for h in served:
         h.close()
 
 
@@ -68,7 +108,7 @@ def test_server_one_slot_serializes_and_matches():
     apc = _apc()
     xs, schemes = _setup(n=64, nf=2)
     served = apc.refactor_batch(xs, schemes)
-    srv = apc.Server(served, budget_bytes=4 << 30, max_slots=1)
+    srv = apc.Server(served, budget_bytes=4 << 30, max_slots=1, max_batch=1)
     reqs = _requests(20, len(xs), seed=7)
     outs = [torch.empty_like(xs[f]) for f, _ in reqs]
     tickets = [srv.submit(f, t, o) for (f, t), o in zip(reqs, outs)]
