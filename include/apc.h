@@ -245,6 +245,24 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
 /* Metadata as a JSON text (groups, streams, staircase, bounds). */
 apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_t* len);
 
+/* Retrieval interpreters (Section V-C; Algorithm 2 "RetrievalInterpreter").
+ * APC_INTERP_GREEDY (the default): steps taken in order of weighted error
+ *   decrease per byte; plans for tighter targets contain looser ones.
+ * APC_INTERP_DP: the fewest bytes within the target by dynamic programming
+ *   over the error budget split into 2048 parts (each unit's error term
+ *   rounded up to whole parts), never more bytes than the greedy plan.
+ * APC_INTERP_BEST_FIRST: for per-level interpolation with decomposition,
+ *   the level-0 staircase's step counts searched cheapest first with pruning,
+ *   the other units by the dynamic program; otherwise APC_INTERP_DP.
+ * APC_INTERP_PAPER: the paper's choice, APC_INTERP_DP for per-region and
+ *   APC_INTERP_BEST_FIRST for per-level interpolation.
+ * The last three are invoked incrementally: planes already decoded on the
+ * handle (and, in a ladder, by its earlier steps) cost nothing.  The server
+ * plans every request as for a fresh handle.  Every interpreter's plan
+ * satisfies the target.  APC_E_INVALID for other values. */
+enum { APC_INTERP_GREEDY = 0, APC_INTERP_DP = 1, APC_INTERP_BEST_FIRST = 2, APC_INTERP_PAPER = 3 };
+apc_status apc_set_interpreter(apc_handle* h, int32_t interp);
+
 /* Shape and dtype of a handle's field: dims (3 int64, the first ndim set),
  * ndim, dtype (APC_F32 / APC_F64); any output may be NULL. */
 apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int32_t* dtype);
@@ -274,6 +292,11 @@ apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int
  *   after the upload.  The handle retrieves exactly as the serialized one. */
 apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64_t* len);
 apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_handle** out);
+/* The same checks, and a handle that holds only the host metadata (no device
+ * needed): apc_plan, apc_set_interpreter and the introspection calls work on
+ * it; retrieval, ladders, the server, blob export and serialization return
+ * APC_E_INVALID.  For planning services away from the data. */
+apc_status apc_deserialize_host(const void* src, int64_t len, apc_handle** out);
 
 /* Host-only helper (no device needed): exact chain norms of the 1D
  * interpolation chain on an axis of length n for levels 0..L-1, rounded to

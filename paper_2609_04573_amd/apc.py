@@ -48,8 +48,10 @@ EXPORTED = [
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
     "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width", "apc_profile_only",
-    "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize",
+    "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize", "apc_deserialize_host",
+    "apc_set_interpreter",
 ]
+INTERPRETERS = {"greedy": 0, "dp": 1, "best_first": 2, "paper": 3}
 
 
 class _Scheme(ctypes.Structure):
@@ -78,6 +80,8 @@ _lib.apc_retrieve_static.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.P
 _lib.apc_field_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 _lib.apc_serialize.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_i64)]
 _lib.apc_deserialize.argtypes = [ctypes.c_char_p, _i64, _vp, ctypes.POINTER(_vp)]
+_lib.apc_deserialize_host.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_vp)]
+_lib.apc_set_interpreter.argtypes = [_vp, _i32]
 _lib.apc_select_pipeline.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, ctypes.POINTER(_Scheme), _vp]
 _lib.apc_free.argtypes = [_vp]
 _lib.apc_free.restype = None
@@ -120,7 +124,8 @@ for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes",
               "apc_profile_report", "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
               "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
-              "apc_profile_only", "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize"):
+              "apc_profile_only", "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize",
+              "apc_deserialize_host", "apc_set_interpreter"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -271,6 +276,11 @@ class Handle:
         _check(_lib.apc_stream_blob(self._h, s, buf, max(1, nb)))
         return buf.raw[:nb]
 
+    def set_interpreter(self, name: str) -> None:
+        """Retrieval interpreter: "greedy" (default), "dp", "best_first" or
+        "paper" (dp for per-region, best_first for per-level)."""
+        _check(_lib.apc_set_interpreter(self._h, INTERPRETERS[name]))
+
     def serialize(self) -> bytes:
         """The stored representation as bytes (apc_serialize)."""
         ln = _i64()
@@ -313,6 +323,16 @@ def deserialize(data: bytes, stream=None) -> Handle:
     _check(_lib.apc_field_info(out, dims, ctypes.byref(nd), ctypes.byref(dt)))
     return Handle(out.value, tuple(dims[i] for i in range(nd.value)),
                   torch.float32 if dt.value == APC_F32 else torch.float64)
+
+
+def deserialize_host(data: bytes) -> Handle:
+    """A planning-only handle from apc_serialize bytes (no device needed)."""
+    out = ctypes.c_void_p()
+    _check(_lib.apc_deserialize_host(data, len(data), ctypes.byref(out)))
+    dims = (ctypes.c_int64 * 3)()
+    nd, dt = _i32(), _i32()
+    _check(_lib.apc_field_info(out, dims, ctypes.byref(nd), ctypes.byref(dt)))
+    return Handle(out.value, tuple(dims[i] for i in range(nd.value)), None)
 
 
 def refactor_batch(fields, schemes, stream=None) -> List[Handle]:

@@ -451,6 +451,8 @@ struct apc_handle {
   PinnedBlock pinned;  // staging of table uploads (its event follows the last upload)
   hipEvent_t ready = nullptr;  // follows the refactor's last kernel (work on other streams waits for it)
   hipEvent_t tab_ev = nullptr;  // follows the last retrieval that read `tables`
+  int interp = INTERP_GREEDY;    // retrieval interpreter
+  bool host_only = false;        // rebuilt from bytes without device data: planning only
   ~apc_handle() {
     g_pinned.put(pinned, nullptr, false);
     if (tab_ev) {
@@ -2052,13 +2054,17 @@ apc_status target_tau(const apc_handle* h, const apc_target* t, double& tau, int
   }
 }
 
-apc_status plan_for(apc_handle* h, const apc_target* target, std::vector<int>& planes, apc_retrieve_info* info) {
+// The plan for a target with the handle's interpreter.  resident: planes
+// already fetched (free for the dynamic program and best-first search;
+// ignored by the greedy, whose plans are nested anyway), or null.
+apc_status plan_for(apc_handle* h, const apc_target* target, std::vector<int>& planes, apc_retrieve_info* info,
+                    const std::vector<int>* resident) {
   double tau;
   int mode;
   APC_TRY(target_tau(h, target, tau, mode));
   double b;
   int nsteps;
-  if (make_plan(h->meta, tau, mode, planes, b, nsteps) != 0)
+  if (make_plan_with(h->meta, h->interp, h->scheme.kind == APC_PER_REGION, tau, mode, resident, planes, b, nsteps) != 0)
     return fail(APC_E_BELOW_FLOOR, "tolerance %.17g is below the floor of this representation", tau);
   if (info) {
     info->bytes_total = plan_bytes(h->meta, planes);
@@ -2069,6 +2075,11 @@ apc_status plan_for(apc_handle* h, const apc_target* target, std::vector<int>& p
     info->n_streams = (int32_t)planes.size();
     info->nsteps = nsteps;
   }
+  return APC_OK;
+}
+
+apc_status need_device(const apc_handle* h) {
+  if (h->host_only) return fail(APC_E_INVALID, "handle holds no device data (rebuilt for planning only)");
   return APC_OK;
 }
 
@@ -2485,7 +2496,7 @@ apc_status apc_refactor_batch(const void* const* fields_dev, int32_t dtype, cons
 apc_status apc_plan(apc_handle* h, const apc_target* target, int32_t* planes_out, apc_retrieve_info* info) {
   if (!h || !target) return fail(APC_E_INVALID, "null argument");
   std::vector<int> planes;
-  APC_TRY(plan_for(h, target, planes, info));
+  APC_TRY(plan_for(h, target, planes, info, &h->k_res));
   if (planes_out)
     for (size_t s = 0; s < planes.size(); ++s) planes_out[s] = planes[s];
   return APC_OK;
@@ -2494,9 +2505,10 @@ apc_status apc_plan(apc_handle* h, const apc_target* target, int32_t* planes_out
 apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev, apc_retrieve_info* info,
                         void* hip_stream) {
   if (!h || !target || !out_dev) return fail(APC_E_INVALID, "null argument");
+  APC_TRY(need_device(h));
   std::vector<int> planes;
   apc_retrieve_info inf{};
-  APC_TRY(plan_for(h, target, planes, &inf));
+  APC_TRY(plan_for(h, target, planes, &inf, &h->k_res));
   int64_t fetched = 0;
   APC_TRY(do_retrieve(h, planes, out_dev, hip_stream, &fetched));
   inf.bytes_fetched = fetched;
@@ -2506,6 +2518,7 @@ apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev, 
 
 apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream) {
   if (!h || !planes || !out_dev) return fail(APC_E_INVALID, "null argument");
+  APC_TRY(need_device(h));
   std::vector<int> p(h->meta.streams.size());
   for (size_t s = 0; s < p.size(); ++s) p[s] = std::max(0, std::min<int>(planes[s], h->meta.streams[s].B));
   return do_retrieve(h, p, out_dev, hip_stream, nullptr);
@@ -2514,9 +2527,10 @@ apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_d
 apc_status apc_retrieve_static(apc_handle* h, const apc_target* target, void* out_dev, apc_retrieve_info* info,
                                void* hip_stream) {
   if (!h || !target || !out_dev) return fail(APC_E_INVALID, "null argument");
+  APC_TRY(need_device(h));
   std::vector<int> planes;
   apc_retrieve_info inf{};
-  APC_TRY(plan_for(h, target, planes, &inf));
+  APC_TRY(plan_for(h, target, planes, &inf, &h->k_res));
   int64_t fetched = 0;
   hipStream_t st = (hipStream_t)hip_stream;
   if (h->dtype == APC_F32)
@@ -2531,6 +2545,7 @@ apc_status apc_retrieve_static(apc_handle* h, const apc_target* target, void* ou
 apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n, void* const* outs_dev,
                              void* hip_stream, apc_ladder** out) {
   if (!h || !targets || !outs_dev || !out || n < 1) return fail(APC_E_INVALID, "bad argument");
+  APC_TRY(need_device(h));
   APC_TRY(ensure_work(h));
   hipStream_t st = (hipStream_t)hip_stream;
   if (h->ready) HIP_TRY(hipStreamWaitEvent(st, h->ready, 0));  // the refactor's last kernels
@@ -2541,7 +2556,7 @@ apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n
   std::vector<int> kres(h->meta.streams.size(), 0);  // a replay starts from nothing resident
   for (int i = 0; i < n; ++i) {
     std::vector<int> planes;
-    APC_TRY(plan_for(h, &targets[i], planes, nullptr));
+    APC_TRY(plan_for(h, &targets[i], planes, nullptr, &kres));
     if (h->dtype == APC_F32)
       build_retrieve<float, int32_t>(h, planes, (float*)outs_dev[i], kres, tb, ls, nullptr, handle_work(h));
     else
@@ -2594,6 +2609,10 @@ void apc_ladder_free(apc_ladder* ld) {
 
 void apc_free(apc_handle* h) {
   if (!h) return;
+  if (h->host_only) {  // no device data, nothing queued
+    delete h;
+    return;
+  }
   // Work queued on any stream may still read this handle's buffers; they go
   // back to the shared pool only once the device is idle.
   (void)hipDeviceSynchronize();
@@ -2618,6 +2637,7 @@ apc_status apc_stream_info(const apc_handle* h, int32_t s, int64_t* n, int32_t* 
 
 apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64_t cap) {
   if (!h || s < 0 || s >= (int32_t)h->meta.streams.size() || !host_dst) return fail(APC_E_INVALID, "bad argument");
+  APC_TRY(need_device(h));
   const Stream& S = h->meta.streams[s];
   if (cap < S.blob_bytes()) return fail(APC_E_INVALID, "buffer too small");
   char* dst = (char*)host_dst;
@@ -2657,6 +2677,7 @@ apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int
 
 apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64_t* len) {
   if (!h || !len) return fail(APC_E_INVALID, "null argument");
+  APC_TRY(need_device(h));
   std::vector<unsigned char> meta;
   rep_meta(h, meta);
   int64_t total = 32 + (int64_t)meta.size();
@@ -2684,6 +2705,23 @@ apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64
     memcpy(d + at + 8, &bh, 8);
     at += 16 + (int64_t)bl;
   }
+  return APC_OK;
+}
+
+apc_status apc_deserialize_host(const void* src, int64_t len, apc_handle** out) {
+  if (!src || len < 0 || !out) return fail(APC_E_INVALID, "null argument");
+  std::unique_ptr<apc_handle> h;
+  std::vector<const unsigned char*> blobs;
+  APC_TRY(rep_parse((const unsigned char*)src, len, h, blobs));
+  h->host_only = true;
+  *out = h.release();
+  return APC_OK;
+}
+
+apc_status apc_set_interpreter(apc_handle* h, int32_t interp) {
+  if (!h) return fail(APC_E_INVALID, "null handle");
+  if (interp < APC_INTERP_GREEDY || interp > APC_INTERP_PAPER) return fail(APC_E_INVALID, "interpreter %d", interp);
+  h->interp = interp;
   return APC_OK;
 }
 
@@ -3332,6 +3370,7 @@ apc_status apc_server_create(apc_handle* const* fields, int32_t nfields, int64_t
   sv->max_batch = max_batch;
   for (int f = 0; f < nfields; ++f) {
     if (!fields[f]) return fail(APC_E_INVALID, "null field handle %d", f);
+    APC_TRY(need_device(fields[f]));
     sv->fields.emplace_back(new SrvField());
     SrvField& F = *sv->fields.back();
     F.h = fields[f];
@@ -3366,7 +3405,9 @@ apc_status apc_server_submit(apc_server* sv, int32_t field, const apc_target* ta
   r->out = out_dev;
   r->t_submit = now_s();
   apc_handle* h = sv->fields[field]->h;
-  APC_TRY(plan_for(h, target, r->planes, &r->info));  // read-only: the sequences exist
+  // read-only on the handle (the greedy sequences exist); other interpreters
+  // plan as for a fresh handle (the worker owns the resident planes)
+  APC_TRY(plan_for(h, target, r->planes, &r->info, nullptr));
   r->footprint = work_bytes(h);
   if (r->footprint > sv->budget)
     return fail(APC_E_BUSY, "request needs %zu bytes of work buffers, budget is %zu", r->footprint, sv->budget);

@@ -95,6 +95,13 @@ void ensure_sequence(Meta& m, int mode);
 // Returns 0 on success, -1 if tau is below the floor.
 int make_plan(Meta& m, double tau, int mode, std::vector<int>& planes, double& bound_out, int& nsteps);
 int64_t plan_bytes(const Meta& m, const std::vector<int>& planes);
+// Interpreters: the greedy above, the dynamic program, the best-first search
+// (the dynamic program without a staircase), or the paper's choice (dynamic
+// program for per-region interpolation, best-first search otherwise).
+// resident: planes already fetched per stream (they cost nothing), or null.
+enum { INTERP_GREEDY = 0, INTERP_DP = 1, INTERP_BEST_FIRST = 2, INTERP_PAPER = 3 };
+int make_plan_with(Meta& m, int interp, bool per_region, double tau, int mode, const std::vector<int>* resident,
+                   std::vector<int>& planes, double& bound_out, int& nsteps);
 std::string meta_json(const Meta& m);
 
 }  // namespace apc

@@ -294,6 +294,281 @@ int64_t plan_bytes(const Meta& m, const std::vector<int>& planes) {
   return total;
 }
 
+// ------------------------------------------------------------------
+// The paper's interpreters (Section V-C; Algorithm 2): dynamic programming
+// for per-region interpolation, best-first search for per-level
+// interpolation with decomposition.  Both minimise the bytes a retrieval
+// fetches beyond the resident planes (incremental invocation) subject to the
+// model bound <= tau, and fall back to the greedy plan when it fetches no
+// more.  The arithmetic follows the definitions step by step in a fixed
+// order, so plans are reproducible bit for bit.
+namespace {
+
+constexpr int kDPParts = 2048;
+constexpr int kDPRetries = 8;
+constexpr int64_t kInf = INT64_MAX / 4;
+
+double wd_of(const Group& g, int mode) { return mode == 0 ? g.wd_inf : g.wd_2; }
+
+std::vector<int> resident_steps(const Meta& m, const std::vector<int>* res) {
+  std::vector<int> out(m.units.size(), 0);
+  if (!res) return out;
+  for (size_t u = 0; u < m.units.size(); ++u) {
+    const Unit& un = m.units[u];
+    if (!un.stair) {
+      out[u] = std::min(m.streams[un.stream].B, (*res)[un.stream]);
+    } else {
+      int s = 0;
+      while (s < (int)un.seg_steps.size()) {
+        bool all = true;
+        for (const auto& sp : un.seg_steps[s]) all = all && sp.second < (*res)[sp.first];
+        if (!all) break;
+        ++s;
+      }
+      out[u] = s;
+    }
+  }
+  return out;
+}
+
+int64_t step_cost(const Meta& m, int u, int k, const std::vector<int>* res) {
+  const Unit& un = m.units[u];
+  if (!un.stair) {
+    if (res && k < (*res)[un.stream]) return 0;
+    return m.streams[un.stream].plane_bytes(k);
+  }
+  int64_t total = 0;
+  for (const auto& sp : un.seg_steps[k])
+    if (!res || sp.second >= (*res)[sp.first]) total += m.streams[sp.first].plane_bytes(sp.second);
+  return total;
+}
+
+int64_t extra_bytes(const Meta& m, const std::vector<int>& planes, const std::vector<int>* res) {
+  int64_t total = 0;
+  for (size_t s = 0; s < m.streams.size(); ++s)
+    for (int j = res ? (*res)[s] : 0; j < planes[s]; ++j) total += m.streams[s].plane_bytes(j);
+  return total;
+}
+
+std::vector<int> stream_planes(const Meta& m, const std::vector<int>& state) {
+  std::vector<int> planes(m.streams.size(), 0);
+  for (size_t u = 0; u < m.units.size(); ++u) {
+    const Unit& un = m.units[u];
+    if (!un.stair) {
+      planes[un.stream] = state[u];
+    } else {
+      for (int j = 0; j < state[u]; ++j)
+        for (const auto& sp : un.seg_steps[j]) planes[sp.first] = std::max(planes[sp.first], sp.second + 1);
+    }
+  }
+  return planes;
+}
+
+// The model's bound for any per-stream plane vector: a staircase group takes
+// the largest summed stream error of its regions.
+double bound_for_planes(const Meta& m, const std::vector<int>& k, int mode) {
+  double E = 0.0;
+  for (int g : m.group_order) {
+    const Group& gr = m.groups[g];
+    const std::vector<int>& us = m.group_units[g];
+    int64_t e = 0;
+    if (us.size() == 1 && m.units[us[0]].stair) {
+      std::map<int, int64_t> per;
+      for (size_t s = 0; s < m.streams.size(); ++s)
+        if (m.streams[s].group == g) per[m.streams[s].rho] += m.streams[s].delta(k[s]);
+      for (const auto& kv : per) e = std::max(e, kv.second);
+    } else {
+      for (int u : us) e += m.streams[m.units[u].stream].delta(k[m.units[u].stream]);
+    }
+    E = E + wd_of(gr, mode) * (0.5 + (double)e);
+  }
+  return E + m.eps_fp;
+}
+
+struct PlanOut {
+  std::vector<int> planes;
+  double bound = 0.0;
+  int nsteps = 0;
+};
+
+PlanOut as_plan(const Meta& m, std::vector<int> planes, int nsteps, int mode, const std::vector<int>* res) {
+  if (res)
+    for (size_t s = 0; s < planes.size(); ++s) planes[s] = std::max(planes[s], (*res)[s]);
+  PlanOut p;
+  p.bound = bound_for_planes(m, planes, mode);
+  p.planes = std::move(planes);
+  p.nsteps = nsteps;
+  return p;
+}
+
+double budget(const Meta& m, double tau, int mode) {
+  double c = m.eps_fp;
+  for (int g : m.group_order) c = c + wd_of(m.groups[g], mode) * 0.5;
+  return tau - c;
+}
+
+// Fewest bytes over `units`, their error terms rounded up to parts of
+// R / kDPParts, summing to at most R; false when no choice fits.
+bool dp_solve(const Meta& m, int mode, const std::vector<int>& units, double R, const std::vector<int>& k0,
+              const std::vector<int>* res, int64_t& bytes, std::vector<int>& state) {
+  if (!(R > 0.0)) return false;
+  const int P = kDPParts;
+  const double q = R / P;
+  std::vector<int64_t> dp(P + 1, 0), nd(P + 1);
+  std::vector<std::vector<int>> ch(units.size(), std::vector<int>(P + 1, -1));
+  std::vector<std::vector<int64_t>> parts_of(units.size());
+  for (size_t i = 0; i < units.size(); ++i) {
+    const int u = units[i];
+    const Unit& un = m.units[u];
+    const double wd = wd_of(m.groups[un.group], mode);
+    const int n = unit_nsteps(m, un);
+    std::fill(nd.begin(), nd.end(), kInf);
+    parts_of[i].assign(n + 1, 0);
+    int64_t c = 0;
+    for (int k = k0[u]; k <= n; ++k) {
+      if (k > k0[u]) c += step_cost(m, u, k - 1, res);
+      const double a = wd * (double)unit_err(m, un, k);
+      int64_t A = 0;
+      if (a > 0.0) {
+        const double v = a / q;
+        A = v > (double)P ? (int64_t)P + 1 : (int64_t)ceil(v);
+      }
+      parts_of[i][k] = A;
+      if (A > P) continue;
+      for (int b = (int)A; b <= P; ++b) {
+        const int64_t prev = dp[b - A];
+        if (prev >= kInf) continue;
+        const int64_t v = c + prev;
+        if (v < nd[b]) {  // ties keep the smaller step count
+          nd[b] = v;
+          ch[i][b] = k;
+        }
+      }
+    }
+    dp.swap(nd);
+  }
+  if (dp[P] >= kInf) return false;
+  bytes = dp[P];
+  int b = P;
+  for (int i = (int)units.size() - 1; i >= 0; --i) {
+    const int k = ch[i][b];
+    state[units[i]] = k;
+    b -= (int)parts_of[i][k];
+  }
+  return true;
+}
+
+PlanOut greedy_plan(Meta& m, double tau, int mode, const std::vector<int>* res, bool& ok) {
+  std::vector<int> planes;
+  double E;
+  int n;
+  ok = make_plan(m, tau, mode, planes, E, n) == 0;
+  if (!ok) return PlanOut();
+  return as_plan(m, planes, n, mode, res);
+}
+
+PlanOut better(const Meta& m, const PlanOut* best, const PlanOut& greedy, const std::vector<int>* res) {
+  if (!best || extra_bytes(m, best->planes, res) > extra_bytes(m, greedy.planes, res)) return greedy;
+  return *best;
+}
+
+int sum_of(const std::vector<int>& v) {
+  int s = 0;
+  for (int x : v) s += x;
+  return s;
+}
+
+PlanOut dp_plan(Meta& m, double tau, int mode, const std::vector<int>* res, bool& ok) {
+  const PlanOut greedy = greedy_plan(m, tau, mode, res, ok);
+  if (!ok) return greedy;
+  const std::vector<int> k0 = resident_steps(m, res);
+  std::vector<int> all(m.units.size());
+  for (size_t u = 0; u < all.size(); ++u) all[u] = (int)u;
+  double R = budget(m, tau, mode);
+  for (int it = 0; it < kDPRetries; ++it) {
+    std::vector<int> state(m.units.size(), 0);
+    int64_t bytes;
+    if (!dp_solve(m, mode, all, R, k0, res, bytes, state)) break;
+    if (bound(m, state, mode) <= tau) {
+      const PlanOut p = as_plan(m, stream_planes(m, state), sum_of(state), mode, res);
+      return better(m, &p, greedy, res);
+    }
+    R = R * (1.0 - ldexp(1.0, -20));
+  }
+  return greedy;
+}
+
+PlanOut best_first_plan(Meta& m, double tau, int mode, const std::vector<int>* res, bool& ok) {
+  int su = -1;
+  for (size_t u = 0; u < m.units.size(); ++u)
+    if (m.units[u].stair) {
+      su = (int)u;
+      break;
+    }
+  if (su < 0) return dp_plan(m, tau, mode, res, ok);
+  const PlanOut greedy = greedy_plan(m, tau, mode, res, ok);
+  if (!ok) return greedy;
+  const Unit& stair = m.units[su];
+  std::vector<int> others;
+  for (size_t u = 0; u < m.units.size(); ++u)
+    if ((int)u != su) others.push_back((int)u);
+  const std::vector<int> k0 = resident_steps(m, res);
+  const double wd0 = wd_of(m.groups[stair.group], mode);
+  double R0 = budget(m, tau, mode);
+  std::vector<std::pair<int64_t, int>> pos;  // (own cost, steps), cheapest first
+  int64_t c = 0;
+  for (int s = k0[su]; s <= unit_nsteps(m, stair); ++s) {
+    if (s > k0[su]) c += step_cost(m, su, s - 1, res);
+    pos.push_back({c, s});
+  }
+  std::sort(pos.begin(), pos.end());
+  for (int it = 0; it < kDPRetries; ++it) {
+    bool found = false;
+    int64_t best_total = 0;
+    std::vector<int> best_state;
+    for (const auto& ps : pos) {
+      if (found && ps.first >= best_total) break;
+      const double a = wd0 * (double)unit_err(m, stair, ps.second);
+      if (a > R0) continue;
+      std::vector<int> state(m.units.size(), 0);
+      int64_t bytes;
+      if (!dp_solve(m, mode, others, R0 - a, k0, res, bytes, state)) continue;
+      if (!found || ps.first + bytes < best_total) {
+        found = true;
+        best_total = ps.first + bytes;
+        state[su] = ps.second;
+        best_state = state;
+      }
+    }
+    if (!found) break;
+    if (bound(m, best_state, mode) <= tau) {
+      const PlanOut p = as_plan(m, stream_planes(m, best_state), sum_of(best_state), mode, res);
+      return better(m, &p, greedy, res);
+    }
+    R0 = R0 * (1.0 - ldexp(1.0, -20));
+  }
+  return greedy;
+}
+
+}  // namespace
+
+int make_plan_with(Meta& m, int interp, bool per_region, double tau, int mode, const std::vector<int>* resident,
+                   std::vector<int>& planes, double& bound_out, int& nsteps) {
+  if (interp == INTERP_GREEDY) return make_plan(m, tau, mode, planes, bound_out, nsteps);
+  if (!(tau > 0.0)) return -1;
+  bool ok = true;
+  PlanOut p;
+  if (interp == INTERP_DP || (interp == INTERP_PAPER && per_region))
+    p = dp_plan(m, tau, mode, resident, ok);
+  else
+    p = best_first_plan(m, tau, mode, resident, ok);
+  if (!ok) return -1;
+  planes = p.planes;
+  bound_out = p.bound;
+  nsteps = p.nsteps;
+  return 0;
+}
+
 std::string meta_json(const Meta& m) {
   std::string o;
   char buf[512];
