@@ -24,6 +24,17 @@ written description) is:
 
 Fetching the first k planes reads k*C index entries, k*M magnitude words and
 the first k sign segments: bytes_j = 4*C + 8*M + 8*ceil(nsig_j / 64) per plane.
+
+Lossless stage (Section V: the coefficients are stored with bitplane
+encoding followed by lossless compression; the paper does not name the
+lossless coder).  Reading: zero-word suppression of each plane's magnitude
+words.  With nnz_j the plane's nonzero magnitude words, the plane is stored
+suppressed when 8*C + 8*ceil(C/2) + 8*nnz_j < 8*M, else raw; a suppressed
+plane is C uint64 presence words (bit i of word c set when word 64*c + i is
+nonzero), C uint32 counts of nonzero words before chunk c (zero padded to 8
+bytes), then its nonzero words in order.  A lossless blob is the index
+section, every plane's magnitude section (raw or suppressed) in plane order,
+then the sign section; bytes_j uses the plane's stored magnitude size.
 Decoding k planes yields |q| with its low B-k bits cleared (truncation toward
 zero), so the error left by a stream after k planes is
   delta(0) = max |q|,  delta(k) = 2**(B-k) - 1  (1 <= k <= B).
@@ -44,6 +55,8 @@ class StreamMeta:
     B: int
     maxabs: int
     nsig: List[int] = field(default_factory=list)
+    lossless: bool = False
+    nnz: List[int] = field(default_factory=list)   # nonzero magnitude words per plane
 
     @property
     def words(self) -> int:
@@ -53,8 +66,19 @@ class StreamMeta:
     def chunks(self) -> int:
         return (self.n + CHUNK - 1) // CHUNK
 
+    def suppressed(self, j: int) -> bool:
+        C = self.chunks
+        return self.lossless and 8 * C + 8 * ((C + 1) // 2) + 8 * self.nnz[j] < 8 * self.words
+
+    def mag_bytes(self, j: int) -> int:
+        """Stored bytes of plane j's magnitude words."""
+        if self.suppressed(j):
+            C = self.chunks
+            return 8 * C + 8 * ((C + 1) // 2) + 8 * self.nnz[j]
+        return 8 * self.words
+
     def plane_bytes(self, j: int) -> int:
-        return 4 * self.chunks + 8 * self.words + 8 * ((self.nsig[j] + 63) // 64)
+        return 4 * self.chunks + self.mag_bytes(j) + 8 * ((self.nsig[j] + 63) // 64)
 
     def delta(self, k: int) -> int:
         if k <= 0:
@@ -81,14 +105,53 @@ def _unpack_bits(buf: bytes, nbits: int) -> np.ndarray:
     return np.unpackbits(arr, bitorder="little")[:nbits].astype(np.int64)
 
 
-def encode(q: np.ndarray):
-    """Encode an int64 stream; returns (blob bytes, StreamMeta)."""
+def suppress_plane(raw: bytes, M: int, C: int) -> bytes:
+    """Zero-word suppressed form of one plane's M magnitude words."""
+    words = np.frombuffer(raw, dtype="<u8")
+    presence, counts, kept = [], [], []
+    before = 0
+    for c in range(C):
+        bits = 0
+        for i in range(64):
+            w = 64 * c + i
+            if w < M and int(words[w]) != 0:
+                bits |= 1 << i
+                kept.append(int(words[w]))
+        presence.append(bits)
+        counts.append(before)
+        before += bin(bits).count("1")
+    out = np.array(presence, dtype="<u8").tobytes()
+    cnt = np.array(counts, dtype="<u4").tobytes()
+    out += cnt + b"\0" * ((-len(cnt)) % 8)
+    return out + np.array(kept, dtype="<u8").tobytes()
+
+
+def expand_plane(sec: bytes, M: int, C: int) -> bytes:
+    """Raw magnitude words of a suppressed plane (inverse of suppress_plane)."""
+    presence = np.frombuffer(sec[: 8 * C], dtype="<u8")
+    off = 8 * C + 8 * ((C + 1) // 2)
+    kept = np.frombuffer(sec[off:], dtype="<u8")
+    words = np.zeros(M, dtype="<u8")
+    k = 0
+    for c in range(C):
+        bits = int(presence[c])
+        for i in range(64):
+            if (bits >> i) & 1:
+                words[64 * c + i] = kept[k]
+                k += 1
+    return words.tobytes()
+
+
+def encode(q: np.ndarray, lossless: bool = False):
+    """Encode an int64 stream; returns (blob bytes, StreamMeta).  With
+    ``lossless`` the magnitude planes are stored zero-word suppressed where
+    that is smaller (see the module description)."""
     q = np.asarray(q, dtype=np.int64).ravel()
     n = q.size
     mag = np.abs(q)
     maxabs = int(mag.max()) if n else 0
     B = maxabs.bit_length()
-    meta = StreamMeta(n=n, B=B, maxabs=maxabs)
+    meta = StreamMeta(n=n, B=B, maxabs=maxabs, lossless=bool(lossless))
     M, C = meta.words, meta.chunks
     blen = bitlength(mag)
     index_parts, mag_parts, sign_parts = [], [], []
@@ -105,6 +168,11 @@ def encode(q: np.ndarray):
         index_parts.append(idx.tobytes())
     index = b"".join(index_parts)
     index += b"\0" * ((-len(index)) % 8)
+    if lossless:
+        for j in range(B):
+            meta.nnz.append(int(np.count_nonzero(np.frombuffer(mag_parts[j], dtype="<u8"))))
+            if meta.suppressed(j):
+                mag_parts[j] = suppress_plane(mag_parts[j], M, C)
     blob = index + b"".join(mag_parts) + b"".join(sign_parts)
     return blob, meta
 
@@ -113,7 +181,17 @@ def section_offsets(meta: StreamMeta):
     """Byte offsets (index, magnitude, sign) of the three sections of a blob."""
     ib = 4 * meta.B * meta.chunks
     ib += (-ib) % 8
-    return 0, ib, ib + 8 * meta.B * meta.words
+    return 0, ib, ib + sum(meta.mag_bytes(j) for j in range(meta.B))
+
+
+def plane_words(blob: bytes, meta: StreamMeta, j: int) -> bytes:
+    """Raw magnitude words of plane j (expanded if stored suppressed)."""
+    _, moff, _ = section_offsets(meta)
+    start = moff + sum(meta.mag_bytes(i) for i in range(j))
+    sec = blob[start: start + meta.mag_bytes(j)]
+    if meta.suppressed(j):
+        return expand_plane(sec, meta.words, meta.chunks)
+    return sec
 
 
 def decode(blob: bytes, meta: StreamMeta, k: int) -> np.ndarray:
@@ -123,11 +201,9 @@ def decode(blob: bytes, meta: StreamMeta, k: int) -> np.ndarray:
     mag = np.zeros(n, dtype=np.int64)
     neg = np.zeros(n, dtype=bool)
     _, moff, soff = section_offsets(meta)
-    M = meta.words
     for j in range(k):
         b = B - 1 - j
-        w0 = moff + 8 * M * j
-        bits = _unpack_bits(blob[w0: w0 + 8 * M], n)
+        bits = _unpack_bits(plane_words(blob, meta, j), n)
         newsig = (mag == 0) & (bits == 1)
         nwords = (meta.nsig[j] + 63) // 64
         sbits = _unpack_bits(blob[soff: soff + 8 * nwords], meta.nsig[j])

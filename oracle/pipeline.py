@@ -162,7 +162,7 @@ def refactor(x: np.ndarray, scheme: Scheme = Scheme(), precision: Optional[int] 
         return len(ref.groups) - 1, q
 
     def add_stream(key, g, codes):
-        blob, meta = bitplane.encode(codes)
+        blob, meta = bitplane.encode(codes, lossless=scheme.lossless)
         ref.streams.append(Stream(key=key, group=g, meta=meta, blob=blob, codes=np.asarray(codes, np.int64).ravel()))
         return len(ref.streams) - 1
 
@@ -216,8 +216,10 @@ def refactor(x: np.ndarray, scheme: Scheme = Scheme(), precision: Optional[int] 
             ref.group_order.append(unit.group)
     ref.eps_fp = eps_fp(ref)
     nseg = sum(len(u.seg_bytes) for u in units if u.kind == "stair")
+    # with the lossless stage every plane also records its nonzero word count
+    per_plane = 8 if scheme.lossless else 4
     ref.meta_bytes = (64 + 16 * len(ref.groups) + 16 * len(ref.streams)
-                      + 4 * sum(st.meta.B for st in ref.streams) + 8 * nseg)
+                      + per_plane * sum(st.meta.B for st in ref.streams) + 8 * nseg)
     return ref
 
 

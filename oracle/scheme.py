@@ -3,7 +3,8 @@
 The configuration space follows Table I (tuning configurations): interpolation
 scheme (per-level, or per-region with one of the d! dimension orders),
 coefficient decomposition along one of d directions or none, and the encoding
-(generic bitplane; negabinary is not built).  Interpolation degree 3 is the
+(generic bitplane; negabinary is not built), optionally followed by the
+lossless stage on the magnitude planes (``oracle.bitplane``).  Interpolation degree 3 is the
 paper's cubic choice (Section IV); degree 1 is the multilinear form the paper
 starts from.
 """
@@ -20,6 +21,7 @@ class Scheme:
     order: Optional[Tuple[int, ...]] = None   # per-region pass order (axes); None = fastest first
     cd_axis: Optional[int] = None    # stacking axis of coefficient decomposition; None = off
     levels: Optional[int] = None     # number of levels L; None = default
+    lossless: bool = False           # zero-word suppression of the magnitude planes
 
     def pass_order(self, d: int) -> Tuple[int, ...]:
         """Order in which the d regions of a level are interpolated.
