@@ -57,6 +57,15 @@ typedef struct {
   int32_t cd_axis;   /* -1 = no coefficient decomposition, else stacking axis
                         0..ndim-1 (ndim >= 2) */
   int32_t levels;    /* 0 = default L = 1 + ceil(log2(max dim - 1)) */
+  int32_t lossless;  /* 1 = lossless stage on the stored planes (Section V:
+                        bitplanes followed by lossless compression): each
+                        plane's magnitude words are stored zero-word
+                        suppressed (C presence words, C uint32 counts of
+                        nonzero words before each chunk padded to whole
+                        words, the nonzero words) where that is smaller than
+                        its M raw words, and plane sizes, plans and blobs use
+                        the stored sizes; 0 = raw planes.  Reconstructions
+                        for the same planes are identical either way. */
 } apc_scheme;
 
 /* Retrieval target (Section III-A).  APC_EB_ABS: max|x - x'| <= value;

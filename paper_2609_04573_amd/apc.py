@@ -56,7 +56,7 @@ INTERPRETERS = {"greedy": 0, "dp": 1, "best_first": 2, "paper": 3}
 
 class _Scheme(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("order", ctypes.c_int32 * 3),
-                ("cd_axis", ctypes.c_int32), ("levels", ctypes.c_int32)]
+                ("cd_axis", ctypes.c_int32), ("levels", ctypes.c_int32), ("lossless", ctypes.c_int32)]
 
 
 class _Target(ctypes.Structure):
@@ -154,6 +154,7 @@ class Scheme:
     order: Optional[Tuple[int, ...]] = None  # per-region pass order (axes)
     cd_axis: Optional[int] = None
     levels: int = 0
+    lossless: bool = False                   # zero-word suppression of stored planes
 
     def _c(self, ndim: int) -> _Scheme:
         s = _Scheme()
@@ -164,13 +165,14 @@ class Scheme:
             s.order[i] = order[i] if i < len(order) else 0
         s.cd_axis = -1 if self.cd_axis is None else int(self.cd_axis)
         s.levels = int(self.levels or 0)
+        s.lossless = 1 if self.lossless else 0
         return s
 
     @staticmethod
     def _from_c(s: _Scheme, ndim: int) -> "Scheme":
         return Scheme(kind="level" if s.kind == PER_LEVEL else "region", degree=s.degree,
                       order=None if s.kind == PER_LEVEL else tuple(s.order[i] for i in range(ndim)),
-                      cd_axis=None if s.cd_axis < 0 else s.cd_axis, levels=s.levels)
+                      cd_axis=None if s.cd_axis < 0 else s.cd_axis, levels=s.levels, lossless=bool(s.lossless))
 
 
 @dataclass(frozen=True)

@@ -443,6 +443,7 @@ struct apc_handle {
   std::vector<int> psb;             // per stream: first entry in pso
   // stored representation
   DevBuf mag, idx, sign, pso;
+  DevBuf zoff;  // lossless stage: per-(plane, chunk) nonzero words before the chunk (layout of idx)
   // retrieval state: decoded codes and planes decoded so far per stream
   DevBuf codes, cd_codes;
   std::vector<int> k_res;
@@ -768,6 +769,7 @@ apc_status setup_geometry(apc_handle* h, const int64_t* dims, int32_t ndim, cons
   if (sc->cd_axis < -1 || sc->cd_axis >= ndim) return fail(APC_E_INVALID, "scheme.cd_axis out of range");
   if (sc->cd_axis >= 0 && ndim < 2) return fail(APC_E_INVALID, "coefficient decomposition needs 2D or 3D data");
   if (sc->levels < 0 || sc->levels > 40) return fail(APC_E_INVALID, "scheme.levels out of range");
+  if (sc->lossless != 0 && sc->lossless != 1) return fail(APC_E_INVALID, "scheme.lossless must be 0 or 1");
   if (sc->kind == APC_PER_LEVEL) {
     for (int j = 0; j < ndim; ++j) g.sigma_user[j] = ndim - 1 - j;
   } else {
@@ -800,6 +802,7 @@ void build_layout(apc_handle* h, int P) {
   m.L = L;
   m.P = P;
   m.n = g.n();
+  m.lossless = h->scheme.lossless != 0;
   h->region_off.assign((size_t)std::max(1, L) * 3, 0);
   int64_t off = 0;
   const int64_t ncoarse = (int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2];
@@ -924,6 +927,7 @@ void build_layout(apc_handle* h, int P) {
       }
     }
   }
+  for (Stream& S : m.streams) S.lossless = m.lossless;
 }
 
 // Weights of every group (exact chain norms of the user axes).
@@ -1385,6 +1389,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   std::vector<int64_t> tot((size_t)njobs);
   PendingRead rd_tot;
   DevBuf prefix, errb;
+  DevBuf zcnt, zsdb, ztot;  // lossless stage: counts, tables, totals
   // ---- sign sections: laid out on the device from the plane totals
   // (k_sign_layout), then placed; the totals come back to the host meanwhile
   // and the host repeats the layout for the metadata.  The layout tables
@@ -1453,8 +1458,81 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
                                 prefix.as<int64_t>(), errb.as<int32_t>(), st));
       LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
     }
+    // lossless stage: nonzero magnitude words per (plane, chunk), then per
+    // plane the counts before each chunk (kept for packing stored sections)
+    // and the totals, read back with the sign totals
+    std::vector<ZwsSeg> zs;
+    std::vector<StreamDev> zsd;
+    std::vector<int32_t> zjob;
+    std::vector<size_t> zof;  // encode-table entry of each lossless stream
+    int64_t zitems = 0, zcnt_n = 0;
+    for (i = 0; i < sds.size(); ++i) {
+      const int f = sd_of[i].first;
+      if (!H[f]->meta.lossless) continue;
+      ZwsSeg z{};
+      z.raw_in = sds[i].mag;
+      z.cnt = (uint32_t*)(intptr_t)zcnt_n;  // rebased below
+      z.M = sds[i].M;
+      z.C = sds[i].C;
+      z.B = sds[i].B;
+      z.blk_begin = zitems;
+      zitems += (int64_t)z.B * z.C;
+      zcnt_n += (int64_t)z.B * z.C;
+      zs.push_back(z);
+      zof.push_back(i);
+    }
+    std::vector<int64_t> ztv;
+    PendingRead rd_z;
+    if (!zs.empty()) {
+      APC_TRY(zcnt.alloc(4 * (size_t)zcnt_n));
+      for (size_t z = 0; z < zs.size(); ++z) {
+        zs[z].cnt = zcnt.as<uint32_t>() + (intptr_t)zs[z].cnt;
+        const int f = sd_of[zof[z]].first, s = sd_of[zof[z]].second;
+        apc_handle* h = H[f];
+        if (!h->zoff.p) {
+          int64_t n = 0;
+          for (const Stream& S : h->meta.streams)
+            if (S.B && S.n) n += (int64_t)S.B * S.chunks();
+          APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, n)));
+        }
+        StreamDev d = sds[zof[z]];
+        d.cnt = zs[z].cnt;
+        d.idx = h->zoff.as<uint32_t>() + h->meta.streams[s].idx_off;
+        for (int j = 0; j < d.B; ++j) zjob.push_back((int32_t)zsd.size());
+        zsd.push_back(d);
+      }
+      std::vector<int32_t> zjj(zjob.size());
+      {
+        size_t k = 0;
+        for (size_t z = 0; z < zsd.size(); ++z)
+          for (int j = 0; j < zsd[z].B; ++j) zjj[k++] = j;
+      }
+      TableBuilder tz;
+      const size_t o_zs = tz.add(zs), o_zd = tz.add(zsd), o_js = tz.add(zjob), o_jj = tz.add(zjj);
+      APC_TRY(zsdb.alloc(tz.bytes.size()));
+      APC_TRY(ztot.alloc(8 * zjob.size()));
+      APC_TRY(stage.put(tz.bytes, zsdb.p, st));
+      const char* zb = (const char*)zsdb.p;
+      double zbytes = 0;
+      for (const ZwsSeg& z : zs) zbytes += 8.0 * z.B * z.M + 4.0 * z.B * z.C;
+      LAUNCH("zws_count", zbytes, st, launch_zws((const ZwsSeg*)(zb + o_zs), (int)zs.size(), zitems, 0, st));
+      LAUNCH("zws_scan", 8.0 * zcnt_n, st,
+             launch_scan((const StreamDev*)(zb + o_zd), (const int32_t*)(zb + o_js), (const int32_t*)(zb + o_jj),
+                         (int)zjob.size(), ztot.as<int64_t>(), st));
+      ztv.assign(zjob.size(), 0);
+      APC_TRY(rd_z.start(ztv.data(), ztot.p, 8 * ztv.size(), st));
+    }
     // the same layout on the host, for the metadata
     APC_TRY(rd_tot.finish());
+    APC_TRY(rd_z.finish());
+    {
+      size_t k = 0;
+      for (size_t z = 0; z < zof.size(); ++z) {
+        Stream& S = H[sd_of[zof[z]].first]->meta.streams[sd_of[zof[z]].second];
+        S.nnz.assign(S.B, 0);
+        for (int j = 0; j < S.B; ++j) S.nnz[j] = ztv[k++];
+      }
+    }
     std::vector<int64_t> sign_words(nf, 0);
     for (int f = 0; f < nf; ++f)
       for (Stream& S : H[f]->meta.streams) {
@@ -1503,7 +1581,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     keep.push_back(std::move(t.codes));
     keep.push_back(std::move(t.cdc));
   }
-  for (DevBuf* b : {&accb, &tab, &tab2, &cntb, &stageb, &sdb, &jobs, &totals, &prefix, &errb})
+  for (DevBuf* b : {&accb, &tab, &tab2, &cntb, &stageb, &sdb, &jobs, &totals, &prefix, &errb, &zcnt, &zsdb, &ztot})
     keep.push_back(std::move(*b));
   APC_TRY(retire(std::move(keep), st));
   drain.armed = false;
@@ -2254,7 +2332,7 @@ void rep_meta(const apc_handle* h, std::vector<unsigned char>& b) {
   put<int32_t>(b, g.L);
   put<int32_t>(b, g.L);
   put<int32_t>(b, m.P);
-  put<int32_t>(b, 0);
+  put<int32_t>(b, m.lossless ? 1 : 0);
   put<double>(b, m.xmin);
   put<double>(b, m.xmax);
   put<double>(b, m.A);
@@ -2267,6 +2345,8 @@ void rep_meta(const apc_handle* h, std::vector<unsigned char>& b) {
     put<int32_t>(b, S.B);
     put<int32_t>(b, 0);
     for (int j = 0; j < S.B; ++j) put<int64_t>(b, S.nsig[j]);
+    if (m.lossless)
+      for (int j = 0; j < S.B; ++j) put<int64_t>(b, S.nnz[j]);
   }
 }
 
@@ -2318,7 +2398,7 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
   sc.cd_axis = r.get<int32_t>();
   sc.levels = r.get<int32_t>();
   const int32_t L = r.get<int32_t>(), P = r.get<int32_t>();
-  (void)r.get<int32_t>();
+  sc.lossless = r.get<int32_t>();
   const double xmin = r.get<double>(), xmax = r.get<double>(), A = r.get<double>();
   const uint32_t ng = r.get<uint32_t>(), ns = r.get<uint32_t>();
   REP_CHECK(r.ok, "metadata truncated");
@@ -2375,6 +2455,13 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
     }
     REP_CHECK(tot <= S.n, "more new-significant codes than codes");
     REP_CHECK(B == 0 || S.nsig[0] > 0, "the top plane holds no new-significant code");
+    if (S.lossless) {
+      S.nnz.assign(B, 0);
+      for (int j = 0; j < B; ++j) {
+        S.nnz[j] = r.get<int64_t>();
+        REP_CHECK(r.ok && S.nnz[j] >= 0 && S.nnz[j] <= S.words(), "nonzero word counts out of range");
+      }
+    }
   }
   REP_CHECK(r.at == r.n, "metadata section has %zu trailing bytes", r.n - r.at);
   // stream blobs
@@ -2403,6 +2490,47 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
     // index entries: per plane, counts before each chunk, starting at zero,
     // non-decreasing by at most a chunk, and within the plane's total
     const int64_t C = S.chunks();
+    if (S.lossless) {
+      // stored magnitude sections: a suppressed plane's presence words stop
+      // at its last word, its counts follow them, its kept words are nonzero
+      // and number nnz; a raw plane holds nnz nonzero words
+      const int64_t ibp = 4 * (int64_t)S.B * C + (8 - (4 * (int64_t)S.B * C) % 8) % 8;
+      const unsigned char* ms = b + ibp;
+      const int64_t M = S.words();
+      for (int j = 0; j < S.B; ++j) {
+        if (S.suppressed(j)) {
+          int64_t run = 0;
+          for (int64_t c = 0; c < C; ++c) {
+            uint64_t pw;
+            uint32_t cv;
+            memcpy(&pw, ms + 8 * c, 8);
+            memcpy(&cv, ms + 8 * C + 4 * c, 4);
+            const int64_t valid = std::min<int64_t>(64, M - 64 * c);
+            REP_CHECK(valid == 64 || (pw >> valid) == 0, "stream %d plane %d: presence past the last word", s, j);
+            REP_CHECK((int64_t)cv == run, "stream %d plane %d: chunk counts out of order", s, j);
+            run += __builtin_popcountll(pw);
+          }
+          REP_CHECK(run == S.nnz[j], "stream %d plane %d: %lld kept words, metadata says %lld", s, j, (long long)run,
+                    (long long)S.nnz[j]);
+          const unsigned char* kept = ms + 8 * S.zws_head_words();
+          for (int64_t k = 0; k < run; ++k) {
+            uint64_t v;
+            memcpy(&v, kept + 8 * k, 8);
+            REP_CHECK(v != 0, "stream %d plane %d: a kept word is zero", s, j);
+          }
+        } else {
+          int64_t nz = 0;
+          for (int64_t w = 0; w < M; ++w) {
+            uint64_t v;
+            memcpy(&v, ms + 8 * w, 8);
+            nz += v != 0;
+          }
+          REP_CHECK(nz == S.nnz[j], "stream %d plane %d: %lld nonzero words, metadata says %lld", s, j,
+                    (long long)nz, (long long)S.nnz[j]);
+        }
+        ms += 8 * S.mag_words(j);
+      }
+    }
     for (int j = 0; j < S.B; ++j) {
       uint32_t prev = 0;
       for (int64_t c = 0; c < C; ++c) {
@@ -2647,8 +2775,37 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
   const int64_t ib = 4 * (int64_t)S.B * S.chunks();
   HIP_TRY(hipMemcpy(dst, h->idx.as<uint32_t>() + S.idx_off, (size_t)ib, hipMemcpyDeviceToHost));
   const int64_t ibp = ib + (8 - ib % 8) % 8;
-  const int64_t mb = 8 * (int64_t)S.B * S.words();
-  HIP_TRY(hipMemcpy(dst + ibp, h->mag.as<uint64_t>() + S.mag_off, (size_t)mb, hipMemcpyDeviceToHost));
+  const int64_t mb = 8 * S.stored_mag_words();
+  if (!S.lossless) {
+    HIP_TRY(hipMemcpy(dst + ibp, h->mag.as<uint64_t>() + S.mag_off, (size_t)mb, hipMemcpyDeviceToHost));
+  } else {
+    // the stored sections, packed on the device from the raw planes
+    std::vector<int64_t> pmo((size_t)S.B + 1, 0);
+    uint64_t zmask = 0;
+    for (int j = 0; j < S.B; ++j) {
+      pmo[j + 1] = pmo[j] + S.mag_words(j);
+      if (S.suppressed(j)) zmask |= 1ull << j;
+    }
+    DevBuf out, tab;
+    APC_TRY(out.alloc((size_t)mb));
+    ZwsSeg z{};
+    z.raw_in = h->mag.as<uint64_t>() + S.mag_off;
+    z.zoff = h->zoff.as<uint32_t>() + S.idx_off;
+    z.comp_out = out.as<uint64_t>();
+    z.zmask = zmask;
+    z.M = S.words();
+    z.C = S.chunks();
+    z.B = S.B;
+    TableBuilder tb;
+    const size_t o_p = tb.add(pmo);
+    APC_TRY(tab.alloc(tb.bytes.size() + 256 + sizeof(ZwsSeg)));
+    z.pmo = (const int64_t*)((char*)tab.p + o_p);
+    const size_t o_z = tb.add(std::vector<ZwsSeg>{z});
+    HIP_TRY(hipMemcpy(tab.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice));
+    HIP_TRY(launch_zws((const ZwsSeg*)((char*)tab.p + o_z), 1, (int64_t)S.B * S.chunks(), 1, nullptr));
+    HIP_TRY(hipMemcpy(dst + ibp, out.p, (size_t)mb, hipMemcpyDeviceToHost));
+    HIP_TRY(hipDeviceSynchronize());  // the temporaries go back to the pool after this
+  }
   const int64_t sb = 8 * S.sign_words();
   if (sb) HIP_TRY(hipMemcpy(dst + ibp + mb, h->sign.as<uint64_t>() + S.sign_off, (size_t)sb, hipMemcpyDeviceToHost));
   return APC_OK;
@@ -2745,6 +2902,7 @@ apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_h
   APC_TRY(h->idx.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
   APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_w)));
   APC_TRY(h->pso.alloc(8 * (size_t)std::max<int64_t>(1, nplanes)));
+  if (m.lossless) APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
   std::vector<int64_t> pso((size_t)std::max<int64_t>(1, nplanes), 0);
   // copies from pageable memory: the runtime has consumed each source when
   // the call returns, and the stream is synchronized before returning
@@ -2757,9 +2915,40 @@ apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_h
     const int64_t mb = 8 * (int64_t)S.B * S.words();
     const int64_t sb = 8 * S.sign_words();
     HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, (size_t)ib, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
+    if (!S.lossless) {
+      HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
+    } else {
+      // stored sections uploaded as they are, expanded to raw planes on the device
+      const int64_t smb = 8 * S.stored_mag_words();
+      std::vector<int64_t> pmo((size_t)S.B + 1, 0);
+      uint64_t zmask = 0;
+      for (int j = 0; j < S.B; ++j) {
+        pmo[j + 1] = pmo[j] + S.mag_words(j);
+        if (S.suppressed(j)) zmask |= 1ull << j;
+      }
+      DevBuf in, tab;
+      APC_TRY(in.alloc((size_t)smb));
+      HIP_TRY(hipMemcpyAsync(in.p, b + ibp, (size_t)smb, hipMemcpyHostToDevice, st));
+      ZwsSeg z{};
+      z.raw_out = h->mag.as<uint64_t>() + S.mag_off;
+      z.zoff = h->zoff.as<uint32_t>() + S.idx_off;
+      z.comp_in = in.as<uint64_t>();
+      z.zmask = zmask;
+      z.M = S.words();
+      z.C = S.chunks();
+      z.B = S.B;
+      TableBuilder tb;
+      const size_t o_p = tb.add(pmo);
+      APC_TRY(tab.alloc(tb.bytes.size() + 256 + sizeof(ZwsSeg)));
+      z.pmo = (const int64_t*)((char*)tab.p + o_p);
+      const size_t o_z = tb.add(std::vector<ZwsSeg>{z});
+      HIP_TRY(hipMemcpyAsync(tab.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_zws((const ZwsSeg*)((char*)tab.p + o_z), 1, (int64_t)S.B * S.chunks(), 2, st));
+      HIP_TRY(hipStreamSynchronize(st));  // before the temporaries go back to the pool
+    }
+    const int64_t mbs = 8 * S.stored_mag_words();
     if (sb)
-      HIP_TRY(hipMemcpyAsync(h->sign.as<uint64_t>() + S.sign_off, b + ibp + mb, (size_t)sb, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(h->sign.as<uint64_t>() + S.sign_off, b + ibp + mbs, (size_t)sb, hipMemcpyHostToDevice, st));
     for (int j = 0; j < S.B; ++j) pso[(size_t)h->psb[s] + j] = S.pso[j];
   }
   HIP_TRY(hipMemcpyAsync(h->pso.p, pso.data(), 8 * pso.size(), hipMemcpyHostToDevice, st));

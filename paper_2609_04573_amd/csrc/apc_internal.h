@@ -138,6 +138,26 @@ struct StreamDev {
   int32_t fresh;        // decode: resident codes are all zero (skip reading them)
 };
 
+// Lossless stage of one stream's magnitude planes (zero-word suppression):
+// work items are (plane, chunk) pairs, item i of the stream = plane i / C,
+// chunk i % C.  A suppressed plane's stored section is C presence words
+// (bit i of word c: raw word 64c + i is nonzero), C uint32 counts of nonzero
+// words before chunk c (padded to whole words) and the nonzero words; a raw
+// plane's section is its M words.
+struct ZwsSeg {
+  const uint64_t* raw_in;    // count, pack: the raw planes (B x M words)
+  uint64_t* raw_out;         // unpack: the raw planes
+  uint32_t* cnt;             // count: nonzero words per (chunk, plane), chunk-major (C x B)
+  uint32_t* zoff;            // pack: per-(plane, chunk) counts before the chunk (read); unpack: written
+  uint64_t* comp_out;        // pack: the stored sections of every plane
+  const uint64_t* comp_in;   // unpack: the stored sections
+  const int64_t* pmo;        // pack, unpack: word offset of each plane's stored section
+  uint64_t zmask;            // bit j: plane j is stored suppressed
+  int64_t M, C;
+  int64_t blk_begin;         // first global item of this stream
+  int32_t B, pad;
+};
+
 // Sign-section layout, computed on the device from the per-(stream, plane)
 // sign counts.  Jobs are the (stream, plane) pairs in stream order, planes
 // most significant first; streams are the encode table's entries.
@@ -189,6 +209,8 @@ hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* j
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
 hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, int max_planes, hipStream_t s);
+// mode 0: count nonzero words; 1: pack the stored sections; 2: unpack them
+hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T>

@@ -36,6 +36,11 @@ struct Stream {
   std::vector<int64_t> nsig;  // per plane (most significant first)
   std::vector<int64_t> pso;   // per plane: sign words before it in this stream
   int64_t mag_off = 0, idx_off = 0, sign_off = 0;
+  // lossless stage: nonzero magnitude words per plane; a plane is stored
+  // zero-word suppressed (presence words, per-chunk counts, nonzero words)
+  // where that is smaller than its raw words
+  bool lossless = false;
+  std::vector<int64_t> nnz;
 
   int64_t words() const { return (n + 63) / 64; }
   int64_t chunks() const { return (n + 4095) / 4096; }
@@ -44,15 +49,23 @@ struct Stream {
     for (int64_t v : nsig) s += (v + 63) / 64;
     return s;
   }
-  int64_t plane_bytes(int j) const { return 4 * chunks() + 8 * words() + 8 * ((nsig[j] + 63) / 64); }
+  int64_t zws_head_words() const { return chunks() + (chunks() + 1) / 2; }
+  bool suppressed(int j) const { return lossless && 8 * (zws_head_words() + nnz[j]) < 8 * words(); }
+  int64_t mag_words(int j) const { return suppressed(j) ? zws_head_words() + nnz[j] : words(); }
+  int64_t plane_bytes(int j) const { return 4 * chunks() + 8 * mag_words(j) + 8 * ((nsig[j] + 63) / 64); }
   int64_t delta(int k) const {
     if (k <= 0) return maxabs;
     return (int64_t)((1ull << (B - k)) - 1ull);
   }
+  int64_t stored_mag_words() const {
+    int64_t w = 0;
+    for (int j = 0; j < B; ++j) w += mag_words(j);
+    return w;
+  }
   int64_t blob_bytes() const {
     int64_t ib = 4 * (int64_t)B * chunks();
     ib += (8 - ib % 8) % 8;
-    return ib + 8 * (int64_t)B * words() + 8 * sign_words();
+    return ib + 8 * stored_mag_words() + 8 * sign_words();
   }
 };
 
@@ -66,6 +79,7 @@ struct Unit {
 
 struct Meta {
   int d = 3, L = 1, P = 29;
+  bool lossless = false;  // planes stored through the lossless stage
   int64_t n = 0;
   double xmin = 0, xmax = 0, A = 0;
   double eps_fp = 0;

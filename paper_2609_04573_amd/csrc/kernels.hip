@@ -1788,6 +1788,66 @@ __global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* _
   }
 }
 
+// ------------------------------------------------ lossless stage (zero words)
+// One wave per (stream, plane, chunk) item, lane per magnitude word of the
+// chunk; a ballot over the lanes gives the chunk's presence word.
+// MODE 0: nonzero words per (chunk, plane) into cnt (the index scan then
+// gives each chunk's count before it and the plane's total).  MODE 1: the
+// stored section of every plane (suppressed: presence word and count by lane
+// 0, each nonzero word at its rank; raw: every word).  MODE 2: the raw words
+// back from the stored sections (and the counts into zoff, for a later
+// MODE 1).  Wave-uniform branches only (on the plane's storage kind).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_zws(const ZwsSeg* __restrict__ segs, int nseg, int64_t items) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); it < items; it += waves) {
+    const int si = find_seg(segs, nseg, it);
+    const ZwsSeg& S = segs[si];
+    const int64_t i = it - S.blk_begin;
+    const int64_t C = S.C, M = S.M;
+    const int j = (int)(i / C);
+    const int64_t c = i - (int64_t)j * C;
+    const int64_t w = 64 * c + lane;
+    const bool inw = w < M;
+    const bool sup = (S.zmask >> j) & 1ull;
+    if (MODE == 0 || MODE == 1) {
+      const GAS uint64_t* raw = (const GAS uint64_t*)S.raw_in + (int64_t)j * M;
+      const uint64_t v = inw ? raw[w] : 0ull;
+      const uint64_t nz = __ballot(v != 0ull);
+      if (MODE == 0) {
+        if (lane == 0) ((GAS uint32_t*)S.cnt)[c * S.B + j] = (uint32_t)__popcll(nz);
+      } else {
+        GAS uint64_t* out = (GAS uint64_t*)S.comp_out + S.pmo[j];
+        if (sup) {
+          const uint32_t before = ((const GAS uint32_t*)S.zoff)[(int64_t)j * C + c];
+          if (lane == 0) {
+            out[c] = nz;
+            ((GAS uint32_t*)(out + C))[c] = before;
+            if (c == C - 1 && (C & 1)) ((GAS uint32_t*)(out + C))[C] = 0u;  // padding of the counts
+          }
+          if (v != 0ull) out[C + (C + 1) / 2 + before + __popcll(nz & lanemask_lt(lane))] = v;
+        } else if (inw) {
+          out[w] = v;
+        }
+      }
+    } else {
+      const GAS uint64_t* in = (const GAS uint64_t*)S.comp_in + S.pmo[j];
+      GAS uint64_t* raw = (GAS uint64_t*)S.raw_out + (int64_t)j * M;
+      if (sup) {
+        const uint64_t nz = in[c];
+        const uint32_t before = ((const GAS uint32_t*)(in + C))[c];
+        const bool has = (nz >> lane) & 1ull;
+        const uint64_t v = has ? in[C + (C + 1) / 2 + before + __popcll(nz & lanemask_lt(lane))] : 0ull;
+        if (inw) raw[w] = v;
+        if (lane == 0) ((GAS uint32_t*)S.zoff)[(int64_t)j * C + c] = before;
+      } else if (inw) {
+        raw[w] = in[w];
+      }
+    }
+  }
+}
+
 // Bits [pos, pos + nb) of a little-endian bit string held in words w.
 __device__ __forceinline__ uint64_t extract_bits(const uint64_t* w, int pos, int nb, int nwords) {
   const int w0 = pos >> 6, sh = pos & 63;
@@ -2333,6 +2393,17 @@ hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* j
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sign_move, dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  return hipGetLastError();
+}
+hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, (int64_t)kMaxGrid);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_zws<0>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_zws<1>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
+  else
+    hipLaunchKernelGGL(k_zws<2>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
   return hipGetLastError();
 }
 template <typename Q>

@@ -227,7 +227,9 @@ void finalize_meta(Meta& m) {
   for (const Unit& u : m.units)
     if (u.stair) nseg += (int64_t)u.seg_bytes.size();
   for (const Stream& s : m.streams) sumB += s.B;
-  m.meta_bytes = 64 + 16 * (int64_t)m.groups.size() + 16 * (int64_t)m.streams.size() + 4 * sumB + 8 * nseg;
+  // with the lossless stage every plane also records its nonzero word count
+  m.meta_bytes = 64 + 16 * (int64_t)m.groups.size() + 16 * (int64_t)m.streams.size() + (m.lossless ? 8 : 4) * sumB +
+                 8 * nseg;
   m.seq_ready[0] = m.seq_ready[1] = false;
 }
 
@@ -591,7 +593,13 @@ std::string meta_json(const Meta& m) {
     add("%s{\"kind\":%d,\"level\":%d,\"rho\":%d,\"t\":%d,\"group\":%d,\"n\":%lld,\"B\":%d,\"maxabs\":%lld,\"nsig\":[",
         s ? "," : "", st.kind, st.level, st.rho, st.t, st.group, (long long)st.n, st.B, (long long)st.maxabs);
     for (size_t j = 0; j < st.nsig.size(); ++j) add("%s%lld", j ? "," : "", (long long)st.nsig[j]);
-    o += "]}";
+    o += "]";
+    if (st.lossless) {
+      o += ",\"nnz\":[";
+      for (size_t j = 0; j < st.nnz.size(); ++j) add("%s%lld", j ? "," : "", (long long)st.nnz[j]);
+      o += "]";
+    }
+    o += "}";
   }
   o += "],\"units\":[";
   for (size_t u = 0; u < m.units.size(); ++u) {

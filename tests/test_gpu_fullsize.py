@@ -84,20 +84,23 @@ def test_fullsize_512_matches_oracle(field512):
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("dtype,scheme", [
-    (np.float32, ("level", 3, None, 0)),
-    (np.float64, ("level", 3, None, 0)),
-    (np.float32, ("level", 1, None, 1)),
-    (np.float32, ("region", 3, (2, 1, 0), None)),
+    (np.float32, ("level", 3, None, 0, False)),
+    (np.float64, ("level", 3, None, 0, False)),
+    (np.float32, ("level", 1, None, 1, False)),
+    (np.float32, ("region", 3, (2, 1, 0), None, False)),
+    (np.float32, ("level", 3, None, 0, True)),
 ], ids=str)
 def test_slab_16_plane_runs_match_oracle(dtype, scheme):
     """64x512x512: level 0 of the per-level sweep runs 16 planes per block
     along axis 0 (the run is shortened from 128 only as far as 1024 blocks
-    per level need), so every pass of the sweep takes its multi-step path."""
+    per level need), so every pass of the sweep takes its multi-step path;
+    the last case adds the lossless stage (stored plane sections of many
+    chunks)."""
     apc = _apc()
     x = fieldgen.power_law_field((64, 512, 512), seed=31, dtype=dtype)
-    kind, degree, order, cd = scheme
-    _compare_with_oracle(apc, x, apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
-                         oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
+    kind, degree, order, cd, ll = scheme
+    _compare_with_oracle(apc, x, apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=ll),
+                         oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=ll),
                          [("rel", 1e-3), ("rel", 1e-6), ("psnr", 80)])
 
 

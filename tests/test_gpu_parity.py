@@ -33,10 +33,10 @@ def _apc():
     return apc
 
 
-def _schemes(kind, degree, order, cd):
+def _schemes(kind, degree, order, cd, lossless=False):
     apc = _apc()
-    return (apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd),
-            oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd))
+    return (apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless),
+            oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless))
 
 
 def _bits(a):
@@ -57,6 +57,7 @@ def _check_metadata(h, ref):
     for gs, os_ in zip(md["streams"], ref.streams):
         assert gs["n"] == os_.meta.n and gs["B"] == os_.meta.B and gs["maxabs"] == os_.meta.maxabs
         assert gs["nsig"] == os_.meta.nsig
+        assert gs.get("nnz", []) == os_.meta.nnz
     assert md["eps_fp"] == ref.eps_fp
     assert md["meta_bytes"] == ref.meta_bytes
 
@@ -104,6 +105,24 @@ def test_config1_parity(config1_field, scheme):
     x = config1_field
     gs, os_ = _schemes(*scheme)
     ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    _check_retrievals(h, ref, x)
+    h.close()
+
+
+@pytest.mark.parametrize("scheme", [("level", 3, None, 0), ("region", 3, (1, 2, 0), None), ("region", 1, None, 2),
+                                    ("level", 3, None, None)], ids=str)
+def test_config1_lossless_parity(config1_field, scheme):
+    """The lossless stage: nonzero word counts, stored (suppressed or raw)
+    plane sections, plans on the stored sizes and reconstructions, bit for
+    bit."""
+    apc = _apc()
+    x = config1_field
+    gs, os_ = _schemes(*scheme, lossless=True)
+    ref = oracle.refactor(x, os_)
+    assert any(st.meta.suppressed(j) for st in ref.streams for j in range(st.meta.B))
     h = apc.refactor(torch.from_numpy(x).cuda(), gs)
     _check_metadata(h, ref)
     _check_streams(h, ref)

@@ -37,13 +37,15 @@ def oracle_bytes(ref) -> bytes:
     order = list(ref.sigma) + [0] * (3 - d)
     meta += struct.pack("<7i", 0 if sc.kind == "level" else 1, sc.degree, *order,
                         -1 if sc.cd_axis is None else sc.cd_axis, ref.L)
-    meta += struct.pack("<iii", ref.L, ref.P, 0)
+    meta += struct.pack("<iii", ref.L, ref.P, 1 if sc.lossless else 0)
     meta += struct.pack("<3d", ref.xmin, ref.xmax, ref.A)
     meta += struct.pack("<II", len(ref.groups), len(ref.streams))
     meta += b"".join(struct.pack("<d", g.M) for g in ref.groups)
     for st in ref.streams:
         m = st.meta
         meta += struct.pack("<qqii", m.n, m.maxabs, m.B, 0) + b"".join(struct.pack("<q", v) for v in m.nsig)
+        if sc.lossless:
+            meta += b"".join(struct.pack("<q", v) for v in m.nnz)
     body = b""
     for st in ref.streams:
         body += struct.pack("<QQ", len(st.blob), rep_hash(st.blob)) + st.blob
@@ -64,7 +66,9 @@ def cases():
     out = []
     for x, sc in ((x1, oracle.Scheme(kind="level", cd_axis=0)), (x1, oracle.Scheme(kind="region", order=(1, 2, 0))),
                   (x2, oracle.Scheme(kind="region", order=(0, 1), cd_axis=1)),
-                  (x3, oracle.Scheme(kind="level", degree=1, cd_axis=2))):
+                  (x3, oracle.Scheme(kind="level", degree=1, cd_axis=2)),
+                  (x1, oracle.Scheme(kind="level", cd_axis=0, lossless=True)),
+                  (x3, oracle.Scheme(kind="region", order=(2, 0, 1), lossless=True))):
         ref = oracle.refactor(x, sc)
         out.append((x, sc, ref, oracle_bytes(ref)))
     return out
@@ -118,6 +122,37 @@ def test_damaged_bytes_are_refused(cases):
     _corrupt(apc, forged)
 
 
+def test_damaged_lossless_sections_are_refused(cases):
+    """A suppressed plane whose presence word, chunk count or kept word is
+    altered (checksum rewritten) is refused by the section checks."""
+    apc = _apc()
+    _, _, ref, data = cases[4]
+    assert ref.scheme.lossless
+    mlen = struct.unpack("<Q", data[16:24])[0]
+    at = 32 + mlen
+    for st in ref.streams:
+        m = st.meta
+        if m.B and m.suppressed(0) and m.nnz[0] > 0:
+            ib = 4 * m.B * m.chunks
+            ib += (-ib) % 8
+            head = 8 * (m.chunks + (m.chunks + 1) // 2)  # presence words and chunk counts
+            for pos, word in ((ib, 0), (ib + 8 * m.chunks, 1), (ib + head, 2)):
+                b = bytearray(st.blob)
+                if word == 0:
+                    b[pos + 7] ^= 0x80  # a presence bit (past the last word when the chunk is short)
+                elif word == 1:
+                    struct.pack_into("<I", b, pos, 7)  # chunk 0's count must be 0
+                else:
+                    struct.pack_into("<Q", b, pos, 0)  # a kept word that is zero
+                forged = bytearray(data)
+                forged[at:at + 16] = struct.pack("<QQ", len(b), rep_hash(bytes(b)))
+                forged[at + 16:at + 16 + len(b)] = b
+                _corrupt(apc, bytes(forged))
+            return
+        at += 16 + len(st.blob)
+    pytest.fail("no suppressed plane")
+
+
 def test_index_entries_out_of_order_are_refused(cases):
     """A blob whose index section is altered, with its checksum rewritten,
     is refused by the index checks (the decoder reads sign words at the
@@ -145,7 +180,7 @@ def test_serialized_bytes_equal_the_oracle_and_round_trip(cases):
 
     apc = _apc()
     for x, sc, ref, data in cases:
-        gs = apc.Scheme(kind=sc.kind, degree=sc.degree, order=sc.order, cd_axis=sc.cd_axis)
+        gs = apc.Scheme(kind=sc.kind, degree=sc.degree, order=sc.order, cd_axis=sc.cd_axis, lossless=sc.lossless)
         h = apc.refactor(torch.from_numpy(x).cuda(), gs)
         got = h.serialize()
         assert got == data, "serialized bytes differ from the oracle-written layout"
