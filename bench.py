@@ -328,7 +328,7 @@ def serve_leg(apc, torch, fieldgen, quick: bool):
            "rates": {}}
     for ri, rate in enumerate(rates):
         res = {}
-        for slots, batch, name in ((4, 16, "continuous"), (1, 1, "fifo")):
+        for slots, batch, name in ((2, 8, "continuous"), (1, 1, "fifo")):
             hs = apc.refactor_batch(xs, schemes)
             srv = apc.Server(hs, budget_bytes=4 << 30, max_slots=slots, max_batch=batch)
             rng = np.random.default_rng(100 + ri)
@@ -428,6 +428,47 @@ def region_and_f64_legs(apc, torch, x512):
     del xd, x64
     torch.cuda.empty_cache()
     return reg, f64
+
+
+def rate_leg(apc, torch, x512):
+    """Bit-rate of the 512^3 field at rel 1e-4 (and 1e-2, 1e-6): without and
+    with the lossless stage, planned by the greedy interpreter and by the
+    paper's (best-first search for this per-level scheme); refactor and first
+    retrieval times with the lossless stage.  Every plan's reconstruction is
+    checked against its bound."""
+    xd = torch.from_numpy(x512).cuda()
+    xf = xd.double()
+    rng = float(xf.max() - xf.min())
+    n = xd.numel()
+    out = {"workload": "512^3 float32 k^-5/3 (seed 1); per-level cubic + decomposition axis 0", "rates": {}}
+    for ll in (False, True):
+        sc = apc.Scheme(kind="level", cd_axis=0, lossless=ll)
+        h = apc.refactor(xd, sc)
+        torch.cuda.synchronize()
+        stored = sum(h.stream_info(s)["blob_bytes"] for s in range(h.num_streams))
+        key = "lossless" if ll else "plain"
+        res = {"stored_bytes": stored, "stored_bits_per_value": 8.0 * stored / n}
+        for interp in ("greedy", "paper"):
+            h.set_interpreter(interp)
+            for rel in (1e-2, 1e-4, 1e-6):
+                t0 = time.perf_counter()
+                _, info = h.plan(apc.Target("rel", rel))
+                t_plan = time.perf_counter() - t0
+                fresh = apc.refactor(xd, sc)
+                fresh.set_interpreter(interp)
+                o, rinfo = fresh.retrieve(apc.Target("rel", rel))
+                err = float((o.double() - xf).abs().max())
+                assert err <= rel * rng, "retrieval violated its error bound"
+                fresh.close()
+                res[f"{interp} rel {rel:g}"] = {"plan_bytes": info["bytes_total"], "bitrate": info["bitrate"],
+                                                "plan_ms": t_plan * 1e3, "max_error": err}
+        h.close()
+        if ll:
+            res["timing"] = _time_pipeline(apc, torch, xd, sc, [apc.Target("rel", 1e-4)], reps=3)
+        out["rates"][key] = res
+    del xd, xf
+    torch.cuda.empty_cache()
+    return out
 
 
 def scale_leg(apc, torch, fieldgen, quick: bool):
@@ -689,6 +730,8 @@ def main():
     if not args.no_systems:
         line["region_512"], line["f64_256"] = region_and_f64_legs(apc, torch, x)
         log("per-region 512^3 and float64 256^3 legs done")
+        line["rate_512"] = rate_leg(apc, torch, x)
+        log("bit-rate leg done")
         line["batch"] = batch_leg(apc, torch, fieldgen, args.quick)
         log("batch leg done")
         line["config5"] = scale_leg(apc, torch, fieldgen, args.quick)

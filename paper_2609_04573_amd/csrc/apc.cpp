@@ -1389,7 +1389,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   std::vector<int64_t> tot((size_t)njobs);
   PendingRead rd_tot;
   DevBuf prefix, errb;
-  DevBuf zcnt, zsdb, ztot;  // lossless stage: counts, tables, totals
+  DevBuf zcnt, ztot;  // lossless stage: per-chunk nonzero words, per-plane totals
   // ---- sign sections: laid out on the device from the plane totals
   // (k_sign_layout), then placed; the totals come back to the host meanwhile
   // and the host repeats the layout for the metadata.  The layout tables
@@ -1436,12 +1436,49 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       sds[i].sign_n = 0;
       sb += 512.0 * sds[i].C + 8.0 * (sds[i].n / 64 + sds[i].B);
     }
+    // lossless stage: the encoder counts each chunk's nonzero words per plane
+    // (zcnt); a scan gives per plane the counts before each chunk (kept on
+    // the handle for packing stored sections) and the totals, read back with
+    // the sign totals
+    std::vector<StreamDev> zsd;
+    std::vector<int32_t> zjs, zjj;
+    std::vector<size_t> zof;  // encode-table entry of each lossless stream
+    int64_t zcnt_n = 0;
+    for (i = 0; i < sds.size(); ++i)
+      if (H[sd_of[i].first]->meta.lossless) zcnt_n += (int64_t)sds[i].B * sds[i].C;
+    if (zcnt_n) APC_TRY(zcnt.alloc(4 * (size_t)zcnt_n));
+    zcnt_n = 0;
+    for (i = 0; i < sds.size(); ++i) {
+      const int f = sd_of[i].first, s = sd_of[i].second;
+      apc_handle* h = H[f];
+      if (!h->meta.lossless) continue;
+      if (!h->zoff.p) {
+        int64_t nz = 0;
+        for (const Stream& S : h->meta.streams)
+          if (S.B && S.n) nz += (int64_t)S.B * S.chunks();
+        APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, nz)));
+      }
+      sds[i].zcnt = zcnt.as<uint32_t>() + zcnt_n;
+      zcnt_n += (int64_t)sds[i].B * sds[i].C;
+      StreamDev d = sds[i];
+      d.cnt = sds[i].zcnt;
+      d.idx = h->zoff.as<uint32_t>() + h->meta.streams[s].idx_off;
+      for (int j = 0; j < d.B; ++j) {
+        zjs.push_back((int32_t)zsd.size());
+        zjj.push_back(j);
+      }
+      zsd.push_back(d);
+      zof.push_back(i);
+    }
+    std::vector<int64_t> ztv(zjs.size(), 0);
+    PendingRead rd_z;
     if (!sds.empty()) {
       TableBuilder tb3;
       const size_t o_sd = tb3.add(sds);
       const size_t o_job = tb3.add(job);
       const size_t o_sj = tb3.add(sj);
       const size_t o_ss = tb3.add(ss);
+      const size_t o_zd = tb3.add(zsd), o_zs = tb3.add(zjs), o_zj = tb3.add(zjj);
       APC_TRY(sdb.alloc(tb3.bytes.size()));
       APC_TRY(totals.alloc(8 * (size_t)njobs));
       APC_TRY(prefix.alloc(8 * ((size_t)njobs + 1)));
@@ -1452,75 +1489,19 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
       LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
       APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
+      if (!zsd.empty()) {
+        APC_TRY(ztot.alloc(8 * ztv.size()));
+        const char* zb = (const char*)sdb.p;
+        LAUNCH("zws_scan", 8.0 * zcnt_n, st,
+               launch_scan((const StreamDev*)(zb + o_zd), (const int32_t*)(zb + o_zs), (const int32_t*)(zb + o_zj),
+                           (int)zjs.size(), ztot.as<int64_t>(), st));
+        APC_TRY(rd_z.start(ztv.data(), ztot.p, 8 * ztv.size(), st));
+      }
       LAUNCH("sign_layout", 16.0 * njobs, st,
              launch_sign_layout(totals.as<int64_t>(), njobs, (const SignJob*)((const char*)sdb.p + o_sj),
                                 (int)sds.size(), (const SignStream*)((const char*)sdb.p + o_ss), sdd,
                                 prefix.as<int64_t>(), errb.as<int32_t>(), st));
       LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
-    }
-    // lossless stage: nonzero magnitude words per (plane, chunk), then per
-    // plane the counts before each chunk (kept for packing stored sections)
-    // and the totals, read back with the sign totals
-    std::vector<ZwsSeg> zs;
-    std::vector<StreamDev> zsd;
-    std::vector<int32_t> zjob;
-    std::vector<size_t> zof;  // encode-table entry of each lossless stream
-    int64_t zitems = 0, zcnt_n = 0;
-    for (i = 0; i < sds.size(); ++i) {
-      const int f = sd_of[i].first;
-      if (!H[f]->meta.lossless) continue;
-      ZwsSeg z{};
-      z.raw_in = sds[i].mag;
-      z.cnt = (uint32_t*)(intptr_t)zcnt_n;  // rebased below
-      z.M = sds[i].M;
-      z.C = sds[i].C;
-      z.B = sds[i].B;
-      z.blk_begin = zitems;
-      zitems += (int64_t)z.B * z.C;
-      zcnt_n += (int64_t)z.B * z.C;
-      zs.push_back(z);
-      zof.push_back(i);
-    }
-    std::vector<int64_t> ztv;
-    PendingRead rd_z;
-    if (!zs.empty()) {
-      APC_TRY(zcnt.alloc(4 * (size_t)zcnt_n));
-      for (size_t z = 0; z < zs.size(); ++z) {
-        zs[z].cnt = zcnt.as<uint32_t>() + (intptr_t)zs[z].cnt;
-        const int f = sd_of[zof[z]].first, s = sd_of[zof[z]].second;
-        apc_handle* h = H[f];
-        if (!h->zoff.p) {
-          int64_t n = 0;
-          for (const Stream& S : h->meta.streams)
-            if (S.B && S.n) n += (int64_t)S.B * S.chunks();
-          APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, n)));
-        }
-        StreamDev d = sds[zof[z]];
-        d.cnt = zs[z].cnt;
-        d.idx = h->zoff.as<uint32_t>() + h->meta.streams[s].idx_off;
-        for (int j = 0; j < d.B; ++j) zjob.push_back((int32_t)zsd.size());
-        zsd.push_back(d);
-      }
-      std::vector<int32_t> zjj(zjob.size());
-      {
-        size_t k = 0;
-        for (size_t z = 0; z < zsd.size(); ++z)
-          for (int j = 0; j < zsd[z].B; ++j) zjj[k++] = j;
-      }
-      TableBuilder tz;
-      const size_t o_zs = tz.add(zs), o_zd = tz.add(zsd), o_js = tz.add(zjob), o_jj = tz.add(zjj);
-      APC_TRY(zsdb.alloc(tz.bytes.size()));
-      APC_TRY(ztot.alloc(8 * zjob.size()));
-      APC_TRY(stage.put(tz.bytes, zsdb.p, st));
-      const char* zb = (const char*)zsdb.p;
-      double zbytes = 0;
-      for (const ZwsSeg& z : zs) zbytes += 8.0 * z.B * z.M + 4.0 * z.B * z.C;
-      LAUNCH("zws_count", zbytes, st, launch_zws((const ZwsSeg*)(zb + o_zs), (int)zs.size(), zitems, 0, st));
-      LAUNCH("zws_scan", 8.0 * zcnt_n, st,
-             launch_scan((const StreamDev*)(zb + o_zd), (const int32_t*)(zb + o_js), (const int32_t*)(zb + o_jj),
-                         (int)zjob.size(), ztot.as<int64_t>(), st));
-      ztv.assign(zjob.size(), 0);
-      APC_TRY(rd_z.start(ztv.data(), ztot.p, 8 * ztv.size(), st));
     }
     // the same layout on the host, for the metadata
     APC_TRY(rd_tot.finish());
@@ -1581,7 +1562,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     keep.push_back(std::move(t.codes));
     keep.push_back(std::move(t.cdc));
   }
-  for (DevBuf* b : {&accb, &tab, &tab2, &cntb, &stageb, &sdb, &jobs, &totals, &prefix, &errb, &zcnt, &zsdb, &ztot})
+  for (DevBuf* b : {&accb, &tab, &tab2, &cntb, &stageb, &sdb, &jobs, &totals, &prefix, &errb, &zcnt, &ztot})
     keep.push_back(std::move(*b));
   APC_TRY(retire(std::move(keep), st));
   drain.armed = false;

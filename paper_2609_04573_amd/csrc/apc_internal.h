@@ -127,6 +127,7 @@ struct StreamDev {
   uint64_t* mag;        // magnitude section (B*M words)
   uint32_t* idx;        // index section (B*C entries)
   uint32_t* cnt;        // per-chunk counts scratch (C*B, chunk-major, refactor)
+  uint32_t* zcnt;       // lossless stage: nonzero words per (chunk, plane), chunk-major (refactor), or null
   uint64_t* stage;      // sign staging scratch (64 words per chunk, refactor)
   uint64_t* sign;       // sign section
   const int64_t* pso;   // per plane: sign words before it
@@ -145,9 +146,8 @@ struct StreamDev {
 // words before chunk c (padded to whole words) and the nonzero words; a raw
 // plane's section is its M words.
 struct ZwsSeg {
-  const uint64_t* raw_in;    // count, pack: the raw planes (B x M words)
+  const uint64_t* raw_in;    // pack: the raw planes (B x M words)
   uint64_t* raw_out;         // unpack: the raw planes
-  uint32_t* cnt;             // count: nonzero words per (chunk, plane), chunk-major (C x B)
   uint32_t* zoff;            // pack: per-(plane, chunk) counts before the chunk (read); unpack: written
   uint64_t* comp_out;        // pack: the stored sections of every plane
   const uint64_t* comp_in;   // unpack: the stored sections
@@ -209,7 +209,7 @@ hipError_t launch_sign_layout(const int64_t* totals, int njobs, const SignJob* j
 hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
 hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, int max_planes, hipStream_t s);
-// mode 0: count nonzero words; 1: pack the stored sections; 2: unpack them
+// mode 1: pack the stored sections; 2: unpack them
 hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);

@@ -1657,6 +1657,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) ==
     cc[b] = b < B ? (uint32_t)__popcll(pw & ~sig) : 0u;
     incl[b] = cc[b];
     sig |= pw;
+    // lossless stage: this chunk's nonzero words of the plane
+    if (S.zcnt && b < B && lane == 0)
+      ((GAS uint32_t*)S.zcnt)[chunk * B + (B - 1 - b)] = (uint32_t)__popcll(__ballot(pw != 0ull));
   }
   wave_incl_scan_n<MAXB>(incl);
   uint32_t toff = 0, mycnt = 0;
@@ -1791,8 +1794,8 @@ __global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* _
 // ------------------------------------------------ lossless stage (zero words)
 // One wave per (stream, plane, chunk) item, lane per magnitude word of the
 // chunk; a ballot over the lanes gives the chunk's presence word.
-// MODE 0: nonzero words per (chunk, plane) into cnt (the index scan then
-// gives each chunk's count before it and the plane's total).  MODE 1: the
+// (The encoder counts each chunk's nonzero words per plane; the index scan
+// gives each chunk's count before it and the plane's total.)  MODE 1: the
 // stored section of every plane (suppressed: presence word and count by lane
 // 0, each nonzero word at its rank; raw: every word).  MODE 2: the raw words
 // back from the stored sections (and the counts into zoff, for a later
@@ -1811,25 +1814,21 @@ __global__ __launch_bounds__(256) void k_zws(const ZwsSeg* __restrict__ segs, in
     const int64_t w = 64 * c + lane;
     const bool inw = w < M;
     const bool sup = (S.zmask >> j) & 1ull;
-    if (MODE == 0 || MODE == 1) {
+    if (MODE == 1) {
       const GAS uint64_t* raw = (const GAS uint64_t*)S.raw_in + (int64_t)j * M;
       const uint64_t v = inw ? raw[w] : 0ull;
       const uint64_t nz = __ballot(v != 0ull);
-      if (MODE == 0) {
-        if (lane == 0) ((GAS uint32_t*)S.cnt)[c * S.B + j] = (uint32_t)__popcll(nz);
-      } else {
-        GAS uint64_t* out = (GAS uint64_t*)S.comp_out + S.pmo[j];
-        if (sup) {
-          const uint32_t before = ((const GAS uint32_t*)S.zoff)[(int64_t)j * C + c];
-          if (lane == 0) {
-            out[c] = nz;
-            ((GAS uint32_t*)(out + C))[c] = before;
-            if (c == C - 1 && (C & 1)) ((GAS uint32_t*)(out + C))[C] = 0u;  // padding of the counts
-          }
-          if (v != 0ull) out[C + (C + 1) / 2 + before + __popcll(nz & lanemask_lt(lane))] = v;
-        } else if (inw) {
-          out[w] = v;
+      GAS uint64_t* out = (GAS uint64_t*)S.comp_out + S.pmo[j];
+      if (sup) {
+        const uint32_t before = ((const GAS uint32_t*)S.zoff)[(int64_t)j * C + c];
+        if (lane == 0) {
+          out[c] = nz;
+          ((GAS uint32_t*)(out + C))[c] = before;
+          if (c == C - 1 && (C & 1)) ((GAS uint32_t*)(out + C))[C] = 0u;  // padding of the counts
         }
+        if (v != 0ull) out[C + (C + 1) / 2 + before + __popcll(nz & lanemask_lt(lane))] = v;
+      } else if (inw) {
+        out[w] = v;
       }
     } else {
       const GAS uint64_t* in = (const GAS uint64_t*)S.comp_in + S.pmo[j];
@@ -2398,12 +2397,12 @@ hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStre
 hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, (int64_t)kMaxGrid);
-  if (mode == 0)
-    hipLaunchKernelGGL(k_zws<0>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
-  else if (mode == 1)
+  if (mode == 1)
     hipLaunchKernelGGL(k_zws<1>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL(k_zws<2>, dim3(grid), dim3(256), 0, s, segs, nseg, items);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 template <typename Q>
