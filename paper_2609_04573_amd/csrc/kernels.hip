@@ -1657,9 +1657,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(Q) ==
     cc[b] = b < B ? (uint32_t)__popcll(pw & ~sig) : 0u;
     incl[b] = cc[b];
     sig |= pw;
-    // lossless stage: this chunk's nonzero words of the plane
-    if (S.zcnt && b < B && lane == 0)
-      ((GAS uint32_t*)S.zcnt)[chunk * B + (B - 1 - b)] = (uint32_t)__popcll(__ballot(pw != 0ull));
+    // lossless stage: this chunk's nonzero words of the plane (the ballot is
+    // taken by the whole wave, the count stored by lane 0)
+    if (S.zcnt && b < B) {
+      const uint64_t nzm = __ballot(pw != 0ull);
+      if (lane == 0) ((GAS uint32_t*)S.zcnt)[chunk * B + (B - 1 - b)] = (uint32_t)__popcll(nzm);
+    }
   }
   wave_incl_scan_n<MAXB>(incl);
   uint32_t toff = 0, mycnt = 0;
