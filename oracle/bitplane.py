@@ -57,6 +57,7 @@ class StreamMeta:
     nsig: List[int] = field(default_factory=list)
     lossless: bool = False
     nnz: List[int] = field(default_factory=list)   # nonzero magnitude words per plane
+    encoding: str = "generic"   # "generic", "negabinary" or "negabinary_xor"
 
     @property
     def words(self) -> int:
@@ -77,13 +78,110 @@ class StreamMeta:
             return 8 * C + 8 * ((C + 1) // 2) + 8 * self.nnz[j]
         return 8 * self.words
 
+    @property
+    def negabinary(self) -> bool:
+        return self.encoding != "generic"
+
     def plane_bytes(self, j: int) -> int:
+        if self.negabinary:  # digit planes only: no index, no signs
+            return self.mag_bytes(j)
         return 4 * self.chunks + self.mag_bytes(j) + 8 * ((self.nsig[j] + 63) // 64)
 
     def delta(self, k: int) -> int:
         if k <= 0:
             return self.maxabs
+        if self.negabinary:
+            return nb_delta(self.B, k)
         return (1 << (self.B - k)) - 1
+
+
+# ---------------------------------------------------------------------------
+# Negabinary encoding (Table I, PSNR mode: "negabinary with XOR").  A code q
+# is written in base -2 with B digits, w = (q + A) ^ A where A has the odd
+# bit positions set; digit planes are stored most significant first, with no
+# sign bits.  B is the fewest digits whose range [-2(4^floor(B/2) - 1)/3,
+# (4^ceil(B/2) - 1)/3] holds [-maxabs, maxabs].  Truncating to the first k
+# planes keeps the top k digits (the rest set to 0); the dropped digits are
+# worth between -2(4^floor(r/2) - 1)/3 and (4^ceil(r/2) - 1)/3 with r = B - k,
+# so the error is at most floor((2^(r+1) - 1) / 3) (0 planes: maxabs).
+# Reading of "XOR" (the paper gives no definition): every stored digit plane
+# after the first is the XOR of the digit plane with the one above it, which
+# the decoder undoes from the planes it has already read.
+# ---------------------------------------------------------------------------
+
+def nb_digits(V: int) -> int:
+    n = 0
+    while (4 ** ((n + 1) // 2) - 1) // 3 < V or 2 * (4 ** (n // 2) - 1) // 3 < V:
+        n += 1
+    return n
+
+
+def nb_delta(B: int, k: int) -> int:
+    r = B - k
+    return (2 ** (r + 1) - 1) // 3
+
+
+def nb_mask(B: int) -> int:
+    return sum(1 << i for i in range(1, B, 2))
+
+
+def to_negabinary(q: np.ndarray, B: int) -> np.ndarray:
+    A = np.int64(nb_mask(B))
+    return (np.asarray(q, dtype=np.int64) + A) ^ A
+
+
+def from_negabinary(w: np.ndarray, B: int) -> np.ndarray:
+    A = np.int64(nb_mask(B))
+    return (np.asarray(w, dtype=np.int64) ^ A) - A
+
+
+def truncate_nb(q: np.ndarray, B: int, k: int) -> np.ndarray:
+    """What decoding the first k digit planes returns."""
+    k = max(0, min(int(k), B))
+    w = to_negabinary(q, B)
+    keep = np.int64(((1 << B) - 1) & ~((1 << (B - k)) - 1))
+    return from_negabinary(w & keep, B)
+
+
+def encode_nb(q: np.ndarray, xor: bool, lossless: bool = False):
+    """Negabinary digit planes (XOR-chained with ``xor``); returns (blob,
+    StreamMeta).  Blob = the stored digit planes in order (raw, or zero-word
+    suppressed with ``lossless``)."""
+    q = np.asarray(q, dtype=np.int64).ravel()
+    n = q.size
+    maxabs = int(np.abs(q).max()) if n else 0
+    B = nb_digits(maxabs)
+    meta = StreamMeta(n=n, B=B, maxabs=maxabs, nsig=[0] * B, lossless=bool(lossless),
+                      encoding="negabinary_xor" if xor else "negabinary")
+    M, C = meta.words, meta.chunks
+    w = to_negabinary(q, B)
+    planes, prev = [], None
+    for j in range(B):
+        bits = ((w >> (B - 1 - j)) & 1).astype(np.uint8)
+        raw = np.frombuffer(_pack_bits(bits, M), dtype="<u8")
+        stored = raw ^ prev if (xor and prev is not None) else raw
+        prev = raw
+        planes.append(stored.astype("<u8").tobytes())
+    if lossless:
+        for j in range(B):
+            meta.nnz.append(int(np.count_nonzero(np.frombuffer(planes[j], dtype="<u8"))))
+            if meta.suppressed(j):
+                planes[j] = suppress_plane(planes[j], M, C)
+    return b"".join(planes), meta
+
+
+def decode_nb(blob: bytes, meta: StreamMeta, k: int) -> np.ndarray:
+    n, B = meta.n, meta.B
+    k = max(0, min(int(k), B))
+    w = np.zeros(n, dtype=np.int64)
+    prev = None
+    for j in range(k):
+        stored = np.frombuffer(plane_words(blob, meta, j), dtype="<u8")
+        raw = stored ^ prev if (meta.encoding == "negabinary_xor" and prev is not None) else stored
+        prev = raw
+        bits = _unpack_bits(raw.astype("<u8").tobytes(), n)
+        w |= bits << (B - 1 - j)
+    return from_negabinary(w, B)
 
 
 def bitlength(mag: np.ndarray) -> np.ndarray:
@@ -178,7 +276,10 @@ def encode(q: np.ndarray, lossless: bool = False):
 
 
 def section_offsets(meta: StreamMeta):
-    """Byte offsets (index, magnitude, sign) of the three sections of a blob."""
+    """Byte offsets (index, magnitude, sign) of the three sections of a blob
+    (a negabinary blob has only the plane section)."""
+    if meta.negabinary:
+        return 0, 0, sum(meta.mag_bytes(j) for j in range(meta.B))
     ib = 4 * meta.B * meta.chunks
     ib += (-ib) % 8
     return 0, ib, ib + sum(meta.mag_bytes(j) for j in range(meta.B))
@@ -196,6 +297,8 @@ def plane_words(blob: bytes, meta: StreamMeta, j: int) -> bytes:
 
 def decode(blob: bytes, meta: StreamMeta, k: int) -> np.ndarray:
     """Decode the first k planes of a stream, reading magnitude and sign bits."""
+    if meta.negabinary:
+        return decode_nb(blob, meta, k)
     n, B = meta.n, meta.B
     k = max(0, min(int(k), B))
     mag = np.zeros(n, dtype=np.int64)

@@ -162,7 +162,10 @@ def refactor(x: np.ndarray, scheme: Scheme = Scheme(), precision: Optional[int] 
         return len(ref.groups) - 1, q
 
     def add_stream(key, g, codes):
-        blob, meta = bitplane.encode(codes, lossless=scheme.lossless)
+        if scheme.encoding == "generic":
+            blob, meta = bitplane.encode(codes, lossless=scheme.lossless)
+        else:
+            blob, meta = bitplane.encode_nb(codes, xor=scheme.encoding == "negabinary_xor", lossless=scheme.lossless)
         ref.streams.append(Stream(key=key, group=g, meta=meta, blob=blob, codes=np.asarray(codes, np.int64).ravel()))
         return len(ref.streams) - 1
 

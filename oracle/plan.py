@@ -30,7 +30,9 @@ Units are ordered coarsest group first, then levels L-2 .. 0, regions in
 ascending order, streams S1..S3.  Starting from no planes: stop as soon as
 E <= tau; otherwise advance the unit with the largest
 ((w_g*Delta_g) * decrease of e_g) / bytes of the step, ties to the lowest unit
-index.  The order does not depend on tau, so plans for tighter targets
+index.  A step ends at the unit's next lower error: planes that do not lower
+it (the first digit planes of a negabinary stream) go with the plane that
+does, in the greedy order and in max ordering alike.  The order does not depend on tau, so plans for tighter targets
 contain the plans for looser ones.
 """
 from __future__ import annotations
@@ -66,25 +68,37 @@ class Unit:
         return self.meta.plane_bytes(k) if self.kind == "plane" else self.seg_bytes[k]
 
 
+def next_lower(err, k: int, n: int) -> int:
+    """The first step count after k whose error is below err(k) (n at most).
+    Steps that do not lower the error (the first digit planes of a
+    negabinary stream) are taken together with the step that does."""
+    k2 = k + 1
+    while k2 < n and err(k2) >= err(k):
+        k2 += 1
+    return k2
+
+
 def build_staircase(group: int, region_streams: List[List[int]], metas: List[StreamMeta]) -> Unit:
     """Max ordering over the regions of the finest per-level level."""
     orders = []
     for trip in region_streams:
         k = [0, 0, 0]
-        steps = []
+        steps = []  # (stream t, planes taken together)
         while True:
-            best, best_r = -1, -1.0
+            best, best_r, best_n = -1, -1.0, 0
             for t in range(3):
                 m = metas[trip[t]]
                 if k[t] < m.B:
-                    gain = m.delta(k[t]) - m.delta(k[t] + 1)
-                    r = float(gain) / float(m.plane_bytes(k[t]))
+                    k2 = next_lower(m.delta, k[t], m.B)
+                    gain = m.delta(k[t]) - m.delta(k2)
+                    nb = sum(m.plane_bytes(j) for j in range(k[t], k2))
+                    r = float(gain) / float(nb)
                     if r > best_r:
-                        best, best_r = t, r
+                        best, best_r, best_n = t, r, k2 - k[t]
             if best < 0:
                 break
-            steps.append(best)
-            k[best] += 1
+            steps.append((best, best_n))
+            k[best] += best_n
         orders.append(steps)
 
     R = len(region_streams)
@@ -103,12 +117,13 @@ def build_staircase(group: int, region_streams: List[List[int]], metas: List[Str
         steps = []
         for r in range(R):
             if e[r] == top:
-                t = orders[r][pos[r]]
+                t, cnt = orders[r][pos[r]]
                 pos[r] += 1
                 u = region_streams[r][t]
-                nb += metas[u].plane_bytes(kk[r][t])
-                steps.append((u, kk[r][t]))
-                kk[r][t] += 1
+                for _ in range(cnt):
+                    nb += metas[u].plane_bytes(kk[r][t])
+                    steps.append((u, kk[r][t]))
+                    kk[r][t] += 1
                 e[r] = err(r)
         unit.levels.append(max(e))
         unit.seg_bytes.append(nb)
@@ -146,24 +161,28 @@ def eps_fp(ref) -> float:
 
 
 def greedy_sequence(ref, mode: str):
-    """Full greedy order: list of (unit advanced, bound after the step)."""
+    """Full greedy order: list of (unit advanced, its step count after the
+    step, bound after the step).  A step runs to the unit's next lower error
+    (one step, except for negabinary digit planes that do not lower it)."""
     state = [0] * len(ref.units)
     seq = []
     E0 = bound(ref, state, mode)
     while True:
-        best, best_s = -1, -1.0
+        best, best_s, best_k = -1, -1.0, 0
         for u, unit in enumerate(ref.units):
             if state[u] < unit.nsteps:
                 grp = ref.groups[unit.group]
                 wd = grp.wd_inf if mode == "inf" else grp.wd_2
-                de = unit.err(state[u]) - unit.err(state[u] + 1)
-                s = (wd * float(de)) / float(unit.step_bytes(state[u]))
+                k = state[u]
+                k2 = next_lower(unit.err, k, unit.nsteps)
+                de = unit.err(k) - unit.err(k2)
+                s = (wd * float(de)) / float(sum(unit.step_bytes(j) for j in range(k, k2)))
                 if s > best_s:
-                    best, best_s = u, s
+                    best, best_s, best_k = u, s, k2
         if best < 0:
             break
-        state[best] += 1
-        seq.append((best, bound(ref, state, mode)))
+        state[best] = best_k
+        seq.append((best, best_k, bound(ref, state, mode)))
     return E0, seq
 
 
@@ -206,8 +225,8 @@ def make_plan(ref, tau: float, mode: str) -> Plan:
     while E > tau:
         if n == len(seq):
             raise BelowFloor(f"tau={tau!r} below the floor {E!r}")
-        u, E = seq[n]
-        state[u] += 1
+        u, k, E = seq[n]
+        state[u] = k
         n += 1
     k = stream_planes(ref, state)
     return Plan(planes=k, units=state, bound=E, bytes=plan_bytes(ref, k), nsteps=n)

@@ -3,8 +3,9 @@
 The configuration space follows Table I (tuning configurations): interpolation
 scheme (per-level, or per-region with one of the d! dimension orders),
 coefficient decomposition along one of d directions or none, and the encoding
-(generic bitplane; negabinary is not built), optionally followed by the
-lossless stage on the magnitude planes (``oracle.bitplane``).  Interpolation degree 3 is the
+(generic bitplane, or negabinary digit planes with or without XOR chaining),
+optionally followed by the lossless stage on the stored planes
+(``oracle.bitplane``).  Interpolation degree 3 is the
 paper's cubic choice (Section IV); degree 1 is the multilinear form the paper
 starts from.
 """
@@ -22,6 +23,7 @@ class Scheme:
     cd_axis: Optional[int] = None    # stacking axis of coefficient decomposition; None = off
     levels: Optional[int] = None     # number of levels L; None = default
     lossless: bool = False           # zero-word suppression of the magnitude planes
+    encoding: str = "generic"        # "generic", "negabinary" or "negabinary_xor" (Table I)
 
     def pass_order(self, d: int) -> Tuple[int, ...]:
         """Order in which the d regions of a level are interpolated.

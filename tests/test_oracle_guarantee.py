@@ -115,7 +115,7 @@ def test_eb_ladder_guarantee(config1_field, sc):
             assert all(a >= b for a, b in zip(pl.planes, prev.planes))
         if pl.nsteps > 0:                          # minimality of the greedy prefix
             E0, seq = ref.sequence("inf")
-            before = seq[pl.nsteps - 2][1] if pl.nsteps >= 2 else E0
+            before = seq[pl.nsteps - 2][2] if pl.nsteps >= 2 else E0
             assert before > tau
         prev = pl
 

@@ -52,8 +52,8 @@ def test_greedy_order_and_bounds_match_the_hand_worked_toy():
     ref = _toy_ref(g)
     E0, seq = greedy_sequence(ref, "inf")
     assert E0 == g["E0"]
-    assert [u for u, _ in seq] == g["sequence"]
-    assert [E for _, E in seq] == g["bounds"]
+    assert [u for u, _, _ in seq] == g["sequence"]
+    assert [E for _, _, E in seq] == g["bounds"]
 
 
 def test_greedy_plans_match_the_hand_worked_toy():
@@ -81,7 +81,7 @@ def test_greedy_tie_goes_to_the_lower_unit():
     # 0.05 between unit 0 (0.5*2/20) and unit 1 (1*1/20): the lower index,
     # unit 0, now goes first; step 3 unit 0 (0.5*2/12); step 4 unit 1 (0.05 >
     # 0.025); step 5 unit 0 (0.025 > 0.0125); then unit 2 twice
-    assert [u for u, _ in seq] == [1, 0, 0, 1, 0, 2, 2]
+    assert [u for u, _, _ in seq] == [1, 0, 0, 1, 0, 2, 2]
 
 
 def test_staircase_matches_the_hand_worked_toy():
