@@ -66,6 +66,14 @@ typedef struct {
                         its M raw words, and plane sizes, plans and blobs use
                         the stored sizes; 0 = raw planes.  Reconstructions
                         for the same planes are identical either way. */
+  int32_t encoding;  /* Table I encodings: 0 = generic bitplanes (sign and
+                        magnitude, the error-bound mode's); 1 = negabinary
+                        digit planes (base -2, B digits, no sign bits; a code
+                        truncated to k planes is off by at most
+                        floor((2^(B-k+1) - 1) / 3)); 2 = negabinary with XOR
+                        chaining (every stored plane after the first is the
+                        XOR of its digit plane and the one above; the PSNR
+                        mode's).  Digit-plane blobs hold only the planes. */
 } apc_scheme;
 
 /* Retrieval target (Section III-A).  APC_EB_ABS: max|x - x'| <= value;

@@ -52,11 +52,13 @@ EXPORTED = [
     "apc_set_interpreter",
 ]
 INTERPRETERS = {"greedy": 0, "dp": 1, "best_first": 2, "paper": 3}
+ENCODINGS = {"generic": 0, "negabinary": 1, "negabinary_xor": 2}
 
 
 class _Scheme(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("order", ctypes.c_int32 * 3),
-                ("cd_axis", ctypes.c_int32), ("levels", ctypes.c_int32), ("lossless", ctypes.c_int32)]
+                ("cd_axis", ctypes.c_int32), ("levels", ctypes.c_int32), ("lossless", ctypes.c_int32),
+                ("encoding", ctypes.c_int32)]
 
 
 class _Target(ctypes.Structure):
@@ -155,6 +157,7 @@ class Scheme:
     cd_axis: Optional[int] = None
     levels: int = 0
     lossless: bool = False                   # zero-word suppression of stored planes
+    encoding: str = "generic"                # "generic", "negabinary" or "negabinary_xor"
 
     def _c(self, ndim: int) -> _Scheme:
         s = _Scheme()
@@ -166,13 +169,15 @@ class Scheme:
         s.cd_axis = -1 if self.cd_axis is None else int(self.cd_axis)
         s.levels = int(self.levels or 0)
         s.lossless = 1 if self.lossless else 0
+        s.encoding = ENCODINGS[self.encoding]
         return s
 
     @staticmethod
     def _from_c(s: _Scheme, ndim: int) -> "Scheme":
         return Scheme(kind="level" if s.kind == PER_LEVEL else "region", degree=s.degree,
                       order=None if s.kind == PER_LEVEL else tuple(s.order[i] for i in range(ndim)),
-                      cd_axis=None if s.cd_axis < 0 else s.cd_axis, levels=s.levels, lossless=bool(s.lossless))
+                      cd_axis=None if s.cd_axis < 0 else s.cd_axis, levels=s.levels, lossless=bool(s.lossless),
+                      encoding={v: k for k, v in ENCODINGS.items()}[s.encoding])
 
 
 @dataclass(frozen=True)

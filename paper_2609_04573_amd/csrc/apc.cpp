@@ -446,6 +446,7 @@ struct apc_handle {
   DevBuf zoff;  // lossless stage: per-(plane, chunk) nonzero words before the chunk (layout of idx)
   // retrieval state: decoded codes and planes decoded so far per stream
   DevBuf codes, cd_codes;
+  DevBuf pcodes, pcd_codes;  // digit-plane handles: truncated integers of the last retrieval
   std::vector<int> k_res;
   DevBuf xc, xb[2], pr[2], cdreg, tables;
   bool work_ready = false;
@@ -492,7 +493,8 @@ enum LaunchKind {
   // two-stream retrieval: the helper stream starts after what the main one
   // queued so far (FORK), marks its end (JOIN_REC), and the main one waits
   // for that mark (JOIN_WAIT); without a helper stream these do nothing
-  K_FORK, K_JOIN_REC, K_JOIN_WAIT
+  K_FORK, K_JOIN_REC, K_JOIN_WAIT,
+  K_DECODE_NB, K_NB_VALUES  // digit planes: decode, truncated integers
 };
 
 struct Launch {
@@ -643,6 +645,12 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
       case K_COARSEST:
         LAUNCH(l.name, l.bytes, st, (launch_coarsest<T, Q>((const FlatSeg*)p, l.nseg, l.nblk, st)));
         break;
+      case K_DECODE_NB:
+        LAUNCH(l.name, l.bytes, st, launch_decode_nb<Q>((const StreamDev*)p, l.nseg, l.nblk, st));
+        break;
+      case K_NB_VALUES:
+        LAUNCH(l.name, l.bytes, st, launch_nb_values<Q>((const FlatSeg*)p, l.nseg, l.nblk, st));
+        break;
       case K_INJECT: LAUNCH(l.name, l.bytes, st, launch_inject<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_RECON: LAUNCH(l.name, l.bytes, st, (launch_recon<T, Q>((const ReconSeg*)p, l.nseg, l.nblk, st))); break;
       case K_LEVEL0:
@@ -770,6 +778,7 @@ apc_status setup_geometry(apc_handle* h, const int64_t* dims, int32_t ndim, cons
   if (sc->cd_axis >= 0 && ndim < 2) return fail(APC_E_INVALID, "coefficient decomposition needs 2D or 3D data");
   if (sc->levels < 0 || sc->levels > 40) return fail(APC_E_INVALID, "scheme.levels out of range");
   if (sc->lossless != 0 && sc->lossless != 1) return fail(APC_E_INVALID, "scheme.lossless must be 0 or 1");
+  if (sc->encoding < 0 || sc->encoding > 2) return fail(APC_E_INVALID, "scheme.encoding must be 0, 1 or 2");
   if (sc->kind == APC_PER_LEVEL) {
     for (int j = 0; j < ndim; ++j) g.sigma_user[j] = ndim - 1 - j;
   } else {
@@ -803,6 +812,7 @@ void build_layout(apc_handle* h, int P) {
   m.P = P;
   m.n = g.n();
   m.lossless = h->scheme.lossless != 0;
+  m.enc = h->scheme.encoding;
   h->region_off.assign((size_t)std::max(1, L) * 3, 0);
   int64_t off = 0;
   const int64_t ncoarse = (int64_t)g.m[L - 1][0] * g.m[L - 1][1] * g.m[L - 1][2];
@@ -927,7 +937,10 @@ void build_layout(apc_handle* h, int P) {
       }
     }
   }
-  for (Stream& S : m.streams) S.lossless = m.lossless;
+  for (Stream& S : m.streams) {
+    S.lossless = m.lossless;
+    S.enc = m.enc;
+  }
 }
 
 // Weights of every group (exact chain norms of the user axes).
@@ -1323,14 +1336,14 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         S.maxabs = gr.M > 0.0 ? (int64_t)rint(ldexp(gr.M, gr.k_shift)) : 0;
       }
       if (S.n == 0) S.maxabs = 0;
-      S.B = bitlen(S.maxabs);
+      S.B = S.enc ? nb_digits(S.maxabs) : bitlen(S.maxabs);
     }
   }
 
   // ---- bitplane encoding of every stream of every field
-  std::vector<StreamDev> sds;
-  std::vector<std::pair<int, int>> sd_of;  // (field, stream)
-  int64_t chunks = 0, cnt_n = 0, stage_w = 0;
+  std::vector<StreamDev> sds, nsd;             // generic streams, negabinary streams
+  std::vector<std::pair<int, int>> sd_of, nsd_of;  // (field, stream)
+  int64_t chunks = 0, cnt_n = 0, stage_w = 0, nchunks = 0;
   for (int f = 0; f < nf; ++f) {
     apc_handle* h = H[f];
     Meta& m = h->meta;
@@ -1347,6 +1360,21 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     for (int s = 0; s < (int)m.streams.size(); ++s) {
       Stream& S = m.streams[s];
       if (S.B == 0 || S.n == 0) continue;
+      if (S.enc) {  // digit planes: no index, no signs
+        StreamDev nd{};
+        nd.codes = (S.use_cd ? tmp[f].cdc.template as<Q>() : tmp[f].codes.template as<Q>()) + S.code_off;
+        nd.mag = h->mag.as<uint64_t>() + S.mag_off;
+        nd.n = S.n;
+        nd.M = S.words();
+        nd.C = S.chunks();
+        nd.chunk_begin = nchunks;
+        nd.B = S.B;
+        nd.xor_chain = S.enc == 2 ? 1 : 0;
+        nchunks += nd.C;
+        nsd.push_back(nd);
+        nsd_of.push_back({f, s});
+        continue;
+      }
       StreamDev sd{};
       sd.codes = (S.use_cd ? tmp[f].cdc.template as<Q>() : tmp[f].codes.template as<Q>()) + S.code_off;
       sd.mag = h->mag.as<uint64_t>() + S.mag_off;
@@ -1443,13 +1471,23 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     std::vector<StreamDev> zsd;
     std::vector<int32_t> zjs, zjj;
     std::vector<size_t> zof;  // encode-table entry of each lossless stream
+    std::vector<StreamDev*> all;  // generic then negabinary encode-table entries
+    std::vector<std::pair<int, int>> all_of;
+    for (i = 0; i < sds.size(); ++i) {
+      all.push_back(&sds[i]);
+      all_of.push_back(sd_of[i]);
+    }
+    for (i = 0; i < nsd.size(); ++i) {
+      all.push_back(&nsd[i]);
+      all_of.push_back(nsd_of[i]);
+    }
     int64_t zcnt_n = 0;
-    for (i = 0; i < sds.size(); ++i)
-      if (H[sd_of[i].first]->meta.lossless) zcnt_n += (int64_t)sds[i].B * sds[i].C;
+    for (i = 0; i < all.size(); ++i)
+      if (H[all_of[i].first]->meta.lossless) zcnt_n += (int64_t)all[i]->B * all[i]->C;
     if (zcnt_n) APC_TRY(zcnt.alloc(4 * (size_t)zcnt_n));
     zcnt_n = 0;
-    for (i = 0; i < sds.size(); ++i) {
-      const int f = sd_of[i].first, s = sd_of[i].second;
+    for (i = 0; i < all.size(); ++i) {
+      const int f = all_of[i].first, s = all_of[i].second;
       apc_handle* h = H[f];
       if (!h->meta.lossless) continue;
       if (!h->zoff.p) {
@@ -1458,10 +1496,10 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
           if (S.B && S.n) nz += (int64_t)S.B * S.chunks();
         APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, nz)));
       }
-      sds[i].zcnt = zcnt.as<uint32_t>() + zcnt_n;
-      zcnt_n += (int64_t)sds[i].B * sds[i].C;
-      StreamDev d = sds[i];
-      d.cnt = sds[i].zcnt;
+      all[i]->zcnt = zcnt.as<uint32_t>() + zcnt_n;
+      zcnt_n += (int64_t)all[i]->B * all[i]->C;
+      StreamDev d = *all[i];
+      d.cnt = all[i]->zcnt;
       d.idx = h->zoff.as<uint32_t>() + h->meta.streams[s].idx_off;
       for (int j = 0; j < d.B; ++j) {
         zjs.push_back((int32_t)zsd.size());
@@ -1472,23 +1510,32 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     }
     std::vector<int64_t> ztv(zjs.size(), 0);
     PendingRead rd_z;
-    if (!sds.empty()) {
+    if (!sds.empty() || !nsd.empty()) {
       TableBuilder tb3;
       const size_t o_sd = tb3.add(sds);
       const size_t o_job = tb3.add(job);
       const size_t o_sj = tb3.add(sj);
       const size_t o_ss = tb3.add(ss);
+      const size_t o_nd = tb3.add(nsd);
       const size_t o_zd = tb3.add(zsd), o_zs = tb3.add(zjs), o_zj = tb3.add(zjj);
       APC_TRY(sdb.alloc(tb3.bytes.size()));
-      APC_TRY(totals.alloc(8 * (size_t)njobs));
+      APC_TRY(totals.alloc(8 * (size_t)std::max(1, njobs)));
       APC_TRY(prefix.alloc(8 * ((size_t)njobs + 1)));
       APC_TRY(errb.alloc(4));
       APC_TRY(stage.put(tb3.bytes, sdb.p, st));
       StreamDev* sdd = (StreamDev*)((char*)sdb.p + o_sd);
       const int32_t* jd = (const int32_t*)((const char*)sdb.p + o_job);
-      LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
-      LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
-      APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
+      if (!sds.empty()) {
+        LAUNCH("encode", eb, st, launch_encode<Q>(sdd, (int)sds.size(), chunks, st));
+        LAUNCH("scan", 8.0 * cnt_n, st, launch_scan(sdd, jd, jd + njobs, njobs, totals.as<int64_t>(), st));
+        APC_TRY(rd_tot.start(tot.data(), totals.p, 8 * (size_t)njobs, st));
+      }
+      if (!nsd.empty()) {
+        double nbb = 0;
+        for (const StreamDev& d : nsd) nbb += (double)sizeof(Q) * d.n + 8.0 * d.B * d.M;
+        LAUNCH("encode_nb", nbb, st,
+               launch_encode_nb<Q>((const StreamDev*)((char*)sdb.p + o_nd), (int)nsd.size(), nchunks, st));
+      }
       if (!zsd.empty()) {
         APC_TRY(ztot.alloc(8 * ztv.size()));
         const char* zb = (const char*)sdb.p;
@@ -1497,11 +1544,11 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
                            (int)zjs.size(), ztot.as<int64_t>(), st));
         APC_TRY(rd_z.start(ztv.data(), ztot.p, 8 * ztv.size(), st));
       }
-      LAUNCH("sign_layout", 16.0 * njobs, st,
+      if (!sds.empty()) LAUNCH("sign_layout", 16.0 * njobs, st,
              launch_sign_layout(totals.as<int64_t>(), njobs, (const SignJob*)((const char*)sdb.p + o_sj),
                                 (int)sds.size(), (const SignStream*)((const char*)sdb.p + o_ss), sdd,
                                 prefix.as<int64_t>(), errb.as<int32_t>(), st));
-      LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
+      if (!sds.empty()) LAUNCH("sign_move", sb, st, launch_sign_move(sdd, (int)sds.size(), chunks, st));
     }
     // the same layout on the host, for the metadata
     APC_TRY(rd_tot.finish());
@@ -1509,7 +1556,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     {
       size_t k = 0;
       for (size_t z = 0; z < zof.size(); ++z) {
-        Stream& S = H[sd_of[zof[z]].first]->meta.streams[sd_of[zof[z]].second];
+        Stream& S = H[all_of[zof[z]].first]->meta.streams[all_of[zof[z]].second];
         S.nnz.assign(S.B, 0);
         for (int j = 0; j < S.B; ++j) S.nnz[j] = ztv[k++];
       }
@@ -1534,6 +1581,12 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         w += (tot[jb] + 63) / 64;
       }
       sign_words[f] += w;
+    }
+    for (const auto& fs : nsd_of) {  // digit planes carry no signs
+      Stream& S = H[fs.first]->meta.streams[fs.second];
+      S.nsig.assign(S.B, 0);
+      S.pso.assign(S.B, 0);
+      S.sign_off = sign_words[fs.first];
     }
     for (int f = 0; f < nf; ++f)
       if (sign_words[f] > sign_ub[f]) return fail(APC_E_INVALID, "internal: sign section exceeds its bound");
@@ -1580,6 +1633,10 @@ struct WorkPtrs {
   // resident buffers
   void* codes = nullptr;
   void* cd_codes = nullptr;
+  // digit-plane handles: the truncated integers of this retrieval (layout of
+  // the decoded codes), which the recomposition and reconstruction read
+  void* pcodes = nullptr;
+  void* pcd_codes = nullptr;
 };
 
 // Bytes of work buffers a retrieval of this handle needs (layout of carve_work).
@@ -1595,6 +1652,8 @@ size_t work_bytes(const apc_handle* h) {
     }
     b += qsize(h->dtype) * (size_t)h->cdreg_n + 256;
   }
+  if (h->meta.enc)  // truncated integers of the digit words
+    b += qsize(h->dtype) * (size_t)(std::max<int64_t>(1, h->code_n) + std::max<int64_t>(1, h->cd_n)) + 512;
   return b;
 }
 
@@ -1618,6 +1677,10 @@ WorkPtrs carve_work(const apc_handle* h, void* base) {
       if (g.d >= 3) w.pr[1] = (double*)take(8 * (size_t)lat_count(lattice(g, 0, 1)));
     }
     w.cdreg = take(qsize(h->dtype) * (size_t)h->cdreg_n);
+  }
+  if (h->meta.enc) {
+    w.pcodes = take(qsize(h->dtype) * (size_t)std::max<int64_t>(1, h->code_n));
+    w.pcd_codes = take(qsize(h->dtype) * (size_t)std::max<int64_t>(1, h->cd_n));
   }
   return w;
 }
@@ -1647,6 +1710,10 @@ apc_status ensure_work(apc_handle* h) {
     }
     if (h->cdreg_n) APC_TRY(h->cdreg.alloc(qs * (size_t)h->cdreg_n));
   }
+  if (h->meta.enc) {
+    APC_TRY(h->pcodes.alloc(qs * (size_t)std::max<int64_t>(1, h->code_n)));
+    APC_TRY(h->pcd_codes.alloc(qs * (size_t)std::max<int64_t>(1, h->cd_n)));
+  }
   h->work_ready = true;
   return APC_OK;
 }
@@ -1659,6 +1726,8 @@ WorkPtrs handle_work(apc_handle* h) {
   w.pr[0] = h->pr[0].as<double>();
   w.pr[1] = h->pr[1].as<double>();
   w.cdreg = h->cdreg.p;
+  w.pcodes = h->pcodes.p;
+  w.pcd_codes = h->pcd_codes.p;
   return w;
 }
 
@@ -1678,10 +1747,21 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   const Geo& g = h->geo;
   const int d = g.d, L = g.L;
   const bool per_level = h->scheme.kind == APC_PER_LEVEL;
-  const bool split_on = split && with_decode && with_recon && per_level && !h->cd.empty() && L >= 3;
+  const bool nb = m.enc != 0;  // digit planes: decoded words are not codes yet
+  const bool split_on = split && with_decode && with_recon && per_level && !h->cd.empty() && L >= 3 && !nb;
   const size_t base = ls.size();
   Q* const codes = w.codes ? (Q*)w.codes : h->codes.as<Q>();
   Q* const cd_codes = w.cd_codes ? (Q*)w.cd_codes : h->cd_codes.as<Q>();
+  // what the recomposition and reconstruction read: the decoded codes
+  // truncated to the plan by each consumer (generic planes), or the
+  // truncated integers this retrieval makes from the digit words
+  Q* const rcodes = nb ? (Q*)w.pcodes : codes;
+  Q* const rcd_codes = nb ? (Q*)w.pcd_codes : cd_codes;
+  auto cB = [&](int s) { return nb ? 64 : m.streams[s].B; };
+  auto ck = [&](int s) { return nb ? 64 : planes[s]; };
+  std::vector<StreamDev> nbv;  // digit-plane decodes
+  int64_t nbch = 0;
+  double nbb = 0;
   // decode launches by (level 0 or not) x (first decode adding at most 16
   // planes, which the windowed kernel takes, or any other)
   std::vector<StreamDev> sdv[4];
@@ -1691,6 +1771,26 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   for (int s = 0; s < (int)m.streams.size() && with_decode; ++s) {
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0 || planes[s] <= kres[s]) continue;
+    if (S.enc) {
+      StreamDev sd{};
+      sd.codes = (S.use_cd ? cd_codes : codes) + S.code_off;
+      sd.mag = h->mag.as<uint64_t>() + S.mag_off;
+      sd.n = S.n;
+      sd.M = S.words();
+      sd.C = S.chunks();
+      sd.chunk_begin = nbch;
+      sd.B = S.B;
+      sd.k0 = kres[s];
+      sd.k1 = planes[s];
+      sd.fresh = kres[s] == 0 ? 1 : 0;
+      sd.xor_chain = S.enc == 2 ? 1 : 0;
+      for (int j = sd.k0; j < sd.k1; ++j) fb += S.plane_bytes(j);
+      nbb += (double)(sd.k1 - sd.k0) * 8.0 * sd.M + (double)sizeof(Q) * S.n * (sd.fresh ? 1 : 2);
+      nbch += sd.C;
+      nbv.push_back(sd);
+      kres[s] = planes[s];
+      continue;
+    }
     const bool fine = split_on && S.level == 0 && S.kind != S_COARSE;
     const bool win = kres[s] == 0 && planes[s] <= 16;
     const int cat = (fine ? 2 : 0) + (win ? 1 : 0);
@@ -1728,7 +1828,29 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     if (!sdv[cat].empty())
       ls.push_back({K_DECODE, tb.add(sdv[cat]), (int)sdv[cat].size(), chv[cat],
                     ((cat & 2) ? 1 : 0) | (frv[cat] ? 2 : 0) | ((cat & 1) ? 4 : 0), dbv[cat], "decode"});
+  if (!nbv.empty()) ls.push_back({K_DECODE_NB, tb.add(nbv), (int)nbv.size(), nbch, 0, nbb, "decode"});
   if (!with_recon) return;
+  if (nb) {  // the plan's truncated integers of every stream
+    std::vector<FlatSeg> vs;
+    double by = 0;
+    for (int s = 0; s < (int)m.streams.size(); ++s) {
+      const Stream& S = m.streams[s];
+      if (S.n == 0) continue;
+      FlatSeg v{};
+      v.src = (S.use_cd ? cd_codes : codes) + S.code_off;
+      v.dst = (S.use_cd ? rcd_codes : rcodes) + S.code_off;
+      v.n = S.n;
+      v.B = S.B;
+      v.k = planes[s];
+      by += 2.0 * sizeof(Q) * S.n;
+      vs.push_back(v);
+    }
+    const int64_t nbk = assign_blocks<FlatSeg>(vs, [](const FlatSeg& v) { return v.n; });
+    if (!vs.empty()) {
+      ls.push_back({K_NB_VALUES, tb.add(vs), (int)vs.size(), nbk, 0, by, "nb_values"});
+      ls.back().stage = 1;
+    }
+  }
   // inverse decomposition of every level-0 region
   if (!h->cd.empty() && L >= 2) {
     std::vector<CDSeg> cs;
@@ -1741,9 +1863,9 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       c.f1 = make_fastdiv((uint32_t)std::max(1, c.c[1]));
       c.Rout = (Q*)w.cdreg + ci.reg_off;
       for (int t = 0; t < 3; ++t) {
-        c.S[t] = cd_codes + ci.s_off[t];
-        c.B[t] = m.streams[ci.s_idx[t]].B;
-        c.k[t] = planes[ci.s_idx[t]];
+        c.S[t] = rcd_codes + ci.s_off[t];
+        c.B[t] = cB(ci.s_idx[t]);
+        c.k[t] = ck(ci.s_idx[t]);
       }
       const int64_t cnt = (int64_t)c.c[0] * c.c[1] * c.c[2];
       if (cnt == 0) continue;
@@ -1755,14 +1877,14 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       if (a3 < 2) {  // v runs along lattice rows: one pass over row tiles
         const int64_t nbk = assign_cd_tile_blocks(cs, a3);
         ls.push_back({K_CDIT, tb.add(cs), (int)cs.size(), nbk, a3, by, "cd_inverse"});
-        ls.back().stage = 1;
+        ls.back().stage = 2;
       } else {
         const int64_t nbk = assign_cd_blocks(cs);
         const size_t off = tb.add(cs);
         ls.push_back({K_CDI0, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
-        ls.back().stage = 1;
-        ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
         ls.back().stage = 2;
+        ls.push_back({K_CDI1, off, (int)cs.size(), nbk, a3, by * 0.5, "cd_inverse"});
+        ls.back().stage = 3;
       }
     }
   }
@@ -1770,17 +1892,17 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
   {
     const Stream& s0 = m.streams[0];
     FlatSeg c{};
-    c.src = codes;
+    c.src = rcodes;
     c.dst = L == 1 ? (void*)out : (void*)w.xc;
     c.n = s0.n;
-    c.B = s0.B;
-    c.k = planes[0];
+    c.B = cB(0);
+    c.k = ck(0);
     c.delta = m.groups[s0.group].delta;
     c.final_out = L == 1 ? 1 : 0;
     std::vector<FlatSeg> cs{c};
     const int64_t nbk = assign_blocks<FlatSeg>(cs, [](const FlatSeg& s) { return s.n; });
     ls.push_back({K_COARSEST, tb.add(cs), 1, nbk, 0, (8.0 + sizeof(Q)) * s0.n, "coarsest"});
-    ls.back().stage = 3;
+    ls.back().stage = 4;
   }
   const double* xin = w.xc;
   for (int l = L - 2; l >= 0; --l) {
@@ -1801,9 +1923,9 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
           c.B[rho] = 64;
           c.k[rho] = 64;
         } else {
-          c.q[rho] = codes + h->region_off[l * 3 + rho];
-          c.B[rho] = m.streams[s].B;
-          c.k[rho] = planes[s];
+          c.q[rho] = rcodes + h->region_off[l * 3 + rho];
+          c.B[rho] = cB(s);
+          c.k[rho] = ck(s);
         }
       }
       std::vector<LevelSeg> cs{c};
@@ -1852,9 +1974,9 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
       } else {
         const int s = stream_of(m, l, rho);
         const Stream& S = m.streams[s];
-        r.q = codes + h->region_off[l * 3 + rho];
-        r.B = S.B;
-        r.k = planes[s];
+        r.q = rcodes + h->region_off[l * 3 + rho];
+        r.B = cB(s);
+        r.k = ck(s);
         r.delta = m.groups[S.group].delta;
       }
       r.out = dst;
@@ -1916,7 +2038,9 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
 // first work block (first chunk for decodes).
 size_t seg_size_of(int kind) {
   switch (kind) {
-    case K_DECODE: return sizeof(StreamDev);
+    case K_DECODE:
+    case K_DECODE_NB: return sizeof(StreamDev);
+    case K_NB_VALUES: return sizeof(FlatSeg);
     case K_CDIT:
     case K_CDI0:
     case K_CDI1: return sizeof(CDSeg);
@@ -1930,7 +2054,9 @@ size_t seg_size_of(int kind) {
 }
 void rebase_seg(int kind, char* seg, int64_t add) {
   switch (kind) {
-    case K_DECODE: ((StreamDev*)seg)->chunk_begin += add; break;
+    case K_DECODE:
+    case K_DECODE_NB: ((StreamDev*)seg)->chunk_begin += add; break;
+    case K_NB_VALUES: ((FlatSeg*)seg)->blk_begin += add; break;
     case K_CDIT:
     case K_CDI0:
     case K_CDI1: ((CDSeg*)seg)->blk_begin += add; break;
@@ -2314,6 +2440,8 @@ void rep_meta(const apc_handle* h, std::vector<unsigned char>& b) {
   put<int32_t>(b, g.L);
   put<int32_t>(b, m.P);
   put<int32_t>(b, m.lossless ? 1 : 0);
+  put<int32_t>(b, m.enc);
+  put<int32_t>(b, 0);
   put<double>(b, m.xmin);
   put<double>(b, m.xmax);
   put<double>(b, m.A);
@@ -2380,6 +2508,8 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
   sc.levels = r.get<int32_t>();
   const int32_t L = r.get<int32_t>(), P = r.get<int32_t>();
   sc.lossless = r.get<int32_t>();
+  sc.encoding = r.get<int32_t>();
+  (void)r.get<int32_t>();
   const double xmin = r.get<double>(), xmax = r.get<double>(), A = r.get<double>();
   const uint32_t ng = r.get<uint32_t>(), ns = r.get<uint32_t>();
   REP_CHECK(r.ok, "metadata truncated");
@@ -2410,14 +2540,15 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
       gr.delta = ldexp(1.0, E - P);
     }
   }
-  const int maxB = dtype == APC_F32 ? 31 : 62;
+  const int maxB = dtype == APC_F32 ? (sc.encoding ? 32 : 31) : 62;
   for (Stream& S : m.streams) {
     const int64_t n = r.get<int64_t>(), mx = r.get<int64_t>();
     const int32_t B = r.get<int32_t>();
     (void)r.get<int32_t>();
     REP_CHECK(r.ok, "metadata truncated");
     REP_CHECK(n == S.n, "stream length %lld, the layout gives %lld", (long long)n, (long long)S.n);
-    REP_CHECK(mx >= 0 && B == bitlen(mx) && B <= maxB, "stream maximum / plane count inconsistent");
+    REP_CHECK(mx >= 0 && B == (S.enc ? nb_digits(mx) : bitlen(mx)) && B <= maxB,
+              "stream maximum / plane count inconsistent");
     const Group& gr = m.groups[S.group];
     if (!S.use_cd) {
       const int64_t want = gr.M > 0.0 ? (int64_t)rint(ldexp(gr.M, gr.k_shift)) : 0;
@@ -2435,7 +2566,10 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
       tot += S.nsig[j];
     }
     REP_CHECK(tot <= S.n, "more new-significant codes than codes");
-    REP_CHECK(B == 0 || S.nsig[0] > 0, "the top plane holds no new-significant code");
+    if (S.enc)
+      REP_CHECK(tot == 0, "digit planes carry no signs");
+    else
+      REP_CHECK(B == 0 || S.nsig[0] > 0, "the top plane holds no new-significant code");
     if (S.lossless) {
       S.nnz.assign(B, 0);
       for (int j = 0; j < B; ++j) {
@@ -2475,8 +2609,7 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
       // stored magnitude sections: a suppressed plane's presence words stop
       // at its last word, its counts follow them, its kept words are nonzero
       // and number nnz; a raw plane holds nnz nonzero words
-      const int64_t ibp = 4 * (int64_t)S.B * C + (8 - (4 * (int64_t)S.B * C) % 8) % 8;
-      const unsigned char* ms = b + ibp;
+      const unsigned char* ms = b + S.index_bytes();
       const int64_t M = S.words();
       for (int j = 0; j < S.B; ++j) {
         if (S.suppressed(j)) {
@@ -2512,7 +2645,7 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
         ms += 8 * S.mag_words(j);
       }
     }
-    for (int j = 0; j < S.B; ++j) {
+    for (int j = 0; j < S.B && !S.enc; ++j) {
       uint32_t prev = 0;
       for (int64_t c = 0; c < C; ++c) {
         uint32_t v;
@@ -2753,9 +2886,9 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
   memset(dst, 0, (size_t)S.blob_bytes());
   if (S.B == 0 || S.n == 0) return APC_OK;
   if (h->ready) HIP_TRY(hipEventSynchronize(h->ready));  // the refactor's last kernels
-  const int64_t ib = 4 * (int64_t)S.B * S.chunks();
-  HIP_TRY(hipMemcpy(dst, h->idx.as<uint32_t>() + S.idx_off, (size_t)ib, hipMemcpyDeviceToHost));
-  const int64_t ibp = ib + (8 - ib % 8) % 8;
+  const int64_t ibp = S.index_bytes();
+  if (ibp)
+    HIP_TRY(hipMemcpy(dst, h->idx.as<uint32_t>() + S.idx_off, 4 * (size_t)S.B * S.chunks(), hipMemcpyDeviceToHost));
   const int64_t mb = 8 * S.stored_mag_words();
   if (!S.lossless) {
     HIP_TRY(hipMemcpy(dst + ibp, h->mag.as<uint64_t>() + S.mag_off, (size_t)mb, hipMemcpyDeviceToHost));
@@ -2891,11 +3024,12 @@ apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_h
     const Stream& S = m.streams[s];
     if (S.B == 0 || S.n == 0) continue;
     const unsigned char* b = blobs[s];
-    const int64_t ib = 4 * (int64_t)S.B * S.chunks();
-    const int64_t ibp = ib + (8 - ib % 8) % 8;
+    const int64_t ibp = S.index_bytes();
     const int64_t mb = 8 * (int64_t)S.B * S.words();
     const int64_t sb = 8 * S.sign_words();
-    HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, (size_t)ib, hipMemcpyHostToDevice, st));
+    if (ibp)
+      HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, 4 * (size_t)S.B * S.chunks(), hipMemcpyHostToDevice,
+                             st));
     if (!S.lossless) {
       HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
     } else {

@@ -137,6 +137,8 @@ struct StreamDev {
   int32_t B;
   int32_t k0, k1;       // decode: planes [k0, k1) to add
   int32_t fresh;        // decode: resident codes are all zero (skip reading them)
+  int32_t xor_chain;    // negabinary streams: stored digit planes XOR-chained
+  int32_t pad;
 };
 
 // Lossless stage of one stream's magnitude planes (zero-word suppression):
@@ -211,6 +213,15 @@ template <typename Q>
 hipError_t launch_decode(const StreamDev* sd, int ns, int64_t chunks, bool all_fresh, int max_planes, hipStream_t s);
 // mode 1: pack the stored sections; 2: unpack them
 hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s);
+// Negabinary digit planes: encode (codes -> stored planes), decode (planes
+// [k0, k1) OR-ed into resident digit words), and the truncated integers of
+// resident digit words (FlatSeg: src words, dst codes, n, B, k).
+template <typename Q>
+hipError_t launch_encode_nb(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
+template <typename Q>
+hipError_t launch_decode_nb(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
+template <typename Q>
+hipError_t launch_nb_values(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T>

@@ -41,6 +41,9 @@ struct Stream {
   // where that is smaller than its raw words
   bool lossless = false;
   std::vector<int64_t> nnz;
+  // encoding: 0 generic bitplanes (sign-magnitude); 1 negabinary digit
+  // planes; 2 negabinary digit planes, XOR-chained
+  int enc = 0;
 
   int64_t words() const { return (n + 63) / 64; }
   int64_t chunks() const { return (n + 4095) / 4096; }
@@ -52,9 +55,16 @@ struct Stream {
   int64_t zws_head_words() const { return chunks() + (chunks() + 1) / 2; }
   bool suppressed(int j) const { return lossless && 8 * (zws_head_words() + nnz[j]) < 8 * words(); }
   int64_t mag_words(int j) const { return suppressed(j) ? zws_head_words() + nnz[j] : words(); }
-  int64_t plane_bytes(int j) const { return 4 * chunks() + 8 * mag_words(j) + 8 * ((nsig[j] + 63) / 64); }
+  int64_t plane_bytes(int j) const {
+    if (enc) return 8 * mag_words(j);  // digit planes only: no index, no signs
+    return 4 * chunks() + 8 * mag_words(j) + 8 * ((nsig[j] + 63) / 64);
+  }
+  // Largest error of a code truncated to k of B planes: sign-magnitude
+  // truncation leaves less than one unit of the first dropped plane; dropped
+  // negabinary digits are worth at most floor((2^(B-k+1) - 1) / 3).
   int64_t delta(int k) const {
     if (k <= 0) return maxabs;
+    if (enc) return (int64_t)(((1ull << (B - k + 1)) - 1ull) / 3ull);
     return (int64_t)((1ull << (B - k)) - 1ull);
   }
   int64_t stored_mag_words() const {
@@ -62,11 +72,12 @@ struct Stream {
     for (int j = 0; j < B; ++j) w += mag_words(j);
     return w;
   }
-  int64_t blob_bytes() const {
-    int64_t ib = 4 * (int64_t)B * chunks();
-    ib += (8 - ib % 8) % 8;
-    return ib + 8 * stored_mag_words() + 8 * sign_words();
+  int64_t index_bytes() const {  // the index section, padded to 8 bytes (none for digit planes)
+    if (enc) return 0;
+    const int64_t ib = 4 * (int64_t)B * chunks();
+    return ib + (8 - ib % 8) % 8;
   }
+  int64_t blob_bytes() const { return index_bytes() + 8 * stored_mag_words() + 8 * sign_words(); }
 };
 
 struct Unit {
@@ -77,9 +88,22 @@ struct Unit {
   std::vector<std::vector<std::pair<int, int>>> seg_steps;  // (stream, plane) per segment
 };
 
+// Fewest negabinary digits whose range holds [-V, V]: B digits hold
+// [-2 (4^floor(B/2) - 1) / 3, (4^ceil(B/2) - 1) / 3].
+inline int nb_digits(int64_t V) {
+  int B = 0;
+  for (;;) {
+    const unsigned __int128 p = (((unsigned __int128)1 << (2 * ((B + 1) / 2))) - 1) / 3;
+    const unsigned __int128 q = 2 * ((((unsigned __int128)1 << (2 * (B / 2))) - 1) / 3);
+    if (p >= (unsigned __int128)V && q >= (unsigned __int128)V) return B;
+    ++B;
+  }
+}
+
 struct Meta {
   int d = 3, L = 1, P = 29;
   bool lossless = false;  // planes stored through the lossless stage
+  int enc = 0;            // encoding of every stream (Stream::enc)
   int64_t n = 0;
   double xmin = 0, xmax = 0, A = 0;
   double eps_fp = 0;
@@ -89,10 +113,15 @@ struct Meta {
   std::vector<Unit> units;
   std::vector<std::vector<int>> group_units;
   std::vector<int> group_order;
-  // greedy sequences, per mode (0 = max error, 1 = RMSE)
+  // greedy sequences, per mode (0 = max error, 1 = RMSE): unit advanced, its
+  // step count after the step, bound after the step
+  struct SeqStep {
+    int unit, k;
+    double E;
+  };
   bool seq_ready[2] = {false, false};
   double seq_E0[2] = {0, 0};
-  std::vector<std::pair<int, double>> seq[2];
+  std::vector<SeqStep> seq[2];
 
   double range() const { return xmax - xmin; }
 };

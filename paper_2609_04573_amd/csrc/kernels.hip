@@ -1794,6 +1794,165 @@ __global__ __launch_bounds__(kLayoutThreads) void k_sign_layout(const int64_t* _
   }
 }
 
+// ------------------------------------------------ negabinary digit planes
+// A code q is written in base -2 with B digits: w = (q + A) ^ A in the code's
+// width, A the odd bit positions below B (modular arithmetic gives the digits
+// exactly whenever q is in the B-digit range).  Digit plane j holds digit
+// B - 1 - j of every code; with XOR chaining, stored plane j > 0 is the XOR
+// of digit planes j and j - 1.  No sign bits: negabinary has none.
+template <typename U>
+__device__ __forceinline__ U nb_mask(int B) {
+  const U odd = (U)0xAAAAAAAAAAAAAAAAull;
+  return B >= (int)(8 * sizeof(U)) ? odd : (odd & (((U)1 << B) - (U)1));
+}
+
+// One wave per 4096-code chunk, lane per 64-code word: digit words through
+// two half-word LDS stagings and bit-matrix transposes into plane words,
+// stored plane-major (with the lossless stage's nonzero-word counts).
+template <typename Q, int MAXB>
+__global__ __launch_bounds__(64) void k_encode_nb(const StreamDev* __restrict__ sd, int ns) {
+  using U = typename UOf<Q>::type;
+  constexpr int QW = (int)sizeof(Q) / 4;
+  __shared__ __align__(16) Q cst[64 * kRow];
+  const int lane = threadIdx.x;
+  const int64_t gch = blockIdx.x;
+  const int u = find_stream(sd, ns, gch);
+  const StreamDev& S = sd[u];
+  const int64_t chunk = gch - S.chunk_begin;
+  const int B = S.B;
+  const int64_t M = S.M, n = S.n;
+  const BufRsrc rc = chunk_rsrc<Q>(S.codes, chunk * kChunk, n);
+  const U A = nb_mask<U>(B);
+  uint64_t P[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) P[b] = 0ull;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    stage_half<Q>(rc, h, cst, lane);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < QW; ++p) {
+      uint32_t r[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        const U w = ((U)cst[lane * kRow + k] + A) ^ A;
+        r[k] = (uint32_t)(w >> (32 * p));
+      }
+      transpose32(r);
+#pragma unroll
+      for (int bb = 0; bb < 32; ++bb)
+        if (32 * p + bb < MAXB) P[32 * p + bb] |= (uint64_t)r[bb] << (32 * h);
+    }
+    __syncthreads();
+  }
+  uint64_t above = 0ull;
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    if (b >= B) continue;
+    const uint64_t pw = P[b];
+    const uint64_t sw = S.xor_chain ? (pw ^ above) : pw;
+    above = pw;
+    buf_store<uint64_t>(sw, plane_rsrc(S.mag, B - 1 - b, M, chunk), 8u * lane, 0u);
+    if (S.zcnt) {
+      const uint64_t nzm = __ballot(sw != 0ull);
+      if (lane == 0) ((GAS uint32_t*)S.zcnt)[chunk * B + (B - 1 - b)] = (uint32_t)__popcll(nzm);
+    }
+  }
+}
+
+// One wave per chunk, lane per word: stored planes [k0, k1) loaded, the XOR
+// chain undone from the digit plane above k0 (read off the resident words),
+// transposed back and OR-ed into the resident digit words.
+template <typename Q, int MAXB>
+__global__ __launch_bounds__(64) void k_decode_nb(const StreamDev* __restrict__ sd, int ns) {
+  using U = typename UOf<Q>::type;
+  constexpr int QW = (int)sizeof(Q) / 4;
+  __shared__ __align__(16) Q cst[64 * kRow];
+  const int lane = threadIdx.x;
+  const int64_t gch = blockIdx.x;
+  const int u = find_stream(sd, ns, gch);
+  const StreamDev& S = sd[u];
+  const int64_t chunk = gch - S.chunk_begin;
+  const int B = S.B, k0 = S.k0, k1 = S.k1;
+  const bool fresh = S.fresh != 0;
+  const int64_t M = S.M, n = S.n;
+  const BufRsrc rc = chunk_rsrc<Q>(S.codes, chunk * kChunk, n);
+  uint64_t above = 0ull;  // digit plane k0 - 1 of this lane's 64 codes
+  if (S.xor_chain && k0 > 0 && !fresh) {
+    const int d = B - k0;  // its digit position
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      stage_half<Q>(rc, h, cst, lane);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 32; ++k) above |= (uint64_t)(((U)cst[lane * kRow + k] >> d) & (U)1) << (32 * h + k);
+      __syncthreads();
+    }
+  }
+  uint64_t P[MAXB];
+#pragma unroll
+  for (int b = MAXB - 1; b >= 0; --b) {
+    const int j = B - 1 - b;
+    P[b] = 0ull;
+    if (b < B && j >= k0 && j < k1) {
+      const uint64_t sw = buf_load<uint64_t>(plane_rsrc(S.mag, j, M, chunk), 8u * lane, 0u);
+      const uint64_t pw = S.xor_chain ? (sw ^ above) : sw;
+      above = pw;
+      P[b] = pw;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (!fresh) {
+      stage_half<Q>(rc, h, cst, lane);
+      __syncthreads();
+    }
+    uint32_t nb[QW][32];
+#pragma unroll
+    for (int p = 0; p < QW; ++p) {
+#pragma unroll
+      for (int bb = 0; bb < 32; ++bb) nb[p][bb] = (32 * p + bb < MAXB) ? (uint32_t)(P[32 * p + bb] >> (32 * h)) : 0u;
+      transpose32(nb[p]);
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      U w = fresh ? (U)0 : (U)cst[lane * kRow + k];
+      w |= (U)nb[0][k];
+      if constexpr (QW == 2) w |= (U)nb[QW - 1][k] << 32;
+      cst[lane * kRow + k] = (Q)w;
+    }
+    __syncthreads();
+    unstage_half<Q>(rc, h, cst, lane);
+    __syncthreads();
+  }
+}
+
+// The integers of resident digit words truncated to their first k of B
+// digit planes: ((w & top k digits) ^ A) - A.
+template <typename Q>
+__global__ __launch_bounds__(kThreads) void k_nb_values(const FlatSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  using U = typename UOf<Q>::type;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int si = find_seg(segs, nseg, b);
+    const FlatSeg& S = segs[si];
+    const GAS U* src = (const GAS U*)S.src;
+    GAS Q* dst = (GAS Q*)S.dst;
+    constexpr int kBits = (int)(8 * sizeof(U));
+    const U A = nb_mask<U>(S.B);
+    const int kk = S.k < S.B ? S.k : S.B;
+    const U all = S.B >= kBits ? ~(U)0 : (((U)1 << S.B) - (U)1);          // the B digits
+    const U low = S.B - kk >= kBits ? ~(U)0 : (((U)1 << (S.B - kk)) - (U)1);  // the dropped ones
+    const U keep = kk <= 0 ? (U)0 : (all & ~low);
+    const int64_t e0 = (b - S.blk_begin) * kBlockElems;
+#pragma unroll 4
+    for (int it = 0; it < kPerThread; ++it) {
+      const int64_t e = e0 + it * kThreads + threadIdx.x;
+      if (e >= S.n) continue;
+      dst[e] = (Q)(((src[e] & keep) ^ A) - A);
+    }
+  }
+}
+
 // ------------------------------------------------ lossless stage (zero words)
 // One wave per (stream, plane, chunk) item, lane per magnitude word of the
 // chunk; a ballot over the lanes gives the chunk's presence word.
@@ -2397,6 +2556,30 @@ hipError_t launch_sign_move(const StreamDev* sd, int ns, int64_t chunks, hipStre
   hipLaunchKernelGGL(k_sign_move, dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
   return hipGetLastError();
 }
+template <typename Q>
+hipError_t launch_encode_nb(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
+  hipLaunchKernelGGL((k_encode_nb<Q, MAXB>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  return hipGetLastError();
+}
+template <typename Q>
+hipError_t launch_decode_nb(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  constexpr int MAXB = sizeof(Q) == 4 ? 32 : 64;
+  hipLaunchKernelGGL((k_decode_nb<Q, MAXB>), dim3((unsigned)chunks), dim3(64), 0, s, sd, ns);
+  return hipGetLastError();
+}
+template <typename Q>
+hipError_t launch_nb_values(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s) {
+  APC_LAUNCH((k_nb_values<Q>), nblk, segs, nseg, nblk);
+}
+template hipError_t launch_encode_nb<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
+template hipError_t launch_encode_nb<int64_t>(const StreamDev*, int, int64_t, hipStream_t);
+template hipError_t launch_decode_nb<int32_t>(const StreamDev*, int, int64_t, hipStream_t);
+template hipError_t launch_decode_nb<int64_t>(const StreamDev*, int, int64_t, hipStream_t);
+template hipError_t launch_nb_values<int32_t>(const FlatSeg*, int, int64_t, hipStream_t);
+template hipError_t launch_nb_values<int64_t>(const FlatSeg*, int, int64_t, hipStream_t);
 hipError_t launch_zws(const ZwsSeg* segs, int nseg, int64_t items, int mode, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, (int64_t)kMaxGrid);

@@ -111,28 +111,42 @@ void axis_norms(int64_t n, int L, int degree, std::vector<double>& inf, std::vec
   if (memo.size() < 4096) memo[key] = {inf, one};
 }
 
+// The first step count after k whose error is below err(k) (n at most):
+// steps that do not lower the error (the first digit planes of a negabinary
+// stream) are taken together with the step that does.
+template <typename F>
+static int next_lower(F err, int k, int n) {
+  int k2 = k + 1;
+  while (k2 < n && err(k2) >= err(k)) ++k2;
+  return k2;
+}
+
 Unit build_staircase(int group, const std::vector<std::vector<int>>& rs, const std::vector<Stream>& st) {
   const int R = (int)rs.size();
-  std::vector<std::vector<int>> orders(R);
+  std::vector<std::vector<std::pair<int, int>>> orders(R);  // (stream t, planes taken together)
   for (int r = 0; r < R; ++r) {
     int k[3] = {0, 0, 0};
     for (;;) {
-      int best = -1;
+      int best = -1, best_n = 0;
       double best_r = -1.0;
       for (int t = 0; t < 3; ++t) {
         const Stream& s = st[rs[r][t]];
         if (k[t] < s.B) {
-          const int64_t gain = s.delta(k[t]) - s.delta(k[t] + 1);
-          const double q = (double)gain / (double)s.plane_bytes(k[t]);
+          const int k2 = next_lower([&](int kk) { return s.delta(kk); }, k[t], s.B);
+          const int64_t gain = s.delta(k[t]) - s.delta(k2);
+          int64_t nb = 0;
+          for (int j = k[t]; j < k2; ++j) nb += s.plane_bytes(j);
+          const double q = (double)gain / (double)nb;
           if (q > best_r) {
             best = t;
             best_r = q;
+            best_n = k2 - k[t];
           }
         }
       }
       if (best < 0) break;
-      orders[r].push_back(best);
-      ++k[best];
+      orders[r].push_back({best, best_n});
+      k[best] += best_n;
     }
   }
   std::vector<int> pos(R, 0);
@@ -158,11 +172,14 @@ Unit build_staircase(int group, const std::vector<std::vector<int>>& rs, const s
     std::vector<std::pair<int, int>> steps;
     for (int r = 0; r < R; ++r) {
       if (e[r] == cur) {
-        const int t = orders[r][pos[r]++];
+        const int t = orders[r][pos[r]].first, cnt = orders[r][pos[r]].second;
+        ++pos[r];
         const int s = rs[r][t];
-        nb += st[s].plane_bytes(kk[r][t]);
-        steps.push_back({s, kk[r][t]});
-        ++kk[r][t];
+        for (int c = 0; c < cnt; ++c) {
+          nb += st[s].plane_bytes(kk[r][t]);
+          steps.push_back({s, kk[r][t]});
+          ++kk[r][t];
+        }
         e[r] = err(r);
       }
     }
@@ -239,24 +256,30 @@ void ensure_sequence(Meta& m, int mode) {
   m.seq[mode].clear();
   m.seq_E0[mode] = bound(m, state, mode);
   for (;;) {
-    int best = -1;
+    int best = -1, best_k = 0;
     double best_s = -1.0;
     for (int u = 0; u < (int)m.units.size(); ++u) {
       const Unit& un = m.units[u];
-      if (state[u] < unit_nsteps(m, un)) {
+      const int n = unit_nsteps(m, un);
+      if (state[u] < n) {
         const Group& gr = m.groups[un.group];
         const double wd = mode == 0 ? gr.wd_inf : gr.wd_2;
-        const int64_t de = unit_err(m, un, state[u]) - unit_err(m, un, state[u] + 1);
-        const double s = (wd * (double)de) / (double)unit_step_bytes(m, un, state[u]);
+        const int k = state[u];
+        const int k2 = next_lower([&](int kk) { return unit_err(m, un, kk); }, k, n);
+        const int64_t de = unit_err(m, un, k) - unit_err(m, un, k2);
+        int64_t c = 0;
+        for (int j = k; j < k2; ++j) c += unit_step_bytes(m, un, j);
+        const double s = (wd * (double)de) / (double)c;
         if (s > best_s) {
           best = u;
           best_s = s;
+          best_k = k2;
         }
       }
     }
     if (best < 0) break;
-    ++state[best];
-    m.seq[mode].push_back({best, bound(m, state, mode)});
+    state[best] = best_k;
+    m.seq[mode].push_back({best, best_k, bound(m, state, mode)});
   }
   m.seq_ready[mode] = true;
 }
@@ -269,9 +292,9 @@ int make_plan(Meta& m, double tau, int mode, std::vector<int>& planes, double& b
   int n = 0;
   while (E > tau) {
     if (n == (int)m.seq[mode].size()) return -1;
-    const auto& st = m.seq[mode][n];
-    ++state[st.first];
-    E = st.second;
+    const Meta::SeqStep& st = m.seq[mode][n];
+    state[st.unit] = st.k;
+    E = st.E;
     ++n;
   }
   planes.assign(m.streams.size(), 0);
@@ -579,8 +602,8 @@ std::string meta_json(const Meta& m) {
     o += buf;
   };
   add("{\"d\":%d,\"L\":%d,\"P\":%d,\"n\":%lld,\"xmin\":%.17g,\"xmax\":%.17g,\"A\":%.17g,\"eps_fp\":%.17g,"
-      "\"meta_bytes\":%lld,\"groups\":[",
-      m.d, m.L, m.P, (long long)m.n, m.xmin, m.xmax, m.A, m.eps_fp, (long long)m.meta_bytes);
+      "\"meta_bytes\":%lld,\"encoding\":%d,\"lossless\":%d,\"groups\":[",
+      m.d, m.L, m.P, (long long)m.n, m.xmin, m.xmax, m.A, m.eps_fp, (long long)m.meta_bytes, m.enc, m.lossless ? 1 : 0);
   for (size_t g = 0; g < m.groups.size(); ++g) {
     const Group& gr = m.groups[g];
     add("%s{\"kind\":%d,\"level\":%d,\"rho\":%d,\"n\":%lld,\"M\":%.17g,\"E\":%d,\"delta\":%.17g,\"w\":%.17g,"

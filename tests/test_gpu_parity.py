@@ -33,10 +33,10 @@ def _apc():
     return apc
 
 
-def _schemes(kind, degree, order, cd, lossless=False):
+def _schemes(kind, degree, order, cd, lossless=False, encoding="generic"):
     apc = _apc()
-    return (apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless),
-            oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless))
+    return (apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless, encoding=encoding),
+            oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=lossless, encoding=encoding))
 
 
 def _bits(a):
@@ -127,6 +127,42 @@ def test_config1_lossless_parity(config1_field, scheme):
     _check_metadata(h, ref)
     _check_streams(h, ref)
     _check_retrievals(h, ref, x)
+    h.close()
+
+
+@pytest.mark.parametrize("scheme", [("region", 3, (1, 2, 0), None, True, "negabinary_xor"),
+                                    ("level", 3, None, 0, False, "negabinary"),
+                                    ("region", 1, None, 2, False, "negabinary_xor"),
+                                    ("level", 3, None, None, True, "negabinary_xor")], ids=str)
+def test_config1_negabinary_parity(config1_field, scheme):
+    """Negabinary digit planes (with and without XOR chaining and the
+    lossless stage): plane counts, stored planes, plans and reconstructions,
+    bit for bit."""
+    apc = _apc()
+    x = config1_field
+    gs, os_ = _schemes(*scheme)
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    _check_retrievals(h, ref, x)
+    h.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_negabinary_incremental_decodes_continue_the_xor_chain(dtype):
+    """Retrievals that add digit planes to resident ones (undoing the XOR
+    chain from the plane above) equal the oracle's reconstruction of each
+    plan, on one handle, in a ladder with targets going both ways."""
+    apc = _apc()
+    x = fieldgen.power_law_field((33, 40, 50), seed=12, dtype=dtype)
+    gs, os_ = _schemes("region", 3, (2, 1, 0), 1, True, "negabinary_xor")
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    for kind, val in (("psnr", 40), ("rel", 1e-3), ("psnr", 90), ("rel", 1e-2), ("rel", 1e-6)):
+        pl = oracle.plan(ref, oracle.Target(kind, val))
+        out, _ = h.retrieve(apc.Target(kind, val))
+        assert np.array_equal(_bits(out.cpu().numpy()), _bits(oracle.retrieve(ref, pl))), (kind, val)
     h.close()
 
 

@@ -24,7 +24,9 @@ def _apc():
 
 @pytest.mark.parametrize("scheme", [oracle.Scheme(kind="level", cd_axis=0), oracle.Scheme(kind="region"),
                                     oracle.Scheme(kind="region", order=(0, 2, 1), cd_axis=1),
-                                    oracle.Scheme(kind="level")], ids=str)
+                                    oracle.Scheme(kind="level"),
+                                    oracle.Scheme(kind="region", encoding="negabinary_xor", lossless=True),
+                                    oracle.Scheme(kind="level", cd_axis=0, encoding="negabinary")], ids=str)
 def test_library_plans_equal_the_oracle(config1_field, scheme):
     apc = _apc()
     ref = oracle.refactor(config1_field, scheme)

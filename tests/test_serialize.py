@@ -37,7 +37,8 @@ def oracle_bytes(ref) -> bytes:
     order = list(ref.sigma) + [0] * (3 - d)
     meta += struct.pack("<7i", 0 if sc.kind == "level" else 1, sc.degree, *order,
                         -1 if sc.cd_axis is None else sc.cd_axis, ref.L)
-    meta += struct.pack("<iii", ref.L, ref.P, 1 if sc.lossless else 0)
+    meta += struct.pack("<iiiii", ref.L, ref.P, 1 if sc.lossless else 0,
+                        {"generic": 0, "negabinary": 1, "negabinary_xor": 2}[sc.encoding], 0)
     meta += struct.pack("<3d", ref.xmin, ref.xmax, ref.A)
     meta += struct.pack("<II", len(ref.groups), len(ref.streams))
     meta += b"".join(struct.pack("<d", g.M) for g in ref.groups)
@@ -68,7 +69,10 @@ def cases():
                   (x2, oracle.Scheme(kind="region", order=(0, 1), cd_axis=1)),
                   (x3, oracle.Scheme(kind="level", degree=1, cd_axis=2)),
                   (x1, oracle.Scheme(kind="level", cd_axis=0, lossless=True)),
-                  (x3, oracle.Scheme(kind="region", order=(2, 0, 1), lossless=True))):
+                  (x3, oracle.Scheme(kind="region", order=(2, 0, 1), lossless=True)),
+                  (x1, oracle.Scheme(kind="region", order=(1, 2, 0), cd_axis=0, encoding="negabinary_xor",
+                                     lossless=True)),
+                  (x3, oracle.Scheme(kind="level", encoding="negabinary"))):
         ref = oracle.refactor(x, sc)
         out.append((x, sc, ref, oracle_bytes(ref)))
     return out
@@ -106,13 +110,13 @@ def test_damaged_bytes_are_refused(cases):
         assert "checksum" in _corrupt(apc, bytes(b)) or "length" in _corrupt(apc, bytes(b))
     # metadata altered with its checksum rewritten: stream 0's plane count
     meta = bytearray(data[32:32 + mlen])
-    off0 = 104 + 8 * len(ref.groups)  # first stream entry
+    off0 = 112 + 8 * len(ref.groups)  # first stream entry
     struct.pack_into("<i", meta, off0 + 16, ref.streams[0].meta.B + 1)
     forged = data[:24] + struct.pack("<Q", rep_hash(bytes(meta))) + bytes(meta) + data[32 + mlen:]
     assert "inconsistent" in _corrupt(apc, forged)
     # a group maximum that no longer matches its stream's maximum
     meta = bytearray(data[32:32 + mlen])
-    struct.pack_into("<d", meta, 104, ref.groups[0].M * 1.5)
+    struct.pack_into("<d", meta, 112, ref.groups[0].M * 1.5)
     forged = data[:24] + struct.pack("<Q", rep_hash(bytes(meta))) + bytes(meta) + data[32 + mlen:]
     assert "group maximum" in _corrupt(apc, forged)
     # a dims field the layout does not fit
@@ -180,7 +184,8 @@ def test_serialized_bytes_equal_the_oracle_and_round_trip(cases):
 
     apc = _apc()
     for x, sc, ref, data in cases:
-        gs = apc.Scheme(kind=sc.kind, degree=sc.degree, order=sc.order, cd_axis=sc.cd_axis, lossless=sc.lossless)
+        gs = apc.Scheme(kind=sc.kind, degree=sc.degree, order=sc.order, cd_axis=sc.cd_axis, lossless=sc.lossless,
+                        encoding=sc.encoding)
         h = apc.refactor(torch.from_numpy(x).cuda(), gs)
         got = h.serialize()
         assert got == data, "serialized bytes differ from the oracle-written layout"
