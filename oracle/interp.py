@@ -97,19 +97,19 @@ def _extra_bytes(ref, planes: List[int], resident: Optional[List[int]]) -> int:
     return total
 
 
-def _as_plan(ref, planes: List[int], units: List[int], mode, resident) -> Plan:
+def _as_plan(ref, planes: List[int], units: List[int], mode, resident, nsteps=None) -> Plan:
     """A plan from per-stream planes (resident planes kept: they cost
     nothing and only lower the error); its bound is the model's for exactly
-    those planes."""
+    those planes; nsteps counts unit steps unless given."""
     if resident is not None:
         planes = [max(a, b) for a, b in zip(planes, resident)]
     return Plan(planes=list(planes), units=list(units), bound=bound_for_planes(ref, planes, mode),
-                bytes=plan_bytes(ref, planes), nsteps=sum(units))
+                bytes=plan_bytes(ref, planes), nsteps=sum(units) if nsteps is None else nsteps)
 
 
 def _greedy(ref, tau, mode, resident):
     pl = make_plan(ref, tau, mode)  # raises BelowFloor when no plan exists
-    return _as_plan(ref, pl.planes, pl.units, mode, resident)
+    return _as_plan(ref, pl.planes, pl.units, mode, resident, nsteps=pl.nsteps)
 
 
 def _budget(ref, tau, mode):
