@@ -315,6 +315,36 @@ apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_h
  * APC_E_INVALID.  For planning services away from the data. */
 apc_status apc_deserialize_host(const void* src, int64_t len, apc_handle** out);
 
+/* Out-of-core blocks (the paper refactors fixed-size blocks independently,
+ * one per core, and stores them: the end-to-end transfer use case).  The
+ * field is host memory (row-major, dims as apc_refactor, caller owned, read
+ * only); it is split into blocks of extents `block` (ragged at the far
+ * edges), each refactored with `scheme` as an independent field and kept
+ * serialized (apc_serialize layout) in host memory owned by the set.  The
+ * device holds one group of at most group_bytes of field at a time (plus
+ * its refactoring buffers), so the field may exceed device memory.
+ * apc_blocks_retrieve turns the target into one absolute bound every block
+ * meets (a relative bound or PSNR uses the range of the whole field; per
+ * block max error <= tau gives max error <= tau overall, per block RMSE <= r
+ * gives RMSE <= r overall), plans each block on host metadata with the
+ * set's interpreter, uploads only the planned planes of each block (the
+ * stored sections' prefixes), reconstructs it on the device and copies it
+ * into out_host (caller owned, the field's size).  info: bytes over all
+ * blocks, the largest block bound (max error) or the pooled RMSE bound.
+ * Both calls synchronize hip_stream.  apc_blocks_blob returns block b's
+ * serialized bytes (owned by the set; blocks in row-major block order). */
+typedef struct apc_blockset apc_blockset;
+apc_status apc_blocks_refactor(const void* field_host, int32_t dtype, const int64_t* dims, int32_t ndim,
+                               const int64_t* block, const apc_scheme* scheme, int64_t group_bytes, void* hip_stream,
+                               apc_blockset** out);
+apc_status apc_blocks_retrieve(apc_blockset* bs, const apc_target* target, void* out_host, apc_retrieve_info* info,
+                               void* hip_stream);
+apc_status apc_blocks_set_interpreter(apc_blockset* bs, int32_t interp);
+apc_status apc_blocks_info(const apc_blockset* bs, int64_t* nblocks, int64_t* stored_bytes, double* xmin,
+                           double* xmax);
+apc_status apc_blocks_blob(const apc_blockset* bs, int64_t b, const void** bytes, int64_t* len);
+void apc_blocks_free(apc_blockset* bs);
+
 /* Host-only helper (no device needed): exact chain norms of the 1D
  * interpolation chain on an axis of length n for levels 0..L-1, rounded to
  * float64 (max row / column abs sums).  inf_out, one_out: L doubles. */

@@ -49,7 +49,8 @@ EXPORTED = [
     "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats", "apc_server_reset_stats",
     "apc_server_destroy", "apc_tune_tiles", "apc_tile_override", "apc_tile_width", "apc_profile_only",
     "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize", "apc_deserialize_host",
-    "apc_set_interpreter",
+    "apc_set_interpreter", "apc_blocks_refactor", "apc_blocks_retrieve", "apc_blocks_set_interpreter",
+    "apc_blocks_info", "apc_blocks_blob", "apc_blocks_free",
 ]
 INTERPRETERS = {"greedy": 0, "dp": 1, "best_first": 2, "paper": 3}
 ENCODINGS = {"generic": 0, "negabinary": 1, "negabinary_xor": 2}
@@ -84,6 +85,15 @@ _lib.apc_serialize.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_i64)]
 _lib.apc_deserialize.argtypes = [ctypes.c_char_p, _i64, _vp, ctypes.POINTER(_vp)]
 _lib.apc_deserialize_host.argtypes = [ctypes.c_char_p, _i64, ctypes.POINTER(_vp)]
 _lib.apc_set_interpreter.argtypes = [_vp, _i32]
+_lib.apc_blocks_refactor.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i64),
+                                     ctypes.POINTER(_Scheme), _i64, _vp, ctypes.POINTER(_vp)]
+_lib.apc_blocks_retrieve.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
+_lib.apc_blocks_set_interpreter.argtypes = [_vp, _i32]
+_lib.apc_blocks_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+_lib.apc_blocks_blob.argtypes = [_vp, _i64, ctypes.POINTER(_vp), ctypes.POINTER(_i64)]
+_lib.apc_blocks_free.argtypes = [_vp]
+_lib.apc_blocks_free.restype = None
 _lib.apc_select_pipeline.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, _i32, ctypes.POINTER(_Scheme), _vp]
 _lib.apc_free.argtypes = [_vp]
 _lib.apc_free.restype = None
@@ -127,7 +137,8 @@ for _name in ("apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes",
               "apc_server_create", "apc_server_submit", "apc_server_poll", "apc_server_wait", "apc_server_stats",
               "apc_server_reset_stats", "apc_tune_tiles", "apc_tile_override", "apc_tile_width",
               "apc_profile_only", "apc_retrieve_static", "apc_field_info", "apc_serialize", "apc_deserialize",
-              "apc_deserialize_host", "apc_set_interpreter"):
+              "apc_deserialize_host", "apc_set_interpreter", "apc_blocks_refactor", "apc_blocks_retrieve",
+              "apc_blocks_set_interpreter", "apc_blocks_info", "apc_blocks_blob"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -436,6 +447,65 @@ class Server:
     def close(self):
         if self._p:
             _lib.apc_server_destroy(self._p)
+            self._p = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BlockSet:
+    """A host-resident field refactored block by block (out of core): the
+    representation stays in host memory; retrievals upload only the planned
+    planes of each block."""
+
+    def __init__(self, field_host, block, scheme: Scheme = Scheme(), group_bytes: int = 4 << 30, stream=None):
+        import numpy as np
+        a = np.ascontiguousarray(field_host)
+        if a.dtype == np.float32:
+            dt = APC_F32
+        elif a.dtype == np.float64:
+            dt = APC_F64
+        else:
+            raise ApcError(APC_E_DTYPE, f"unsupported dtype {a.dtype}")
+        self.shape, self.dtype = a.shape, a.dtype
+        dims = (ctypes.c_int64 * a.ndim)(*a.shape)
+        blk = (ctypes.c_int64 * a.ndim)(*[int(b) for b in block])
+        out = ctypes.c_void_p()
+        _check(_lib.apc_blocks_refactor(ctypes.c_void_p(a.ctypes.data), dt, dims, a.ndim, blk,
+                                        ctypes.byref(scheme._c(a.ndim)), int(group_bytes), _stream_ptr(stream),
+                                        ctypes.byref(out)))
+        self._p = out
+
+    def info(self) -> dict:
+        nb, sb = _i64(), _i64()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.apc_blocks_info(self._p, ctypes.byref(nb), ctypes.byref(sb), ctypes.byref(lo), ctypes.byref(hi)))
+        return {"blocks": nb.value, "stored_bytes": sb.value, "xmin": lo.value, "xmax": hi.value}
+
+    def blob(self, b: int) -> bytes:
+        p, n = ctypes.c_void_p(), _i64()
+        _check(_lib.apc_blocks_blob(self._p, int(b), ctypes.byref(p), ctypes.byref(n)))
+        return ctypes.string_at(p, n.value)
+
+    def set_interpreter(self, name: str) -> None:
+        _check(_lib.apc_blocks_set_interpreter(self._p, INTERPRETERS[name]))
+
+    def retrieve(self, target: Target, out=None, stream=None):
+        import numpy as np
+        if out is None:
+            out = np.empty(self.shape, dtype=self.dtype)
+        assert out.flags.c_contiguous and out.dtype == self.dtype and out.shape == self.shape
+        inf = _Info()
+        _check(_lib.apc_blocks_retrieve(self._p, ctypes.byref(target._c()), ctypes.c_void_p(out.ctypes.data),
+                                        ctypes.byref(inf), _stream_ptr(stream)))
+        return out, _info_dict(inf)
+
+    def close(self):
+        if self._p:
+            _lib.apc_blocks_free(self._p)
             self._p = ctypes.c_void_p(0)
 
     def __del__(self):

@@ -2675,6 +2675,86 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
   return APC_OK;
 }
 
+// Device arenas of a handle rebuilt from bytes, and its planes uploaded:
+// every plane, or per stream only the first kmax[s] (index entries, stored
+// magnitude sections and sign words of those planes are prefixes of their
+// sections, so a partial upload is three prefix copies per stream).
+// Copies from pageable memory: the runtime has consumed each source when a
+// copy call returns, and the stream is synchronized before returning.
+apc_status upload_planes(apc_handle* h, const std::vector<const unsigned char*>& blobs, const std::vector<int>* kmax,
+                         hipStream_t st) {
+  Meta& m = h->meta;
+  int64_t mag_w = 0, idx_n = 0, sign_w = 0, nplanes = 0;
+  for (const Stream& S : m.streams) {
+    if (S.B == 0 || S.n == 0) continue;
+    mag_w += (int64_t)S.B * S.words();
+    idx_n += (int64_t)S.B * S.chunks();
+    sign_w += S.sign_words();
+    nplanes += S.B;
+  }
+  APC_TRY(h->mag.alloc(8 * (size_t)std::max<int64_t>(1, mag_w)));
+  APC_TRY(h->idx.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
+  APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_w)));
+  APC_TRY(h->pso.alloc(8 * (size_t)std::max<int64_t>(1, nplanes)));
+  if (m.lossless) APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
+  std::vector<int64_t> pso((size_t)std::max<int64_t>(1, nplanes), 0);
+  // copies from pageable memory: the runtime has consumed each source when
+  // the call returns, and the stream is synchronized before returning
+  for (int s = 0; s < (int)m.streams.size(); ++s) {
+    const Stream& S = m.streams[s];
+    if (S.B == 0 || S.n == 0) continue;
+    const unsigned char* b = blobs[s];
+    const int K = kmax ? std::min(S.B, std::max(0, (*kmax)[s])) : S.B;  // planes uploaded
+    for (int j = 0; j < S.B; ++j) pso[(size_t)h->psb[s] + j] = S.pso[j];
+    if (K == 0) continue;
+    const int64_t ibp = S.index_bytes();
+    const int64_t mb = 8 * (int64_t)K * S.words();
+    const int64_t sb = 8 * (K < S.B ? S.pso[K] : S.sign_words());
+    int64_t stored_k = 0;  // stored magnitude words of the first K planes
+    for (int j = 0; j < K; ++j) stored_k += S.mag_words(j);
+    if (ibp)
+      HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, 4 * (size_t)K * S.chunks(), hipMemcpyHostToDevice,
+                             st));
+    if (!S.lossless) {
+      HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
+    } else {
+      // stored sections uploaded as they are, expanded to raw planes on the device
+      const int64_t smb = 8 * stored_k;
+      std::vector<int64_t> pmo((size_t)K + 1, 0);
+      uint64_t zmask = 0;
+      for (int j = 0; j < K; ++j) {
+        pmo[j + 1] = pmo[j] + S.mag_words(j);
+        if (S.suppressed(j)) zmask |= 1ull << j;
+      }
+      DevBuf in, tab;
+      APC_TRY(in.alloc((size_t)smb));
+      HIP_TRY(hipMemcpyAsync(in.p, b + ibp, (size_t)smb, hipMemcpyHostToDevice, st));
+      ZwsSeg z{};
+      z.raw_out = h->mag.as<uint64_t>() + S.mag_off;
+      z.zoff = h->zoff.as<uint32_t>() + S.idx_off;
+      z.comp_in = in.as<uint64_t>();
+      z.zmask = zmask;
+      z.M = S.words();
+      z.C = S.chunks();
+      z.B = K;
+      TableBuilder tb;
+      const size_t o_p = tb.add(pmo);
+      APC_TRY(tab.alloc(tb.bytes.size() + 256 + sizeof(ZwsSeg)));
+      z.pmo = (const int64_t*)((char*)tab.p + o_p);
+      const size_t o_z = tb.add(std::vector<ZwsSeg>{z});
+      HIP_TRY(hipMemcpyAsync(tab.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_zws((const ZwsSeg*)((char*)tab.p + o_z), 1, (int64_t)K * S.chunks(), 2, st));
+      HIP_TRY(hipStreamSynchronize(st));  // before the temporaries go back to the pool
+    }
+    const int64_t mbs = 8 * S.stored_mag_words();
+    if (sb)
+      HIP_TRY(hipMemcpyAsync(h->sign.as<uint64_t>() + S.sign_off, b + ibp + mbs, (size_t)sb, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(h->pso.p, pso.data(), 8 * pso.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return APC_OK;
+}
+
 #undef REP_CHECK
 
 }  // namespace
@@ -3002,75 +3082,249 @@ apc_status apc_deserialize(const void* src, int64_t len, void* hip_stream, apc_h
   std::vector<const unsigned char*> blobs;
   APC_TRY(rep_parse((const unsigned char*)src, len, h, blobs));
   if (!out) return APC_OK;  // checked only
-  hipStream_t st = (hipStream_t)hip_stream;
-  Meta& m = h->meta;
-  int64_t mag_w = 0, idx_n = 0, sign_w = 0, nplanes = 0;
-  for (const Stream& S : m.streams) {
-    if (S.B == 0 || S.n == 0) continue;
-    mag_w += (int64_t)S.B * S.words();
-    idx_n += (int64_t)S.B * S.chunks();
-    sign_w += S.sign_words();
-    nplanes += S.B;
-  }
-  APC_TRY(h->mag.alloc(8 * (size_t)std::max<int64_t>(1, mag_w)));
-  APC_TRY(h->idx.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
-  APC_TRY(h->sign.alloc(8 * (size_t)std::max<int64_t>(1, sign_w)));
-  APC_TRY(h->pso.alloc(8 * (size_t)std::max<int64_t>(1, nplanes)));
-  if (m.lossless) APC_TRY(h->zoff.alloc(4 * (size_t)std::max<int64_t>(1, idx_n)));
-  std::vector<int64_t> pso((size_t)std::max<int64_t>(1, nplanes), 0);
-  // copies from pageable memory: the runtime has consumed each source when
-  // the call returns, and the stream is synchronized before returning
-  for (int s = 0; s < (int)m.streams.size(); ++s) {
-    const Stream& S = m.streams[s];
-    if (S.B == 0 || S.n == 0) continue;
-    const unsigned char* b = blobs[s];
-    const int64_t ibp = S.index_bytes();
-    const int64_t mb = 8 * (int64_t)S.B * S.words();
-    const int64_t sb = 8 * S.sign_words();
-    if (ibp)
-      HIP_TRY(hipMemcpyAsync(h->idx.as<uint32_t>() + S.idx_off, b, 4 * (size_t)S.B * S.chunks(), hipMemcpyHostToDevice,
-                             st));
-    if (!S.lossless) {
-      HIP_TRY(hipMemcpyAsync(h->mag.as<uint64_t>() + S.mag_off, b + ibp, (size_t)mb, hipMemcpyHostToDevice, st));
-    } else {
-      // stored sections uploaded as they are, expanded to raw planes on the device
-      const int64_t smb = 8 * S.stored_mag_words();
-      std::vector<int64_t> pmo((size_t)S.B + 1, 0);
-      uint64_t zmask = 0;
-      for (int j = 0; j < S.B; ++j) {
-        pmo[j + 1] = pmo[j] + S.mag_words(j);
-        if (S.suppressed(j)) zmask |= 1ull << j;
-      }
-      DevBuf in, tab;
-      APC_TRY(in.alloc((size_t)smb));
-      HIP_TRY(hipMemcpyAsync(in.p, b + ibp, (size_t)smb, hipMemcpyHostToDevice, st));
-      ZwsSeg z{};
-      z.raw_out = h->mag.as<uint64_t>() + S.mag_off;
-      z.zoff = h->zoff.as<uint32_t>() + S.idx_off;
-      z.comp_in = in.as<uint64_t>();
-      z.zmask = zmask;
-      z.M = S.words();
-      z.C = S.chunks();
-      z.B = S.B;
-      TableBuilder tb;
-      const size_t o_p = tb.add(pmo);
-      APC_TRY(tab.alloc(tb.bytes.size() + 256 + sizeof(ZwsSeg)));
-      z.pmo = (const int64_t*)((char*)tab.p + o_p);
-      const size_t o_z = tb.add(std::vector<ZwsSeg>{z});
-      HIP_TRY(hipMemcpyAsync(tab.p, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, st));
-      HIP_TRY(launch_zws((const ZwsSeg*)((char*)tab.p + o_z), 1, (int64_t)S.B * S.chunks(), 2, st));
-      HIP_TRY(hipStreamSynchronize(st));  // before the temporaries go back to the pool
-    }
-    const int64_t mbs = 8 * S.stored_mag_words();
-    if (sb)
-      HIP_TRY(hipMemcpyAsync(h->sign.as<uint64_t>() + S.sign_off, b + ibp + mbs, (size_t)sb, hipMemcpyHostToDevice, st));
-    for (int j = 0; j < S.B; ++j) pso[(size_t)h->psb[s] + j] = S.pso[j];
-  }
-  HIP_TRY(hipMemcpyAsync(h->pso.p, pso.data(), 8 * pso.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  APC_TRY(upload_planes(h.get(), blobs, nullptr, (hipStream_t)hip_stream));
   *out = h.release();
   return APC_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------ out-of-core blocks
+// A field held in host memory, split into independent blocks (the paper
+// refactors fixed-size blocks independently, one per core, and stores them).
+// Each block is refactored on the device and kept serialized in host memory;
+// a retrieval plans every block on its host-side metadata, uploads only the
+// planes the plan needs (prefixes of the stored sections), reconstructs the
+// block on the device and copies it into the host output.  The device holds
+// one group of blocks at a time, so the field can exceed device memory.
+struct apc_blockset {
+  int dtype = APC_F32;
+  int ndim = 3;
+  int64_t N[3] = {1, 1, 1}, bs[3] = {1, 1, 1}, nb[3] = {1, 1, 1};
+  apc_scheme scheme{};
+  int interp = INTERP_GREEDY;
+  double xmin = 0, xmax = 0;
+  std::vector<std::vector<unsigned char>> blobs;
+  std::vector<std::unique_ptr<apc_handle>> plan_h;  // planning-only handles, one per block
+  int64_t nblocks() const { return nb[0] * nb[1] * nb[2]; }
+  void block(int64_t b, int64_t lo[3], int64_t ext[3]) const {
+    const int64_t i[3] = {b / (nb[1] * nb[2]), (b / nb[2]) % nb[1], b % nb[2]};
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = i[a] * bs[a];
+      ext[a] = std::min(N[a], lo[a] + bs[a]) - lo[a];
+    }
+  }
+};
+
+namespace {
+
+// Rows of a block between a row-major host field and a dense block buffer.
+void block_copy(const apc_blockset* B, int64_t b, size_t es, const char* field, char* dense, bool to_dense,
+                char* field_out) {
+  int64_t lo[3], ext[3];
+  B->block(b, lo, ext);
+  const size_t row = (size_t)ext[2] * es;
+  for (int64_t z = 0; z < ext[0]; ++z)
+    for (int64_t y = 0; y < ext[1]; ++y) {
+      const size_t fo = (size_t)(((lo[0] + z) * B->N[1] + (lo[1] + y)) * B->N[2] + lo[2]) * es;
+      const size_t bo = (size_t)((z * ext[1] + y) * ext[2]) * es;
+      if (to_dense)
+        memcpy(dense + bo, field + fo, row);
+      else
+        memcpy(field_out + fo, dense + bo, row);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+apc_status apc_blocks_refactor(const void* field_host, int32_t dtype, const int64_t* dims, int32_t ndim,
+                               const int64_t* block, const apc_scheme* scheme, int64_t group_bytes, void* hip_stream,
+                               apc_blockset** out) {
+  if (!field_host || !dims || !block || !scheme || !out || ndim < 1 || ndim > 3 || group_bytes <= 0)
+    return fail(APC_E_INVALID, "bad argument");
+  if (dtype != APC_F32 && dtype != APC_F64) return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::unique_ptr<apc_blockset> B(new apc_blockset());
+  B->dtype = dtype;
+  B->ndim = ndim;
+  B->scheme = *scheme;
+  for (int a = 0; a < ndim; ++a) {
+    if (dims[a] < 1 || block[a] < 1) return fail(APC_E_INVALID, "dims and block extents must be positive");
+    B->N[3 - ndim + a] = dims[a];
+    B->bs[3 - ndim + a] = std::min(dims[a], block[a]);
+  }
+  for (int a = 0; a < 3; ++a) B->nb[a] = (B->N[a] + B->bs[a] - 1) / B->bs[a];
+  const size_t es = qsize(dtype);
+  const int64_t nbk = B->nblocks();
+  B->blobs.resize((size_t)nbk);
+  B->plan_h.resize((size_t)nbk);
+  // groups of blocks that fit the device budget, refactored in one batch
+  int64_t b0 = 0;
+  while (b0 < nbk) {
+    std::vector<int64_t> bl;
+    size_t bytes = 0;
+    for (int64_t b = b0; b < nbk; ++b) {
+      int64_t lo[3], ext[3];
+      B->block(b, lo, ext);
+      const size_t nbyte = (size_t)(ext[0] * ext[1] * ext[2]) * es;
+      if (!bl.empty() && bytes + nbyte > (size_t)group_bytes) break;
+      bl.push_back(b);
+      bytes += nbyte;
+    }
+    PinnedBlock pin;
+    if (!g_pinned.get(bytes, pin)) return fail(APC_E_OOM, "pinned staging of %zu bytes", bytes);
+    DevBuf dev;
+    apc_status r = dev.alloc(bytes);
+    std::vector<const void*> ptrs;
+    std::vector<int64_t> bd;
+    std::vector<int32_t> nds;
+    size_t off = 0;
+    for (int64_t b : bl) {
+      int64_t lo[3], ext[3];
+      B->block(b, lo, ext);
+      block_copy(B.get(), b, es, (const char*)field_host, (char*)pin.p + off, true, nullptr);
+      ptrs.push_back((const char*)dev.p + off);
+      for (int a = 3 - ndim; a < 3; ++a) bd.push_back(ext[a]);
+      nds.push_back(ndim);
+      off += (size_t)(ext[0] * ext[1] * ext[2]) * es;
+    }
+    if (r == APC_OK && hipMemcpyAsync(dev.p, pin.p, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+      r = fail(APC_E_HIP, "block upload failed");
+    std::vector<std::unique_ptr<apc_handle>> own;
+    if (r == APC_OK) {
+      std::vector<apc_scheme> sc(bl.size(), *scheme);
+      r = refactor_many(ptrs.data(), dtype, bd.data(), nds.data(), sc.data(), (int32_t)bl.size(), st, own);
+    }
+    g_pinned.put(pin, st, true);
+    for (size_t i = 0; i < bl.size() && r == APC_OK; ++i) {
+      int64_t len = 0;
+      r = apc_serialize(own[i].get(), nullptr, 0, &len);
+      if (r != APC_OK) break;
+      std::vector<unsigned char>& blob = B->blobs[(size_t)bl[i]];
+      blob.resize((size_t)len);
+      r = apc_serialize(own[i].get(), blob.data(), len, &len);
+      if (r != APC_OK) break;
+      std::vector<const unsigned char*> bp;
+      r = rep_parse(blob.data(), len, B->plan_h[(size_t)bl[i]], bp);
+      if (r == APC_OK) B->plan_h[(size_t)bl[i]]->host_only = true;
+    }
+    (void)hipStreamSynchronize(st);
+    for (auto& h : own) apc_free(h.release());
+    APC_TRY(r);
+    b0 += (int64_t)bl.size();
+  }
+  B->xmin = B->plan_h[0]->meta.xmin;
+  B->xmax = B->plan_h[0]->meta.xmax;
+  for (auto& h : B->plan_h) {
+    B->xmin = std::min(B->xmin, h->meta.xmin);
+    B->xmax = std::max(B->xmax, h->meta.xmax);
+  }
+  *out = B.release();
+  return APC_OK;
+}
+
+apc_status apc_blocks_info(const apc_blockset* B, int64_t* nblocks, int64_t* stored_bytes, double* xmin,
+                           double* xmax) {
+  if (!B) return fail(APC_E_INVALID, "null block set");
+  if (nblocks) *nblocks = B->nblocks();
+  if (stored_bytes) {
+    int64_t t = 0;
+    for (const auto& b : B->blobs) t += (int64_t)b.size();
+    *stored_bytes = t;
+  }
+  if (xmin) *xmin = B->xmin;
+  if (xmax) *xmax = B->xmax;
+  return APC_OK;
+}
+
+apc_status apc_blocks_blob(const apc_blockset* B, int64_t b, const void** bytes, int64_t* len) {
+  if (!B || b < 0 || b >= B->nblocks() || !bytes || !len) return fail(APC_E_INVALID, "bad argument");
+  *bytes = B->blobs[(size_t)b].data();
+  *len = (int64_t)B->blobs[(size_t)b].size();
+  return APC_OK;
+}
+
+apc_status apc_blocks_set_interpreter(apc_blockset* B, int32_t interp) {
+  if (!B) return fail(APC_E_INVALID, "null block set");
+  if (interp < APC_INTERP_GREEDY || interp > APC_INTERP_PAPER) return fail(APC_E_INVALID, "interpreter %d", interp);
+  B->interp = interp;
+  for (auto& h : B->plan_h) h->interp = interp;
+  return APC_OK;
+}
+
+apc_status apc_blocks_retrieve(apc_blockset* B, const apc_target* target, void* out_host, apc_retrieve_info* info,
+                               void* hip_stream) {
+  if (!B || !target || !out_host) return fail(APC_E_INVALID, "null argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the target as an absolute bound every block must meet: a max error
+  // within tau in every block is one within tau overall, and an RMSE within
+  // r in every block is one within r overall
+  const double rng = B->xmax - B->xmin;
+  apc_target t = *target;
+  switch (target->kind) {
+    case APC_EB_REL:
+      t.kind = APC_EB_ABS;
+      t.value = target->value * rng;
+      break;
+    case APC_PSNR:
+      t.kind = APC_RMSE_ABS;
+      t.value = rng * pow(10.0, -target->value / 20.0);
+      break;
+    case APC_EB_ABS:
+    case APC_RMSE_ABS: break;
+    default: return fail(APC_E_INVALID, "unknown target kind %d", target->kind);
+  }
+  const size_t es = qsize(B->dtype);
+  size_t maxb = 0;
+  for (int64_t b = 0; b < B->nblocks(); ++b) {
+    int64_t lo[3], ext[3];
+    B->block(b, lo, ext);
+    maxb = std::max(maxb, (size_t)(ext[0] * ext[1] * ext[2]) * es);
+  }
+  DevBuf dout;
+  APC_TRY(dout.alloc(maxb));
+  PinnedBlock pin;
+  if (!g_pinned.get(maxb, pin)) return fail(APC_E_OOM, "pinned staging of %zu bytes", maxb);
+  struct PinBack {
+    PinnedBlock* p;
+    hipStream_t st;
+    ~PinBack() { g_pinned.put(*p, st, true); }
+  } pb{&pin, st};
+  apc_retrieve_info tot{};
+  double sq = 0.0, worst = 0.0;
+  const bool l2 = t.kind == APC_RMSE_ABS;
+  for (int64_t b = 0; b < B->nblocks(); ++b) {
+    apc_handle* ph = B->plan_h[(size_t)b].get();
+    std::vector<int> planes;
+    apc_retrieve_info bi{};
+    APC_TRY(plan_for(ph, &t, planes, &bi, nullptr));
+    std::unique_ptr<apc_handle> h;
+    std::vector<const unsigned char*> bp;
+    const std::vector<unsigned char>& blob = B->blobs[(size_t)b];
+    APC_TRY(rep_parse(blob.data(), (int64_t)blob.size(), h, bp));
+    APC_TRY(upload_planes(h.get(), bp, &planes, st));
+    APC_TRY(do_retrieve(h.get(), planes, dout.p, st, nullptr));
+    HIP_TRY(hipMemcpyAsync(pin.p, dout.p, (size_t)ph->meta.n * es, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    block_copy(B, b, es, nullptr, (char*)pin.p, false, (char*)out_host);
+    tot.bytes_total += bi.bytes_total;
+    tot.bytes_fetched += bi.bytes_total;
+    tot.nsteps += bi.nsteps;
+    tot.n_streams += bi.n_streams;
+    worst = std::max(worst, bi.bound);
+    sq += (double)ph->meta.n * bi.bound * bi.bound;
+  }
+  const double n = (double)(B->N[0] * B->N[1] * B->N[2]);
+  tot.tau = t.value;
+  tot.bound = l2 ? sqrt(sq / n) : worst;
+  tot.bitrate = 8.0 * (double)tot.bytes_total / n;
+  if (info) *info = tot;
+  return APC_OK;
+}
+
+void apc_blocks_free(apc_blockset* B) { delete B; }
 
 apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out, double* one_out) {
   if (n < 1 || L < 1 || (degree != 1 && degree != 3) || !inf_out || !one_out)
