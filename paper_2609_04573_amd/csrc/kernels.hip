@@ -241,6 +241,25 @@ __device__ __forceinline__ void wave_incl_scan_n(uint32_t (&x)[N]) {
   wave_scan_step<0x143, 0xc, false>(x);
 }
 
+// Workgroups go to the device's 8 XCDs in turn (workgroup i to XCD i mod 8,
+// also for the blocks a grid-stride loop takes on, the grid being a multiple
+// of 8 or the whole table), and every XCD has an L2 of its own.  This
+// renumbers the n blocks of one segment so that runs of g consecutive tiles
+// go to one XCD, the runs dealt to the XCDs in turn: neighbouring tiles of a
+// run then meet each other's halo reads in that L2 instead of fetching them
+// again, while all XCDs still work on one window of the segment at a time
+// (ranges far apart, a power of two bytes from each other, would meet in
+// the same memory channels).  A bijection of [0, n): block lb is the i-th
+// of its class x = lb mod 8; blocks past the last whole round of 8 runs keep
+// their number.
+__device__ __forceinline__ int64_t xcd_local(int64_t lb, int64_t n, int64_t g) {
+  constexpr int64_t kXcd = 8;
+  const int64_t whole = n / (kXcd * g) * (kXcd * g);
+  if (lb >= whole) return lb;
+  const int64_t x = lb % kXcd, i = lb / kXcd;
+  return ((i / g) * kXcd + x) * g + i % g;
+}
+
 // Segment of global work block b (segments are sorted by blk_begin).
 template <typename S>
 __device__ __forceinline__ int find_seg(const S* segs, int nseg, int64_t b) {
@@ -572,7 +591,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int m0 = S.m[0], m1 = S.m[1], m2 = S.m[2];
     const int mc0 = S.mc[0], mc1 = S.mc[1], mc2 = S.mc[2];
     const int deg = S.degree;
-    int lb = (int)(b - S.blk_begin);
+    const int nrun = (m0 + S.ch - 1) / S.ch;
+    int lb = (int)xcd_local(b - S.blk_begin, (int64_t)S.nt1 * S.nt2 * nrun, S.nt2);
     const int t2 = (lb % S.nt2) * kT2;
     lb /= S.nt2;
     const int t1 = (lb % S.nt1) * kT1;
@@ -1200,7 +1220,8 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const CDSeg& S = segs[si];
     const int Nu = S.c[U], Nv = S.c[2];
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    int lb = (int)(b - S.blk_begin);
+    const int64_t send = si + 1 < nseg ? segs[si + 1].blk_begin : nblk;
+    int lb = (int)xcd_local(b - S.blk_begin, send - S.blk_begin, 4 * nTv);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
@@ -1391,7 +1412,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     }
     const int Nu = A == 0 ? c1 : c0, Nv = c2;
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    int lb = (int)(b - blk0);
+    int lb = (int)xcd_local(b - blk0, seg_end - blk0, 4 * nTv);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
