@@ -658,7 +658,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         coff[k] = MODE >= 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * xs1 + (int64_t)(2 * c2) * xs2;
     }
     const int64_t cplane = MODE >= 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
-    double cpre[kCPer];
+    // The next coarse tile: in the max pass converted as it arrives; in the
+    // other passes held as loaded (the field's type, or float64) and
+    // converted, or zeroed outside the grid, when it goes to LDS, so that
+    // the load's wait falls there and not right after the load.
+    using CT = typename std::conditional<MODE == 1, T, double>::type;
+    CT cpre[kCPer];
     // Loads are issued on every lane, a lane without a point reading a
     // harmless address (the segment table) and dropping the value: branches
     // around per-lane loads cost more than the loads.
@@ -676,13 +681,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
           }
           continue;
         }
-        double x;
         if (MODE >= 2)
-          x = *(ok ? (const GAS double*)src + o : (const GAS double*)safe);
+          cpre[k] = *(ok ? (const GAS double*)src + o : (const GAS double*)safe);
         else
-          x = (double)*(ok ? (const GAS T*)src + o : (const GAS T*)safe);
-        cpre[k] = ok ? x : 0.0;
-        if (MODE == 0 && racc && ok) take((T)cpre[k]);
+          cpre[k] = *(ok ? (const GAS T*)src + o : (const GAS T*)safe);
       }
     };
 
@@ -695,7 +697,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       // before u2 is written again.
 #pragma unroll
       for (int k = 0; k < kCPer; ++k)
-        if (tid + k * kThreads < kC1 * kC2) ctile[tid + k * kThreads] = cpre[k];
+        if (tid + k * kThreads < kC1 * kC2) ctile[tid + k * kThreads] = coff[k] >= 0 ? (double)cpre[k] : 0.0;
       if (cc + 1 < mc0) fetch_tile(cc + 1);
       __syncthreads();
 #pragma unroll
