@@ -658,11 +658,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         coff[k] = MODE >= 2 ? (int64_t)c1 * mc2 + c2 : (int64_t)(2 * c1) * xs1 + (int64_t)(2 * c2) * xs2;
     }
     const int64_t cplane = MODE >= 2 ? (int64_t)mc1 * mc2 : 2 * xs0;  // coarse plane stride
-    // The next coarse tile: in the max pass converted as it arrives; in the
-    // other passes held as loaded (the field's type, or float64) and
-    // converted, or zeroed outside the grid, when it goes to LDS, so that
-    // the load's wait falls there and not right after the load.
-    using CT = typename std::conditional<MODE == 1, T, double>::type;
+    // The next coarse tile, held as loaded (the field's type, or float64)
+    // and converted, zeroed outside the grid and (max pass over level 0)
+    // taken into the range when it goes to LDS, so that the load's wait
+    // falls there and not right after the load.
+    using CT = typename std::conditional<MODE <= 1, T, double>::type;
     CT cpre[kCPer];
     // Loads are issued on every lane, a lane without a point reading a
     // harmless address (the segment table) and dropping the value: branches
@@ -674,11 +674,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         const bool ok = coff[k] >= 0;
         const int64_t o = (int64_t)cc * cplane + coff[k];
         if (MODE == 0) {  // as in fetch_in
-          cpre[k] = 0.0;
-          if (ok) {
-            cpre[k] = (double)((const GAS T*)src)[o];
-            if (racc) take((T)cpre[k]);
-          }
+          cpre[k] = (T)0;
+          if (ok) cpre[k] = ((const GAS T*)src)[o];
           continue;
         }
         if (MODE >= 2)
@@ -696,8 +693,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       // barrier, and the readers of u2 (its axis-1 pass) pass the next one
       // before u2 is written again.
 #pragma unroll
-      for (int k = 0; k < kCPer; ++k)
+      for (int k = 0; k < kCPer; ++k) {
+        if (MODE == 0 && racc && coff[k] >= 0) take(cpre[k]);
         if (tid + k * kThreads < kC1 * kC2) ctile[tid + k * kThreads] = coff[k] >= 0 ? (double)cpre[k] : 0.0;
+      }
       if (cc + 1 < mc0) fetch_tile(cc + 1);
       __syncthreads();
 #pragma unroll
@@ -1222,8 +1221,7 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const CDSeg& S = segs[si];
     const int Nu = S.c[U], Nv = S.c[2];
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    const int64_t send = si + 1 < nseg ? segs[si + 1].blk_begin : nblk;
-    int lb = (int)xcd_local(b - S.blk_begin, send - S.blk_begin, 4 * nTv);
+    int lb = (int)(b - S.blk_begin);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
@@ -1414,7 +1412,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     }
     const int Nu = A == 0 ? c1 : c0, Nv = c2;
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    int lb = (int)xcd_local(b - blk0, seg_end - blk0, 4 * nTv);
+    int lb = (int)(b - blk0);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
