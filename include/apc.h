@@ -292,9 +292,10 @@ apc_status apc_field_info(const apc_handle* h, int64_t* dims, int32_t* ndim, int
  * layout, each section with its length and a 64-bit checksum:
  *   [0,8) magic "APCREP01"; [8,16) total length; [16,24) metadata length;
  *   [24,32) metadata checksum; metadata (int32 dtype, ndim; int64 dims[3];
- *   int32 kind, degree, order[3], cd_axis, levels, L, P, 0; float64 xmin,
- *   xmax, A; uint32 group and stream counts; float64 M per group; per
- *   stream int64 n, maxabs, int32 B, 0, int64 nsig[B]); then per stream
+ *   int32 kind, degree, order[3], cd_axis, levels, L, P, lossless,
+ *   encoding, 0; float64 xmin, xmax, A; uint32 group and stream counts;
+ *   float64 M per group; per stream int64 n, maxabs, int32 B, 0, int64
+ *   nsig[B], and with the lossless stage int64 nnz[B]); then per stream
  *   uint64 blob length, uint64 blob checksum, blob.  Little endian.
  * apc_serialize: with host_dst NULL only *len is set (the size needed);
  *   otherwise host_dst (caller owned, cap >= *len bytes) receives the
