@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -944,6 +945,26 @@ void build_layout(apc_handle* h, int P) {
 }
 
 // Weights of every group (exact chain norms of the user axes).
+// f(i) for i in [0, n) on up to 16 host threads (the caller's among them);
+// for independent per-handle host work of a batch.  f must not throw.
+template <typename F>
+void parallel_for(size_t n, F&& f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>(n, std::min<size_t>(16, hw));
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  auto work = [&] {
+    for (size_t i; (i = next.fetch_add(1)) < n;) f(i);
+  };
+  std::vector<std::thread> th;
+  for (size_t t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (std::thread& t : th) t.join();
+}
+
 void assign_weights(apc_handle* h) {
   Geo& g = h->geo;
   Meta& m = h->meta;
@@ -1595,12 +1616,13 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   // runs while the sign placement is on the device, and so does the
   // interpreter's greedy sequence for error-bound targets (kept in the
   // handle for its first retrieval).
-  for (int f = 0; f < nf; ++f) {
+  // (independent per field: spread over host threads for large batches)
+  parallel_for((size_t)nf, [&](size_t f) {
     assign_weights(H[f]);
     finalize_units(H[f]);
     H[f]->k_res.assign(H[f]->meta.streams.size(), 0);
     ensure_sequence(H[f]->meta, 0);
-  }
+  });
   // The call returns while the sign placement may still run: each handle
   // gets an event behind it (work on other streams waits for that), and the
   // temporaries stay allocated until it has finished.  (The layout kernel's
@@ -3499,18 +3521,24 @@ apc_status select_impl(const T* field, int32_t dtype, const Geo& g, int mode, ap
       std::vector<apc_scheme> sc(nb, cands[c]);
       std::vector<std::unique_ptr<apc_handle>> own;
       APC_TRY(refactor_many(fptr.data(), dtype, dims.data(), nds.data(), sc.data(), nb, st, own));
-      for (int t = 0; t < 9; ++t) {
-        int64_t total = 0;
-        for (auto& h : own) {
+      // the blocks' plans are independent host work: spread over threads
+      std::vector<std::array<int64_t, 9>> per(own.size());
+      parallel_for(own.size(), [&](size_t i) {
+        Meta& m = own[i]->meta;
+        for (int t = 0; t < 9; ++t) {
           std::vector<int> planes;
           double b;
           int ns;
-          if (make_plan(h->meta, kTuneTol[t] * rng, mode, planes, b, ns) != 0) {
-            planes.assign(h->meta.streams.size(), 0);
-            for (size_t s = 0; s < planes.size(); ++s) planes[s] = h->meta.streams[s].B;
+          if (make_plan(m, kTuneTol[t] * rng, mode, planes, b, ns) != 0) {
+            planes.assign(m.streams.size(), 0);
+            for (size_t s = 0; s < planes.size(); ++s) planes[s] = m.streams[s].B;
           }
-          total += plan_bytes(h->meta, planes);
+          per[i][t] = plan_bytes(m, planes);
         }
+      });
+      for (int t = 0; t < 9; ++t) {
+        int64_t total = 0;
+        for (const auto& p : per) total += p[t];
         sizes[c][t] = total;
       }
     }
