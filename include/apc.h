@@ -139,6 +139,22 @@ apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev,
  * clamped to the stream's plane count). */
 apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream);
 
+/* Many retrievals in shared launches (Algorithm 2 for each request; the
+ * retrieval counterpart of apc_refactor_batch): request i retrieves handle
+ * hs[i] to targets[i] into outs_dev[i] (caller owned, that handle's size and
+ * dtype).  All handles hold one dtype; a handle may appear more than once.
+ * Each handle decodes once, up to the largest plan among its requests
+ * (incremental, as apc_retrieve); every request's recomposition and
+ * reconstruction read the codes truncated to its own plan, so each output
+ * equals apc_retrieve of that request alone.  infos (n entries, may be
+ * NULL): each request's plan, bytes_fetched crediting the planes it adds in
+ * request order.  Returns once the work is queued on hip_stream.
+ * APC_E_BELOW_FLOOR (nothing queued, no output written) if any target is
+ * below its handle's floor; APC_E_INVALID for null arguments or mixed
+ * dtypes. */
+apc_status apc_retrieve_batch(apc_handle* const* hs, int32_t n, const apc_target* targets, void* const* outs_dev,
+                              apc_retrieve_info* infos, void* hip_stream);
+
 /* Retrieval that allocates nothing, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same plan and same output bytes as apc_retrieve with

@@ -42,7 +42,7 @@ TARGET_KINDS = {"abs": 0, "rel": 1, "psnr": 2, "rmse": 3}
 MODES = {"eb": 0, "psnr": 1}
 
 EXPORTED = [
-    "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_select_pipeline", "apc_free",
+    "apc_refactor", "apc_plan", "apc_retrieve", "apc_retrieve_planes", "apc_retrieve_batch", "apc_select_pipeline", "apc_free",
     "apc_strerror", "apc_last_error", "apc_num_streams", "apc_num_groups", "apc_num_points", "apc_stream_info",
     "apc_stream_blob", "apc_metadata_json", "apc_axis_norms", "apc_profile_enable", "apc_profile_report",
     "apc_refactor_batch", "apc_ladder_create", "apc_ladder_launch", "apc_ladder_free", "apc_server_create",
@@ -79,6 +79,8 @@ _lib.apc_refactor.argtypes = [_vp, _i32, ctypes.POINTER(_i64), _i32, ctypes.POIN
 _lib.apc_plan.argtypes = [_vp, ctypes.POINTER(_Target), ctypes.POINTER(_i32), ctypes.POINTER(_Info)]
 _lib.apc_retrieve.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
 _lib.apc_retrieve_planes.argtypes = [_vp, ctypes.POINTER(_i32), _vp, _vp]
+_lib.apc_retrieve_batch.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_Target), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_Info), _vp]
 _lib.apc_retrieve_static.argtypes = [_vp, ctypes.POINTER(_Target), _vp, ctypes.POINTER(_Info), _vp]
 _lib.apc_field_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 _lib.apc_serialize.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_i64)]
@@ -351,6 +353,25 @@ def deserialize_host(data: bytes) -> Handle:
     nd, dt = _i32(), _i32()
     _check(_lib.apc_field_info(out, dims, ctypes.byref(nd), ctypes.byref(dt)))
     return Handle(out.value, tuple(dims[i] for i in range(nd.value)), None)
+
+
+def retrieve_batch(handles, targets, outs=None, stream=None):
+    """Retrieve many handles (one dtype; a handle may repeat) in shared
+    launches; returns (outputs, infos), each output equal to that request's
+    retrieve() alone."""
+    import torch
+    n = len(handles)
+    assert n == len(targets) and n > 0
+    if outs is None:
+        outs = [torch.empty(h.shape, dtype=h.dtype, device="cuda") for h in handles]
+    for h, o in zip(handles, outs):
+        assert o.is_contiguous() and o.dtype == h.dtype and tuple(o.shape) == h.shape
+    hs = (_vp * n)(*[h._h for h in handles])
+    tg = (_Target * n)(*[t._c() for t in targets])
+    ptrs = (_vp * n)(*[o.data_ptr() for o in outs])
+    infs = (_Info * n)()
+    _check(_lib.apc_retrieve_batch(hs, n, tg, ptrs, infs, _stream_ptr(stream)))
+    return outs, [_info_dict(i) for i in infs]
 
 
 def refactor_batch(fields, schemes, stream=None) -> List[Handle]:

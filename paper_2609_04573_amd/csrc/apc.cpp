@@ -2290,6 +2290,81 @@ apc_status need_device(const apc_handle* h) {
   return APC_OK;
 }
 
+// Many retrievals in shared launches (Algorithm 2 for each request): every
+// handle decodes once, up to the largest plan among its requests, and the
+// recomposition and reconstruction of every request run merged, each reading
+// the resident codes truncated to its own plan into its own work buffers
+// (the handle's for its first request, temporaries for further ones).
+template <typename T, typename Q>
+apc_status retrieve_batch_impl(apc_handle* const* hs, int32_t n, const apc_target* targets, void* const* outs,
+                               apc_retrieve_info* infos, hipStream_t st) {
+  DrainScope drain(st);
+  std::vector<std::vector<int>> planes((size_t)n);
+  std::vector<apc_retrieve_info> inf((size_t)n);
+  std::vector<apc_handle*> uniq;
+  std::map<apc_handle*, size_t> idx;
+  for (int32_t i = 0; i < n; ++i) {
+    apc_handle* h = hs[i];
+    APC_TRY(plan_for(h, &targets[i], planes[i], &inf[i], &h->k_res));
+    if (!idx.count(h)) {
+      idx[h] = uniq.size();
+      uniq.push_back(h);
+    }
+  }
+  for (apc_handle* h : uniq) {
+    if (h->ready) HIP_TRY(hipStreamWaitEvent(st, h->ready, 0));  // the refactor's last kernels
+    APC_TRY(ensure_work(h));
+  }
+  // decodes: each request is credited with the planes it adds, in order
+  std::vector<std::vector<int>> want(uniq.size()), kres(uniq.size());
+  for (size_t u = 0; u < uniq.size(); ++u) want[u] = kres[u] = uniq[u]->k_res;
+  for (int32_t i = 0; i < n; ++i) inf[i].bytes_fetched = fetch_bytes(hs[i]->meta, want[idx[hs[i]]], planes[i]);
+  std::vector<TableBuilder> tbs(uniq.size() + (size_t)n);
+  std::vector<std::vector<Launch>> lss(uniq.size() + (size_t)n);
+  std::vector<LaunchPart> parts;
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    build_retrieve<T, Q>(uniq[u], want[u], nullptr, kres[u], tbs[u], lss[u], nullptr, WorkPtrs(), true, false);
+    if (!lss[u].empty()) parts.push_back({&tbs[u], &lss[u]});
+  }
+  std::vector<DevBuf> tmp;
+  tmp.reserve((size_t)n);
+  std::vector<bool> own_used(uniq.size(), false);
+  for (int32_t i = 0; i < n; ++i) {
+    apc_handle* h = hs[i];
+    const size_t u = idx[h];
+    WorkPtrs w;
+    if (!own_used[u]) {
+      w = handle_work(h);
+      own_used[u] = true;
+    } else {
+      tmp.emplace_back();
+      APC_TRY(tmp.back().alloc(work_bytes(h)));
+      w = carve_work(h, tmp.back().p);
+    }
+    std::vector<int> kdone = kres[u];  // decoded above
+    const size_t j = uniq.size() + (size_t)i;
+    build_retrieve<T, Q>(h, planes[i], (T*)outs[i], kdone, tbs[j], lss[j], nullptr, w, false, true);
+    parts.push_back({&tbs[j], &lss[j]});
+  }
+  TableBuilder tb;
+  std::vector<Launch> ls;
+  merge_launches(parts, tb, ls);
+  // the merged table travels in the first handle's table buffer, as a
+  // retrieval of that handle's own would
+  apc_handle* h0 = uniq[0];
+  APC_TRY(upload_tables(h0, tb.bytes, st));
+  APC_TRY((issue<T, Q>(ls, (const char*)h0->tables.p, st)));
+  if (!h0->tab_ev) HIP_TRY(hipEventCreateWithFlags(&h0->tab_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(h0->tab_ev, st));
+  for (size_t u = 0; u < uniq.size(); ++u) uniq[u]->k_res = kres[u];
+  if (infos)
+    for (int32_t i = 0; i < n; ++i) infos[i] = inf[i];
+  // the temporary work buffers stay allocated until the queued work has finished
+  APC_TRY(retire(std::move(tmp), st));
+  drain.armed = false;
+  return APC_OK;
+}
+
 apc_status do_retrieve(apc_handle* h, const std::vector<int>& planes, void* out_dev, void* hip_stream,
                        int64_t* fetched) {
   hipStream_t st = (hipStream_t)hip_stream;
@@ -2858,6 +2933,19 @@ apc_status apc_retrieve(apc_handle* h, const apc_target* target, void* out_dev, 
   inf.bytes_fetched = fetched;
   if (info) *info = inf;
   return APC_OK;
+}
+
+apc_status apc_retrieve_batch(apc_handle* const* hs, int32_t n, const apc_target* targets, void* const* outs_dev,
+                              apc_retrieve_info* infos, void* hip_stream) {
+  if (!hs || !targets || !outs_dev || n < 1) return fail(APC_E_INVALID, "bad argument");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!hs[i] || !outs_dev[i]) return fail(APC_E_INVALID, "null handle or output at %d", i);
+    if (hs[i]->dtype != hs[0]->dtype) return fail(APC_E_INVALID, "a batch holds handles of one dtype");
+    APC_TRY(need_device(hs[i]));
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hs[0]->dtype == APC_F32) return retrieve_batch_impl<float, int32_t>(hs, n, targets, outs_dev, infos, st);
+  return retrieve_batch_impl<double, int64_t>(hs, n, targets, outs_dev, infos, st);
 }
 
 apc_status apc_retrieve_planes(apc_handle* h, const int32_t* planes, void* out_dev, void* hip_stream) {

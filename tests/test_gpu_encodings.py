@@ -1,8 +1,8 @@
 """GPU tests of the lossless stage and the negabinary encodings on the paths
 that share launches or capture them: a batched refactor of fields with
 different encodings, a retrieval ladder replayed as one graph, the serving
-loop merging requests of differently encoded fields, and the retrieval that
-allocates nothing.  Streams, plans and reconstructions must equal the
+loop merging requests of differently encoded fields, the retrieval that
+allocates nothing, and batched retrieval (repeated handles included).  Streams, plans and reconstructions must equal the
 oracle's bit for bit (Table I encodings; Section V lossless stage)."""
 import numpy as np
 import pytest
@@ -126,4 +126,40 @@ def test_static_retrieval_of_negabinary_and_lossless_fields(fields):
             pl = oracle.plan(refs[f], oracle.Target(t.kind, t.value))
             assert info["bytes_total"] == pl.bytes
             assert np.array_equal(_bits(out.cpu().numpy()), _bits(oracle.retrieve(refs[f], pl))), (f, t)
+        h.close()
+
+
+def test_batched_retrieval_equals_single_retrievals_and_the_oracle(fields):
+    """apc_retrieve_batch over the differently encoded fields, a handle
+    repeated with tighter and looser targets: every output equals the
+    oracle's reconstruction for its plan, plans and byte counts equal the
+    oracle's, and a later single retrieval continues from the planes the
+    batch decoded."""
+    apc = _apc()
+    xs, refs = fields
+    hs = [apc.refactor(torch.from_numpy(x).cuda(), _schemes(c)[0]) for x, c in zip(xs, CASES)]
+    reqs = [(0, apc.Target("rel", 1e-4)), (1, apc.Target("psnr", 70)), (0, apc.Target("rel", 1e-2)),
+            (2, apc.Target("rel", 1e-3)), (3, apc.Target("psnr", 90)), (0, apc.Target("rel", 1e-5)),
+            (1, apc.Target("psnr", 50))]
+    outs, infos = apc.retrieve_batch([hs[f] for f, _ in reqs], [t for _, t in reqs])
+    kcur = {f: [0] * len(refs[f].streams) for f in range(len(hs))}
+    for (f, t), o, inf in zip(reqs, outs, infos):
+        pl = oracle.plan(refs[f], oracle.Target(t.kind, t.value))
+        assert inf["bytes_total"] == pl.bytes, (f, t)
+        added = 0
+        for s, st in enumerate(refs[f].streams):
+            for j in range(kcur[f][s], pl.planes[s]):
+                added += st.meta.plane_bytes(j)
+            kcur[f][s] = max(kcur[f][s], pl.planes[s])
+        assert inf["bytes_fetched"] == added, (f, t)
+        want = oracle.retrieve(refs[f], pl)
+        assert np.array_equal(_bits(o.cpu().numpy()), _bits(want)), (f, t)
+    # what the batch decoded stays resident: a looser single retrieval fetches nothing
+    out, inf = hs[0].retrieve(apc.Target("rel", 1e-3))
+    assert inf["bytes_fetched"] == 0
+    pl = oracle.plan(refs[0], oracle.Target("rel", 1e-3))
+    assert np.array_equal(_bits(out.cpu().numpy()), _bits(oracle.retrieve(refs[0], pl)))
+    with pytest.raises(apc.BelowFloor):
+        apc.retrieve_batch([hs[0], hs[1]], [apc.Target("rel", 1e-2), apc.Target("abs", 0.0)])
+    for h in hs:
         h.close()
