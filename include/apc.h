@@ -43,14 +43,20 @@ enum {
 };
 
 enum { APC_F32 = 0, APC_F64 = 1 };                 /* dtype */
-enum { APC_PER_LEVEL = 0, APC_PER_REGION = 1 };    /* apc_scheme.kind */
+enum { APC_PER_LEVEL = 0, APC_PER_REGION = 1, APC_AUTO = 2, APC_AUTO_PSNR = 3 };  /* apc_scheme.kind */
 enum { APC_EB_ABS = 0, APC_EB_REL = 1, APC_PSNR = 2, APC_RMSE_ABS = 3 };  /* apc_target.kind */
 enum { APC_MODE_EB = 0, APC_MODE_PSNR = 1 };       /* select_pipeline mode */
 
 /* Pipeline configuration (Table I: interpolation scheme, dimension order of
  * per-region interpolation, coefficient-decomposition direction or none). */
 typedef struct {
-  int32_t kind;      /* APC_PER_LEVEL or APC_PER_REGION */
+  int32_t kind;      /* APC_PER_LEVEL or APC_PER_REGION; or, for the refactor
+                        calls, APC_AUTO / APC_AUTO_PSNR: the field's kind,
+                        order and decomposition direction are chosen first by
+                        apc_select_pipeline in error-bound / PSNR mode
+                        (Section VI-A), keeping this scheme's levels,
+                        lossless and encoding fields; the handle's metadata
+                        JSON names the scheme used */
   int32_t degree;    /* 1 = multilinear, 3 = cubic (Section IV) */
   int32_t order[3];  /* per-region pass order, a permutation of 0..ndim-1
                         (ignored for per-level, which goes fastest axis first) */

@@ -164,7 +164,7 @@ def _check(status: int):
 
 @dataclass(frozen=True)
 class Scheme:
-    kind: str = "level"                      # "level" or "region"
+    kind: str = "level"                      # "level", "region", or (refactor only) "auto" / "auto_psnr"
     degree: int = 3
     order: Optional[Tuple[int, ...]] = None  # per-region pass order (axes)
     cd_axis: Optional[int] = None
@@ -174,7 +174,7 @@ class Scheme:
 
     def _c(self, ndim: int) -> _Scheme:
         s = _Scheme()
-        s.kind = PER_LEVEL if self.kind == "level" else PER_REGION
+        s.kind = {"level": PER_LEVEL, "region": PER_REGION, "auto": 2, "auto_psnr": 3}[self.kind]
         s.degree = self.degree
         order = self.order if self.order is not None else tuple(range(ndim - 1, -1, -1))
         for i in range(3):
@@ -308,6 +308,17 @@ class Handle:
         buf = ctypes.create_string_buffer(max(1, ln.value))
         _check(_lib.apc_serialize(self._h, buf, ln.value, ctypes.byref(ln)))
         return buf.raw[:ln.value]
+
+    @property
+    def scheme(self) -> "Scheme":
+        """The scheme the field was refactored with (the chosen one for
+        "auto" kinds)."""
+        c = self.metadata()["scheme"]
+        d = len(self.shape)
+        return Scheme(kind="level" if c["kind"] == PER_LEVEL else "region", degree=c["degree"],
+                      order=None if c["kind"] == PER_LEVEL else tuple(c["order"][:d]),
+                      cd_axis=None if c["cd_axis"] < 0 else c["cd_axis"], levels=c["levels"],
+                      lossless=bool(c["lossless"]), encoding={v: k for k, v in ENCODINGS.items()}[c["encoding"]])
 
     def metadata(self) -> dict:
         ln = _i64()

@@ -2390,7 +2390,22 @@ apc_status refactor_many(const void* const* fields, int32_t dtype, const int64_t
                          const apc_scheme* schemes, int32_t nf, hipStream_t st,
                          std::vector<std::unique_ptr<apc_handle>>& own) {
   if (dtype != APC_F32 && dtype != APC_F64) return fail(APC_E_DTYPE, "dtype must be APC_F32 or APC_F64");
-  APC_TRY(make_handles(nf, dtype, dims, ndims, schemes, own));
+  // target-driven selection first for the fields that ask for it
+  std::vector<apc_scheme> sc(schemes, schemes + nf);
+  int64_t doff = 0;
+  for (int f = 0; f < nf; ++f) {
+    if (sc[f].kind == APC_AUTO || sc[f].kind == APC_AUTO_PSNR) {
+      apc_scheme chosen{};
+      APC_TRY(apc_select_pipeline(fields[f], dtype, dims + doff, ndims[f],
+                                  sc[f].kind == APC_AUTO ? APC_MODE_EB : APC_MODE_PSNR, &chosen, st));
+      chosen.levels = sc[f].levels;
+      chosen.lossless = sc[f].lossless;
+      chosen.encoding = sc[f].encoding;
+      sc[f] = chosen;
+    }
+    doff += ndims[f];
+  }
+  APC_TRY(make_handles(nf, dtype, dims, ndims, sc.data(), own));
   std::vector<apc_handle*> hs;
   for (auto& h : own) hs.push_back(h.get());
   if (dtype == APC_F32) {
@@ -3117,7 +3132,18 @@ apc_status apc_stream_blob(const apc_handle* h, int32_t s, void* host_dst, int64
 
 apc_status apc_metadata_json(const apc_handle* h, char* buf, int64_t cap, int64_t* len) {
   if (!h) return fail(APC_E_INVALID, "null handle");
-  const std::string js = meta_json(h->meta);
+  std::string js = meta_json(h->meta);
+  {  // the scheme the handle was refactored with (levels: the number used)
+    const apc_scheme& c = h->scheme;
+    char tmp[320];
+    snprintf(tmp, sizeof(tmp),
+             ",\"scheme\":{\"kind\":%d,\"degree\":%d,\"order\":[%d,%d,%d],\"cd_axis\":%d,\"levels\":%d,"
+             "\"lossless\":%d,\"encoding\":%d}}",
+             c.kind, c.degree, h->geo.sigma_user[0], h->geo.sigma_user[1], h->geo.sigma_user[2], c.cd_axis, h->geo.L,
+             c.lossless, c.encoding);
+    js.pop_back();  // the closing brace
+    js += tmp;
+  }
   if (len) *len = (int64_t)js.size();
   if (buf) {
     if (cap < (int64_t)js.size() + 1) return fail(APC_E_INVALID, "buffer too small");

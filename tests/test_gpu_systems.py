@@ -199,3 +199,31 @@ def test_refactor_returns_before_its_last_kernels():
     assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
     assert blobs == [h.stream_blob(s) for s in range(h.num_streams)]
     h.close()
+
+
+def test_auto_schemes_refactor_with_the_selected_pipeline():
+    """APC_AUTO / APC_AUTO_PSNR: the refactor first runs the target-driven
+    selection (Section VI-A) and then refactors with what it picked, keeping
+    the requested lossless stage and encoding; the result is the same handle
+    as refactoring with that scheme, and the oracle's selection agrees."""
+    import paper_2609_04573_amd as apc
+
+    x = fieldgen.power_law_field((64, 80, 96), seed=12)
+    xd = torch.from_numpy(x).cuda()
+    for kind, mode in (("auto", "eb"), ("auto_psnr", "psnr")):
+        sel = apc.select_pipeline(xd, mode)
+        want = oracle.select_pipeline(x, mode)
+        assert sel.kind == want.kind and sel.cd_axis == want.cd_axis, (mode, sel, want)
+        h = apc.refactor(xd, apc.Scheme(kind=kind, lossless=True, encoding="negabinary_xor"))
+        got = h.scheme
+        assert got.kind == sel.kind and got.cd_axis == sel.cd_axis and got.degree == sel.degree, (got, sel)
+        assert got.lossless and got.encoding == "negabinary_xor"
+        ref = apc.refactor(xd, apc.Scheme(kind=sel.kind, degree=sel.degree, order=sel.order, cd_axis=sel.cd_axis,
+                                          lossless=True, encoding="negabinary_xor"))
+        assert h.metadata() == ref.metadata()
+        for s in range(h.num_streams):
+            assert h.stream_blob(s) == ref.stream_blob(s)
+        hb = apc.refactor_batch([xd, xd], [apc.Scheme(kind=kind), apc.Scheme(kind="level")])
+        assert hb[0].scheme.kind == sel.kind and hb[1].scheme.kind == "level"
+        for hh in [h, ref] + hb:
+            hh.close()
