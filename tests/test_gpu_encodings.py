@@ -163,3 +163,34 @@ def test_batched_retrieval_equals_single_retrievals_and_the_oracle(fields):
         apc.retrieve_batch([hs[0], hs[1]], [apc.Target("rel", 1e-2), apc.Target("abs", 0.0)])
     for h in hs:
         h.close()
+
+
+def test_batched_retrieval_of_float64_fields_of_every_dimensionality():
+    """float64 fields of 1, 2 and 3 dims (tiny and ragged ones included) in
+    one batched retrieval, a field repeated, against the oracle."""
+    apc = _apc()
+    rng = np.random.default_rng(8)
+    shapes = [(1,), (2,), (3, 3), (700,), (45, 61), (9, 17, 30)]
+    schemes = [("level", 3, None, None, False, "generic"), ("region", 1, None, None, True, "generic"),
+               ("level", 3, None, 1, False, "negabinary_xor"), ("region", 3, None, None, True, "negabinary"),
+               ("level", 3, None, 0, True, "generic"), ("region", 3, (1, 2, 0), 2, False, "negabinary_xor")]
+    xs = [np.cumsum(rng.standard_normal(s), axis=-1).astype(np.float64) for s in shapes]
+    hs, refs = [], []
+    for x, c in zip(xs, schemes):
+        kind, degree, order, cd, ll, enc = c
+        if order is not None and len(order) != x.ndim:
+            order = None
+        gs = apc.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=ll, encoding=enc)
+        osc = oracle.Scheme(kind=kind, degree=degree, order=order, cd_axis=cd, lossless=ll, encoding=enc)
+        hs.append(apc.refactor(torch.from_numpy(x).cuda(), gs))
+        refs.append(oracle.refactor(x, osc))
+    reqs = [(f, apc.Target("abs", 1e-3)) for f in range(len(xs))] + [(4, apc.Target("psnr", 80)),
+                                                                      (5, apc.Target("rel", 1e-6))]
+    outs, infos = apc.retrieve_batch([hs[f] for f, _ in reqs], [t for _, t in reqs])
+    for (f, t), o, inf in zip(reqs, outs, infos):
+        pl = oracle.plan(refs[f], oracle.Target(t.kind, t.value))
+        assert inf["bytes_total"] == pl.bytes, (f, t)
+        want = oracle.retrieve(refs[f], pl)
+        assert np.array_equal(_bits(o.cpu().numpy()), _bits(want)), (f, t)
+    for h in hs:
+        h.close()
