@@ -591,6 +591,8 @@ int64_t assign_cd_tile_blocks(std::vector<CDSeg>& segs, int a) {
   for (CDSeg& s : segs) {
     s.blk_begin = b;
     const int64_t nu = s.c[a == 0 ? 1 : 0];
+    s.ftu = make_fastdiv((uint32_t)std::max<int64_t>(1, (nu + 7) / 8));
+    s.ftv = make_fastdiv((uint32_t)std::max<int64_t>(1, (s.c[2] + 255) / 256));
     b += (int64_t)s.c[a] * ((nu + 7) / 8) * ((s.c[2] + 255) / 256);
   }
   return b;

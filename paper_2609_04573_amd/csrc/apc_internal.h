@@ -119,6 +119,7 @@ struct CDSeg {
   unsigned long long* smax[3];
   int64_t blk_begin;
   int32_t B[3], k[3];  // decode masks (inverse)
+  FastDiv ftv, ftu;    // row-tile inverse pass: division by the tiles along v and along u
 };
 
 // Device-side description of one bitplane stream for the codec kernels.

@@ -1220,12 +1220,13 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const int si = find_seg(segs, nseg, b);
     const CDSeg& S = segs[si];
     const int Nu = S.c[U], Nv = S.c[2];
-    const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
-    int lb = (int)(b - S.blk_begin);
-    const int V0 = (lb % nTv) * kCITV;
-    lb /= nTv;
-    const int U0 = (lb % nTu) * kCITU;
-    const int sa = lb / nTu;  // index along the stacking axis
+    // tile coordinates by multiply-high division (tiles along v, then u)
+    const uint32_t lb = (uint32_t)(b - S.blk_begin);
+    const uint32_t lq = fdiv(lb, S.ftv);
+    const int V0 = (int)(lb - lq * S.ftv.d) * kCITV;
+    const uint32_t sq = fdiv(lq, S.ftu);
+    const int U0 = (int)(lq - sq * S.ftu.d) * kCITU;
+    const int sa = (int)sq;  // index along the stacking axis
     auto tt = [&](int u, int& t0, int& t1) {
       t0 = A == 0 ? sa : u;
       t1 = A == 0 ? u : sa;
