@@ -35,7 +35,7 @@ KERNEL_CATEGORY = [
     ("k_decode", "", "decode"), ("k_sign_move", "", "sign_move"), ("k_sign_layout", "", "sign_layout"),
     ("k_scan", "", "scan"),
     ("k_range", "", "range"), ("k_gather", "", "subsample"), ("k_coarsest", "", "coarsest"),
-    ("k_coarse<", "", "coarse"), ("k_inject", "", "inject"),
+    ("k_coarse<", "", "coarse"), ("k_inject", "", "inject"), ("k_zero_words", "", "sign_clear"),
 ]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cubed_f32.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_04573_amd", "csrc", f) for f in ("kernels.hip", "apc_internal.h")]

@@ -495,7 +495,8 @@ enum LaunchKind {
   // queued so far (FORK), marks its end (JOIN_REC), and the main one waits
   // for that mark (JOIN_WAIT); without a helper stream these do nothing
   K_FORK, K_JOIN_REC, K_JOIN_WAIT,
-  K_DECODE_NB, K_NB_VALUES  // digit planes: decode, truncated integers
+  K_DECODE_NB, K_NB_VALUES,  // digit planes: decode, truncated integers
+  K_ZERO                     // clear 64-bit words (sign arenas)
 };
 
 struct Launch {
@@ -654,6 +655,7 @@ apc_status issue(const std::vector<Launch>& ls, const char* base, hipStream_t st
       case K_NB_VALUES:
         LAUNCH(l.name, l.bytes, st, launch_nb_values<Q>((const FlatSeg*)p, l.nseg, l.nblk, st));
         break;
+      case K_ZERO: LAUNCH(l.name, l.bytes, st, launch_zero_words((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_INJECT: LAUNCH(l.name, l.bytes, st, launch_inject<T>((const FlatSeg*)p, l.nseg, l.nblk, st)); break;
       case K_RECON: LAUNCH(l.name, l.bytes, st, (launch_recon<T, Q>((const ReconSeg*)p, l.nseg, l.nblk, st))); break;
       case K_LEVEL0:
@@ -1305,22 +1307,32 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       ls.push_back({K_CDF, tb2.add(cs), (int)cs.size(), nbk, a3, by, "cd_forward"});
     }
   }
+  // Sign arenas, sized by a bound known before any count (each code takes at
+  // most one sign bit and each plane's run is rounded up to whole words) and
+  // cleared (one launch for the batch) behind the passes above, instead of
+  // between the count read-back and the sign placement.
+  std::vector<int64_t> sign_ub(nf, 0);
+  {
+    std::vector<FlatSeg> zs;
+    for (int f = 0; f < nf; ++f) {
+      apc_handle* h = H[f];
+      for (const Stream& S : h->meta.streams) sign_ub[f] += (S.n + 63) / 64 + 8 * (int64_t)sizeof(Q);
+      sign_ub[f] = std::max<int64_t>(1, sign_ub[f]);
+      APC_TRY(h->sign.alloc(8 * (size_t)sign_ub[f]));
+      FlatSeg z{};
+      z.dst = h->sign.p;
+      z.n = sign_ub[f];
+      zs.push_back(z);
+    }
+    const int64_t nbk = assign_blocks<FlatSeg>(zs, [](const FlatSeg& z) { return z.n; });
+    double by = 0;
+    for (const FlatSeg& z : zs) by += 8.0 * (double)z.n;
+    ls.push_back({K_ZERO, tb2.add(zs), (int)zs.size(), nbk, 0, by, "sign_clear"});
+  }
   DevBuf tab2;
   APC_TRY(tab2.alloc(tb2.bytes.size()));
   APC_TRY(stage.put(tb2.bytes, tab2.p, st));
   APC_TRY((issue<T, Q>(ls, (const char*)tab2.p, st)));
-  // Sign arenas, sized by a bound known before any count (each code takes at
-  // most one sign bit and each plane's run is rounded up to whole words) and
-  // cleared now, so that the clear is queued behind the passes above instead
-  // of between the count read-back and the sign placement.
-  std::vector<int64_t> sign_ub(nf, 0);
-  for (int f = 0; f < nf; ++f) {
-    apc_handle* h = H[f];
-    for (const Stream& S : h->meta.streams) sign_ub[f] += (S.n + 63) / 64 + 8 * (int64_t)sizeof(Q);
-    sign_ub[f] = std::max<int64_t>(1, sign_ub[f]);
-    APC_TRY(h->sign.alloc(8 * (size_t)sign_ub[f]));
-    HIP_TRY(hipMemsetAsync(h->sign.p, 0, 8 * (size_t)sign_ub[f], st));
-  }
   std::vector<unsigned long long> hv((size_t)nacc);
   APC_TRY(read_back(hv.data(), acc, 8 * hv.size(), st));
   for (int f = 0; f < nf; ++f) {

@@ -223,6 +223,8 @@ template <typename Q>
 hipError_t launch_decode_nb(const StreamDev* sd, int ns, int64_t chunks, hipStream_t s);
 template <typename Q>
 hipError_t launch_nb_values(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
+// Zero the n 64-bit words at dst of every segment (FlatSeg: dst, n).
+hipError_t launch_zero_words(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T, typename Q>
 hipError_t launch_coarsest(const FlatSeg* segs, int nseg, int64_t nblk, hipStream_t s);
 template <typename T>

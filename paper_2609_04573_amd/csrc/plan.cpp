@@ -252,34 +252,50 @@ void finalize_meta(Meta& m) {
 
 void ensure_sequence(Meta& m, int mode) {
   if (m.seq_ready[mode]) return;
-  std::vector<int> state(m.units.size(), 0);
+  const int nu = (int)m.units.size();
+  std::vector<int> state(nu, 0);
   m.seq[mode].clear();
   m.seq_E0[mode] = bound(m, state, mode);
-  for (;;) {
-    int best = -1, best_k = 0;
-    double best_s = -1.0;
-    for (int u = 0; u < (int)m.units.size(); ++u) {
-      const Unit& un = m.units[u];
-      const int n = unit_nsteps(m, un);
-      if (state[u] < n) {
-        const Group& gr = m.groups[un.group];
-        const double wd = mode == 0 ? gr.wd_inf : gr.wd_2;
-        const int k = state[u];
-        const int k2 = next_lower([&](int kk) { return unit_err(m, un, kk); }, k, n);
-        const int64_t de = unit_err(m, un, k) - unit_err(m, un, k2);
-        int64_t c = 0;
-        for (int j = k; j < k2; ++j) c += unit_step_bytes(m, un, j);
-        const double s = (wd * (double)de) / (double)c;
-        if (s > best_s) {
-          best = u;
-          best_s = s;
-          best_k = k2;
-        }
-      }
+  // a unit's score and next step depend only on its own state: kept per
+  // unit and recomputed for the unit that advances (the same choices, in
+  // the same order, as recomputing every unit at every step)
+  std::vector<double> score(nu, -1.0);
+  std::vector<int> next_k(nu, 0);
+  auto rescore = [&](int u) {
+    const Unit& un = m.units[u];
+    const int n = unit_nsteps(m, un);
+    if (state[u] >= n) {
+      score[u] = -1.0;
+      return;
     }
+    const Group& gr = m.groups[un.group];
+    const double wd = mode == 0 ? gr.wd_inf : gr.wd_2;
+    const int k = state[u];
+    const int k2 = next_lower([&](int kk) { return unit_err(m, un, kk); }, k, n);
+    const int64_t de = unit_err(m, un, k) - unit_err(m, un, k2);
+    int64_t c = 0;
+    for (int j = k; j < k2; ++j) c += unit_step_bytes(m, un, j);
+    score[u] = (wd * (double)de) / (double)c;
+    next_k[u] = k2;
+  };
+  std::vector<bool> live(nu, false);
+  for (int u = 0; u < nu; ++u) {
+    live[u] = state[u] < unit_nsteps(m, m.units[u]);
+    if (live[u]) rescore(u);
+  }
+  for (;;) {
+    int best = -1;
+    double best_s = -1.0;
+    for (int u = 0; u < nu; ++u)
+      if (live[u] && score[u] > best_s) {
+        best = u;
+        best_s = score[u];
+      }
     if (best < 0) break;
-    state[best] = best_k;
-    m.seq[mode].push_back({best, best_k, bound(m, state, mode)});
+    state[best] = next_k[best];
+    m.seq[mode].push_back({best, next_k[best], bound(m, state, mode)});
+    live[best] = state[best] < unit_nsteps(m, m.units[best]);
+    if (live[best]) rescore(best);
   }
   m.seq_ready[mode] = true;
 }
