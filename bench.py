@@ -327,6 +327,13 @@ def batch_leg(apc, torch, fieldgen, quick: bool):
             h.close()
         if rep == 0:
             same_r = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(outs_p, outs_b))
+            # every batched output within its bound (max error <= 1e-4 * the field's range)
+            worst = 0.0
+            for x, o in zip(xs, outs_b):
+                xd64 = x.double()
+                r = float(xd64.max() - xd64.min())
+                worst = max(worst, float((o.double() - xd64).abs().max()) / (1e-4 * r))
+            assert worst <= 1.0, "a batched retrieval violated its error bound"
     rp, rb = sorted(rp)[1], sorted(rb)[1]
     del xs, outs_p, outs_b
     torch.cuda.empty_cache()
@@ -337,7 +344,7 @@ def batch_leg(apc, torch, fieldgen, quick: bool):
             "retrieve_rel_1e-4": {"per_field_s": rp, "batched_s": rb, "per_field_GBps": nbytes / rp / 1e9,
                                   "batched_GBps": nbytes / rb / 1e9, "speedup": rp / rb,
                                   "batched_hbm_frac": (nbytes + plan_bytes) / rb / HBM_PEAK,
-                                  "identical_output": bool(same_r)},
+                                  "identical_output": bool(same_r), "max_error_over_bound": worst},
             "workload": f"{n2} x 1800x3600 zonal bands + k^-3, {n3} x 100x500x500 and {nc} cubes 64..384 "
                         "k^-5/3 (seed 2, drawn on the device); per-level cubic + decomposition axis 0; "
                         "median of 3"}
@@ -373,6 +380,7 @@ def serve_leg(apc, torch, fieldgen, quick: bool):
                     apc.Target("psnr", float(rng.choice(psnr)))
                 reqs.append((f, t))
             outs = [torch.empty_like(xs[0]) for _ in range(64)]  # more than can be in flight at once
+            kept = {k: torch.empty_like(xs[0]) for k in range(0, nreq, 100)}  # checked after the run
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             due = t0
@@ -381,16 +389,29 @@ def serve_leg(apc, torch, fieldgen, quick: bool):
                 due += g
                 while time.perf_counter() < due:
                     pass
-                tickets.append(srv.submit(f, t, outs[k % len(outs)]))
+                tickets.append(srv.submit(f, t, kept[k] if k in kept else outs[k % len(outs)]))
             for tk in tickets:
                 srv.wait(tk)
             wall = time.perf_counter() - t0
+            for k, o in kept.items():  # the sampled outputs meet their targets
+                f, t = reqs[k]
+                x64 = xs[f].double()
+                r = float(x64.max() - x64.min())
+                err = (o.double() - x64).abs()
+                if t.kind == "rel":
+                    assert float(err.max()) <= t.value * r, "a served retrieval violated its error bound"
+                else:
+                    mse = float((err ** 2).mean())
+                    assert mse == 0.0 or 20 * math.log10(r / math.sqrt(mse)) >= t.value, \
+                        "a served retrieval missed its PSNR target"
+            del kept
             st = srv.stats()
             srv.close()
             for h in hs:
                 h.close()
             res[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-                         "req_per_s": nreq / wall, "max_concurrent": st["max_running"]}
+                         "req_per_s": nreq / wall, "max_concurrent": st["max_running"],
+                         "outputs_checked": (nreq + 99) // 100}
         out["rates"][str(rate)] = res
         log(f"serve: {rate} req/s done")
     return out
