@@ -70,4 +70,14 @@ def test_host_only_handle_refuses_device_work(config1_field):
     assert ei.value.status == -1 and "no device data" in str(ei.value)
     with pytest.raises(apc.ApcError):
         apc.apc._check(apc.apc.library().apc_set_interpreter(h._h, 9))
+    # batched retrieval refuses it before touching any output (the output
+    # pointer below is never dereferenced), and refuses null arguments
+    import ctypes
+    lib = apc.apc.library()
+    hs = (ctypes.c_void_p * 1)(h._h)
+    tg = (apc.apc._Target * 1)(apc.Target("rel", 1e-3)._c())
+    outs = (ctypes.c_void_p * 1)(16)
+    assert lib.apc_retrieve_batch(hs, 1, tg, outs, None, None) == -1
+    assert lib.apc_retrieve_batch(None, 1, tg, outs, None, None) == -1
+    assert lib.apc_retrieve_batch(hs, 0, tg, outs, None, None) == -1
     h.close()
