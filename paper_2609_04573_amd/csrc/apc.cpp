@@ -549,8 +549,9 @@ int tile_for(int dtype, int m1, int m2) {
   return it != g_tiles.end() ? it->second : default_tile(m2);
 }
 
-// Per-level pass geometry of level l (the coarser level is l + 1) for tiles t2 wide.
-LevelSeg level_seg(const apc_handle* h, int l, int t2) {
+// Per-level pass geometry of level l (the coarser level is l + 1) for tiles
+// t2 wide; the caller fills in the operands and then calls shape_level_seg.
+LevelSeg level_seg(const apc_handle* h, int l) {
   const Geo& g = h->geo;
   LevelSeg s{};
   for (int a = 0; a < 3; ++a) {
@@ -558,14 +559,42 @@ LevelSeg level_seg(const apc_handle* h, int l, int t2) {
     s.mc[a] = g.m[l + 1][a];
   }
   s.degree = h->scheme.degree;
+  return s;
+}
+// Tile counts and runs of a level segment whose operands (xs, q, B, k) are
+// set for the field's own axes and regions; returns the tile width it takes.
+// A level with one plane along axis 0 (every level of a 2D or 1D field, the
+// coarse levels of a thin 3D one) is presented as m1 x m2 x 1 and swept with
+// one-column tiles of 1024 points of a row, a block walking a run of rows as
+// it walks planes of a 3D level.  The flat index of every point, the region
+// lattices and the stencil order (axis 2, then 1, then 0) are unchanged:
+// region 0 (odd along axis 2) is then empty and regions 0 and 1 become 1
+// and 2.
+int shape_level_seg(LevelSeg& s, int t2, int64_t min_blocks = 1024) {
+  if (s.m[0] == 1) {
+    for (int a = 0; a < 2; ++a) {
+      s.m[a] = s.m[a + 1];
+      s.mc[a] = s.mc[a + 1];
+      s.xs[a] = s.xs[a + 1];
+    }
+    s.m[2] = s.mc[2] = 1;
+    s.xs[2] = 0;
+    for (int r = 2; r > 0; --r) {
+      s.q[r] = s.q[r - 1];
+      s.B[r] = s.B[r - 1];
+      s.k[r] = s.k[r - 1];
+    }
+    s.q[0] = nullptr;  // never addressed: no point is odd along axis 2
+    t2 = 1;
+  }
   const int t1 = 1024 / t2;
   s.nt1 = (s.m[1] + t1 - 1) / t1;
   s.nt2 = (s.m[2] + t2 - 1) / t2;
   // runs along axis 0: as long as possible while the level still spreads
-  // over enough blocks to fill the device
+  // over min_blocks blocks
   s.ch = kLvlCH;
-  while (s.ch > 2 && (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch) < 1024) s.ch /= 2;
-  return s;
+  while (s.ch > 2 && (int64_t)s.nt1 * s.nt2 * ((s.m[0] + s.ch - 1) / s.ch) < min_blocks) s.ch /= 2;
+  return t2;
 }
 int64_t assign_level_blocks(std::vector<LevelSeg>& segs) {
   int64_t b = 0;
@@ -586,15 +615,16 @@ int64_t assign_cd_blocks(std::vector<CDSeg>& segs) {
   return b;
 }
 
-// One-pass inverse decomposition: tiles of 8 rows x 256 columns per slice.
+// One-pass decomposition passes: tiles of 8 rows x 256 columns per slice,
+// or of eight slices one row deep (tiles along v first).
 int64_t assign_cd_tile_blocks(std::vector<CDSeg>& segs, int a) {
   int64_t b = 0;
   for (CDSeg& s : segs) {
     s.blk_begin = b;
-    const int64_t nu = s.c[a == 0 ? 1 : 0];
+    const int64_t nu = s.c[a == 0 ? 1 : 0], ns = s.c[a];
     s.ftu = make_fastdiv((uint32_t)std::max<int64_t>(1, (nu + 7) / 8));
     s.ftv = make_fastdiv((uint32_t)std::max<int64_t>(1, (s.c[2] + 255) / 256));
-    b += (int64_t)s.c[a] * ((nu + 7) / 8) * ((s.c[2] + 255) / 256);
+    b += (nu == 1 ? (ns + 7) / 8 : ns * ((nu + 7) / 8)) * ((s.c[2] + 255) / 256);
   }
   return b;
 }
@@ -1110,7 +1140,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     int64_t big = -1;
     for (int f = 0; f < nf; ++f) {
       const apc_handle* h = H[f];
-      if (h->scheme.kind != APC_PER_LEVEL || h->geo.L < 2) continue;
+      if (h->scheme.kind != APC_PER_LEVEL || h->geo.L < 2 || h->geo.m[0][0] == 1) continue;
       const Geo& g = h->geo;
       const int64_t n = g.n();
       if (n > big) {
@@ -1119,13 +1149,26 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
       }
     }
   }
-  auto level_segs = [&](int mode, double& by) {
+  // runs along axis 0: a field alone spreads each level over 1024 blocks or
+  // more; in a batch the fields share the launch, and each level is cut
+  // into fewer, longer runs (the coarse planes a run needs before its first
+  // step are fewer per point)
+  int64_t lvl_min_blocks = 1024;
+  {
+    int nlev = 0;
+    for (int f = 0; f < nf; ++f) nlev += H[f]->scheme.kind == APC_PER_LEVEL;
+    lvl_min_blocks = std::max<int64_t>(64, 1024 / std::max(1, nlev));
+  }
+  // segments of levels with several planes (tiles lvl_t2 wide) and of
+  // single-plane levels (one-column tiles): one launch each
+  auto level_segs = [&](int mode, double& by, bool flat) {
     std::vector<LevelSeg> ls2;
     for (int f = 0; f < nf; ++f) {
       const apc_handle* h = H[f];
       if (h->scheme.kind != APC_PER_LEVEL) continue;
       for (int l = 0; l < h->geo.L - 1; ++l) {
-        LevelSeg c = level_seg(h, l, lvl_t2);
+        if ((h->geo.m[l][0] == 1) != flat) continue;
+        LevelSeg c = level_seg(h, l);
         const Geo& g = h->geo;
         c.src = X[f];
         const int64_t sl = (int64_t)1 << l;
@@ -1136,6 +1179,7 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
         const int gi = group_of(h->meta, l, 0);
         c.gmax = acc + tmp[f].acc + 4 + gi;
         for (int rho = 0; rho < h->geo.d; ++rho) c.q[rho] = tmp[f].codes.template as<Q>() + h->region_off[l * 3 + rho];
+        shape_level_seg(c, lvl_t2, lvl_min_blocks);
         // bytes the method moves: each fine point of the level read once (and
         // its code written in the quantization pass); coarse points are
         // counted at their own, coarser level, the coarsest by its own pass
@@ -1183,11 +1227,11 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
     const int64_t b2 = assign_blocks<FlatSeg>(gs, [](const FlatSeg& s) { return s.n; });
     if (!rs.empty()) ls.push_back({K_RANGE, tb.add(rs), (int)rs.size(), b1, 0, nb, "range"});
     if (!gs.empty()) ls.push_back({K_GATHER, tb.add(gs), (int)gs.size(), b2, 0, gb, "subsample"});
-    {
+    for (int flat = 0; flat < 2; ++flat) {
       double by = 0;
-      std::vector<LevelSeg> lv = level_segs(0, by);
+      std::vector<LevelSeg> lv = level_segs(0, by, flat);
       const int64_t nbk = assign_level_blocks(lv);
-      if (!lv.empty()) ls.push_back({K_LEVEL0, tb.add(lv), (int)lv.size(), nbk, lvl_t2, by, "coef_max"});
+      if (!lv.empty()) ls.push_back({K_LEVEL0, tb.add(lv), (int)lv.size(), nbk, flat ? 1 : lvl_t2, by, "coef_max"});
     }
     for (int rho = 0; rho < 3; ++rho) {  // per-region fields: one pass per region
       std::vector<CoefSeg> cs;
@@ -1233,11 +1277,11 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   // once, after the decomposition.
   TableBuilder tb2;
   ls.clear();
-  {
+  for (int flat = 0; flat < 2; ++flat) {
     double by = 0;
-    std::vector<LevelSeg> lv = level_segs(1, by);
+    std::vector<LevelSeg> lv = level_segs(1, by, flat);
     const int64_t nbk = assign_level_blocks(lv);
-    if (!lv.empty()) ls.push_back({K_LEVEL1, tb2.add(lv), (int)lv.size(), nbk, lvl_t2, by, "coef_quant"});
+    if (!lv.empty()) ls.push_back({K_LEVEL1, tb2.add(lv), (int)lv.size(), nbk, flat ? 1 : lvl_t2, by, "coef_quant"});
   }
   for (int rho = 0; rho < 3; ++rho) {
     std::vector<CoefSeg> cs;
@@ -1945,8 +1989,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
     double* xout = l > 0 ? w.xb[l % 2] : nullptr;
     void* dst = l > 0 ? (void*)xout : (void*)out;
     if (per_level) {  // one tensor-product pass writes the whole level grid
-      const int t2 = tile_for(h->dtype, g.m[l][1], g.m[l][2]);
-      LevelSeg c = level_seg(h, l, t2);
+      LevelSeg c = level_seg(h, l);
       c.src = xin;
       c.out = dst;
       c.final_out = l == 0 ? 1 : 0;
@@ -1964,6 +2007,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
           c.k[rho] = ck(s);
         }
       }
+      const int t2 = shape_level_seg(c, tile_for(h->dtype, g.m[l][1], g.m[l][2]));
       std::vector<LevelSeg> cs{c};
       const int64_t nbk = assign_level_blocks(cs);
       // codes of the level's fine points and the coarser grid read, every
@@ -3735,17 +3779,18 @@ apc_status tune_impl(const T* field, int32_t dtype, const Geo& g, int degree, hi
   if (tile0) *tile0 = 0;
   for (int l = 0; l + 1 < g.L; ++l) {
     const int64_t n = (int64_t)g.m[l][0] * g.m[l][1] * g.m[l][2];
-    if (n < ((int64_t)1 << 18)) break;
+    if (n < ((int64_t)1 << 18) || g.m[l][0] == 1) break;  // single-plane levels take one-column tiles
     double best = 1e300;
     int bw = 64;
     for (int k = 0; k < 3; ++k) {
-      LevelSeg c = level_seg(&probe, l, kWidths[k]);
+      LevelSeg c = level_seg(&probe, l);
       c.src = field;
       const int64_t sl = (int64_t)1 << l;
       c.xs[0] = sl * g.N[1] * g.N[2];
       c.xs[1] = sl * g.N[2];
       c.xs[2] = sl;
       c.gmax = acc.as<unsigned long long>();
+      shape_level_seg(c, kWidths[k]);
       std::vector<LevelSeg> cs{c};
       const int64_t nbk = assign_level_blocks(cs);
       APC_TRY(tab.alloc(sizeof(LevelSeg)));

@@ -520,7 +520,11 @@ __global__ __launch_bounds__(kThreads) void k_coef(const CoefSeg* __restrict__ s
 // grid (coarse points are copied), written as float64 for the next level;
 // MODE 3: the same for level 0, written as the output field (type T).
 // Tile shapes: kT2 columns (axis 2) by kT1 = 4 * (256 / kT2) rows (axis 1);
-// every thread owns one column and four consecutive rows.
+// every thread owns one column and four consecutive rows.  Levels with a
+// single plane along axis 0 come presented as m1 x m2 x 1 and take
+// one-column tiles (kT2 = 1: 1024 rows, contiguous in memory); there a
+// thread owns two pairs of adjacent rows half a tile apart, so that a wave's
+// loads of one of its points cover adjacent addresses.
 // With 4-byte per-point inputs (float32 fields; codes of float32 fields),
 // the quantization and reconstruction passes fetch a step's inputs one
 // whole step ahead, at four waves per SIMD (the extra registers cost the
@@ -532,9 +536,10 @@ constexpr bool level_ahead() {
 template <typename T, typename Q, int MODE, int kT2>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     (level_ahead<T, Q, MODE>() || sizeof(T) == 8) ? 4 : 5))) void k_level(const LevelSeg* __restrict__ segs, int nseg, int64_t nblk) {
+  constexpr bool kCol = kT2 == 1;        // one-column tiles
   constexpr int kNRG = kThreads / kT2;  // row groups
   constexpr int kT1 = 4 * kNRG;
-  constexpr int kC1 = kT1 / 2 + 3, kC2 = kT2 / 2 + 3;
+  constexpr int kC1 = kT1 / 2 + 3, kC2 = kCol ? 1 : kT2 / 2 + 3;
   constexpr int kCPer = (kC1 * kC2 + kThreads - 1) / kThreads;  // coarse tile entries per thread
   using V = typename std::conditional<MODE >= 2, Q, T>::type;  // per-point input: code or value
   __shared__ double ctile[kC1 * kC2];
@@ -598,7 +603,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int t1 = (lb % S.nt1) * kT1;
     const int f0a = (lb / S.nt1) * S.ch;
     const int f0b = min(m0, f0a + S.ch);
-    const int c1s = t1 / 2 - 1, c2s = t2 / 2 - 1;
+    const int c1s = t1 / 2 - 1, c2s = kCol ? 0 : t2 / 2 - 1;
     // segment operands, held in registers (stores through the segment's
     // pointers must not force the table to be reloaded; a lane picks the
     // operands of its region)
@@ -615,17 +620,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 
     // in-plane geometry of this thread (constant along axis 0)
     const int f2 = t2 + col;
-    const bool odd2 = f2 & 1;
+    const bool odd2 = !kCol && (f2 & 1);
     const int sk2 = odd2 ? stencil_kind(f2, m2, deg) : 0;
     const int tc2 = odd2 ? ((f2 - 1) >> 1) - c2s : (f2 >> 1) - c2s;  // coarse tile column of f2 (or left of it)
-    // The thread's four points are on rows f1b + i, i = 0..3, with f1b even
-    // (tiles start on even rows), so odd i means an odd row.  Everything
-    // about point i is a cheap function of i and a few per-thread values,
-    // recomputed where used instead of being held in registers.
-    const int f1b = t1 + 4 * rg;
-    const int sk1o[2] = {stencil_kind(f1b + 1, m1, deg), stencil_kind(f1b + 3, m1, deg)};
+    // The thread's four points are on rows f1b + ro(i), i = 0..3, with f1b
+    // even (tiles start on even rows) and ro(i) of the parity of i, so odd i
+    // means an odd row.  Everything about point i is a cheap function of i
+    // and a few per-thread values, recomputed where used instead of being
+    // held in registers.
+    const int f1b = t1 + (kCol ? 2 : 4) * rg;
+    auto ro = [](int i) { return kCol ? (i >> 1) * (kT1 / 2) + (i & 1) : i; };
+    const int sk1o[2] = {stencil_kind(f1b + ro(1), m1, deg), stencil_kind(f1b + ro(3), m1, deg)};
     auto sk1 = [&](int i) { return (i & 1) ? sk1o[i >> 1] : 0; };
-    auto tr1 = [&](int i) { return (f1b >> 1) + (i >> 1) - c1s; };  // coarse tile row of the row (or above it)
+    auto tr1 = [&](int i) { return (f1b >> 1) + (ro(i) >> 1) - c1s; };  // coarse tile row of the row (or above it)
     // offsets of the thread's four points, split into a per-plane part and a
     // part fixed along axis 0 (all below 2^32: fields hold < 2^32 points):
     // grid offset = f0 * m1 * m2 + rg2(i); region lattice index = c * P + R
@@ -638,13 +645,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const uint32_t pe_even = (uint32_t)((m1 + 1) >> 1) * (uint32_t)(m2 >> 1);  // region 0 plane size
     const uint32_t re_odd = (uint32_t)(f1b >> 1) * (uint32_t)m2 + (uint32_t)f2;
     const uint32_t re_even = (uint32_t)(f1b >> 1) * (uint32_t)(m2 >> 1) + (uint32_t)(f2 >> 1);
-    auto okp = [&](int i) { return f1b + i < m1 && f2 < m2; };
-    auto rg2 = [&](int i) { return rg2b + (uint32_t)i * (uint32_t)m2; };
-    auto rsrc = [&](int i) { return rsrcb + (uint32_t)i * (uint32_t)xs1; };
+    auto okp = [&](int i) { return f1b + ro(i) < m1 && f2 < m2; };
+    auto rg2 = [&](int i) { return rg2b + (uint32_t)ro(i) * (uint32_t)m2; };
+    auto rsrc = [&](int i) { return rsrcb + (uint32_t)ro(i) * (uint32_t)xs1; };
     auto rre = [&](int i) { return (i & 1) ? 1 : (odd2 ? 0 : -1); };  // region on even planes (-1: coarse point)
     auto pe = [&](int i) { return (i & 1) ? pe_odd : pe_even; };
     auto re = [&](int i) {
-      return (i & 1) ? re_odd + (uint32_t)(i >> 1) * (uint32_t)m2 : re_even + (uint32_t)(i >> 1) * (uint32_t)(m2 >> 1);
+      return (i & 1) ? re_odd + (uint32_t)(ro(i) >> 1) * (uint32_t)m2
+                     : re_even + (uint32_t)(ro(i) >> 1) * (uint32_t)(m2 >> 1);
     };
     // coarse tile entries of this thread: global offsets within a plane (-1 = outside the grid)
     int64_t coff[kCPer];
@@ -1198,7 +1206,9 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse(const CDSeg* __restrict
 // slice: the stride-2 points of the tile and a one-point halo go to LDS first
 // (from the S1/S2 streams), then every row of the tile is written whole, the
 // remaining points rebuilt from S3 and those LDS values.  Whole rows keep the
-// stores full-width (no partial-line writes).
+// stores full-width (no partial-line writes).  Slices one row deep (the
+// region lattices of 2D fields) are rebuilt eight to a tile, each u = 0 row
+// by one wave straight from its streams, four columns a lane.
 constexpr int kCITU = 8, kCITV = 256;
 constexpr int kCIHU = kCITU / 2 + 1, kCIHV = kCITV / 2 + 1;  // stride-2 rows/columns incl. halo
 // staged stream runs: S1 rows (3 x 65 points), S2 of the u = 0 mod 4 rows
@@ -1226,7 +1236,35 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
     const int V0 = (int)(lb - lq * S.ftv.d) * kCITV;
     const uint32_t sq = fdiv(lq, S.ftu);
     const int U0 = (int)(lq - sq * S.ftu.d) * kCITU;
-    const int sa = (int)sq;  // index along the stacking axis
+    const int sa = (int)sq;  // index along the stacking axis (slices one row deep: the group of eight)
+    if (Nu == 1) {
+      // a u = 0 row: S1 at v = 0 mod 4; S2 at v = 2 mod 4 plus the average
+      // of the S1 points two columns away; S3 at odd v plus the average of
+      // its even neighbours (an absent right neighbour repeats the left one)
+      const int Ns = S.c[A];
+      using UM = typename UOf<Q>::type;
+      const UM M0 = code_mask<Q>(S.B[0], S.k[0]), M1 = code_mask<Q>(S.B[1], S.k[1]), M2 = code_mask<Q>(S.B[2], S.k[2]);
+      const int v = V0 + 4 * lane;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int sl = sa * kCITU + wave + 4 * k;
+        if (sl >= Ns || v >= Nv) continue;
+        const int t0 = A == 0 ? sl : 0, t1 = A == 0 ? 0 : sl;
+        const GAS Q* s1 = (const GAS Q*)S.S[0] + cd_row_base<A>(S, 0, t0, t1) + (v >> 2);
+        const GAS Q* s2 = (const GAS Q*)S.S[1] + cd_row_base<A>(S, 1, t0, t1) + (v >> 2);
+        const GAS Q* s3 = (const GAS Q*)S.S[2] + cd_row_base<A>(S, 2, t0, t1) + (v >> 1);
+        GAS Q* o = (GAS Q*)S.Rout + ((int64_t)t0 * S.c[1] + t1) * S.c[2] + v;
+        const bool e1 = v + 1 <= Nv - 1, e2 = v + 2 <= Nv - 1, e3 = v + 3 <= Nv - 1, e4 = v + 4 <= Nv - 1;
+        const W x0 = (W)apply_mask<Q>(s1[0], M0);
+        const W x4 = e4 ? (W)apply_mask<Q>(s1[1], M0) : x0;
+        const W x2 = e2 ? (W)apply_mask<Q>(s2[0], M1) + avgw<W>(x0, x4) : x0;
+        o[0] = (Q)x0;
+        if (e1) o[1] = (Q)((W)apply_mask<Q>(s3[0], M2) + avgw<W>(x0, x2));
+        if (e2) o[2] = (Q)x2;
+        if (e3) o[3] = (Q)((W)apply_mask<Q>(s3[1], M2) + avgw<W>(x2, e4 ? x4 : x2));
+      }
+      continue;
+    }
     auto tt = [&](int u, int& t0, int& t1) {
       t0 = A == 0 ? sa : u;
       t1 = A == 0 ? u : sa;
@@ -1371,6 +1409,9 @@ __global__ __launch_bounds__(kThreads) void k_cd_inverse_tile(const CDSeg* __res
 // average of four LDS values; an absent neighbour repeats the present one,
 // and since the floor average of a value with itself is that value this is
 // the same result as averaging only over the neighbours that exist.
+// Slices one row deep (the region lattices of 2D fields) have only u = 0
+// rows and no neighbours across rows: there the tile's eight rows are eight
+// consecutive slices, each lifted as a u = 0 row by its own wave.
 constexpr int kCFP = kCITV + 4;  // LDS row pitch: two halo columns each side
 
 template <typename Q, int A>
@@ -1411,20 +1452,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       R = (const GAS Q*)F.R;
       Sp[0] = (GAS Q*)F.S[0], Sp[1] = (GAS Q*)F.S[1], Sp[2] = (GAS Q*)F.S[2];
     }
-    const int Nu = A == 0 ? c1 : c0, Nv = c2;
+    const int Nu = A == 0 ? c1 : c0, Nv = c2, Ns = A == 0 ? c0 : c1;
+    const bool flat = Nu == 1;  // tile rows are slices
     const int nTu = (Nu + kCITU - 1) / kCITU, nTv = (Nv + kCITV - 1) / kCITV;
     int lb = (int)(b - blk0);
     const int V0 = (lb % nTv) * kCITV;
     lb /= nTv;
     const int U0 = (lb % nTu) * kCITU;
-    const int sa = lb / nTu;  // index along the stacking axis
-    auto tt = [&](int u, int& t0, int& t1) {
-      t0 = A == 0 ? sa : u;
-      t1 = A == 0 ? u : sa;
+    const int sa = flat ? lb * kCITU : lb / nTu;  // index along the stacking axis (of row 0)
+    // lattice row of tile row r, and whether it exists
+    auto tt = [&](int r, int& t0, int& t1) {
+      const int u = flat ? 0 : U0 + r, a = flat ? sa + r : sa;
+      t0 = A == 0 ? a : u;
+      t1 = A == 0 ? u : a;
     };
-    auto rowoff = [&](int u) -> int64_t {
+    auto row_ok = [&](int r) { return flat ? r < kCITU && sa + r < Ns : U0 + r < Nu; };
+    auto rowoff = [&](int r) -> int64_t {
       int t0, t1;
-      tt(u, t0, t1);
+      tt(r, t0, t1);
       return ((int64_t)t0 * c1 + t1) * c2;
     };
     __syncthreads();  // LDS of the previous tile is free
@@ -1434,14 +1479,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     W xv[kCITU + 1], xh = 0;
 #pragma unroll
     for (int r = 0; r < kCITU + 1; ++r) {
-      const int u = U0 + r;
       xv[r] = 0;
-      if (u < Nu && V0 + tid < Nv) xv[r] = (W)R[rowoff(u) + V0 + tid];
+      if (row_ok(r) && V0 + tid < Nv) xv[r] = (W)R[rowoff(r) + V0 + tid];
     }
     const int hr = tid >> 2, hc = (tid & 3) < 2 ? (tid & 3) : kCITV + (tid & 3);
     {
-      const int u = U0 + hr, v = V0 - 2 + hc;
-      if (tid < 4 * (kCITU + 1) && u < Nu && v >= 0 && v < Nv) xh = (W)R[rowoff(u) + v];
+      const int v = V0 - 2 + hc;
+      if (tid < 4 * (kCITU + 1) && row_ok(hr) && v >= 0 && v < Nv) xh = (W)R[rowoff(hr) + v];
     }
 #pragma unroll
     for (int r = 0; r < kCITU + 1; ++r) L[r * kCFP + 2 + tid] = xv[r];
@@ -1456,7 +1500,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
       const int r = wave + 4 * k;
       const int u = U0 + r;
       const W* Lr = L + r * kCFP + 2;  // column v at Lr[v - V0]
-      if (wave == 0) {  // u = 0 mod 4: S1 at v = 0 mod 4, S2 at v = 2 mod 4, S3 at odd v
+      if (wave == 0 || flat) {  // u = 0 mod 4: S1 at v = 0 mod 4, S2 at v = 2 mod 4, S3 at odd v
         res[k][0] = Lr[jc];
         res[k][1] = Lr[jc + 2] - avgw<W>(Lr[jc], Lr[V0 + jc + 4 <= Nv - 1 ? jc + 4 : jc]);
 #pragma unroll
@@ -1493,11 +1537,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int u = U0 + wave + 4 * k;
-      if (u >= Nu) continue;
+      const int r = wave + 4 * k;
+      if (!row_ok(r)) continue;
       int t0, t1;
-      tt(u, t0, t1);
-      if (wave == 0) {
+      tt(r, t0, t1);
+      if (wave == 0 || flat) {
         GAS Q* s1 = Sp[0] + cd_row_base<A>(c1, c2, 0, t0, t1) + (V0 >> 2);
         GAS Q* s2 = Sp[1] + cd_row_base<A>(c1, c2, 1, t0, t1) + (V0 >> 2);
         GAS Q* s3 = Sp[2] + cd_row_base<A>(c1, c2, 2, t0, t1) + (V0 >> 1);
@@ -2528,6 +2572,7 @@ hipError_t launch_coef(const CoefSeg* segs, int nseg, int64_t nblk, int mode, hi
 }
 template <typename T, typename Q, int MODE>
 hipError_t launch_level_mode(const LevelSeg* segs, int nseg, int64_t nblk, int t2, hipStream_t s) {
+  if (t2 == 1) APC_LAUNCH((k_level<T, Q, MODE, 1>), nblk, segs, nseg, nblk);
   if (t2 == 32) APC_LAUNCH((k_level<T, Q, MODE, 32>), nblk, segs, nseg, nblk);
   if (t2 == 128) APC_LAUNCH((k_level<T, Q, MODE, 128>), nblk, segs, nseg, nblk);
   APC_LAUNCH((k_level<T, Q, MODE, 64>), nblk, segs, nseg, nblk);

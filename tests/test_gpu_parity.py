@@ -197,6 +197,34 @@ def test_ragged_shapes_parity(shape, scheme):
     h.close()
 
 
+@pytest.mark.parametrize("shape,scheme,dtype", [
+    ((301, 2600), ("level", 3, None, 0), np.float32),
+    ((1030, 1500), ("level", 1, None, 0), np.float64),
+    ((1499, 3300), ("level", 3, None, 0), np.float32),
+    ((3, 700, 1100), ("level", 3, None, 0), np.float32),
+    ((20, 1, 700), ("region", 3, None, 0), np.float32),
+    ((3900,), ("level", 3, None, None), np.float64),
+], ids=str)
+def test_single_plane_levels_and_one_row_slices(shape, scheme, dtype):
+    """Levels with one plane along the leading axis (2D and 1D fields, the
+    coarse levels of a thin 3D one) are swept a row of up to 1024 points at
+    a time, runs of rows per block; decomposition slices one row deep (2D
+    region lattices, a 3D lattice of extent 1 across the slice) are lifted
+    eight to a tile.  Shapes span several such tiles with ragged tails
+    (rows past the last whole run, columns past the last whole tile, slices
+    past the last group of eight); streams and reconstructions must equal
+    the oracle's."""
+    apc = _apc()
+    x = fieldgen.power_law_field(shape, seed=11, dtype=dtype)
+    gs, os_ = _schemes(*scheme)
+    ref = oracle.refactor(x, os_)
+    h = apc.refactor(torch.from_numpy(x).cuda(), gs)
+    _check_metadata(h, ref)
+    _check_streams(h, ref)
+    _check_retrievals(h, ref, x)
+    h.close()
+
+
 @pytest.mark.parametrize("scheme", [("level", 3, None, 0), ("region", 3, None, None)], ids=str)
 def test_float64_parity(scheme):
     apc = _apc()

@@ -49,6 +49,32 @@ def test_batch_refactor_equals_single_and_oracle():
         h.close()
 
 
+def test_batch_of_many_fields_takes_long_runs_and_matches_the_oracle():
+    """In a batch of sixteen fields each level is cut into fewer blocks than
+    for a field alone: the large 2D fields are swept 32 rows to a block (the
+    last run ragged), the thin 3D field's coarse levels are single planes.
+    Streams and a reconstruction of every field equal the oracle's."""
+    apc = _apc()
+    rng = np.random.default_rng(31)
+    fs = [(fieldgen.zonal_bands((2100, 1000), seed=3), ("level", 3, None, 0)),
+          (fieldgen.power_law_field((1100, 2100), seed=4), ("level", 3, None, 1)),
+          (fieldgen.power_law_field((3, 400, 500), seed=5), ("level", 3, None, 0))]
+    for i in range(13):
+        shape = tuple(int(v) for v in rng.integers(5, 48, size=3))
+        fs.append((fieldgen.power_law_field(shape, seed=40 + i), ("level", 3, None, i % 3)))
+    xs = [torch.from_numpy(x).cuda() for x, _ in fs]
+    schemes = [apc.Scheme(kind=k, degree=d, order=o, cd_axis=c) for _, (k, d, o, c) in fs]
+    hb = apc.refactor_batch(xs, schemes)
+    for i, ((x, (k, d, o, c)), h) in enumerate(zip(fs, hb)):
+        ref = oracle.refactor(x, oracle.Scheme(kind=k, degree=d, order=o, cd_axis=c))
+        for s, st in enumerate(ref.streams):
+            assert h.stream_blob(s) == st.blob, (i, s)
+        got, _ = h.retrieve(apc.Target("rel", 1e-4))
+        want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target("rel", 1e-4)))
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want.view(np.uint32)), i
+        h.close()
+
+
 def test_batch_rejects_mixed_dtypes_and_bad_fields():
     apc = _apc()
     a = torch.zeros((8, 8, 8), device="cuda")
