@@ -243,15 +243,19 @@ apc_status apc_select_pipeline(const void* field_dev, int32_t dtype, const int64
 /* Sweep-tile autotuner for batched per-level passes.  The per-level
  * interpolation sweep (the tensor-product refinement of Section IV) runs on
  * tiles of t2 columns (the fastest axis) by 1024/t2 rows, t2 in {32, 64,
- * 128}.  apc_tune_tiles times the level's max pass with each width on the
- * given device field (dims and dtype as apc_refactor; degree 1 or 3) for
- * every level of at least 2^18 points, and records the fastest width for
- * that level shape (dtype, log2 of the axis-1 and axis-2 extents) in a
+ * 128}.  apc_tune_tiles times the level's max and quantization passes
+ * (together) with each width on the given device field (dims and dtype as
+ * apc_refactor; degree 1 or 3) for every level of at least 2^18 points with
+ * more than one plane along axis 0, and records the width for that level
+ * shape (the fastest, or a wider one within 3% of it; dtype, log2 of the
+ * axis-1 and axis-2 extents) in a
  * process-wide table that later refactors and retrievals of any field use.
+ * It allocates a scratch buffer of one code per point while it runs.
  * Outputs (optional): the width chosen for level 0 (0 if no level was
  * timed) and the level-0 times in microseconds for widths 32, 64, 128
  * (us0: 3 doubles).  The field is only read.  Tile widths never change
- * results, only speed.
+ * results, only speed; levels with one plane along axis 0 (2D and 1D
+ * fields) always take one-column tiles.
  * apc_tile_override forces one width for every pass (0 restores the table);
  * APC_E_INVALID for other values.  apc_tile_width reports the width used
  * for a level of extents m1 x m2. */

@@ -557,8 +557,9 @@ def select_pipeline(field, mode: str = "eb", stream=None) -> Scheme:
 
 
 def tune_tiles(field, degree: int = 3, stream=None) -> dict:
-    """Time the per-level sweep with every tile width on this field and keep
-    the fastest for its level shapes (a process-wide table)."""
+    """Time the per-level max and quantization sweeps with every tile width
+    on this field and keep the fastest (or a wider one within 3% of it) for
+    its level shapes (a process-wide table)."""
     assert field.is_cuda and field.is_contiguous()
     dims = (ctypes.c_int64 * field.dim())(*field.shape)
     t0 = ctypes.c_int32()
