@@ -125,6 +125,32 @@ def test_ladder_graph_replays_match_single_shot(config1_field):
     h.close()
 
 
+def test_ladder_and_static_retrieval_of_a_2d_field_match_the_oracle():
+    """A 2D field's levels take one-column sweep tiles and its one-row
+    decomposition slices are rebuilt eight to a tile; the same launches
+    captured in a graph ladder (replayed twice, eager work between) and run
+    from the static scratch give the oracle's reconstructions."""
+    apc = _apc()
+    x = fieldgen.zonal_bands((257, 2100), seed=8)
+    ref = oracle.refactor(x, oracle.Scheme(kind="level", cd_axis=0))
+    xd = torch.from_numpy(x).cuda()
+    h = apc.refactor(xd, apc.Scheme(kind="level", cd_axis=0))
+    targets = [apc.Target("rel", 1e-2), apc.Target("psnr", 70), apc.Target("rel", 1e-5)]
+    wants = [oracle.retrieve(ref, oracle.plan(ref, oracle.Target(t.kind, t.value))) for t in targets]
+    ladder = apc.Ladder(h, targets)
+    for rep in range(2):
+        outs = ladder.launch()
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(outs, wants)):
+            assert np.array_equal(o.cpu().numpy().view(np.uint32), w.view(np.uint32)), (rep, i)
+        _ = (xd * 2).sum().item()
+    ladder.close()
+    for t, w in zip(targets, wants):
+        out, _ = h.retrieve_static(t)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), w.view(np.uint32)), t
+    h.close()
+
+
 @pytest.mark.parametrize("mode", ["eb", "psnr"])
 def test_select_pipeline_matches_oracle(config1_field, mode):
     apc = _apc()
