@@ -1829,7 +1829,8 @@ WorkPtrs handle_work(apc_handle* h) {
 template <typename T, typename Q>
 void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::vector<int>& kres,
                     TableBuilder& tb, std::vector<Launch>& ls, int64_t* fetched, const WorkPtrs& w,
-                    bool with_decode = true, bool with_recon = true, bool split = false) {
+                    bool with_decode = true, bool with_recon = true, bool split = false,
+                    int64_t lvl_min_blocks = 1024) {
   Meta& m = h->meta;
   const Geo& g = h->geo;
   const int d = g.d, L = g.L;
@@ -2014,7 +2015,7 @@ void build_retrieve(apc_handle* h, const std::vector<int>& planes, T* out, std::
           c.k[rho] = ck(s);
         }
       }
-      const int t2 = shape_level_seg(c, tile_for(h->dtype, g.m[l][1], g.m[l][2]));
+      const int t2 = shape_level_seg(c, tile_for(h->dtype, g.m[l][1], g.m[l][2]), lvl_min_blocks);
       std::vector<LevelSeg> cs{c};
       const int64_t nbk = assign_level_blocks(cs);
       // codes of the level's fine points and the coarser grid read, every
@@ -2408,7 +2409,9 @@ apc_status retrieve_batch_impl(apc_handle* const* hs, int32_t n, const apc_targe
     }
     std::vector<int> kdone = kres[u];  // decoded above
     const size_t j = uniq.size() + (size_t)i;
-    build_retrieve<T, Q>(h, planes[i], (T*)outs[i], kdone, tbs[j], lss[j], nullptr, w, false, true);
+    // the requests share each launch: longer level runs, as in a batched refactor
+    build_retrieve<T, Q>(h, planes[i], (T*)outs[i], kdone, tbs[j], lss[j], nullptr, w, false, true, false,
+                         std::max<int64_t>(64, 1024 / std::max(1, n)));
     parts.push_back({&tbs[j], &lss[j]});
   }
   TableBuilder tb;
@@ -4031,7 +4034,8 @@ struct apc_server {
       APC_TRY(r->work.alloc(r->footprint));
       const WorkPtrs w = carve_work(h, r->work.p);
       std::vector<int> kdone = fields[r->field]->k_issued;  // no decode in this part
-      build_retrieve<T, Q>(h, r->planes, (T*)r->out, kdone, rtb[j], rls[j], nullptr, w, false, true);
+      build_retrieve<T, Q>(h, r->planes, (T*)r->out, kdone, rtb[j], rls[j], nullptr, w, false, true, false,
+                           std::max<int64_t>(64, 1024 / (int64_t)batch.size()));
       parts.push_back({&rtb[j], &rls[j]});
     }
     TableBuilder tb;
