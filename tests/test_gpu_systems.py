@@ -75,6 +75,29 @@ def test_batch_of_many_fields_takes_long_runs_and_matches_the_oracle():
         h.close()
 
 
+def test_batch_of_float64_fields_with_single_plane_levels_matches_the_oracle():
+    """float64 1D, 2D and thin 3D fields refactored in one batch (one-column
+    sweep tiles, one-row decomposition slices) give the oracle's streams and
+    reconstructions."""
+    apc = _apc()
+    fs = [(fieldgen.power_law_field((3900,), seed=51, dtype=np.float64), ("level", 3, None, None)),
+          (fieldgen.power_law_field((300, 1100), seed=52, dtype=np.float64), ("level", 3, None, 0)),
+          (fieldgen.power_law_field((2, 500, 600), seed=53, dtype=np.float64), ("level", 1, None, 0)),
+          (fieldgen.power_law_field((130, 2050), seed=54, dtype=np.float64), ("region", 3, None, 0))]
+    xs = [torch.from_numpy(x).cuda() for x, _ in fs]
+    schemes = [apc.Scheme(kind=k, degree=d, order=o, cd_axis=c) for _, (k, d, o, c) in fs]
+    hb = apc.refactor_batch(xs, schemes)
+    for i, ((x, (k, d, o, c)), h) in enumerate(zip(fs, hb)):
+        ref = oracle.refactor(x, oracle.Scheme(kind=k, degree=d, order=o, cd_axis=c))
+        for s_, st in enumerate(ref.streams):
+            assert h.stream_blob(s_) == st.blob, (i, s_)
+        for t in (apc.Target("rel", 1e-3), apc.Target("psnr", 120)):
+            got, _ = h.retrieve(t)
+            want = oracle.retrieve(ref, oracle.plan(ref, oracle.Target(t.kind, t.value)))
+            assert np.array_equal(got.cpu().numpy().view(np.uint64), want.view(np.uint64)), (i, t)
+        h.close()
+
+
 def test_batch_rejects_mixed_dtypes_and_bad_fields():
     apc = _apc()
     a = torch.zeros((8, 8, 8), device="cuda")
