@@ -542,7 +542,7 @@ def rate_leg(apc, torch, x512):
 
 
 def blocks_leg(apc, torch, fieldgen, quick: bool):
-    """Out of core: a host-resident 1024x512x512 float32 k^-5/3 field (2 GiB)
+    """Out of core: a host-resident 1024x512x512 float32 k^-5/3 field (1 GiB)
     in the paper's per-core blocks of 256x512x512, one block on the device
     at a time; refactor, then retrieve at rel 1e-4 (only the planned planes
     of each block uploaded).  Times include host gathers and scatters and the

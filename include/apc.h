@@ -358,7 +358,9 @@ apc_status apc_deserialize_host(const void* src, int64_t len, apc_handle** out);
  * stored sections' prefixes), reconstructs it on the device and copies it
  * into out_host (caller owned, the field's size).  info: bytes over all
  * blocks, the largest block bound (max error) or the pooled RMSE bound.
- * Both calls synchronize hip_stream.  apc_blocks_blob returns block b's
+ * The set's own blobs are not re-verified against their stream checksums
+ * (they are computed when the set writes them; apc_deserialize of a block's
+ * bytes verifies them).  Both calls synchronize hip_stream.  apc_blocks_blob returns block b's
  * serialized bytes (owned by the set; blocks in row-major block order). */
 typedef struct apc_blockset apc_blockset;
 apc_status apc_blocks_refactor(const void* field_host, int32_t dtype, const int64_t* dims, int32_t ndim,

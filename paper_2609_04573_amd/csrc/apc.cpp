@@ -987,18 +987,23 @@ void build_layout(apc_handle* h, int P) {
 
 // Weights of every group (exact chain norms of the user axes).
 // f(i) for i in [0, n) on up to 16 host threads (the caller's among them);
-// for independent per-handle host work of a batch.  f must not throw.
+// for independent per-handle host work of a batch.  f must not throw.  A
+// call made from inside f runs on its own thread only (no nested pools).
+thread_local bool g_in_parallel = false;
 template <typename F>
 void parallel_for(size_t n, F&& f) {
   const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-  const size_t nt = std::min<size_t>(n, std::min<size_t>(16, hw));
+  const size_t nt = g_in_parallel ? 1 : std::min<size_t>(n, std::min<size_t>(16, hw));
   if (nt <= 1) {
     for (size_t i = 0; i < n; ++i) f(i);
     return;
   }
   std::atomic<size_t> next{0};
   auto work = [&] {
+    const bool was = g_in_parallel;
+    g_in_parallel = true;
     for (size_t i; (i = next.fetch_add(1)) < n;) f(i);
+    g_in_parallel = was;
   };
   std::vector<std::thread> th;
   for (size_t t = 1; t < nt; ++t) th.emplace_back(work);
@@ -2665,7 +2670,7 @@ struct RepReader {
 // (geometry, layout, metadata, the interpreter's sequence); blobs[s] points
 // at stream s's blob inside src.  No device work.
 apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_handle>& out,
-                     std::vector<const unsigned char*>& blobs) {
+                     std::vector<const unsigned char*>& blobs, bool verify_streams = true) {
   REP_CHECK(len >= 32, "%lld bytes: shorter than the header", (long long)len);
   REP_CHECK(memcmp(src, kRepMagic, 8) == 0, "bad magic");
   uint64_t tl, ml, mh;
@@ -2774,7 +2779,7 @@ apc_status rep_parse(const unsigned char* src, int64_t len, std::unique_ptr<apc_
               (unsigned long long)bl, (long long)S.blob_bytes());
     REP_CHECK((uint64_t)len - at - 16 >= bl, "stream %d blob truncated", s);
     const unsigned char* b = src + at + 16;
-    REP_CHECK(rep_hash(b, (size_t)bl) == bh, "stream %d checksum mismatch", s);
+    REP_CHECK(!verify_streams || rep_hash(b, (size_t)bl) == bh, "stream %d checksum mismatch", s);
     blobs[s] = b;
     at += 16 + (size_t)bl;
     S.mag_off = mag_w;
@@ -3249,17 +3254,26 @@ apc_status apc_serialize(const apc_handle* h, void* host_dst, int64_t cap, int64
   memcpy(d + 16, &ml, 8);
   memcpy(d + 24, &mh, 8);
   memcpy(d + 32, meta.data(), meta.size());
+  // the stream blobs copied out in turn, then their checksums on the host
+  // threads (each over its own blob)
+  const int ns = (int)h->meta.streams.size();
+  std::vector<int64_t> at_s((size_t)ns);
   int64_t at = 32 + (int64_t)meta.size();
-  for (int s = 0; s < (int)h->meta.streams.size(); ++s) {
+  for (int s = 0; s < ns; ++s) {
     const Stream& S = h->meta.streams[s];
     const uint64_t bl = (uint64_t)S.blob_bytes();
-    unsigned char* blob = d + at + 16;
-    if (bl) APC_TRY(apc_stream_blob(h, s, blob, (int64_t)bl));
-    const uint64_t bh = rep_hash(blob, (size_t)bl);
+    at_s[(size_t)s] = at;
+    if (bl) APC_TRY(apc_stream_blob(h, s, d + at + 16, (int64_t)bl));
     memcpy(d + at, &bl, 8);
-    memcpy(d + at + 8, &bh, 8);
     at += 16 + (int64_t)bl;
   }
+  parallel_for((size_t)ns, [&](size_t s) {
+    const int64_t a = at_s[s];
+    uint64_t bl;
+    memcpy(&bl, d + a, 8);
+    const uint64_t bh = rep_hash(d + a + 16, (size_t)bl);
+    memcpy(d + a + 8, &bh, 8);
+  });
   return APC_OK;
 }
 
@@ -3328,15 +3342,22 @@ void block_copy(const apc_blockset* B, int64_t b, size_t es, const char* field, 
   int64_t lo[3], ext[3];
   B->block(b, lo, ext);
   const size_t row = (size_t)ext[2] * es;
-  for (int64_t z = 0; z < ext[0]; ++z)
+  auto plane = [&](size_t z) {
     for (int64_t y = 0; y < ext[1]; ++y) {
-      const size_t fo = (size_t)(((lo[0] + z) * B->N[1] + (lo[1] + y)) * B->N[2] + lo[2]) * es;
-      const size_t bo = (size_t)((z * ext[1] + y) * ext[2]) * es;
+      const size_t fo = (size_t)(((lo[0] + (int64_t)z) * B->N[1] + (lo[1] + y)) * B->N[2] + lo[2]) * es;
+      const size_t bo = (size_t)(((int64_t)z * ext[1] + y) * ext[2]) * es;
       if (to_dense)
         memcpy(dense + bo, field + fo, row);
       else
         memcpy(field_out + fo, dense + bo, row);
     }
+  };
+  // large blocks copy their planes on the host threads (one thread's memcpy
+  // moves about 9 GB/s, far below what the host memory takes)
+  if ((size_t)ext[1] * row * (size_t)ext[0] >= ((size_t)8 << 20))
+    parallel_for((size_t)ext[0], plane);
+  else
+    for (int64_t z = 0; z < ext[0]; ++z) plane((size_t)z);
 }
 
 }  // namespace
@@ -3384,16 +3405,20 @@ apc_status apc_blocks_refactor(const void* field_host, int32_t dtype, const int6
     std::vector<const void*> ptrs;
     std::vector<int64_t> bd;
     std::vector<int32_t> nds;
+    std::vector<size_t> offs;
     size_t off = 0;
     for (int64_t b : bl) {
       int64_t lo[3], ext[3];
       B->block(b, lo, ext);
-      block_copy(B.get(), b, es, (const char*)field_host, (char*)pin.p + off, true, nullptr);
+      offs.push_back(off);
       ptrs.push_back((const char*)dev.p + off);
       for (int a = 3 - ndim; a < 3; ++a) bd.push_back(ext[a]);
       nds.push_back(ndim);
       off += (size_t)(ext[0] * ext[1] * ext[2]) * es;
     }
+    // the blocks' gathers into the staging block (each on the host threads)
+    for (size_t i = 0; i < bl.size(); ++i)
+      block_copy(B.get(), bl[i], es, (const char*)field_host, (char*)pin.p + offs[i], true, nullptr);
     if (r == APC_OK && hipMemcpyAsync(dev.p, pin.p, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
       r = fail(APC_E_HIP, "block upload failed");
     std::vector<std::unique_ptr<apc_handle>> own;
@@ -3402,17 +3427,36 @@ apc_status apc_blocks_refactor(const void* field_host, int32_t dtype, const int6
       r = refactor_many(ptrs.data(), dtype, bd.data(), nds.data(), sc.data(), (int32_t)bl.size(), st, own);
     }
     g_pinned.put(pin, st, true);
-    for (size_t i = 0; i < bl.size() && r == APC_OK; ++i) {
-      int64_t len = 0;
-      r = apc_serialize(own[i].get(), nullptr, 0, &len);
-      if (r != APC_OK) break;
-      std::vector<unsigned char>& blob = B->blobs[(size_t)bl[i]];
-      blob.resize((size_t)len);
-      r = apc_serialize(own[i].get(), blob.data(), len, &len);
-      if (r != APC_OK) break;
-      std::vector<const unsigned char*> bp;
-      r = rep_parse(blob.data(), len, B->plan_h[(size_t)bl[i]], bp);
-      if (r == APC_OK) B->plan_h[(size_t)bl[i]]->host_only = true;
+    // serialization of each block (device reads, checksums) and its host
+    // planning handle, on the host threads; a failure is reported with the
+    // message of the thread that met it
+    if (r == APC_OK) {
+      int dev_id = 0;
+      HIP_TRY(hipGetDevice(&dev_id));
+      std::vector<apc_status> rs(bl.size(), APC_OK);
+      std::vector<std::string> msg(bl.size());
+      parallel_for(bl.size(), [&](size_t i) {
+        apc_status q = hipSetDevice(dev_id) == hipSuccess ? APC_OK : fail(APC_E_HIP, "hipSetDevice failed");
+        int64_t len = 0;
+        if (q == APC_OK) q = apc_serialize(own[i].get(), nullptr, 0, &len);
+        std::vector<unsigned char>& blob = B->blobs[(size_t)bl[i]];
+        if (q == APC_OK) {
+          blob.resize((size_t)len);
+          q = apc_serialize(own[i].get(), blob.data(), len, &len);
+        }
+        if (q == APC_OK) {
+          std::vector<const unsigned char*> bp;
+          // the blob was just written here: its stream checksums are not re-verified
+          q = rep_parse(blob.data(), len, B->plan_h[(size_t)bl[i]], bp, false);
+          if (q == APC_OK) B->plan_h[(size_t)bl[i]]->host_only = true;
+        }
+        if (q != APC_OK) {
+          rs[i] = q;
+          msg[i] = g_last_error;
+        }
+      });
+      for (size_t i = 0; i < bl.size() && r == APC_OK; ++i)
+        if (rs[i] != APC_OK) r = fail(rs[i], "block %lld: %s", (long long)bl[i], msg[i].c_str());
     }
     (void)hipStreamSynchronize(st);
     for (auto& h : own) apc_free(h.release());
@@ -3507,7 +3551,9 @@ apc_status apc_blocks_retrieve(apc_blockset* B, const apc_target* target, void* 
     std::unique_ptr<apc_handle> h;
     std::vector<const unsigned char*> bp;
     const std::vector<unsigned char>& blob = B->blobs[(size_t)b];
-    APC_TRY(rep_parse(blob.data(), (int64_t)blob.size(), h, bp));
+    // blobs this blockset wrote and holds: their stream checksums are not
+    // re-verified at every retrieval (deserializing outside input does)
+    APC_TRY(rep_parse(blob.data(), (int64_t)blob.size(), h, bp, false));
     APC_TRY(upload_planes(h.get(), bp, &planes, st));
     APC_TRY(do_retrieve(h.get(), planes, dout.p, st, nullptr));
     HIP_TRY(hipMemcpyAsync(pin.p, dout.p, (size_t)ph->meta.n * es, hipMemcpyDeviceToHost, st));
