@@ -1006,7 +1006,13 @@ void parallel_for(size_t n, F&& f) {
     g_in_parallel = was;
   };
   std::vector<std::thread> th;
-  for (size_t t = 1; t < nt; ++t) th.emplace_back(work);
+  for (size_t t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work);
+    } catch (...) {  // no more threads to be had: the ones running (and this one) take the rest
+      break;
+    }
+  }
   work();
   for (std::thread& t : th) t.join();
 }
