@@ -15,6 +15,7 @@
 #include <condition_variable>
 #include <deque>
 #include <thread>
+#include <unistd.h>
 #include <functional>
 #include <map>
 #include <memory>
@@ -453,6 +454,7 @@ struct apc_handle {
   bool work_ready = false;
   PinnedBlock pinned;  // staging of table uploads (its event follows the last upload)
   hipEvent_t ready = nullptr;  // follows the refactor's last kernel (work on other streams waits for it)
+  std::shared_ptr<void> ready_owner;  // the handles of one batch share `ready`: destroyed with the last
   hipEvent_t tab_ev = nullptr;  // follows the last retrieval that read `tables`
   int interp = INTERP_GREEDY;    // retrieval interpreter
   bool host_only = false;        // rebuilt from bytes without device data: planning only
@@ -464,7 +466,7 @@ struct apc_handle {
     }
     if (ready) {  // the buffers go back to the shared pool only after the refactor's last kernels
       (void)hipEventSynchronize(ready);
-      (void)hipEventDestroy(ready);
+      if (!ready_owner) (void)hipEventDestroy(ready);
     }
   }
 };
@@ -986,35 +988,89 @@ void build_layout(apc_handle* h, int P) {
 }
 
 // Weights of every group (exact chain norms of the user axes).
-// f(i) for i in [0, n) on up to 16 host threads (the caller's among them);
-// for independent per-handle host work of a batch.  f must not throw.  A
-// call made from inside f runs on its own thread only (no nested pools).
+// Host worker threads kept for the life of the process (starting threads
+// for every call costs tens of microseconds each): up to 15 workers plus
+// the calling thread.  One call uses them at a time.  A worker runs every
+// job once; the caller waits until all have.
+struct HostPool {
+  std::mutex busy;  // held by the call using the workers
+  std::mutex mu;
+  std::condition_variable wake, done;
+  const std::function<void()>* job = nullptr;
+  uint64_t gen = 0;
+  size_t pending = 0;
+  size_t nworkers = 0;
+  pid_t pid;
+  HostPool() : pid(getpid()) {
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t want = std::min<size_t>(16, hw) - 1;
+    for (size_t t = 0; t < want; ++t) {
+      try {
+        std::thread([this] { loop(); }).detach();
+      } catch (...) {  // no more threads to be had
+        break;
+      }
+      ++nworkers;
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void()>* j;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        wake.wait(lk, [&] { return gen != seen; });
+        seen = gen;
+        j = job;
+      }
+      (*j)();
+      std::lock_guard<std::mutex> lk(mu);
+      if (--pending == 0) done.notify_one();
+    }
+  }
+  void run(const std::function<void()>& f) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      job = &f;
+      pending = nworkers;
+      ++gen;
+    }
+    wake.notify_all();
+    f();
+    std::unique_lock<std::mutex> lk(mu);
+    done.wait(lk, [&] { return pending == 0; });
+  }
+};
+HostPool& host_pool() {
+  static HostPool* p = new HostPool();  // never destroyed: its threads wait until the process ends
+  return *p;
+}
+
+// f(i) for i in [0, n) on the host pool (the caller among the threads); for
+// independent per-handle host work of a batch.  f must not throw.  A call
+// made from inside f, or while another call holds the pool, or in a process
+// forked from the one that started the pool, runs on its own thread.
 thread_local bool g_in_parallel = false;
 template <typename F>
 void parallel_for(size_t n, F&& f) {
-  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-  const size_t nt = g_in_parallel ? 1 : std::min<size_t>(n, std::min<size_t>(16, hw));
-  if (nt <= 1) {
+  if (n <= 1 || g_in_parallel) {
+    for (size_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  HostPool& pool = host_pool();
+  if (pool.nworkers == 0 || pool.pid != getpid() || !pool.busy.try_lock()) {
     for (size_t i = 0; i < n; ++i) f(i);
     return;
   }
   std::atomic<size_t> next{0};
-  auto work = [&] {
+  const std::function<void()> work = [&] {
     const bool was = g_in_parallel;
     g_in_parallel = true;
     for (size_t i; (i = next.fetch_add(1)) < n;) f(i);
     g_in_parallel = was;
   };
-  std::vector<std::thread> th;
-  for (size_t t = 1; t < nt; ++t) {
-    try {
-      th.emplace_back(work);
-    } catch (...) {  // no more threads to be had: the ones running (and this one) take the rest
-      break;
-    }
-  }
-  work();
-  for (std::thread& t : th) t.join();
+  pool.run(work);
+  pool.busy.unlock();
 }
 
 void assign_weights(apc_handle* h) {
@@ -1703,9 +1759,17 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   // gets an event behind it (work on other streams waits for that), and the
   // temporaries stay allocated until it has finished.  (The layout kernel's
   // bound check repeats the host's, above, which has already passed.)
-  for (int f = 0; f < nf; ++f) {
-    if (!H[f]->ready) HIP_TRY(hipEventCreateWithFlags(&H[f]->ready, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(H[f]->ready, st));
+  {  // one event for the whole batch, shared by its handles
+    hipEvent_t ev = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    std::shared_ptr<void> owner((void*)ev, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
+    HIP_TRY(hipEventRecord(ev, st));
+    for (int f = 0; f < nf; ++f) {
+      apc_handle* h = H[f];
+      if (h->ready && !h->ready_owner) (void)hipEventDestroy(h->ready);
+      h->ready = ev;
+      h->ready_owner = owner;
+    }
   }
   std::vector<DevBuf> keep;
   for (Tmp& t : tmp) {
