@@ -1173,9 +1173,10 @@ apc_status refactor_batch(std::vector<apc_handle*>& H, const std::vector<const T
   };
   std::vector<Tmp> tmp(nf);
   int64_t nacc = 0;
+  // each field's layout (groups, streams, units, offsets) is its own host work
+  parallel_for((size_t)nf, [&](size_t f) { build_layout(H[f], P); });
   for (int f = 0; f < nf; ++f) {
     apc_handle* h = H[f];
-    build_layout(h, P);
     const Geo& g = h->geo;
     Tmp& t = tmp[f];
     t.goff.assign(g.L, 0);
