@@ -178,6 +178,9 @@ def test_negabinary_incremental_decodes_continue_the_xor_chain(dtype):
     ((1, 1, 1), ("level", 3, None, None)),
     ((3, 1, 2), ("region", 3, (2, 1, 0), None)),
     ((9, 9, 9), ("level", 3, None, 0)),
+    ((300, 1), ("level", 3, None, 0)),
+    ((1, 300), ("level", 3, None, 1)),
+    ((2, 1500), ("level", 1, None, 0)),
 ], ids=str)
 def test_ragged_shapes_parity(shape, scheme):
     apc = _apc()
