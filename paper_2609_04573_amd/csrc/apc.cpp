@@ -476,8 +476,30 @@ namespace {
 size_t qsize(int dtype) { return dtype == APC_F32 ? 4 : 8; }
 
 // ------------------------------------------------------------ segment tables
+// Byte buffers of segment tables, kept per thread from call to call: a
+// table then lands in memory whose pages exist and whose capacity fits (a
+// fresh buffer of megabytes pays page faults and regrowth copies on every
+// call).  At most 8 buffers of at most 64 MiB each are kept.
+thread_local std::vector<std::vector<char>> g_table_bufs;
 struct TableBuilder {
   std::vector<char> bytes;
+  TableBuilder() {
+    if (!g_table_bufs.empty()) {
+      bytes.swap(g_table_bufs.back());
+      g_table_bufs.pop_back();
+      bytes.clear();
+    }
+  }
+  ~TableBuilder() {
+    if (bytes.capacity() >= ((size_t)64 << 10) && bytes.capacity() <= ((size_t)64 << 20) && g_table_bufs.size() < 8) {
+      bytes.clear();
+      g_table_bufs.push_back(std::move(bytes));
+    }
+  }
+  TableBuilder(TableBuilder&&) = default;
+  TableBuilder& operator=(TableBuilder&&) = default;
+  TableBuilder(const TableBuilder&) = delete;
+  TableBuilder& operator=(const TableBuilder&) = delete;
   template <typename S>
   size_t add(const std::vector<S>& v) {
     return add_raw(v.data(), sizeof(S) * v.size());
