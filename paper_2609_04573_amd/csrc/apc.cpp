@@ -67,11 +67,13 @@ struct ProfRec {
   double bytes;
 };
 struct Profiler {
-  bool on = false;
+  std::atomic<bool> on{false};
+  std::atomic<bool> filtered{false};  // `only` is set
+  std::mutex mu;     // guards only, recs, pool (launches may come from several threads)
   std::string only;  // if set, only launches of this name are timed
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
-  hipEvent_t get() {
+  hipEvent_t get() {  // with mu held
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
       pool.pop_back();
@@ -83,20 +85,22 @@ struct Profiler {
   }
 };
 Profiler g_prof;
+thread_local bool g_prof_suppress = false;  // this thread's launches are not timed (graph capture)
 
 struct ProfMark {
-  int rec = -1;
+  hipEvent_t b = nullptr;
   hipStream_t st;
   ProfMark(const char* name, double bytes, hipStream_t s) : st(s) {
-    if (!g_prof.on) return;
+    if (!g_prof.on.load(std::memory_order_relaxed) || g_prof_suppress) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
     if (!g_prof.only.empty() && g_prof.only != name) return;
     ProfRec r{name, g_prof.get(), g_prof.get(), bytes};
     (void)hipEventRecord(r.a, st);
     g_prof.recs.push_back(r);
-    rec = (int)g_prof.recs.size() - 1;
+    b = r.b;
   }
   void stop() {
-    if (rec >= 0) (void)hipEventRecord(g_prof.recs[rec].b, st);
+    if (b) (void)hipEventRecord(b, st);
   }
 };
 
@@ -2383,7 +2387,7 @@ apc_status retrieve_impl(apc_handle* h, const std::vector<int>& planes, T* out, 
   // two streams, except while every launch is timed (the per-kernel
   // breakdown is taken on one stream so that no kernel's time includes
   // another's running beside it)
-  bool split = !(g_prof.on && g_prof.only.empty());
+  bool split = !(g_prof.on && !g_prof.filtered);
   bool marks = false;
   for (const Launch& l : ls) marks = marks || l.kind == K_FORK;
   split = split && marks;
@@ -3188,11 +3192,10 @@ apc_status apc_ladder_create(apc_handle* h, const apc_target* targets, int32_t n
     (void)hipStreamDestroy(cs);
     return fail(APC_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e0));
   }
-  const bool prof = g_prof.on;
-  g_prof.on = false;  // no timing events inside a capture
+  g_prof_suppress = true;  // no timing events inside a capture
   apc_status s = h->dtype == APC_F32 ? issue<float, int32_t>(ls, (const char*)ld->tables.p, cs)
                                      : issue<double, int64_t>(ls, (const char*)ld->tables.p, cs);
-  g_prof.on = prof;
+  g_prof_suppress = false;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);
@@ -3687,7 +3690,9 @@ apc_status apc_profile_enable(int32_t on) {
 }
 
 apc_status apc_profile_only(const char* name) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.only = name ? name : "";
+  g_prof.filtered = !g_prof.only.empty();
   return APC_OK;
 }
 
@@ -3697,6 +3702,7 @@ apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len) {
   // Per kernel name: launches, total milliseconds, total bytes moved.  The
   // records are consumed once; the text stays available for a second call
   // (callers ask for the length first).
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   if (!g_prof.recs.empty()) {
     std::vector<std::string> names;
     std::vector<double> ms, bytes;
