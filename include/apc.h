@@ -383,7 +383,9 @@ apc_status apc_axis_norms(int64_t n, int32_t L, int32_t degree, double* inf_out,
  * is bracketed by HIP events recorded on the stream it runs on.
  * apc_profile_report waits for the recorded events and returns, per kernel,
  * {"count", "ms" (summed event time), "bytes" (data the launches must read
- * and write)} as JSON, then clears the records.  Not thread-safe. */
+ * and write)} as JSON, then clears the records.  Launches may come from
+ * several threads while it is enabled (the server's worker, the caller);
+ * launches captured into a graph are not timed. */
 apc_status apc_profile_enable(int32_t on);
 apc_status apc_profile_report(char* buf, int64_t cap, int64_t* len);
 /* Restrict profiling to launches of one kernel name (as reported above);
